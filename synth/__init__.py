@@ -1,0 +1,407 @@
+"""Seeded synthetic inputs for the close-coupling Hamiltonian build.
+
+This module only draws random numbers and enumerates determinants; it holds
+none of the Hamiltonian arithmetic. Both the CPU oracle and the GPU library
+are fed from it, so it must never import either of them.
+
+What is generated (the paper's problem statement, Sec. 2, Eqs. 1-2):
+  * orbital symmetries: an abelian point group with irreps 0..n_irrep-1 whose
+    product is XOR; target orbital p has irrep p mod n_irrep; continuum
+    orbitals come n_c[a] per irrep a, irrep-major, after all target orbitals;
+  * real one-electron integrals h (all orbitals) and the two-electron classes
+    with at most two continuum indices (each N+1 function holds at most one
+    continuum electron): tttt, tttc, ttcc, tctc (chemists' notation);
+  * target determinants per target symmetry, as bitstrings over target
+    spin-orbitals k = 2*orbital + spin (alpha = 0), 64 per uint64 word;
+  * target CI vectors (Eq. 2): orthonormal columns from a seeded QR;
+  * L2 determinants with N+1 electrons in target orbitals (Eq. 1, second sum).
+
+Distributions (global orbital indices in the decay factors):
+  h_pq ~ N(0, 1) * exp(-|p-q|/4), zero unless irrep(p) == irrep(q);
+  (pq|rs) ~ N(0, 0.1) * exp(-(|p-q|+|r-s|)/4), drawn once per 8-fold
+  canonical index, zero unless irrep(p)^irrep(q)^irrep(r)^irrep(s) == 0.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Instance", "TargetSym", "make_instance", "det_to_occ", "occ_to_det",
+    "tiny", "small", "wide", "medium", "precision", "learned_test",
+    "learned_train", "batch_instance", "micro", "CONFIGS",
+]
+
+
+@dataclass
+class TargetSym:
+    irrep: int
+    dets: np.ndarray      # uint64 [M, W]
+    ci: np.ndarray        # float64 [M, S] row-major
+
+
+@dataclass
+class Instance:
+    n_o: int
+    n_elec: int                  # N, target electrons
+    n_irrep: int
+    tgt_irrep: np.ndarray        # uint8 [n_o]
+    n_c: np.ndarray              # int32 [n_irrep], continuum orbitals per irrep
+    total_irrep: int
+    h: np.ndarray                # [n_orb, n_orb]
+    tttt: np.ndarray             # [n_o, n_o, n_o, n_o]      (pq|rs)
+    tttc: np.ndarray             # [n_o, n_o, n_o, n_cont]   (pq|rj)
+    ttcc: np.ndarray             # [n_o, n_o, n_cont, n_cont] (pq|jj')
+    tctc: np.ndarray             # [n_o, n_cont, n_o, n_cont] (pj|qj')
+    e_core: float
+    syms: list = field(default_factory=list)   # list[TargetSym]
+    l2_dets: np.ndarray = None   # uint64 [n_l2, W]
+    name: str = ""
+    seed: int = 0
+
+    @property
+    def n_cont(self) -> int:
+        return int(np.sum(self.n_c))
+
+    @property
+    def n_orb(self) -> int:
+        return self.n_o + self.n_cont
+
+    @property
+    def n_words(self) -> int:
+        return (2 * self.n_o + 63) // 64
+
+    @property
+    def cont_irrep(self) -> np.ndarray:
+        return np.repeat(np.arange(self.n_irrep, dtype=np.uint8), self.n_c)
+
+    @property
+    def orb_irrep(self) -> np.ndarray:
+        return np.concatenate([self.tgt_irrep, self.cont_irrep]).astype(np.uint8)
+
+    @property
+    def n_l2(self) -> int:
+        return 0 if self.l2_dets is None else int(self.l2_dets.shape[0])
+
+    def cont_range(self, irrep: int) -> tuple[int, int]:
+        """Continuum orbitals of one irrep, as a [start, stop) range of j."""
+        off = int(np.sum(self.n_c[:irrep]))
+        return off, off + int(self.n_c[irrep])
+
+    def dim(self) -> int:
+        d = self.n_l2
+        for s in self.syms:
+            a = s.irrep ^ self.total_irrep
+            d += s.ci.shape[1] * int(self.n_c[a])
+        return d
+
+    def n_cont_rows(self) -> int:
+        return self.dim() - self.n_l2
+
+
+# ----------------------------------------------------------------------------
+# bitstring helpers (pure data conversion)
+# ----------------------------------------------------------------------------
+
+def occ_to_det(occ, n_words: int) -> np.ndarray:
+    w = np.zeros(n_words, dtype=np.uint64)
+    for k in occ:
+        w[k >> 6] |= np.uint64(1) << np.uint64(k & 63)
+    return w
+
+
+def det_to_occ(det) -> list:
+    occ = []
+    for wi, word in enumerate(np.asarray(det, dtype=np.uint64)):
+        word = int(word)
+        b = 0
+        while word:
+            if word & 1:
+                occ.append(64 * wi + b)
+            word >>= 1
+            b += 1
+    return occ
+
+
+# ----------------------------------------------------------------------------
+# integrals
+# ----------------------------------------------------------------------------
+
+def _irreps(n_o, n_irrep, n_c):
+    tgt = (np.arange(n_o) % n_irrep).astype(np.uint8)
+    cont = np.repeat(np.arange(n_irrep, dtype=np.uint8), n_c)
+    return tgt, cont
+
+
+def _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, sd2=0.1):
+    n_cont = len(cont_irrep)
+    n_orb = n_o + n_cont
+    oi = np.concatenate([tgt_irrep, cont_irrep]).astype(np.int64)
+    g = np.arange(n_orb, dtype=np.float64)          # global orbital index
+
+    # one-electron: symmetric, decaying, symmetry-blocked
+    x = rng.standard_normal((n_orb, n_orb))
+    x = np.tril(x) + np.tril(x, -1).T
+    h = x * np.exp(-np.abs(g[:, None] - g[None, :]) / 4.0)
+    h[oi[:, None] != oi[None, :]] = 0.0
+
+    t = np.arange(n_o)
+    ti = oi[:n_o]
+    # tttt: canonical over pq >= rs with p >= q, r >= s
+    P, Q, R, S = np.meshgrid(t, t, t, t, indexing="ij")
+    pq = np.maximum(P, Q) * (np.maximum(P, Q) + 1) // 2 + np.minimum(P, Q)
+    rs = np.maximum(R, S) * (np.maximum(R, S) + 1) // 2 + np.minimum(R, S)
+    key = np.maximum(pq, rs) * (np.maximum(pq, rs) + 1) // 2 + np.minimum(pq, rs)
+    npair = n_o * (n_o + 1) // 2
+    draws = rng.standard_normal(npair * (npair + 1) // 2) * sd2
+    tttt = draws[key] * np.exp(-(np.abs(P - Q) + np.abs(R - S)) / 4.0)
+    tttt[(ti[P] ^ ti[Q] ^ ti[R] ^ ti[S]) != 0] = 0.0
+    del P, Q, R, S, pq, rs, key
+
+    gc = g[n_o:]
+    ci = oi[n_o:]
+    # tttc (pq|rj): symmetric in p, q only
+    tttc = np.empty((n_o, n_o, n_o, n_cont))
+    for p in range(n_o):
+        for q in range(p + 1):
+            blk = rng.standard_normal((n_o, n_cont)) * sd2
+            blk *= np.exp(-(abs(p - q) + np.abs(t[:, None] - gc[None, :])) / 4.0)
+            blk[(ti[p] ^ ti[q] ^ ti[:, None] ^ ci[None, :]) != 0] = 0.0
+            tttc[p, q] = blk
+            tttc[q, p] = blk
+    # ttcc (pq|jj'): symmetric in p, q and in j, j'
+    ttcc = np.empty((n_o, n_o, n_cont, n_cont))
+    dcc = np.exp(-np.abs(gc[:, None] - gc[None, :]) / 4.0)
+    mcc = (ci[:, None] ^ ci[None, :])
+    for p in range(n_o):
+        for q in range(p + 1):
+            x = rng.standard_normal((n_cont, n_cont)) * sd2
+            x = np.tril(x) + np.tril(x, -1).T
+            x *= dcc * math.exp(-abs(p - q) / 4.0)
+            x[(mcc ^ ti[p] ^ ti[q]) != 0] = 0.0
+            ttcc[p, q] = x
+            ttcc[q, p] = x
+    # tctc (pj|qj'): symmetric under (p,j) <-> (q,j')
+    tctc = np.empty((n_o, n_cont, n_o, n_cont))
+    for p in range(n_o):
+        dp = np.exp(-np.abs(p - gc) / 4.0)
+        for q in range(p + 1):
+            dq = np.exp(-np.abs(q - gc) / 4.0)
+            x = rng.standard_normal((n_cont, n_cont)) * sd2
+            if p == q:
+                x = np.tril(x) + np.tril(x, -1).T
+            x *= dp[:, None] * dq[None, :]
+            x[(mcc ^ ti[p] ^ ti[q]) != 0] = 0.0
+            tctc[p, :, q, :] = x
+            tctc[q, :, p, :] = x.T
+    return h, tttt, tttc, ttcc, tctc
+
+
+# ----------------------------------------------------------------------------
+# determinant spaces
+# ----------------------------------------------------------------------------
+
+def _strings(n_o, n_e, max_level):
+    """Occupation strings of one spin with at most max_level excitations
+    from the aufbau string, as (level, tuple(occupied orbitals))."""
+    ref = list(range(n_e))
+    virt = list(range(n_e, n_o))
+    out = []
+    for lev in range(0, max_level + 1):
+        if lev > min(n_e, n_o - n_e):
+            break
+        for holes in itertools.combinations(ref, lev):
+            keep = [o for o in ref if o not in holes]
+            for parts in itertools.combinations(virt, lev):
+                out.append((lev, tuple(sorted(keep + list(parts)))))
+    return out
+
+
+def _det_space(rng, n_o, n_a, n_b, tgt_irrep, irrep, count):
+    """CISD-like determinant space: alpha/beta strings by excitation level
+    from the aufbau reference, combined, filtered by irrep, ordered by
+    (total level, seeded key); the first `count` are taken."""
+    n_words = (2 * n_o + 63) // 64
+    tir = np.asarray(tgt_irrep, dtype=np.int64)
+    for max_level in range(2, 2 * n_o + 1):
+        sa = _strings(n_o, n_a, max_level)
+        sb = _strings(n_o, n_b, max_level)
+        la = np.array([l for l, _ in sa]); lb = np.array([l for l, _ in sb])
+        ia = np.array([np.bitwise_xor.reduce(tir[list(o)]) if o else 0 for _, o in sa])
+        ib = np.array([np.bitwise_xor.reduce(tir[list(o)]) if o else 0 for _, o in sb])
+        cand = []
+        for x_l in range(max_level + 1):
+            xs = np.nonzero(la == x_l)[0]
+            for y_l in range(max_level + 1 - x_l):
+                ys = np.nonzero(lb == y_l)[0]
+                if len(xs) == 0 or len(ys) == 0:
+                    continue
+                X, Y = np.meshgrid(xs, ys, indexing="ij")
+                X = X.ravel(); Y = Y.ravel()
+                ok = (ia[X] ^ ib[Y]) == irrep
+                cand.append(np.stack([np.full(ok.sum(), x_l + y_l), X[ok], Y[ok]], 1))
+        cand = np.concatenate(cand) if cand else np.zeros((0, 3), dtype=np.int64)
+        if len(cand) >= count:
+            break
+    else:
+        raise ValueError("determinant space too small for the requested count")
+    keys = rng.random(len(cand))
+    order = np.lexsort((keys, cand[:, 0]))[:count]
+    dets = np.zeros((count, n_words), dtype=np.uint64)
+    for r, c in enumerate(order):
+        _, x, y = cand[c]
+        occ = [2 * o for o in sa[x][1]] + [2 * o + 1 for o in sb[y][1]]
+        dets[r] = occ_to_det(sorted(occ), n_words)
+    return dets
+
+
+def _ci(rng, m, s):
+    a = rng.standard_normal((m, s))
+    q, r = np.linalg.qr(a)
+    sg = np.sign(np.diag(r))
+    sg[sg == 0] = 1.0
+    return np.ascontiguousarray(q * sg[None, :])
+
+
+# ----------------------------------------------------------------------------
+# instances
+# ----------------------------------------------------------------------------
+
+def make_instance(n_o, n_elec, n_irrep, n_c, sym_irreps, n_det, n_states,
+                  n_l2, seed, e_core=0.0, name="", total_irrep=0):
+    """n_c: continuum orbitals per irrep (int or list); sym_irreps: irreps of
+    the target symmetries; n_det/n_states: per symmetry (int or list)."""
+    if n_elec % 2:
+        raise ValueError("n_elec must be even (n_alpha = n_beta = N/2)")
+    rng = np.random.default_rng(seed)
+    if np.isscalar(n_c):
+        n_c = [int(n_c)] * n_irrep
+    n_c = np.asarray(n_c, dtype=np.int32)
+    nsym = len(sym_irreps)
+    n_det = [n_det] * nsym if np.isscalar(n_det) else list(n_det)
+    n_states = [n_states] * nsym if np.isscalar(n_states) else list(n_states)
+    tgt_irrep, cont_irrep = _irreps(n_o, n_irrep, n_c)
+    h, tttt, tttc, ttcc, tctc = _gen_integrals(rng, n_o, tgt_irrep, cont_irrep)
+    na = nb = n_elec // 2
+    syms = []
+    for irr, m, s in zip(sym_irreps, n_det, n_states):
+        dets = _det_space(rng, n_o, na, nb, tgt_irrep, irr, m)
+        syms.append(TargetSym(int(irr), dets, _ci(rng, m, s)))
+    l2 = _det_space(rng, n_o, na + 1, nb, tgt_irrep, total_irrep, n_l2) if n_l2 else \
+        np.zeros((0, (2 * n_o + 63) // 64), dtype=np.uint64)
+    return Instance(n_o=n_o, n_elec=n_elec, n_irrep=n_irrep, tgt_irrep=tgt_irrep,
+                    n_c=n_c, total_irrep=total_irrep, h=h, tttt=tttt, tttc=tttc,
+                    ttcc=ttcc, tctc=tctc, e_core=float(e_core), syms=syms,
+                    l2_dets=l2, name=name, seed=seed)
+
+
+def tiny(seed=101):
+    """10 target orbitals, N=6, 40 dets in 1 symmetry, 3 states, 20 continuum
+    orbitals, 50 L2 configurations: D = 110."""
+    return make_instance(10, 6, 1, 20, [0], 40, 3, 50, seed, name="tiny")
+
+
+def small(seed=111):
+    """Multi-tile parity case: 2 symmetries (irreps 0, 1) x 120 dets x 4 states,
+    40 continuum orbitals per irrep, 300 L2 functions: D = 620."""
+    return make_instance(12, 6, 2, [40, 37], [0, 1], [120, 97], [4, 3], 301, seed,
+                         name="small")
+
+
+def wide(seed=121):
+    """Two-word determinants (36 target orbitals = 72 spin-orbitals): the
+    64-bit word boundary is crossed by occupied orbitals and excitations."""
+    return make_instance(36, 8, 1, 30, [0], 150, 5, 200, seed, name="wide")
+
+
+def medium(seed=202):
+    """30 target orbitals, N=10, 4 symmetries x 500 dets x 5 states,
+    150 continuum orbitals per irrep, 5000 L2: D = 8000."""
+    return make_instance(30, 10, 4, 150, [0, 1, 2, 3], 500, 5, 5000, seed,
+                         name="medium")
+
+
+def precision(seed=303):
+    """40 target orbitals, N=12, 8000 dets, 1 symmetry, 40 states,
+    300 continuum orbitals, 28000 L2: D = 40000."""
+    return make_instance(40, 12, 1, 300, [0], 8000, 40, 28000, seed,
+                         name="precision")
+
+
+def learned_test(seed=999):
+    """40 target orbitals, N=12, 8000 dets, 50 states, 400 continuum,
+    40000 L2: D = 60000."""
+    return make_instance(40, 12, 1, 400, [0], 8000, 50, 40000, seed,
+                         name="learned_test")
+
+
+def _batch_like(rng, seed, d_lo, d_hi, name):
+    while True:
+        d = int(rng.integers(d_lo, d_hi + 1))
+        n_o = int(rng.integers(12, 41))
+        n_sym = int(rng.choice([1, 2, 4]))
+        n_irrep = n_sym
+        s = int(rng.integers(5, 31))
+        nc = int(rng.integers(50, 201))
+        n_elec = int(rng.choice([4, 6, 8, 10, 12]))
+        n_l2 = d - n_sym * s * nc
+        if n_l2 >= 0:
+            break
+    m = max(s, int(rng.integers(2 * s, 8 * s + 1)))
+    return make_instance(n_o, n_elec, n_irrep, nc, list(range(n_sym)), m, s, n_l2,
+                         seed, name=name)
+
+
+def batch_instance(i):
+    """One of the 64 batched instances: D ~ U[500, 6000], 12-40 target
+    orbitals, 5-30 states, 50-200 continuum orbitals per irrep."""
+    rng = np.random.default_rng(400 + i)
+    return _batch_like(rng, 400 + i, 500, 6000, f"batch{i}")
+
+
+def learned_train(i):
+    rng = np.random.default_rng(500 + i)
+    return _batch_like(rng, 500 + i, 2000, 20000, f"train{i}")
+
+
+def micro(seed, n_o=3, n_elec=2, n_c=2, n_irrep=1, n_det=None, n_states=None,
+          n_l2=None):
+    """Instances small enough for a Fock-space brute force: all N-electron
+    determinants of the requested irreps may be used."""
+    rng = np.random.default_rng(seed)
+    n_irrep_syms = list(range(n_irrep))
+    tgt_irrep, _ = _irreps(n_o, n_irrep, [n_c] * n_irrep)
+    na = n_elec // 2
+    # count available dets per irrep
+    dets_avail = []
+    for irr in n_irrep_syms:
+        cnt = 0
+        for oa in itertools.combinations(range(n_o), na):
+            for ob in itertools.combinations(range(n_o), na):
+                r = 0
+                for o in oa + ob:
+                    r ^= int(tgt_irrep[o])
+                cnt += (r == irr)
+        dets_avail.append(cnt)
+    nd = [min(dets_avail[i], n_det if n_det else dets_avail[i]) for i in n_irrep_syms]
+    ns = [max(1, min(nd[i], n_states if n_states else max(1, nd[i] // 2)))
+          for i in n_irrep_syms]
+    cnt_l2 = 0
+    for oa in itertools.combinations(range(n_o), na + 1):
+        for ob in itertools.combinations(range(n_o), na):
+            r = 0
+            for o in oa + ob:
+                r ^= int(tgt_irrep[o])
+            cnt_l2 += (r == 0)
+    nl2 = cnt_l2 if n_l2 is None else min(cnt_l2, n_l2)
+    return make_instance(n_o, n_elec, n_irrep, n_c, n_irrep_syms, nd, ns, nl2,
+                         int(rng.integers(1 << 30)), name=f"micro{seed}")
+
+
+CONFIGS = {
+    "tiny": tiny, "small": small, "wide": wide, "medium": medium,
+    "precision": precision, "learned_test": learned_test,
+}

@@ -1,0 +1,67 @@
+"""Shared test helpers: basis bookkeeping written from the definitions
+(Eq. 1 basis, Eq. 2 contraction), independent of both the oracle's C code
+and the GPU library."""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+import synth
+
+
+def uncontracted_functions(inst):
+    """(N+1)-electron determinants of the uncontracted basis, in the order
+    (symmetry i, target det m, continuum j) then L2 l; continuum electron
+    u_j = spin-orbital 2*(n_o + j), alpha, last."""
+    funcs = []
+    for s in inst.syms:
+        a = s.irrep ^ inst.total_irrep
+        j0, j1 = inst.cont_range(a)
+        for m in range(s.dets.shape[0]):
+            occ = synth.det_to_occ(s.dets[m])
+            for j in range(j0, j1):
+                funcs.append(occ + [2 * (inst.n_o + j)])
+    for l in range(inst.n_l2):
+        funcs.append(synth.det_to_occ(inst.l2_dets[l]))
+    return funcs
+
+
+def contraction_matrix(inst):
+    """T = (+)_i (C_i x I_nc) (+) I_L2, mapping contracted rows (i, n, j)
+    to uncontracted (i, m, j)."""
+    blocks = []
+    for s in inst.syms:
+        a = s.irrep ^ inst.total_irrep
+        nc = int(inst.n_c[a])
+        blocks.append(np.kron(s.ci, np.eye(nc)))
+    blocks.append(np.eye(inst.n_l2))
+    rows = sum(b.shape[0] for b in blocks)
+    cols = sum(b.shape[1] for b in blocks)
+    T = np.zeros((rows, cols))
+    r = c = 0
+    for b in blocks:
+        T[r:r + b.shape[0], c:c + b.shape[1]] = b
+        r += b.shape[0]
+        c += b.shape[1]
+    return T
+
+
+def perm_parity(seq):
+    """(-1)^(number of inversions)."""
+    inv = 0
+    for a, b in itertools.combinations(range(len(seq)), 2):
+        inv += seq[a] > seq[b]
+    return -1 if inv % 2 else 1
+
+
+def substitution_sign(A, B):
+    """Sign s with A = s * (ket B with each hole replaced in place by its
+    particle): the parity of the permutation that sorts the substituted ket.
+    Holes/particles paired in ascending order."""
+    holes = sorted(set(B) - set(A))
+    parts = sorted(set(A) - set(B))
+    sub = list(B)
+    for h, p in zip(holes, parts):
+        sub[sub.index(h)] = p
+    return perm_parity(sub), holes, parts
