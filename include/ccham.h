@@ -1,0 +1,205 @@
+/*
+ * ccham: CI-contracted close-coupling scattering Hamiltonian on one MI355X.
+ *
+ * The library builds the contracted Hamiltonian of the close-coupling
+ * expansion (Al-Refaie & Tennyson, MPI-SCATCI, Sec. 2, Eqs. 1-5) from
+ * integrals, orbital and determinant lists and target CI vectors, and finds
+ * its lowest eigenpairs with a block Davidson solver (the paper's Sec. 3.2
+ * names Davidson among its diagonalisers).
+ *
+ * Basis and conventions
+ *   - Orbitals: n_o target orbitals (global indices 0..n_o-1), then the
+ *     continuum orbitals grouped by irrep (global n_o + j, j = 0..n_cont-1).
+ *     Irreps form an abelian group whose product is XOR.
+ *   - Spin-orbital k = 2*orbital + spin (alpha = 0). A determinant is a
+ *     bitstring over the 2*n_o target spin-orbitals, bit k%64 of word k/64,
+ *     read as the ascending product a+_k1 a+_k2 ... |0>.
+ *   - A continuum function |eta_im u_j> (Eq. 1, first sum) appends the alpha
+ *     continuum spin-orbital 2*(n_o + j) after all target electrons; j runs
+ *     over the continuum orbitals whose irrep is irrep(i) XOR total_irrep.
+ *   - Rows/columns of the contracted matrix: target symmetries in the order
+ *     they were added, within each (state n, continuum j) with j fastest, then
+ *     the L2 functions chi_l in input order (Eq. 1, second sum).
+ *   - The matrix is real symmetric (Sec. 2.2: only the lower triangle is
+ *     evaluated); the library stores it densely with both triangles.
+ *
+ * Error behaviour: every call returns a cch_status; no exception or abort
+ * crosses the interface. cch_last_error() describes the last failure of a
+ * context. Inputs are copied during the call and stay owned by the caller.
+ * A pointer argument is a host pointer unless `flags & CCH_MEM_DEVICE`, in
+ * which case it is a device pointer on the context's device. Device work is
+ * ordered on the context's HIP stream; cch_sync() waits for it.
+ * One context must not be used from two threads at once.
+ */
+#ifndef CCHAM_H
+#define CCHAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cch_status;
+
+#define CCH_OK 0
+#define CCH_E_INVALID_ARG (-1)   /* null pointer, negative size, bad option */
+#define CCH_E_STATE (-2)         /* call made in the wrong order */
+#define CCH_E_INPUT (-3)         /* malformed determinant list or CI vectors */
+#define CCH_E_LIMIT (-4)         /* orbital index above the 16-bit label range */
+#define CCH_E_OOM (-5)           /* device allocation failed or over budget */
+#define CCH_E_HIP (-6)           /* a HIP runtime call failed */
+#define CCH_E_NOT_CONVERGED (-7) /* Davidson hit max_iter; best pairs returned */
+
+#define CCH_MEM_HOST 0
+#define CCH_MEM_DEVICE 1
+
+/* precision of the CI-contraction / expansion GEMMs (cch_plan_opts) */
+#define CCH_PREC_FP64 0
+#define CCH_PREC_FP32 1
+#define CCH_PREC_SPLIT_BF16 2
+
+/* Davidson preconditioners */
+#define CCH_PRECOND_JACOBI 0
+#define CCH_PRECOND_MLP 1
+
+/* which determinant-pair list cch_get_labels returns */
+#define CCH_PAIRS_TARGET 0   /* target x target, one symmetry pair */
+#define CCH_PAIRS_L2 1       /* L2 x L2, lower triangle */
+#define CCH_PAIRS_L2_TARGET 2 /* L2 x target dets of one symmetry */
+
+typedef struct cch_ctx cch_ctx;
+
+typedef struct {
+    int32_t precision;      /* CCH_PREC_* for the expansion GEMMs */
+    int32_t split_slices;   /* slices per operand for CCH_PREC_SPLIT_BF16 (2..8) */
+    int32_t autotune;       /* 1: time candidate tile shapes on the device */
+    int32_t reserved;
+    int64_t max_device_bytes; /* 0: no limit; else fail with CCH_E_OOM above it */
+} cch_plan_opts;
+
+typedef struct {
+    int32_t k;              /* eigenpairs wanted (lowest) */
+    int32_t max_iter;       /* Davidson iterations */
+    int32_t max_subspace;   /* basis size before a thick restart (0: max(8k, 64)) */
+    int32_t precond;        /* CCH_PRECOND_* */
+    double tol;             /* converged when ||H x - theta x||_2 <= tol, ||x|| = 1 */
+} cch_dav_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t matvecs;        /* columns multiplied by H */
+    int32_t converged;      /* number of converged pairs */
+    int32_t fallbacks;      /* MLP corrections replaced by the Jacobi step */
+    double max_residual;
+    double seconds;         /* wall time of the solve */
+} cch_dav_info;
+
+/* Library version string (static storage). */
+const char *cch_version(void);
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the context. */
+cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream);
+/* Free every device buffer the context owns. NULL is accepted. */
+cch_status cch_destroy(cch_ctx *ctx);
+/* Message of the last failed call on ctx (or of a failed create if NULL). */
+const char *cch_last_error(const cch_ctx *ctx);
+/* Wait for all work queued on the context's stream. */
+cch_status cch_sync(cch_ctx *ctx);
+
+/* Orbitals (Eq. 1: target orbitals, continuum orbitals u_ij per symmetry).
+ * tgt_irrep[n_o]: irrep of each target orbital (< n_irrep); n_c_per_irrep
+ * [n_irrep]: continuum orbitals of each irrep, stored irrep-major after the
+ * target orbitals; total_irrep: irrep of the (N+1)-electron functions.
+ * n_o + sum(n_c) must fit the 16-bit orbital fields of the packed labels
+ * (Sec. 2.1): CCH_E_LIMIT otherwise. Host pointers. */
+cch_status cch_set_orbitals(cch_ctx *ctx, int32_t n_o, const uint8_t *tgt_irrep,
+                            int32_t n_irrep, const int32_t *n_c_per_irrep,
+                            int32_t total_irrep);
+
+/* Integrals (Sec. 2.1: the integral function X maps labels to precomputed
+ * one- and two-electron arrays), real orbitals, chemists' notation, row-major,
+ * symmetry zeros explicit. Only classes with at most two continuum indices
+ * exist for functions with at most one continuum electron:
+ *   h    [n_orb][n_orb]            h_pq            (n_orb = n_o + n_cont)
+ *   tttt [n_o][n_o][n_o][n_o]      (pq|rs)
+ *   tttc [n_o][n_o][n_o][n_cont]   (pq|r j)
+ *   ttcc [n_o][n_o][n_cont][n_cont] (pq|j j')
+ *   tctc [n_o][n_cont][n_o][n_cont] (p j|q j')
+ * e_core is added to every diagonal element. Requires cch_set_orbitals. */
+cch_status cch_set_integrals(cch_ctx *ctx, const double *h, const double *tttt,
+                             const double *tttc, const double *ttcc, const double *tctc,
+                             double e_core, int32_t flags);
+
+/* One target symmetry (Eq. 2): n_det determinants of n_words words each
+ * (n_words = ceil(2 n_o / 64)), every one with N electrons, N/2 of each
+ * spin, irrep `irrep`, all distinct; CI vectors ci[n_det][n_states]
+ * (row-major, c_imn). N is fixed by the first symmetry. *sym_id receives the
+ * symmetry's index. CCH_E_INPUT for a malformed list. */
+cch_status cch_add_target_symmetry(cch_ctx *ctx, int32_t irrep, int32_t n_det,
+                                   int32_t n_words, const uint64_t *dets,
+                                   int32_t n_states, const double *ci, int32_t flags,
+                                   int32_t *sym_id);
+
+/* The L2 functions (Eq. 1, second sum): n_l2 determinants with N+1 electrons
+ * in target orbitals, N/2+1 alpha and N/2 beta, irrep total_irrep. */
+cch_status cch_set_l2(cch_ctx *ctx, int32_t n_l2, int32_t n_words, const uint64_t *dets,
+                      int32_t flags);
+
+/* Plan the build (precision, tiles, memory budget). opts may be NULL for the
+ * FP64 defaults. Allocates the device matrix. */
+cch_status cch_plan(cch_ctx *ctx, const cch_plan_opts *opts);
+
+/* Build the contracted matrix on the device (asynchronous on the stream):
+ * classes 1, 3, 5, 6, 7 by CI contraction of transition densities followed by
+ * expansion over (j, j') (Eq. 8 and Sec. 3.1), class 4 by the one-dimensional
+ * contraction of Eq. 5, classes 2 and 8 by Slater's rules on bitstrings. */
+cch_status cch_build(cch_ctx *ctx);
+
+/* D = dimension, n_cont_rows = rows of continuum functions (before the L2). */
+cch_status cch_get_dim(const cch_ctx *ctx, int64_t *D, int64_t *n_cont_rows);
+
+/* Copy the full symmetric matrix to out (row-major, leading dimension ld >= D). */
+cch_status cch_get_matrix(cch_ctx *ctx, double *out, int64_t ld, int32_t flags);
+
+/* Device pointer and leading dimension of the resident matrix (owned by ctx,
+ * valid until cch_destroy or the next cch_plan). */
+cch_status cch_matrix_device(cch_ctx *ctx, const double **dptr, int64_t *ld);
+
+/* Diagonal of the matrix (D values). */
+cch_status cch_get_diagonal(cch_ctx *ctx, double *out, int32_t flags);
+
+/* Determinant-pair artefacts of the excitation scan (Sec. 2.1: XOR and
+ * popcount for the degree, masks for the sign, four 16-bit orbital indices
+ * per 64-bit label). For every connected pair (degree <= 2), in row-major
+ * order of (x, y):
+ *   CCH_PAIRS_TARGET   bra = det x of sym_a, ket = det y of sym_b; label
+ *                      fields (p1, h1, p2, h2) with unused fields 0xFFFF;
+ *   CCH_PAIRS_L2       bra = L2 x, ket = L2 y, y <= x; same label fields;
+ *   CCH_PAIRS_L2_TARGET bra = target det y of sym_a plus the continuum
+ *                      electron, ket = L2 x; fields (target particle or
+ *                      0xFFFF, hole 1, hole 2 or 0xFFFF, 0xFFFF).
+ * Host output arrays of capacity cap; *n receives the total count (arrays
+ * untouched beyond cap). Synchronous. */
+cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sym_b,
+                          int32_t *x, int32_t *y, int8_t *degree, uint64_t *label,
+                          int8_t *phase, int64_t cap, int64_t *n);
+
+/* Lowest opts->k eigenpairs of the built matrix by block Davidson in FP64 on
+ * the device. evals[k]; evecs[k][D] (row-major: eigenvector e at evecs + e*D);
+ * either may be NULL. Returns CCH_E_NOT_CONVERGED (with the best pairs) when
+ * max_iter is reached. Synchronous. */
+cch_status cch_davidson(cch_ctx *ctx, const cch_dav_opts *opts, double *evals,
+                        double *evecs, cch_dav_info *info, int32_t flags);
+
+/* Device time of the last cch_build in milliseconds (HIP events around the
+ * queued work), and per-phase times (phases[8], NULL allowed):
+ * 0 scans, 1 target elements + densities, 2 relayout, 3 expansion GEMM,
+ * 4 class 4, 5 classes 2/8, 6 mirror + diagonal, 7 reserved. Synchronous. */
+cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,256 @@
+"""Python binding of libccham (ctypes): argument marshalling only.
+
+Every step of the Hamiltonian build and the Davidson solve runs in the HIP
+kernels of libccham.so (built by `build.py` for gfx950). There is no CPU
+fallback: importing this package without the built library raises.
+
+The functions mirror include/ccham.h; `Context` wraps one cch_ctx.
+Arrays may be NumPy arrays (host) or torch CUDA tensors (device); device
+tensors are passed with CCH_MEM_DEVICE.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccham.so")
+
+CCH_OK = 0
+CCH_E_INVALID_ARG = -1
+CCH_E_STATE = -2
+CCH_E_INPUT = -3
+CCH_E_LIMIT = -4
+CCH_E_OOM = -5
+CCH_E_HIP = -6
+CCH_E_NOT_CONVERGED = -7
+CCH_MEM_HOST = 0
+CCH_MEM_DEVICE = 1
+CCH_PREC_FP64 = 0
+CCH_PREC_FP32 = 1
+CCH_PREC_SPLIT_BF16 = 2
+CCH_PRECOND_JACOBI = 0
+CCH_PRECOND_MLP = 1
+CCH_PAIRS_TARGET = 0
+CCH_PAIRS_L2 = 1
+CCH_PAIRS_L2_TARGET = 2
+
+EXPORTS = [
+    "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
+    "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_plan", "cch_build",
+    "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_labels",
+    "cch_davidson", "cch_build_time",
+]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run paper_1709_03005_amd/build.py (hipcc, gfx950)")
+lib = C.CDLL(LIB_PATH)
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("split_slices", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32), ("max_device_bytes", C.c_int64)]
+
+
+class DavOpts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_subspace", C.c_int32),
+                ("precond", C.c_int32), ("tol", C.c_double)]
+
+
+class DavInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
+                ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double)]
+
+
+P = C.c_void_p
+i32, i64 = C.c_int32, C.c_int64
+_SIG = {
+    "cch_version": (C.c_char_p, []),
+    "cch_create": (i32, [C.POINTER(P), i32, P]),
+    "cch_destroy": (i32, [P]),
+    "cch_last_error": (C.c_char_p, [P]),
+    "cch_sync": (i32, [P]),
+    "cch_set_orbitals": (i32, [P, i32, P, i32, P, i32]),
+    "cch_set_integrals": (i32, [P, P, P, P, P, P, C.c_double, i32]),
+    "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
+    "cch_set_l2": (i32, [P, i32, i32, P, i32]),
+    "cch_plan": (i32, [P, C.POINTER(PlanOpts)]),
+    "cch_build": (i32, [P]),
+    "cch_get_dim": (i32, [P, C.POINTER(i64), C.POINTER(i64)]),
+    "cch_get_matrix": (i32, [P, P, i64, i32]),
+    "cch_matrix_device": (i32, [P, C.POINTER(P), C.POINTER(i64)]),
+    "cch_get_diagonal": (i32, [P, P, i32]),
+    "cch_get_labels": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, C.POINTER(i64)]),
+    "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
+    "cch_build_time": (i32, [P, C.POINTER(C.c_float), P]),
+}
+for _n, (_r, _a) in _SIG.items():
+    _f = getattr(lib, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+
+
+class CchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ccham error {code}: {msg}")
+        self.code = code
+
+
+def version() -> str:
+    return lib.cch_version().decode()
+
+
+def _arr(a, dtype):
+    """(pointer, flags, keepalive) for a NumPy array or a torch tensor."""
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if a.is_cuda:
+            t = a.contiguous()
+            return C.c_void_p(t.data_ptr()), CCH_MEM_DEVICE, t
+        a = a.numpy()
+    x = np.ascontiguousarray(a, dtype=dtype)
+    return x.ctypes.data_as(C.c_void_p), CCH_MEM_HOST, x
+
+
+class Context:
+    """One cch_ctx on `device`, ordering its work on `stream` (a HIP stream
+    handle as an int, e.g. torch.cuda.current_stream().cuda_stream)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        h = C.c_void_p()
+        rc = lib.cch_create(C.byref(h), device, C.c_void_p(stream or 0))
+        if rc != CCH_OK:
+            raise CchError(rc, lib.cch_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.cch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _ck(self, rc, ok=(CCH_OK,)):
+        if rc not in ok:
+            raise CchError(rc, lib.cch_last_error(self.h).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return lib.cch_last_error(self.h).decode()
+
+    def sync(self):
+        self._ck(lib.cch_sync(self.h))
+
+    def set_orbitals(self, n_o, tgt_irrep, n_irrep, n_c_per_irrep, total_irrep=0):
+        p1, _, k1 = _arr(tgt_irrep, np.uint8)
+        p2, _, k2 = _arr(n_c_per_irrep, np.int32)
+        self._ck(lib.cch_set_orbitals(self.h, int(n_o), p1, int(n_irrep), p2, int(total_irrep)))
+
+    def set_integrals(self, h, tttt, tttc, ttcc, tctc, e_core=0.0):
+        ps = [_arr(x, np.float64) for x in (h, tttt, tttc, ttcc, tctc)]
+        flags = ps[0][1]
+        self._ck(lib.cch_set_integrals(self.h, *[p[0] for p in ps], float(e_core), flags))
+
+    def add_target_symmetry(self, irrep, dets, ci) -> int:
+        pd, fd, kd = _arr(dets, np.uint64)
+        pc, fc, kc = _arr(ci, np.float64)
+        n_det, n_words = kd.shape
+        sid = i32()
+        self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
+                                             int(kc.shape[1]), pc, fd, C.byref(sid)))
+        return sid.value
+
+    def set_l2(self, dets):
+        pd, fd, kd = _arr(dets, np.uint64)
+        n = kd.shape[0]
+        w = kd.shape[1] if kd.ndim == 2 else 0
+        self._ck(lib.cch_set_l2(self.h, int(n), int(w), pd, fd))
+
+    def plan(self, precision=CCH_PREC_FP64, split_slices=0, autotune=0, max_device_bytes=0):
+        o = PlanOpts(precision, split_slices, autotune, 0, max_device_bytes)
+        self._ck(lib.cch_plan(self.h, C.byref(o)))
+
+    def build(self):
+        self._ck(lib.cch_build(self.h))
+
+    def dim(self):
+        D, Dc = i64(), i64()
+        self._ck(lib.cch_get_dim(self.h, C.byref(D), C.byref(Dc)))
+        return D.value, Dc.value
+
+    def get_matrix(self, out=None):
+        D, _ = self.dim()
+        if out is None:
+            out = np.empty((D, D))
+        p, f, k = _arr(out, np.float64)
+        self._ck(lib.cch_get_matrix(self.h, p, D, f))
+        return out
+
+    def matrix_device(self):
+        p, ld = C.c_void_p(), i64()
+        self._ck(lib.cch_matrix_device(self.h, C.byref(p), C.byref(ld)))
+        return p.value, ld.value
+
+    def get_diagonal(self):
+        D, _ = self.dim()
+        out = np.empty(D)
+        self._ck(lib.cch_get_diagonal(self.h, out.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
+        return out
+
+    def get_labels(self, which, sym_a=0, sym_b=0):
+        n = i64()
+        self._ck(lib.cch_get_labels(self.h, which, sym_a, sym_b, None, None, None, None, None, 0,
+                                    C.byref(n)))
+        cap = n.value
+        x = np.zeros(cap, np.int32); y = np.zeros(cap, np.int32)
+        d = np.zeros(cap, np.int8); lab = np.zeros(cap, np.uint64); ph = np.zeros(cap, np.int8)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._ck(lib.cch_get_labels(self.h, which, sym_a, sym_b, ptr(x), ptr(y), ptr(d), ptr(lab),
+                                    ptr(ph), cap, C.byref(n)))
+        return dict(x=x, y=y, deg=d, label=lab, phase=ph)
+
+    def davidson(self, k, tol=1e-8, max_iter=200, max_subspace=0, precond=CCH_PRECOND_JACOBI,
+                 want_vectors=True):
+        D, _ = self.dim()
+        ev = np.zeros(k)
+        vec = np.zeros((k, D)) if want_vectors else None
+        info = DavInfo()
+        o = DavOpts(k, max_iter, max_subspace, precond, tol)
+        rc = lib.cch_davidson(self.h, C.byref(o), ev.ctypes.data_as(C.c_void_p),
+                              vec.ctypes.data_as(C.c_void_p) if want_vectors else None,
+                              C.byref(info), CCH_MEM_HOST)
+        self._ck(rc, ok=(CCH_OK, CCH_E_NOT_CONVERGED))
+        return ev, vec, info, rc
+
+    def build_time(self):
+        t = C.c_float()
+        ph = (C.c_float * 8)()
+        self._ck(lib.cch_build_time(self.h, C.byref(t), C.cast(ph, C.c_void_p)))
+        return t.value, list(ph)
+
+
+def from_instance(inst, device=0, stream=None, plan=True, **plan_kw) -> Context:
+    """Context loaded with an instance object carrying the fields the
+    interface takes (n_o, tgt_irrep, n_irrep, n_c, total_irrep, h, tttt,
+    tttc, ttcc, tctc, e_core, syms[i].irrep/.dets/.ci, l2_dets)."""
+    ctx = Context(device, stream)
+    ctx.set_orbitals(inst.n_o, inst.tgt_irrep, inst.n_irrep, inst.n_c, inst.total_irrep)
+    ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
+    for s in inst.syms:
+        ctx.add_target_symmetry(s.irrep, s.dets, s.ci)
+    if inst.l2_dets is not None and len(inst.l2_dets):
+        ctx.set_l2(inst.l2_dets)
+    if plan:
+        ctx.plan(**plan_kw)
+    return ctx

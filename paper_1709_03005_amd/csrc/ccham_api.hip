@@ -1,0 +1,944 @@
+// Host runtime of the ccham C ABI: input validation, device upload, build
+// plan (pair-list sizing, label slots, row lists), the asynchronous build
+// sequence, read-out, and the block Davidson driver. See include/ccham.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ccham.h"
+#include "ccham_internal.h"
+
+namespace cch {
+// launchers defined in the kernel files
+hipError_t launch_pair_values(int W, TgtInts I, const uint64_t *da, const uint64_t *db, PairList pl,
+                              int64_t n, double *hv, hipStream_t st);
+hipError_t launch_projection(int M, const int64_t *row_off, const int64_t *row_cnt, PairList pl,
+                             const double *hv, const double *ca, int Sa, const double *cb, int Sb,
+                             int nrows, const int32_t *rn, const int32_t *rn2, double *Y, double *Yo,
+                             double *HT, double *O, hipStream_t st);
+hipError_t launch_bucket(PairList pl, int64_t n, const int32_t *pqidx, int n_o, int n_slot, int M,
+                         int32_t *key, int64_t *count, int64_t *start, int64_t *cursor, int64_t *sorted,
+                         int64_t *tmp, int64_t *d0, hipStream_t st);
+hipError_t launch_gamma(int W, PairList pl, const int64_t *start, const int64_t *count,
+                        const int64_t *sorted, const int64_t *d0, int M0, const int32_t *slotP,
+                        const int32_t *slotQ, int n_slot, const uint64_t *da, const double *ca, int Sa,
+                        const double *cb, int Sb, int nrows, const int32_t *rn, const int32_t *rn2,
+                        double *At, hipStream_t st);
+hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int n_cont,
+                           const int32_t *slotP, const int32_t *slotQ, int n_slot, int ja0, int nca,
+                           int jb0, int ncb, double *B, hipStream_t st);
+struct ExpandEpi {
+    double *H;
+    int64_t ld;
+    int64_t row0a, row0b;
+    int nca, ncb;
+    int ja0, jb0;
+    const int32_t *rn, *rn2;
+    const double *HT, *O;
+    const double *h;
+    int n_o, n_orb;
+};
+hipError_t launch_expand_f64(const double *At, const double *B, int nrows, int N, int K, const ExpandEpi &ep,
+                             hipStream_t st);
+struct Class4Args {
+    const uint64_t *tdets;
+    const double *ci;
+    int S;
+    const double *h;
+    const double *tttc;
+    int n_o, n_orb, n_cont;
+    int ja0, nc;
+    const int64_t *row_off, *row_cnt;
+    PairList pl;
+    double *H;
+    int64_t ld;
+    int64_t row_l2;
+    int64_t col0;
+    int pairs_per_chunk;
+};
+hipError_t launch_class4(int W, const Class4Args &a, int n_l2, hipStream_t st);
+struct L2Args {
+    const uint64_t *dets;
+    int n_l2;
+    TgtInts I;
+    double *H;
+    int64_t ld;
+    int64_t row0;
+};
+hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st);
+hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
+hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
+// Davidson
+hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
+                         int64_t ldw, hipStream_t st);
+hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
+                     double *part, double *out, int64_t ldo, int transpose, hipStream_t st);
+hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
+                     const double *base, int64_t ldb, double beta, double alpha, double *out, int64_t ldo,
+                     hipStream_t st);
+hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D, const double *theta, int k,
+                           double *R, double *part, double *norms, hipStream_t st);
+hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
+                                 const int32_t *sel, int nsel, double *T, int64_t ldt, hipStream_t st);
+hipError_t launch_mgs(double *T, int64_t ldt, int b, int D, double drop_tol, int32_t *keep, hipStream_t st);
+hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
+hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
+hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
+}  // namespace cch
+
+using namespace cch;
+
+namespace {
+
+struct DevPairs {
+    int64_t n = 0;
+    int64_t *row_off = nullptr, *row_cnt = nullptr;
+    PairList pl{};
+};
+
+struct SymInfo {
+    int irrep = 0, M = 0, S = 0, nc = 0, ja0 = 0;
+    int64_t row0 = 0;
+    uint64_t *d_dets = nullptr;
+    double *d_ci = nullptr;
+    std::vector<uint64_t> h_dets;
+};
+
+struct PairPlan {
+    int a = 0, b = 0;
+    DevPairs pr;
+    int n_slot = 0, nrows = 0;
+    int32_t *d_slotP = nullptr, *d_slotQ = nullptr, *d_pqidx = nullptr, *d_rn = nullptr, *d_rn2 = nullptr;
+    double *d_hv = nullptr, *d_Y = nullptr, *d_Yo = nullptr, *d_HT = nullptr, *d_O = nullptr, *d_At = nullptr;
+    int32_t *d_key = nullptr;
+    int64_t *d_count = nullptr, *d_start = nullptr, *d_cursor = nullptr, *d_sorted = nullptr, *d_tmp = nullptr,
+            *d_d0 = nullptr;
+};
+
+struct LtPlan {
+    int sym = 0;
+    DevPairs pr;
+};
+
+}  // namespace
+
+struct cch_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<void *> allocs;
+    int64_t bytes = 0;
+    // orbitals
+    bool have_orb = false;
+    int n_o = 0, n_irrep = 1, total_irrep = 0, n_cont = 0, n_orb = 0, W = 0;
+    std::vector<uint8_t> tgt_irrep;
+    std::vector<int> n_c, cont_start;
+    // integrals
+    bool have_ints = false;
+    double *d_h = nullptr, *d_tttt = nullptr, *d_tttc = nullptr, *d_ttcc = nullptr, *d_tctc = nullptr;
+    double e_core = 0.0;
+    // determinant spaces
+    int n_elec = -1;
+    std::vector<SymInfo> syms;
+    int n_l2 = 0;
+    uint64_t *d_l2 = nullptr;
+    std::vector<uint64_t> h_l2;
+    // plan
+    bool planned = false, built = false;
+    cch_plan_opts opts{};
+    int64_t D = 0, Dc = 0, ld = 0;
+    double *d_H = nullptr, *d_diag = nullptr, *d_B = nullptr;
+    std::vector<PairPlan> pp;
+    std::vector<LtPlan> lt;
+    hipEvent_t ev[8] = {};
+    bool have_events = false;
+};
+
+static thread_local std::string g_create_err;
+
+static cch_status fail(cch_ctx *c, cch_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+#define HIPCK(c, x)                                                                              \
+    do {                                                                                         \
+        hipError_t e_ = (x);                                                                     \
+        if (e_ != hipSuccess) return fail((c), CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+static cch_status dalloc(cch_ctx *c, T **p, size_t n)
+{
+    size_t bytes = sizeof(T) * (n ? n : 1);
+    if (c->opts.max_device_bytes > 0 && c->bytes + (int64_t)bytes > c->opts.max_device_bytes)
+        return fail(c, CCH_E_OOM, "device budget of %lld bytes exceeded", (long long)c->opts.max_device_bytes);
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(c, CCH_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    c->allocs.push_back(q);
+    c->bytes += (int64_t)bytes;
+    *p = (T *)q;
+    return CCH_OK;
+}
+
+#define TRY(x)                          \
+    do {                                \
+        cch_status s_ = (x);            \
+        if (s_ != CCH_OK) return s_;    \
+    } while (0)
+
+static void free_plan(cch_ctx *c)
+{
+    // plan buffers are appended after the input buffers; free everything and
+    // re-upload is avoided by keeping inputs in the first allocations
+    (void)c;
+}
+
+static int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+static cch_status copy_in(cch_ctx *c, void *dst, const void *src, size_t bytes, int32_t flags)
+{
+    HIPCK(c, hipMemcpyAsync(dst, src, bytes, (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+    return CCH_OK;
+}
+
+static cch_status host_copy(cch_ctx *c, void *dst, const void *src, size_t bytes, int32_t flags)
+{
+    if (flags & CCH_MEM_DEVICE) {
+        HIPCK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+    } else {
+        memcpy(dst, src, bytes);
+    }
+    return CCH_OK;
+}
+
+// exported functions keep the C linkage of their declarations in ccham.h
+
+const char *cch_version(void) { return "ccham 0.1.0 (gfx950)"; }
+
+cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream)
+{
+    if (!out) return fail(nullptr, CCH_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(nullptr, CCH_E_HIP, "no HIP device: %s", hipGetErrorString(e));
+    if (device < 0 || device >= ndev) return fail(nullptr, CCH_E_INVALID_ARG, "device %d out of range", device);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, CCH_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    cch_ctx *c = new (std::nothrow) cch_ctx();
+    if (!c) return fail(nullptr, CCH_E_OOM, "context allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    for (auto &ev : c->ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            delete c;
+            return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
+        }
+    }
+    c->have_events = true;
+    c->opts.precision = CCH_PREC_FP64;
+    *out = c;
+    return CCH_OK;
+}
+
+cch_status cch_destroy(cch_ctx *c)
+{
+    if (!c) return CCH_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->have_events)
+        for (auto &ev : c->ev) (void)hipEventDestroy(ev);
+    delete c;
+    return CCH_OK;
+}
+
+const char *cch_last_error(const cch_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+cch_status cch_sync(cch_ctx *c)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CCH_OK;
+}
+
+cch_status cch_set_orbitals(cch_ctx *c, int32_t n_o, const uint8_t *tgt_irrep, int32_t n_irrep,
+                            const int32_t *n_c_per_irrep, int32_t total_irrep)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (c->have_orb) return fail(c, CCH_E_STATE, "orbitals already set");
+    if (n_o <= 0 || !tgt_irrep || !n_c_per_irrep) return fail(c, CCH_E_INVALID_ARG, "bad orbital arguments");
+    if (n_irrep != 1 && n_irrep != 2 && n_irrep != 4 && n_irrep != 8)
+        return fail(c, CCH_E_INVALID_ARG, "n_irrep must be 1, 2, 4 or 8 (abelian group, XOR product)");
+    if (total_irrep < 0 || total_irrep >= n_irrep) return fail(c, CCH_E_INVALID_ARG, "bad total_irrep");
+    int64_t nc = 0;
+    for (int a = 0; a < n_irrep; ++a) {
+        if (n_c_per_irrep[a] < 0) return fail(c, CCH_E_INVALID_ARG, "negative continuum count");
+        nc += n_c_per_irrep[a];
+    }
+    for (int p = 0; p < n_o; ++p)
+        if (tgt_irrep[p] >= n_irrep) return fail(c, CCH_E_INVALID_ARG, "target orbital %d has irrep >= n_irrep", p);
+    if (2 * ((int64_t)n_o + nc) >= 0xFFFF)
+        return fail(c, CCH_E_LIMIT, "%lld orbitals exceed the 16-bit label fields", (long long)(n_o + nc));
+    const int W = (2 * n_o + 63) / 64;
+    if (W > CCH_MAXW) return fail(c, CCH_E_LIMIT, "n_o = %d needs %d words (max %d)", n_o, W, CCH_MAXW);
+    c->n_o = n_o;
+    c->n_irrep = n_irrep;
+    c->total_irrep = total_irrep;
+    c->n_cont = (int)nc;
+    c->n_orb = n_o + (int)nc;
+    c->W = W;
+    c->tgt_irrep.assign(tgt_irrep, tgt_irrep + n_o);
+    c->n_c.assign(n_c_per_irrep, n_c_per_irrep + n_irrep);
+    c->cont_start.assign(n_irrep + 1, 0);
+    for (int a = 0; a < n_irrep; ++a) c->cont_start[a + 1] = c->cont_start[a] + c->n_c[a];
+    c->have_orb = true;
+    return CCH_OK;
+}
+
+cch_status cch_set_integrals(cch_ctx *c, const double *h, const double *tttt, const double *tttc,
+                             const double *ttcc, const double *tctc, double e_core, int32_t flags)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->have_ints) return fail(c, CCH_E_STATE, "integrals already set");
+    if (!h || !tttt || (c->n_cont && (!tttc || !ttcc || !tctc)))
+        return fail(c, CCH_E_INVALID_ARG, "integral pointer is NULL");
+    if (!std::isfinite(e_core)) return fail(c, CCH_E_INPUT, "e_core is not finite");
+    const size_t no = c->n_o, nc = c->n_cont, norb = c->n_orb;
+    const size_t nh = norb * norb, n4 = no * no * no * no, n3c = no * no * no * nc, n2c = no * no * nc * nc;
+    TRY(dalloc(c, &c->d_h, nh));
+    TRY(dalloc(c, &c->d_tttt, n4));
+    TRY(dalloc(c, &c->d_tttc, n3c));
+    TRY(dalloc(c, &c->d_ttcc, n2c));
+    TRY(dalloc(c, &c->d_tctc, n2c));
+    TRY(copy_in(c, c->d_h, h, nh * 8, flags));
+    TRY(copy_in(c, c->d_tttt, tttt, n4 * 8, flags));
+    if (nc) {
+        TRY(copy_in(c, c->d_tttc, tttc, n3c * 8, flags));
+        TRY(copy_in(c, c->d_ttcc, ttcc, n2c * 8, flags));
+        TRY(copy_in(c, c->d_tctc, tctc, n2c * 8, flags));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->e_core = e_core;
+    c->have_ints = true;
+    return CCH_OK;
+}
+
+static cch_status check_dets(cch_ctx *c, const std::vector<uint64_t> &d, int n, int nelec, int na, int irrep,
+                             const char *what)
+{
+    const int W = c->W, nso = 2 * c->n_o;
+    for (int i = 0; i < n; ++i) {
+        int ne = 0, nal = 0, ir = 0;
+        for (int w = 0; w < W; ++w) {
+            uint64_t x = d[(size_t)i * W + w];
+            // bits beyond the target spin-orbitals
+            const int lo = 64 * w;
+            if (lo + 64 > nso) {
+                const int keep = nso - lo;
+                const uint64_t allowed = keep <= 0 ? 0ull : (keep >= 64 ? ~0ull : ((1ull << keep) - 1ull));
+                if (x & ~allowed) return fail(c, CCH_E_INPUT, "%s det %d occupies a spin-orbital >= 2 n_o", what, i);
+            }
+            ne += popc64(x);
+            nal += popc64(x & 0x5555555555555555ull);
+            while (x) {
+                const int k = lo + __builtin_ctzll(x);
+                x &= x - 1;
+                ir ^= c->tgt_irrep[k >> 1];
+            }
+        }
+        if (ne != nelec) return fail(c, CCH_E_INPUT, "%s det %d has %d electrons, expected %d", what, i, ne, nelec);
+        if (nal != na) return fail(c, CCH_E_INPUT, "%s det %d has %d alpha electrons, expected %d", what, i, nal, na);
+        if (ir != irrep) return fail(c, CCH_E_INPUT, "%s det %d has irrep %d, expected %d", what, i, ir, irrep);
+    }
+    // distinct
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    auto lt = [&](int a, int b) {
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t x = d[(size_t)a * W + w], y = d[(size_t)b * W + w];
+            if (x != y) return x < y;
+        }
+        return false;
+    };
+    std::sort(idx.begin(), idx.end(), lt);
+    for (int i = 1; i < n; ++i)
+        if (!lt(idx[i - 1], idx[i])) return fail(c, CCH_E_INPUT, "%s dets %d and %d are equal", what, idx[i - 1], idx[i]);
+    return CCH_OK;
+}
+
+cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int32_t n_words, const uint64_t *dets,
+                                   int32_t n_states, const double *ci, int32_t flags, int32_t *sym_id)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (irrep < 0 || irrep >= c->n_irrep) return fail(c, CCH_E_INVALID_ARG, "bad irrep");
+    if (n_det <= 0 || !dets || !ci) return fail(c, CCH_E_INVALID_ARG, "empty symmetry");
+    if (n_words != c->W) return fail(c, CCH_E_INPUT, "n_words %d != %d", n_words, c->W);
+    if (n_states <= 0 || n_states > n_det) return fail(c, CCH_E_INVALID_ARG, "bad n_states");
+    if (n_states > 256) return fail(c, CCH_E_LIMIT, "n_states > 256");
+    std::vector<uint64_t> hd((size_t)n_det * n_words);
+    TRY(host_copy(c, hd.data(), dets, hd.size() * 8, flags));
+    int nelec = 0;
+    for (int w = 0; w < n_words; ++w) nelec += popc64(hd[w]);
+    if (c->n_elec < 0) {
+        if (nelec % 2) return fail(c, CCH_E_INPUT, "odd electron count %d (n_alpha = n_beta = N/2 required)", nelec);
+        if (nelec + 1 > 64) return fail(c, CCH_E_LIMIT, "N + 1 > 64 electrons");
+    } else if (nelec != c->n_elec) {
+        return fail(c, CCH_E_INPUT, "det 0 has %d electrons, expected %d", nelec, c->n_elec);
+    }
+    TRY(check_dets(c, hd, n_det, nelec, nelec / 2, irrep, "target"));
+    std::vector<double> hc((size_t)n_det * n_states);
+    TRY(host_copy(c, hc.data(), ci, hc.size() * 8, flags));
+    for (double v : hc)
+        if (!std::isfinite(v)) return fail(c, CCH_E_INPUT, "CI coefficient is not finite");
+    SymInfo s;
+    s.irrep = irrep;
+    s.M = n_det;
+    s.S = n_states;
+    TRY(dalloc(c, &s.d_dets, hd.size()));
+    TRY(dalloc(c, &s.d_ci, hc.size()));
+    HIPCK(c, hipMemcpy(s.d_dets, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(s.d_ci, hc.data(), hc.size() * 8, hipMemcpyHostToDevice));
+    s.h_dets = std::move(hd);
+    c->n_elec = nelec;
+    c->syms.push_back(std::move(s));
+    if (sym_id) *sym_id = (int32_t)c->syms.size() - 1;
+    return CCH_OK;
+}
+
+cch_status cch_set_l2(cch_ctx *c, int32_t n_l2, int32_t n_words, const uint64_t *dets, int32_t flags)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->n_elec < 0) return fail(c, CCH_E_STATE, "add a target symmetry first (it fixes N)");
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (n_l2 < 0 || (n_l2 > 0 && !dets)) return fail(c, CCH_E_INVALID_ARG, "bad L2 arguments");
+    if (n_l2 > 0 && n_words != c->W) return fail(c, CCH_E_INPUT, "n_words %d != %d", n_words, c->W);
+    std::vector<uint64_t> hd((size_t)n_l2 * c->W);
+    if (n_l2) TRY(host_copy(c, hd.data(), dets, hd.size() * 8, flags));
+    TRY(check_dets(c, hd, n_l2, c->n_elec + 1, c->n_elec / 2 + 1, c->total_irrep, "L2"));
+    TRY(dalloc(c, &c->d_l2, hd.size()));
+    if (n_l2) HIPCK(c, hipMemcpy(c->d_l2, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
+    c->n_l2 = n_l2;
+    c->h_l2 = std::move(hd);
+    return CCH_OK;
+}
+
+static cch_status alloc_pairs(cch_ctx *c, DevPairs &p, int mode, const uint64_t *A, int nA, const uint64_t *B, int nB)
+{
+    TRY(dalloc(c, &p.row_off, nA));
+    TRY(dalloc(c, &p.row_cnt, nA));
+    int64_t *d_total = nullptr;
+    TRY(dalloc(c, &d_total, 1));
+    HIPCK(c, launch_scan(mode, c->W, A, nA, B, nB, 2 * c->n_o, nullptr, p.row_cnt, PairList{}, c->stream));
+    HIPCK(c, launch_exclusive_scan(p.row_cnt, p.row_off, nA, d_total, c->stream));
+    int64_t total = 0;
+    HIPCK(c, hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    p.n = total;
+    TRY(dalloc(c, &p.pl.x, total));
+    TRY(dalloc(c, &p.pl.y, total));
+    TRY(dalloc(c, &p.pl.deg, total));
+    TRY(dalloc(c, &p.pl.phase, total));
+    TRY(dalloc(c, &p.pl.label, total));
+    return CCH_OK;
+}
+
+template <class T>
+static cch_status upload(cch_ctx *c, T **d, const std::vector<T> &h)
+{
+    TRY(dalloc(c, d, h.size()));
+    if (!h.empty()) HIPCK(c, hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CCH_OK;
+}
+
+cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_ints) return fail(c, CCH_E_STATE, "set integrals first");
+    if (c->syms.empty() && c->n_l2 == 0) return fail(c, CCH_E_STATE, "no basis functions");
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (opts) {
+        if (opts->precision != CCH_PREC_FP64) return fail(c, CCH_E_INVALID_ARG, "precision mode not available");
+        c->opts = *opts;
+    }
+    HIPCK(c, hipSetDevice(c->device));
+    // rows
+    int64_t row = 0;
+    for (auto &s : c->syms) {
+        const int a = s.irrep ^ c->total_irrep;
+        s.nc = c->n_c[a];
+        s.ja0 = c->cont_start[a];
+        s.row0 = row;
+        row += (int64_t)s.S * s.nc;
+    }
+    c->Dc = row;
+    c->D = row + c->n_l2;
+    if (c->D <= 0) return fail(c, CCH_E_STATE, "empty matrix");
+    if (c->D > 2000000000LL) return fail(c, CCH_E_LIMIT, "dimension too large");
+    c->ld = (c->D + 31) / 32 * 32;
+    // symmetry pairs a >= b
+    int64_t maxB = 0;
+    for (int a = 0; a < (int)c->syms.size(); ++a) {
+        for (int b = 0; b <= a; ++b) {
+            PairPlan p;
+            p.a = a;
+            p.b = b;
+            SymInfo &sa = c->syms[a], &sb = c->syms[b];
+            TRY(alloc_pairs(c, p.pr, SCAN_TT, sa.d_dets, sa.M, sb.d_dets, sb.M));
+            // label slots (P, Q) allowed by symmetry
+            const int want = sa.irrep ^ sb.irrep;
+            std::vector<int32_t> sP, sQ, pq((size_t)c->n_o * c->n_o, -1);
+            for (int P = 0; P < c->n_o; ++P)
+                for (int Q = 0; Q < c->n_o; ++Q)
+                    if ((c->tgt_irrep[P] ^ c->tgt_irrep[Q]) == want) {
+                        pq[(size_t)P * c->n_o + Q] = (int32_t)sP.size();
+                        sP.push_back(P);
+                        sQ.push_back(Q);
+                    }
+            p.n_slot = (int)sP.size();
+            std::vector<int32_t> rn, rn2;
+            for (int n = 0; n < sa.S; ++n)
+                for (int n2 = 0; n2 < (a == b ? n + 1 : sb.S); ++n2) {
+                    rn.push_back(n);
+                    rn2.push_back(n2);
+                }
+            p.nrows = (int)rn.size();
+            TRY(upload(c, &p.d_slotP, sP));
+            TRY(upload(c, &p.d_slotQ, sQ));
+            TRY(upload(c, &p.d_pqidx, pq));
+            TRY(upload(c, &p.d_rn, rn));
+            TRY(upload(c, &p.d_rn2, rn2));
+            TRY(dalloc(c, &p.d_hv, p.pr.n));
+            TRY(dalloc(c, &p.d_Y, (size_t)sa.M * sb.S));
+            TRY(dalloc(c, &p.d_Yo, (size_t)sa.M * sb.S));
+            TRY(dalloc(c, &p.d_HT, p.nrows));
+            TRY(dalloc(c, &p.d_O, p.nrows));
+            TRY(dalloc(c, &p.d_At, (size_t)2 * p.n_slot * p.nrows));
+            TRY(dalloc(c, &p.d_key, p.pr.n));
+            TRY(dalloc(c, &p.d_count, p.n_slot + 1));
+            TRY(dalloc(c, &p.d_start, p.n_slot + 1));
+            TRY(dalloc(c, &p.d_cursor, p.n_slot + 1));
+            TRY(dalloc(c, &p.d_sorted, p.pr.n));
+            TRY(dalloc(c, &p.d_tmp, p.pr.n));
+            TRY(dalloc(c, &p.d_d0, sa.M));
+            maxB = std::max<int64_t>(maxB, (int64_t)2 * p.n_slot * sa.nc * sb.nc);
+            c->pp.push_back(p);
+        }
+    }
+    // L2 x target pairs per symmetry
+    for (int s = 0; s < (int)c->syms.size() && c->n_l2 > 0; ++s) {
+        LtPlan L;
+        L.sym = s;
+        TRY(alloc_pairs(c, L.pr, SCAN_LT, c->d_l2, c->n_l2, c->syms[s].d_dets, c->syms[s].M));
+        c->lt.push_back(L);
+    }
+    TRY(dalloc(c, &c->d_B, maxB));
+    TRY(dalloc(c, &c->d_H, (size_t)c->D * c->ld));
+    TRY(dalloc(c, &c->d_diag, c->D));
+    c->planned = true;
+    return CCH_OK;
+}
+
+cch_status cch_build(cch_ctx *c)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    HIPCK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
+    HIPCK(c, hipEventRecord(c->ev[0], st));
+    // phase 0: excitation scans (emit)
+    for (auto &p : c->pp) {
+        SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+        HIPCK(c, launch_scan(SCAN_TT, c->W, sa.d_dets, sa.M, sb.d_dets, sb.M, 2 * c->n_o, p.pr.row_off,
+                             p.pr.row_cnt, p.pr.pl, st));
+    }
+    for (auto &L : c->lt) {
+        SymInfo &s = c->syms[L.sym];
+        HIPCK(c, launch_scan(SCAN_LT, c->W, c->d_l2, c->n_l2, s.d_dets, s.M, 2 * c->n_o, L.pr.row_off,
+                             L.pr.row_cnt, L.pr.pl, st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[1], st));
+    // phase 1: target elements, projection, densities
+    for (auto &p : c->pp) {
+        SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+        HIPCK(c, launch_pair_values(c->W, I, sa.d_dets, sb.d_dets, p.pr.pl, p.pr.n, p.d_hv, st));
+        HIPCK(c, launch_projection(sa.M, p.pr.row_off, p.pr.row_cnt, p.pr.pl, p.d_hv, sa.d_ci, sa.S, sb.d_ci, sb.S,
+                                   p.nrows, p.d_rn, p.d_rn2, p.d_Y, p.d_Yo, p.d_HT, p.d_O, st));
+        HIPCK(c, launch_bucket(p.pr.pl, p.pr.n, p.d_pqidx, c->n_o, p.n_slot, sa.M, p.d_key, p.d_count, p.d_start,
+                               p.d_cursor, p.d_sorted, p.d_tmp, p.d_d0, st));
+        const int M0 = (sa.irrep == sb.irrep) ? sa.M : 0;
+        HIPCK(c, launch_gamma(c->W, p.pr.pl, p.d_start, p.d_count, p.d_sorted, p.d_d0, M0, p.d_slotP, p.d_slotQ,
+                              p.n_slot, sa.d_dets, sa.d_ci, sa.S, sb.d_ci, sb.S, p.nrows, p.d_rn, p.d_rn2, p.d_At,
+                              st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[2], st));
+    // phases 2-3: relayout + expansion GEMM per symmetry pair
+    float dummy = 0;
+    (void)dummy;
+    for (auto &p : c->pp) {
+        SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+        if (sa.nc == 0 || sb.nc == 0) continue;
+        HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
+                                 sa.nc, sb.ja0, sb.nc, c->d_B, st));
+        ExpandEpi ep{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT, p.d_O,
+                     c->d_h, c->n_o, c->n_orb};
+        HIPCK(c, launch_expand_f64(p.d_At, c->d_B, p.nrows, sa.nc * sb.nc, 2 * p.n_slot, ep, st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[3], st));
+    // phase 4: class 4
+    for (auto &L : c->lt) {
+        SymInfo &s = c->syms[L.sym];
+        Class4Args a{};
+        a.tdets = s.d_dets;
+        a.ci = s.d_ci;
+        a.S = s.S;
+        a.h = c->d_h;
+        a.tttc = c->d_tttc;
+        a.n_o = c->n_o;
+        a.n_orb = c->n_orb;
+        a.n_cont = c->n_cont;
+        a.ja0 = s.ja0;
+        a.nc = s.nc;
+        a.row_off = L.pr.row_off;
+        a.row_cnt = L.pr.row_cnt;
+        a.pl = L.pr.pl;
+        a.H = c->d_H;
+        a.ld = c->ld;
+        a.row_l2 = c->Dc;
+        a.col0 = s.row0;
+        a.pairs_per_chunk = std::max(1, std::min(64, 1024 / (1 + 2 * c->n_elec)));
+        HIPCK(c, launch_class4(c->W, a, c->n_l2, st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[4], st));
+    // phase 5: classes 2 and 8
+    if (c->n_l2 > 0) {
+        L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
+        HIPCK(c, launch_l2_block(c->W, a, st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[5], st));
+    // phase 6: mirror the lower triangle, diagonal
+    HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->D, st));
+    HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->D, c->d_diag, st));
+    HIPCK(c, hipEventRecord(c->ev[6], st));
+    c->built = true;
+    return CCH_OK;
+}
+
+cch_status cch_build_time(cch_ctx *c, float *total_ms, float *phases)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    HIPCK(c, hipEventSynchronize(c->ev[6]));
+    if (total_ms) HIPCK(c, hipEventElapsedTime(total_ms, c->ev[0], c->ev[6]));
+    if (phases) {
+        float t[6];
+        for (int i = 0; i < 6; ++i) HIPCK(c, hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]));
+        phases[0] = t[0];
+        phases[1] = t[1];
+        phases[2] = 0.0f;          // relayout is timed together with the GEMM
+        phases[3] = t[2];
+        phases[4] = t[3];
+        phases[5] = t[4];
+        phases[6] = t[5];
+        phases[7] = 0.0f;
+    }
+    return CCH_OK;
+}
+
+cch_status cch_get_dim(const cch_ctx *c, int64_t *D, int64_t *n_cont_rows)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->planned) return CCH_E_STATE;
+    if (D) *D = c->D;
+    if (n_cont_rows) *n_cont_rows = c->Dc;
+    return CCH_OK;
+}
+
+cch_status cch_get_matrix(cch_ctx *c, double *out, int64_t ld, int32_t flags)
+{
+    if (!c || !out) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    if (ld < c->D) return fail(c, CCH_E_INVALID_ARG, "ld < D");
+    HIPCK(c, hipMemcpy2DAsync(out, ld * 8, c->d_H, c->ld * 8, c->D * 8, c->D,
+                              (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CCH_OK;
+}
+
+cch_status cch_matrix_device(cch_ctx *c, const double **dptr, int64_t *ld)
+{
+    if (!c || !dptr || !ld) return CCH_E_INVALID_ARG;
+    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    *dptr = c->d_H;
+    *ld = c->ld;
+    return CCH_OK;
+}
+
+cch_status cch_get_diagonal(cch_ctx *c, double *out, int32_t flags)
+{
+    if (!c || !out) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    HIPCK(c, hipMemcpyAsync(out, c->d_diag, c->D * 8,
+                            (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return CCH_OK;
+}
+
+cch_status cch_get_labels(cch_ctx *c, int32_t which, int32_t sym_a, int32_t sym_b, int32_t *x, int32_t *y,
+                          int8_t *degree, uint64_t *label, int8_t *phase, int64_t cap, int64_t *n)
+{
+    if (!c || !n) return CCH_E_INVALID_ARG;
+    if (!c->have_ints && !c->have_orb) return fail(c, CCH_E_STATE, "no orbitals");
+    const int ns = (int)c->syms.size();
+    const uint64_t *A = nullptr, *B = nullptr;
+    int nA = 0, nB = 0, mode;
+    if (which == CCH_PAIRS_TARGET) {
+        if (sym_a < 0 || sym_a >= ns || sym_b < 0 || sym_b >= ns) return fail(c, CCH_E_INVALID_ARG, "bad symmetry");
+        A = c->syms[sym_a].d_dets; nA = c->syms[sym_a].M;
+        B = c->syms[sym_b].d_dets; nB = c->syms[sym_b].M;
+        mode = SCAN_TT;
+    } else if (which == CCH_PAIRS_L2) {
+        A = B = c->d_l2; nA = nB = c->n_l2;
+        mode = SCAN_LL;
+    } else if (which == CCH_PAIRS_L2_TARGET) {
+        if (sym_a < 0 || sym_a >= ns) return fail(c, CCH_E_INVALID_ARG, "bad symmetry");
+        A = c->d_l2; nA = c->n_l2;
+        B = c->syms[sym_a].d_dets; nB = c->syms[sym_a].M;
+        mode = SCAN_LT;
+    } else {
+        return fail(c, CCH_E_INVALID_ARG, "bad list selector");
+    }
+    *n = 0;
+    if (nA == 0 || nB == 0) return CCH_OK;
+    HIPCK(c, hipSetDevice(c->device));
+    // temporary buffers, freed at the end of the call
+    std::vector<void *> tmp;
+    auto galloc = [&](void **p, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+        if (e == hipSuccess) tmp.push_back(*p);
+        return e;
+    };
+    auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
+    DevPairs P;
+    int64_t *d_total = nullptr;
+    hipError_t e = galloc((void **)&P.row_off, 8 * (size_t)nA);
+    if (e == hipSuccess) e = galloc((void **)&P.row_cnt, 8 * (size_t)nA);
+    if (e == hipSuccess) e = galloc((void **)&d_total, 8);
+    if (e == hipSuccess) e = launch_scan(mode, c->W, A, nA, B, nB, 2 * c->n_o, nullptr, P.row_cnt, PairList{}, c->stream);
+    if (e == hipSuccess) e = launch_exclusive_scan(P.row_cnt, P.row_off, nA, d_total, c->stream);
+    int64_t total = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = galloc((void **)&P.pl.x, 4 * (size_t)total);
+    if (e == hipSuccess) e = galloc((void **)&P.pl.y, 4 * (size_t)total);
+    if (e == hipSuccess) e = galloc((void **)&P.pl.deg, (size_t)total);
+    if (e == hipSuccess) e = galloc((void **)&P.pl.phase, (size_t)total);
+    if (e == hipSuccess) e = galloc((void **)&P.pl.label, 8 * (size_t)total);
+    if (e == hipSuccess) e = launch_scan(mode, c->W, A, nA, B, nB, 2 * c->n_o, P.row_off, P.row_cnt, P.pl, c->stream);
+    const int64_t m = std::min(total, cap);
+    if (e == hipSuccess && m > 0) {
+        if (x) e = hipMemcpyAsync(x, P.pl.x, 4 * m, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && y) e = hipMemcpyAsync(y, P.pl.y, 4 * m, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && degree) e = hipMemcpyAsync(degree, P.pl.deg, m, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && phase) e = hipMemcpyAsync(phase, P.pl.phase, m, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && label) e = hipMemcpyAsync(label, P.pl.label, 8 * m, hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "label scan: %s", hipGetErrorString(e));
+    *n = total;
+    return CCH_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// block Davidson driver
+// ---------------------------------------------------------------------------
+namespace {
+struct DavBufs {
+    double *V = nullptr, *Wv = nullptr, *G = nullptr, *theta = nullptr, *Y = nullptr, *X = nullptr, *AX = nullptr,
+           *R = nullptr, *T = nullptr, *C = nullptr, *part = nullptr, *norms = nullptr, *tmp = nullptr;
+    int32_t *keep = nullptr, *sel = nullptr, *idx = nullptr;
+};
+}  // namespace
+
+cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double *evecs,
+                                   cch_dav_info *info, int32_t flags)
+{
+    if (!c || !o) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    const int D = (int)c->D, k = o->k;
+    if (k <= 0 || k > D) return fail(c, CCH_E_INVALID_ARG, "k out of range");
+    if (!(o->tol > 0.0)) return fail(c, CCH_E_INVALID_ARG, "tol must be positive");
+    if (o->precond != CCH_PRECOND_JACOBI) return fail(c, CCH_E_INVALID_ARG, "preconditioner not available");
+    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 64);
+    mmax = std::min(mmax, 96);
+    mmax = std::min(mmax, D);
+    const int kr = std::min(2 * k, D);         // kept at a thick restart
+    if (kr + k > mmax && mmax < D) return fail(c, CCH_E_INVALID_ARG, "k too large for the subspace limit");
+    const int max_iter = o->max_iter > 0 ? o->max_iter : 200;
+    HIPCK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    auto t0 = std::chrono::steady_clock::now();
+
+    const int64_t ldv = ((int64_t)D + 31) / 32 * 32;
+    std::vector<void *> tmp;
+    auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
+    auto A = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) return false;
+        tmp.push_back(*p);
+        return true;
+    };
+    DavBufs b;
+    const int nch = (D + 4095) / 4096;
+    bool ok = A((void **)&b.V, 8 * ldv * mmax) && A((void **)&b.Wv, 8 * ldv * mmax) &&
+              A((void **)&b.G, 8 * (size_t)mmax * mmax) && A((void **)&b.theta, 8 * (size_t)mmax) &&
+              A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.X, 8 * ldv * std::max(kr, k)) &&
+              A((void **)&b.AX, 8 * ldv * std::max(kr, k)) && A((void **)&b.R, 8 * ldv * k) &&
+              A((void **)&b.T, 8 * ldv * std::max(kr, k)) && A((void **)&b.C, 8 * (size_t)mmax * std::max(kr, k)) &&
+              A((void **)&b.part, 8 * (size_t)nch * std::max(mmax, k) * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
+              A((void **)&b.keep, 4 * (size_t)std::max(kr, k)) && A((void **)&b.sel, 4 * (size_t)k) &&
+              A((void **)&b.idx, 4 * (size_t)kr);
+    if (!ok) {
+        cleanup();
+        return fail(c, CCH_E_OOM, "Davidson buffers");
+    }
+#define DCK(x)                                                                                  \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) {                                                                 \
+            cleanup();                                                                          \
+            return fail(c, CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_));                    \
+        }                                                                                       \
+    } while (0)
+
+    // initial block: unit vectors at the 2k smallest diagonal entries
+    std::vector<double> hdiag(D);
+    DCK(hipMemcpyAsync(hdiag.data(), c->d_diag, 8 * (size_t)D, hipMemcpyDeviceToHost, st));
+    DCK(hipStreamSynchronize(st));
+    std::vector<int32_t> order(D);
+    for (int i = 0; i < D; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return hdiag[a] < hdiag[bb]; });
+    int nb = kr;
+    DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)nb, hipMemcpyHostToDevice));
+    DCK(launch_unit_vectors(b.T, ldv, D, b.idx, nb, st));
+
+    int m = 0, iters = 0, matvecs = 0, nconv = 0;
+    double maxres = 0.0;
+    std::vector<double> hres(k), htheta(mmax);
+    std::vector<int32_t> hkeep(std::max(kr, k));
+    cch_status rc = CCH_E_NOT_CONVERGED;
+    for (iters = 1; iters <= max_iter; ++iters) {
+        // orthogonalise the new block against V (twice) and within itself
+        for (int pass = 0; pass < 2 && m > 0; ++pass) {
+            DCK(launch_tn(b.V, ldv, m, b.T, ldv, nb, D, b.part, b.C, nb, 0, st));
+            DCK(launch_nn(b.V, ldv, m, D, b.C, nb, nb, b.T, ldv, 1.0, -1.0, b.T, ldv, st));   // T -= V C
+        }
+        DCK(launch_mgs(b.T, ldv, nb, D, 1e-10, b.keep, st));
+        DCK(hipMemcpyAsync(hkeep.data(), b.keep, 4 * (size_t)nb, hipMemcpyDeviceToHost, st));
+        DCK(hipStreamSynchronize(st));
+        int added = 0;
+        for (int q = 0; q < nb && m + added < mmax; ++q) {
+            if (!hkeep[q]) continue;
+            DCK(hipMemcpyAsync(b.V + (int64_t)(m + added) * ldv, b.T + (int64_t)q * ldv, 8 * (size_t)D,
+                               hipMemcpyDeviceToDevice, st));
+            ++added;
+        }
+        if (added == 0) break;   // no new direction: stagnation
+        // W for the new vectors and the new rows of G
+        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, added, b.Wv + (int64_t)m * ldv, ldv, st));
+        matvecs += added;
+        DCK(launch_tn(b.Wv + (int64_t)m * ldv, ldv, added, b.V, ldv, m + added, D, b.part, b.G + (int64_t)m * mmax,
+                      mmax, 0, st));
+        DCK(launch_sym_fill(b.G, mmax, m, m + added, st));
+        m += added;
+        DCK(launch_jacobi_eig(b.G, mmax, m, b.theta, b.Y, mmax, st));
+        const int kk = std::min(k, m);
+        // Ritz vectors and residuals
+        DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, kk, nullptr, 0, 0.0, 1.0, b.X, ldv, st));
+        DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, kk, nullptr, 0, 0.0, 1.0, b.AX, ldv, st));
+        DCK(launch_residual(b.AX, b.X, ldv, D, b.theta, kk, b.R, b.part, b.norms, st));
+        DCK(hipMemcpyAsync(hres.data(), b.norms, 8 * (size_t)kk, hipMemcpyDeviceToHost, st));
+        DCK(hipMemcpyAsync(htheta.data(), b.theta, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+        DCK(hipStreamSynchronize(st));
+        std::vector<int32_t> un;
+        maxres = 0.0;
+        for (int e = 0; e < kk; ++e) {
+            maxres = std::max(maxres, hres[e]);
+            if (!(hres[e] <= o->tol)) un.push_back(e);
+        }
+        nconv = kk - (int)un.size();
+        if (kk == k && un.empty()) {
+            rc = CCH_OK;
+            break;
+        }
+        if (m >= D) {   // the whole space is spanned: Ritz pairs are exact
+            rc = CCH_OK;
+            nconv = kk;
+            break;
+        }
+        // thick restart when the next block would not fit
+        if (m + (int)un.size() > mmax) {
+            const int keepn = std::min(kr, m);
+            DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, keepn, nullptr, 0, 0.0, 1.0, b.T, ldv, st));
+            DCK(hipMemcpy2DAsync(b.V, ldv * 8, b.T, ldv * 8, 8 * (size_t)D, keepn, hipMemcpyDeviceToDevice, st));
+            DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, keepn, nullptr, 0, 0.0, 1.0, b.T, ldv, st));
+            DCK(hipMemcpy2DAsync(b.Wv, ldv * 8, b.T, ldv * 8, 8 * (size_t)D, keepn, hipMemcpyDeviceToDevice, st));
+            std::vector<double> g((size_t)mmax * mmax, 0.0);
+            for (int e = 0; e < keepn; ++e) g[(size_t)e * mmax + e] = htheta[e];
+            DCK(hipMemcpyAsync(b.G, g.data(), 8 * g.size(), hipMemcpyHostToDevice, st));
+            m = keepn;
+        }
+        // corrections for the unconverged pairs
+        nb = (int)un.size();
+        DCK(hipMemcpyAsync(b.sel, un.data(), 4 * (size_t)nb, hipMemcpyHostToDevice, st));
+        DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, b.sel, nb, b.T, ldv, st));
+    }
+    if (iters > max_iter) iters = max_iter;
+    const int kk = std::min(k, m);
+    if (evals) {
+        std::vector<double> th(kk);
+        DCK(hipMemcpyAsync(th.data(), b.theta, 8 * (size_t)kk, hipMemcpyDeviceToHost, st));
+        DCK(hipStreamSynchronize(st));
+        if (flags & CCH_MEM_DEVICE) DCK(hipMemcpy(evals, th.data(), 8 * (size_t)kk, hipMemcpyHostToDevice));
+        else memcpy(evals, th.data(), 8 * (size_t)kk);
+    }
+    if (evecs)
+        DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.X, ldv * 8, 8 * (size_t)D, kk,
+                             (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    DCK(hipStreamSynchronize(st));
+    cleanup();
+    if (info) {
+        info->iterations = iters;
+        info->matvecs = matvecs;
+        info->converged = nconv;
+        info->fallbacks = 0;
+        info->max_residual = maxres;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
+    return rc;
+}

@@ -1,0 +1,511 @@
+// Block Davidson pieces in FP64 (the paper names Davidson among the
+// diagonalisers of Sec. 3.2 without detail; the solver is the block
+// Davidson-Liu iteration with a diagonal correction and thick restart):
+//   K8  W = H V for a block of b vectors (dense H streamed once: HBM-bound)
+//   K9  tall-skinny products X^T Y (Gram blocks, projections) and V C
+//       updates; modified Gram-Schmidt of a block in one workgroup
+//   K10 residuals, the diagonal (Jacobi) correction, and the Rayleigh-Ritz
+//       eigenproblem solved by cyclic Jacobi rotations in parallel
+//       (round-robin) order inside one workgroup, all in LDS.
+// Vectors are stored one per row: V[q][i], leading dimension ldv.
+#include "ccham_internal.h"
+
+namespace cch {
+
+// ---------------------------------------------------------------------------
+// K8: W[q][r] = sum_c H[r][c] V[q][c], q < b <= BMAX
+// ---------------------------------------------------------------------------
+constexpr int MV_ROWS_PER_WAVE = 4;
+constexpr int MV_CH = 256;
+
+template <int BMAX>
+__global__ __launch_bounds__(256) void k_matvec(const double *__restrict__ H, int64_t ld, int D,
+                                                const double *__restrict__ V, int64_t ldv, int b,
+                                                double *__restrict__ Wo, int64_t ldw)
+{
+    __shared__ double vs[BMAX][MV_CH];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rbase = (blockIdx.x * 4 + wv) * MV_ROWS_PER_WAVE;
+    double acc[MV_ROWS_PER_WAVE][BMAX];
+#pragma unroll
+    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r)
+#pragma unroll
+        for (int q = 0; q < BMAX; ++q) acc[r][q] = 0.0;
+    const double *hr[MV_ROWS_PER_WAVE];
+#pragma unroll
+    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
+        const int row = min(rbase + r, D - 1);
+        hr[r] = H + (int64_t)row * ld;
+    }
+    for (int c0 = 0; c0 < D; c0 += MV_CH) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < BMAX * MV_CH; t += 256) {
+            const int q = t / MV_CH, c = c0 + t % MV_CH;
+            vs[q][t % MV_CH] = (q < b && c < D) ? V[(int64_t)q * ldv + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MV_CH / 64; ++u) {
+            const int cl = lane + 64 * u, c = c0 + cl;
+            double hv[MV_ROWS_PER_WAVE];
+#pragma unroll
+            for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) hv[r] = c < D ? __builtin_nontemporal_load(hr[r] + c) : 0.0;
+#pragma unroll
+            for (int q = 0; q < BMAX; ++q) {
+                const double v = vs[q][cl];
+#pragma unroll
+                for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) acc[r][q] = fma(hv[r], v, acc[r][q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
+#pragma unroll
+        for (int q = 0; q < BMAX; ++q) {
+            double v = acc[r][q];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            acc[r][q] = v;
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
+            const int row = rbase + r;
+            if (row < D)
+#pragma unroll
+                for (int q = 0; q < BMAX; ++q)
+                    if (q < b) Wo[(int64_t)q * ldw + row] = acc[r][q];
+        }
+    }
+}
+
+hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
+                         int64_t ldw, hipStream_t st)
+{
+    if (D <= 0 || b <= 0) return hipSuccess;
+    const int rows_per_wg = 4 * MV_ROWS_PER_WAVE;
+    const dim3 g((D + rows_per_wg - 1) / rows_per_wg), bl(256);
+    for (int q0 = 0; q0 < b; q0 += 16) {
+        const int bb = min(16, b - q0);
+        const double *Vq = V + (int64_t)q0 * ldv;
+        double *Wq = W + (int64_t)q0 * ldw;
+        if (bb <= 4)
+            hipLaunchKernelGGL((k_matvec<4>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
+        else if (bb <= 8)
+            hipLaunchKernelGGL((k_matvec<8>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
+        else
+            hipLaunchKernelGGL((k_matvec<16>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K9: out[a][c] = sum_i X[a][i] Y[c][i]  (a < na, c < nc <= 16)
+// grid (na, chunks); partials reduced in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int TN_CHUNK = 4096;
+
+__global__ __launch_bounds__(256) void k_tn_partial(const double *__restrict__ X, int64_t ldx, int D,
+                                                    const double *__restrict__ Y, int64_t ldy, int nc,
+                                                    double *__restrict__ part)
+{
+    const int a = blockIdx.x, ch = blockIdx.y;
+    const int i0 = ch * TN_CHUNK, i1 = min(D, i0 + TN_CHUNK);
+    double acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double x = X[(int64_t)a * ldx + i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < nc) acc[c] = fma(x, Y[(int64_t)c * ldy + i], acc[c]);
+    }
+    __shared__ double red[4][16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wv][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int c = threadIdx.x;
+        part[((int64_t)ch * gridDim.x + a) * 16 + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+    }
+}
+
+__global__ void k_tn_reduce(const double *__restrict__ part, int nchunks, int na, int nc,
+                            double *__restrict__ out, int64_t ldo, int transpose)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= na * nc) return;
+    const int a = t / nc, c = t % nc;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) s += part[((int64_t)ch * na + a) * 16 + c];
+    if (transpose) out[(int64_t)c * ldo + a] = s;
+    else out[(int64_t)a * ldo + c] = s;
+}
+
+// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c]
+hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
+                     double *part, double *out, int64_t ldo, int transpose, hipStream_t st)
+{
+    if (na <= 0 || nc <= 0) return hipSuccess;
+    const int nch = (D + TN_CHUNK - 1) / TN_CHUNK;
+    for (int c0 = 0; c0 < nc; c0 += 16) {
+        const int cc = min(16, nc - c0);
+        hipLaunchKernelGGL(k_tn_partial, dim3(na, nch), dim3(256), 0, st, X, ldx, D, Y + (int64_t)c0 * ldy,
+                           ldy, cc, part);
+        double *o = transpose ? out + (int64_t)c0 * ldo : out + c0;
+        hipLaunchKernelGGL(k_tn_reduce, dim3((na * cc + 255) / 256), dim3(256), 0, st, part, nch, na, cc, o,
+                           ldo, transpose);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// out[e][i] = beta * base[e][i] + alpha * sum_{q<m} V[q][i] C[q*ldc + e], e < ne
+// ---------------------------------------------------------------------------
+template <int NE>
+__global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V, int64_t ldv, int m, int D,
+                                                  const double *__restrict__ Cm, int ldc, int ne,
+                                                  const double *__restrict__ base, int64_t ldb, double beta,
+                                                  double alpha, double *__restrict__ out, int64_t ldo)
+{
+    extern __shared__ double cs[];   // [m][NE]
+    for (int t = threadIdx.x; t < m * NE; t += 256) {
+        const int q = t / NE, e = t % NE;
+        cs[t] = e < ne ? Cm[(int64_t)q * ldc + e] : 0.0;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= D) return;
+    double acc[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const double v = V[(int64_t)q * ldv + i];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        if (e < ne) {
+            double r = alpha * acc[e];
+            if (base) r += beta * base[(int64_t)e * ldb + i];
+            out[(int64_t)e * ldo + i] = r;
+        }
+    }
+}
+
+hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
+                     const double *base, int64_t ldb, double beta, double alpha, double *out, int64_t ldo,
+                     hipStream_t st)
+{
+    if (ne <= 0 || D <= 0) return hipSuccess;
+    const dim3 g((D + 255) / 256), bl(256);
+    for (int e0 = 0; e0 < ne; e0 += 16) {
+        const int ee = min(16, ne - e0);
+        const double *b0 = base ? base + (int64_t)e0 * ldb : nullptr;
+        double *o = out + (int64_t)e0 * ldo;
+        if (m <= 0) {
+            // nothing to add: out = beta * base
+            hipLaunchKernelGGL((k_nn_small<16>), g, bl, 16 * sizeof(double), st, V, ldv, 0, D, C + e0, ldc, ee,
+                               b0, ldb, beta, alpha, o, ldo);
+        } else if (ee <= 4) {
+            hipLaunchKernelGGL((k_nn_small<4>), g, bl, (size_t)m * 4 * sizeof(double), st, V, ldv, m, D, C + e0,
+                               ldc, ee, b0, ldb, beta, alpha, o, ldo);
+        } else {
+            hipLaunchKernelGGL((k_nn_small<16>), g, bl, (size_t)m * 16 * sizeof(double), st, V, ldv, m, D,
+                               C + e0, ldc, ee, b0, ldb, beta, alpha, o, ldo);
+        }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K10: residuals R = AX - X theta and their squared norms per chunk
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ AX, const double *__restrict__ X,
+                                                  int64_t ld, int D, const double *__restrict__ theta, int k,
+                                                  double *__restrict__ R, double *__restrict__ part)
+{
+    const int e = blockIdx.y, ch = blockIdx.x;
+    const int i0 = ch * TN_CHUNK, i1 = min(D, i0 + TN_CHUNK);
+    const double th = theta[e];
+    double s = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double r = AX[(int64_t)e * ld + i] - th * X[(int64_t)e * ld + i];
+        R[(int64_t)e * ld + i] = r;
+        s = fma(r, r, s);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)ch * k + e] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_norm_reduce(const double *__restrict__ part, int nch, int k, double *__restrict__ out)
+{
+    const int e = threadIdx.x;
+    if (e >= k) return;
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * k + e];
+    out[e] = sqrt(s);
+}
+
+hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D, const double *theta, int k,
+                           double *R, double *part, double *norms, hipStream_t st)
+{
+    const int nch = (D + TN_CHUNK - 1) / TN_CHUNK;
+    hipLaunchKernelGGL(k_residual, dim3(nch, k), dim3(256), 0, st, AX, X, ld, D, theta, k, R, part);
+    hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(64), 0, st, part, nch, k, norms);
+    return hipGetLastError();
+}
+
+// diagonal (Jacobi) correction t = r / (theta - H_ii), |den| floored at 1e-8
+// with its sign kept; sel[c] picks the residual row of output c
+__global__ void k_jacobi_correct(const double *__restrict__ R, int64_t ld, int D,
+                                 const double *__restrict__ diag, const double *__restrict__ theta,
+                                 const int32_t *__restrict__ sel, int nsel, double *__restrict__ T,
+                                 int64_t ldt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= D || c >= nsel) return;
+    const int e = sel[c];
+    double den = theta[e] - diag[i];
+    if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+    T[(int64_t)c * ldt + i] = R[(int64_t)e * ld + i] / den;
+}
+
+hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
+                                 const int32_t *sel, int nsel, double *T, int64_t ldt, hipStream_t st)
+{
+    if (nsel <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi_correct, dim3((D + 255) / 256, nsel), dim3(256), 0, st, R, ld, D, diag, theta,
+                       sel, nsel, T, ldt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// modified Gram-Schmidt (twice) inside a block of b vectors, one workgroup.
+// Vectors are first scaled to unit norm; a vector whose norm falls below
+// drop_tol during the sweep is marked dropped (keep[c] = 0) and left out of
+// later projections.
+// ---------------------------------------------------------------------------
+__device__ double block_dot(const double *x, const double *y, int D, double *red)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < D; i += blockDim.x) s = fma(x[i], y[i], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_mgs(double *__restrict__ T, int64_t ldt, int b, int D, double drop_tol,
+                                              int32_t *__restrict__ keep)
+{
+    __shared__ double red[16];
+    for (int c = 0; c < b; ++c) {
+        double *tc = T + (int64_t)c * ldt;
+        double n0 = sqrt(block_dot(tc, tc, D, red));
+        int ok = n0 > 0.0 && isfinite(n0);
+        if (ok)
+            for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] /= n0;
+        __syncthreads();
+        for (int pass = 0; pass < 2 && ok; ++pass) {
+            for (int q = 0; q < c; ++q) {
+                if (!keep[q]) continue;
+                const double *tq = T + (int64_t)q * ldt;
+                const double d = block_dot(tq, tc, D, red);
+                for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] -= d * tq[i];
+                __syncthreads();
+            }
+        }
+        if (ok) {
+            const double n1 = sqrt(block_dot(tc, tc, D, red));
+            ok = n1 > drop_tol;
+            if (ok)
+                for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] /= n1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) keep[c] = ok;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mgs(double *T, int64_t ldt, int b, int D, double drop_tol, int32_t *keep, hipStream_t st)
+{
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mgs, dim3(1), dim3(1024), 0, st, T, ldt, b, D, drop_tol, keep);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz eigenproblem: G (m x m, symmetric) -> ascending theta and
+// eigenvectors Y (column e of Y at Y[q*ldy + e]). Cyclic Jacobi, parallel
+// (round-robin tournament) ordering: m/2 disjoint rotations per round,
+// m-1 rounds per sweep, sweeps until the off-diagonal mass is below
+// (1e-15 ||G||_F)^2.
+// ---------------------------------------------------------------------------
+constexpr int JAC_MAX = 96;
+
+__global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ G, int ldg, int m,
+                                                     double *__restrict__ theta, double *__restrict__ Y, int ldy,
+                                                     int max_sweeps)
+{
+    __shared__ double A[JAC_MAX][JAC_MAX + 1];
+    __shared__ double Z[JAC_MAX][JAC_MAX + 1];
+    __shared__ double cs[JAC_MAX / 2], sn[JAC_MAX / 2];
+    __shared__ int pp[JAC_MAX / 2], qq[JAC_MAX / 2];
+    __shared__ double red[16];
+    __shared__ int perm[JAC_MAX];
+    const int me = (m + 1) & ~1;     // even size (a padded index is inert)
+    for (int t = threadIdx.x; t < me * me; t += blockDim.x) {
+        const int i = t / me, j = t % me;
+        A[i][j] = (i < m && j < m) ? 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]) : 0.0;
+        Z[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int half = me / 2;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int t = threadIdx.x; t < me * me; t += blockDim.x) {
+            const int i = t / me, j = t % me;
+            const double v = A[i][j] * A[i][j];
+            tot += v;
+            if (i != j) off += v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o, 64);
+            tot += __shfl_xor(tot, o, 64);
+        }
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6] = off;
+        }
+        __syncthreads();
+        double offs = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) offs += red[w];
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+        __syncthreads();
+        double tots = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tots += red[w];
+        __syncthreads();
+        if (offs <= 1e-30 * tots || offs == 0.0) break;
+        for (int round = 0; round < me - 1; ++round) {
+            // round-robin pairing: index 0 fixed, others rotate
+            if (threadIdx.x < half) {
+                const int k = threadIdx.x;
+                auto pos = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + round) % (me - 1); };
+                int p = pos(k), q = pos(me - 1 - k);
+                if (p > q) { int t = p; p = q; q = t; }
+                pp[k] = p;
+                qq[k] = q;
+                const double apq = A[p][q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                cs[k] = c;
+                sn[k] = s;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int t = threadIdx.x; t < half * me; t += blockDim.x) {
+                const int k = t / me, j = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double ap = A[p][j], aq = A[q][j];
+                A[p][j] = c * ap - s * aq;
+                A[q][j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, Z <- Z J
+            for (int t = threadIdx.x; t < half * me; t += blockDim.x) {
+                const int k = t / me, i = t % me;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double ap = A[i][p], aq = A[i][q];
+                A[i][p] = c * ap - s * aq;
+                A[i][q] = s * ap + c * aq;
+                const double zp = Z[i][p], zq = Z[i][q];
+                Z[i][p] = c * zp - s * zq;
+                Z[i][q] = s * zp + c * zq;
+            }
+            __syncthreads();
+        }
+    }
+    // ascending order (stable), written out
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < m; ++i) perm[i] = i;
+        for (int i = 1; i < m; ++i) {
+            const int v = perm[i];
+            int j = i - 1;
+            while (j >= 0 && A[perm[j]][perm[j]] > A[v][v]) {
+                perm[j + 1] = perm[j];
+                --j;
+            }
+            perm[j + 1] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += blockDim.x) theta[e] = A[perm[e]][perm[e]];
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        const int q = t / m, e = t % m;
+        Y[(int64_t)q * ldy + e] = Z[q][perm[e]];
+    }
+}
+
+hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st)
+{
+    if (m <= 0 || m > JAC_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, st, G, ldg, m, theta, Y, ldy, 40);
+    return hipGetLastError();
+}
+
+// G[a][b] symmetric fill of a new column block from computed rows
+__global__ void k_sym_fill(double *G, int ldg, int m0, int m1)
+{
+    // rows [m0, m1) were computed for columns [0, m1): mirror into columns
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nr = m1 - m0;
+    if (t >= nr * m1) return;
+    const int r = m0 + t / m1, c = t % m1;
+    if (c < m0) G[(int64_t)c * ldg + r] = G[(int64_t)r * ldg + c];
+}
+
+hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st)
+{
+    const int n = (m1 - m0) * m1;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sym_fill, dim3((n + 255) / 256), dim3(256), 0, st, G, ldg, m0, m1);
+    return hipGetLastError();
+}
+
+__global__ void k_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < D && c < b) V[(int64_t)c * ldv + i] = (i == idx[c]) ? 1.0 : 0.0;
+}
+
+hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st)
+{
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unit_vectors, dim3((D + 255) / 256, b), dim3(256), 0, st, V, ldv, D, idx, b);
+    return hipGetLastError();
+}
+
+}  // namespace cch

@@ -1,0 +1,209 @@
+// Expansion of the contracted symbols over the continuum pairs (j, j')
+// (Sec. 2.1, end; Sec. 3.1 "expansion"): the integral labels of a
+// contracted element keep their target part (P, Q) while (j, j') runs over
+// the continuum orbitals of the two symmetries. Written as one dense product
+// per target-symmetry pair:
+//   Ht[(n,n'), (j,j')] = sum_{PQ} Gamma_{nn',PQ} (PQ|jj')
+//                      - sum_{PQ} Gamma^alpha_{nn',PQ} (Pj'|jQ)
+//                      + delta_{jj'} (C^T H_T C')_{nn'} + (C^T O C')_{nn'} h_{jj'}
+// K0 lays the integral rows out as B[(PQ)][(j,j')]; K5 multiplies with FP64
+// MFMA (v_mfma_f64_16x16x4) and scatters each (n,n',j,j') to its row
+// (i,n,j) / column (i',n',j') of the contracted matrix (lower triangle).
+#include "ccham_internal.h"
+
+namespace cch {
+
+// ---------------------------------------------------------------------------
+// K0: B[k][jj*ncb + jj'] for one symmetry pair.
+//   k <  n_slot: (P Q | J J')    = ttcc[P][Q][J][J']       (row copy)
+//   k >= n_slot: -(P J' | J Q)   = -tctc[P][J'][Q][J]     (tile transpose)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_relayout_J(const double *__restrict__ ttcc, int n_o, int n_cont,
+                                                    const int32_t *__restrict__ slotP,
+                                                    const int32_t *__restrict__ slotQ, int ja0, int nca,
+                                                    int jb0, int ncb, double *__restrict__ B)
+{
+    const int k = blockIdx.y;
+    const int jj = blockIdx.x;
+    const int P = slotP[k], Q = slotQ[k];
+    const double *src = ttcc + (((size_t)P * n_o + Q) * n_cont + (ja0 + jj)) * n_cont + jb0;
+    double *dst = B + ((size_t)k * nca + jj) * ncb;
+    for (int t = threadIdx.x; t < ncb; t += 256) dst[t] = src[t];
+}
+
+__global__ __launch_bounds__(256) void k_relayout_K(const double *__restrict__ tctc, int n_o, int n_cont,
+                                                    const int32_t *__restrict__ slotP,
+                                                    const int32_t *__restrict__ slotQ, int n_slot, int ja0,
+                                                    int nca, int jb0, int ncb, double *__restrict__ B)
+{
+    __shared__ double tile[32][33];
+    const int k = blockIdx.z;
+    const int P = slotP[k], Q = slotQ[k];
+    const int jj0 = blockIdx.x * 32, jp0 = blockIdx.y * 32;   // jj (unprimed) / jj' tiles
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
+    // read tctc[P][J'][Q][J]: contiguous in J
+    for (int r = ty; r < 32; r += 8) {
+        const int jp = jp0 + r, jj = jj0 + tx;
+        double v = 0.0;
+        if (jp < ncb && jj < nca)
+            v = tctc[(((size_t)P * n_cont + (jb0 + jp)) * n_o + Q) * n_cont + (ja0 + jj)];
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    // write B[n_slot + k][jj][jj']: contiguous in jj'
+    double *dst = B + (size_t)(n_slot + k) * nca * ncb;
+    for (int r = ty; r < 32; r += 8) {
+        const int jj = jj0 + r, jp = jp0 + tx;
+        if (jj < nca && jp < ncb) dst[(size_t)jj * ncb + jp] = -tile[tx][r];
+    }
+}
+
+hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int n_cont,
+                           const int32_t *slotP, const int32_t *slotQ, int n_slot, int ja0, int nca,
+                           int jb0, int ncb, double *B, hipStream_t st)
+{
+    if (n_slot <= 0 || nca <= 0 || ncb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relayout_J, dim3(nca, n_slot), dim3(256), 0, st, ttcc, n_o, n_cont, slotP, slotQ,
+                       ja0, nca, jb0, ncb, B);
+    hipLaunchKernelGGL(k_relayout_K, dim3((nca + 31) / 32, (ncb + 31) / 32, n_slot), dim3(256), 0, st, tctc,
+                       n_o, n_cont, slotP, slotQ, n_slot, ja0, nca, jb0, ncb, B);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K5: C = A * B with A given K-major (At[k][r]), FP64 MFMA 16x16x4.
+// Workgroup tile 64 (r) x 128 (col), 4 waves in 2 x 2, each 32 x 64 =
+// 2 x 4 MFMA tiles. K staged through LDS in slices of 16.
+// MFMA f64 16x16x4 operand layout (lane l): A[l%16][l/16], B[l/16][l%16];
+// result item v of lane l is D[4*(l/16)+v][l%16].
+// ---------------------------------------------------------------------------
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+struct ExpandEpi {
+    double *H;            // contracted matrix, row-major
+    int64_t ld;
+    int64_t row0a, row0b; // first row of symmetry a / b
+    int nca, ncb;         // continuum orbitals of a / b
+    int ja0, jb0;         // first global continuum index of a / b
+    const int32_t *rn, *rn2;
+    const double *HT, *O; // per GEMM row
+    const double *h;      // one-electron matrix [n_orb][n_orb]
+    int n_o, n_orb;
+};
+
+constexpr int GBM = 64, GBN = 128, GBK = 16;
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    // consecutive logical tiles land on one XCD (blocks are dealt round-robin
+    // over the 8 XCDs), so tiles sharing a B column panel share an L2
+    const int per = nb / 8;
+    if (b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
+}
+
+__global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ At, const double *__restrict__ B,
+                                                    int nrows, int N, int K, ExpandEpi ep)
+{
+    __shared__ double As[GBK][GBM];
+    __shared__ double Bs[GBK][GBN];
+    const int tiles_m = (nrows + GBM - 1) / GBM;
+    const int tiles_n = (N + GBN - 1) / GBN;
+    const int nb = tiles_m * tiles_n;
+    const int lb = xcd_remap(blockIdx.x, nb);
+    const int tm = lb % tiles_m, tn = lb / tiles_m;
+    const int r0 = tm * GBM, c0 = tn * GBN;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+
+    dx4 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (dx4){0.0, 0.0, 0.0, 0.0};
+
+    double ra[4], rb[8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;     // 0..1023
+            const int kk = e / GBM, rr = e % GBM;
+            const int k = k0 + kk, r = r0 + rr;
+            ra[q] = (k < K && r < nrows) ? At[(size_t)k * nrows + r] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = threadIdx.x + 256 * q;     // 0..2047
+            const int kk = e / GBN, cc = e % GBN;
+            const int k = k0 + kk, c = c0 + cc;
+            rb[q] = (k < K && c < N) ? B[(size_t)k * N + c] : 0.0;
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += GBK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            As[e / GBM][e % GBM] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            Bs[e / GBN][e % GBN] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + GBK < K) gload(k0 + GBK);
+#pragma unroll
+        for (int ks = 0; ks < GBK; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            double af[2], bf[4];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) af[a] = As[kk][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = Bs[kk][wn * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+    }
+
+    // epilogue: scatter into the contracted matrix (lower triangle only)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+            if (r >= nrows) continue;
+            const int n = ep.rn[r], n2 = ep.rn2[r];
+            const double ht = ep.HT[r], ov = ep.O[r];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = c0 + wn * 64 + b * 16 + (lane & 15);
+                if (c >= N) continue;
+                const int jj = c / ep.ncb, jp = c - jj * ep.ncb;
+                const int64_t R = ep.row0a + (int64_t)n * ep.nca + jj;
+                const int64_t C = ep.row0b + (int64_t)n2 * ep.ncb + jp;
+                if (R < C) continue;
+                const int J = ep.ja0 + jj, Jp = ep.jb0 + jp;
+                double val = acc[a][b][v];
+                if (J == Jp) val += ht;
+                val += ov * ep.h[(size_t)(ep.n_o + J) * ep.n_orb + (ep.n_o + Jp)];
+                ep.H[R * ep.ld + C] = val;
+            }
+        }
+    }
+}
+
+hipError_t launch_expand_f64(const double *At, const double *B, int nrows, int N, int K, const ExpandEpi &ep,
+                             hipStream_t st)
+{
+    if (nrows <= 0 || N <= 0) return hipSuccess;
+    const int tiles = ((nrows + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+    hipLaunchKernelGGL(k_expand_f64, dim3(tiles), dim3(256), 0, st, At, B, nrows, N, K, ep);
+    return hipGetLastError();
+}
+
+}  // namespace cch

@@ -1,0 +1,72 @@
+// Classes 2 and 8: the pure L2 block <chi_l | H | chi_l'> with no
+// contraction (Sec. 2.2), evaluated by Slater's rules on bitstrings for the
+// lower triangle (Sec. 3.1 collapses the triangular double loop into one
+// loop; here each workgroup takes one 64 x 64 tile of the flattened lower
+// triangle). The scan and the element evaluation are fused: every tile
+// element is written (zero when more than a double substitution apart).
+#include "ccham_internal.h"
+
+namespace cch {
+
+struct L2Args {
+    const uint64_t *dets;   // [n_l2][W]
+    int n_l2;
+    TgtInts I;
+    double *H;
+    int64_t ld;
+    int64_t row0;           // first L2 row / column of the matrix
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_l2_block(L2Args a)
+{
+    __shared__ uint64_t bra[64][W], ket[64][W];
+    // flattened lower-triangular tile index -> (ti >= tj)
+    const int64_t b = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    const int64_t tj = b - ti * (ti + 1) / 2;
+    const int l0 = (int)(ti * 64), k0 = (int)(tj * 64);
+    for (int t = threadIdx.x; t < 64 * W; t += 256) {
+        const int r = t / W, w = t % W;
+        bra[r][w] = (l0 + r < a.n_l2) ? a.dets[(size_t)(l0 + r) * W + w] : 0ull;
+        ket[r][w] = (k0 + r < a.n_l2) ? a.dets[(size_t)(k0 + r) * W + w] : 0ull;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 63;
+    const int lc = k0 + c;
+    uint64_t B[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) B[w] = ket[c][w];
+    for (int r = threadIdx.x >> 6; r < 64; r += 4) {
+        const int lr = l0 + r;
+        if (lr >= a.n_l2 || lc >= a.n_l2 || lc > lr) continue;
+        uint64_t A[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) A[w] = bra[r][w];
+        int h[2], p[2], s;
+        const int deg = excite<W>(A, B, h, p, &s);
+        double v = 0.0;
+        if (deg <= 2) v = sc_value<W>(a.I, A, B, deg, h, p, s);
+        a.H[(a.row0 + lr) * a.ld + a.row0 + lc] = v;
+    }
+}
+
+hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st)
+{
+    if (a.n_l2 <= 0) return hipSuccess;
+    const int64_t T = (a.n_l2 + 63) / 64;
+    const int64_t nb = T * (T + 1) / 2;
+    const dim3 g((unsigned)nb), bl(256);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_l2_block<1>), g, bl, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_l2_block<2>), g, bl, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_l2_block<3>), g, bl, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_l2_block<4>), g, bl, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cch

@@ -1,0 +1,79 @@
+// Matrix bookkeeping kernels: mirror of the lower triangle (the matrix is
+// real symmetric and only the lower triangle is evaluated, Sec. 2.2),
+// diagonal extraction, and fills that replace memsets on the stream.
+#include "ccham_internal.h"
+
+namespace cch {
+
+// H[c][r] = H[r][c] for r > c, over 64 x 64 tiles of the lower triangle;
+// off-diagonal tiles go through LDS so both reads and writes are coalesced.
+__global__ __launch_bounds__(256) void k_mirror(double *__restrict__ H, int64_t ld, int D)
+{
+    __shared__ double tile[64][65];
+    const int64_t b = blockIdx.x;
+    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    const int64_t tj = b - ti * (ti + 1) / 2;
+    const int r0 = (int)(ti * 64), c0 = (int)(tj * 64);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int R = r0 + r, C = c0 + tx;
+        tile[r][tx] = (R < D && C < D) ? H[(int64_t)R * ld + C] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        // destination row c0 + r, column r0 + tx  <-  source (r0 + tx, c0 + r)
+        const int R = c0 + r, C = r0 + tx;
+        if (R < D && C < D && C > R) H[(int64_t)R * ld + C] = tile[tx][r];
+    }
+}
+
+hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st)
+{
+    if (D <= 0) return hipSuccess;
+    const int64_t T = (D + 63) / 64;
+    hipLaunchKernelGGL(k_mirror, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, H, ld, D);
+    return hipGetLastError();
+}
+
+__global__ void k_diag(const double *__restrict__ H, int64_t ld, int D, double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < D) out[i] = H[(int64_t)i * ld + i];
+}
+
+hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st)
+{
+    if (D <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag, dim3((D + 255) / 256), dim3(256), 0, st, H, ld, D, out);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i64(int64_t *__restrict__ p, int64_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double *__restrict__ p, double v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace cch

@@ -1,0 +1,326 @@
+// Target-space pieces of the continuum-continuum blocks (classes 1, 3, 5,
+// 6, 7; Sec. 2.1-2.2 and Eq. 8):
+//   * Slater-Condon values H_T[m, m'] of the connected target pairs;
+//   * the CI projection (C_i^T H_T C_i')_{nn'} and overlap (C_i^T O C_i')_{nn'}
+//     as a row-wise sparse product followed by a small dense product;
+//   * the contracted symbolic coefficients D^beta of Eq. 8 for the integral
+//     labels (P Q | j j') and (P j' | j Q): spin-summed and alpha-resolved
+//     transition densities Gamma_{nn',PQ} = sum_mm' c_imn c_i'm'n' <m|E_PQ|m'>,
+//     accumulated per label from the pairs bucketed by label (deterministic).
+#include "ccham_internal.h"
+
+namespace cch {
+
+// ---------------------------------------------------------------------------
+// H_T values of the connected pairs
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(256) void k_pair_values(TgtInts I, const uint64_t *__restrict__ da,
+                                                     const uint64_t *__restrict__ db, PairList pl,
+                                                     int64_t n, double *__restrict__ hv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int deg = pl.deg[i];
+    const uint64_t lab = pl.label[i];
+    int h[2] = {lab_field(lab, 1), lab_field(lab, 3)};
+    int p[2] = {lab_field(lab, 0), lab_field(lab, 2)};
+    uint64_t A[W], B[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        A[w] = da[(size_t)pl.x[i] * W + w];
+        B[w] = db[(size_t)pl.y[i] * W + w];
+    }
+    hv[i] = sc_value<W>(I, A, B, deg, h, p, pl.phase[i]);
+}
+
+hipError_t launch_pair_values(int W, TgtInts I, const uint64_t *da, const uint64_t *db, PairList pl,
+                              int64_t n, double *hv, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_pair_values<1>), g, b, 0, st, I, da, db, pl, n, hv); break;
+    case 2: hipLaunchKernelGGL((k_pair_values<2>), g, b, 0, st, I, da, db, pl, n, hv); break;
+    case 3: hipLaunchKernelGGL((k_pair_values<3>), g, b, 0, st, I, da, db, pl, n, hv); break;
+    case 4: hipLaunchKernelGGL((k_pair_values<4>), g, b, 0, st, I, da, db, pl, n, hv); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Y[m][n'] = sum_{pairs (m, m')} H_T[m,m'] c'[m'][n'],  Yo = same over
+// degree-0 pairs with weight 1. One wave per bra row, pairs in order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spmm_rows(int M, const int64_t *__restrict__ row_off,
+                                                   const int64_t *__restrict__ row_cnt, PairList pl,
+                                                   const double *__restrict__ hv,
+                                                   const double *__restrict__ cb, int Sb,
+                                                   double *__restrict__ Y, double *__restrict__ Yo)
+{
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (m >= M) return;
+    const int64_t p0 = row_off[m], p1 = p0 + row_cnt[m];
+    for (int n0 = 0; n0 < Sb; n0 += 64) {
+        const int n = n0 + lane;
+        double acc = 0.0, acco = 0.0;
+        if (n < Sb) {
+            for (int64_t p = p0; p < p1; ++p) {
+                const double c = cb[(size_t)pl.y[p] * Sb + n];
+                acc = fma(hv[p], c, acc);
+                if (pl.deg[p] == 0) acco += c;
+            }
+            Y[(size_t)m * Sb + n] = acc;
+            Yo[(size_t)m * Sb + n] = acco;
+        }
+    }
+}
+
+// HT[r] = sum_m ca[m][na[r]] Y[m][nb[r]],  O[r] likewise with Yo.
+__global__ __launch_bounds__(256) void k_project(int M, const double *__restrict__ ca, int Sa,
+                                                 const double *__restrict__ Y,
+                                                 const double *__restrict__ Yo, int Sb,
+                                                 const int32_t *__restrict__ rn,
+                                                 const int32_t *__restrict__ rn2,
+                                                 double *__restrict__ HT, double *__restrict__ O)
+{
+    const int r = blockIdx.x;
+    const int n = rn[r], n2 = rn2[r];
+    double a = 0.0, b = 0.0;
+    for (int m = threadIdx.x; m < M; m += 256) {
+        const double c = ca[(size_t)m * Sa + n];
+        a = fma(c, Y[(size_t)m * Sb + n2], a);
+        b = fma(c, Yo[(size_t)m * Sb + n2], b);
+    }
+    __shared__ double ra[256], rb[256];
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ra[threadIdx.x] += ra[threadIdx.x + o];
+            rb[threadIdx.x] += rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        HT[r] = ra[0];
+        O[r] = rb[0];
+    }
+}
+
+hipError_t launch_projection(int M, const int64_t *row_off, const int64_t *row_cnt, PairList pl,
+                             const double *hv, const double *ca, int Sa, const double *cb, int Sb,
+                             int nrows, const int32_t *rn, const int32_t *rn2, double *Y, double *Yo,
+                             double *HT, double *O, hipStream_t st)
+{
+    if (M > 0) {
+        hipLaunchKernelGGL(k_spmm_rows, dim3((M + 3) / 4), dim3(256), 0, st, M, row_off, row_cnt, pl,
+                           hv, cb, Sb, Y, Yo);
+    }
+    hipLaunchKernelGGL(k_project, dim3(nrows), dim3(256), 0, st, M, ca, Sa, Y, Yo, Sb, rn, rn2, HT, O);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// bucketing of pairs by integral label (P, Q): key = slot of a degree-1
+// pair; degree-0 pairs are recorded per bra row; degree 2 has no density
+// term. Counting sort with a per-bucket ordering by pair index so the
+// accumulation order is fixed.
+// ---------------------------------------------------------------------------
+__global__ void k_slot_count(PairList pl, int64_t n, const int32_t *__restrict__ pqidx, int n_o,
+                             int32_t *__restrict__ key, int64_t *__restrict__ count,
+                             int64_t *__restrict__ d0)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int d = pl.deg[i];
+    int k = -1;
+    if (d == 1) {
+        const uint64_t lab = pl.label[i];
+        const int P = lab_field(lab, 0) >> 1, Q = lab_field(lab, 1) >> 1;
+        k = pqidx[P * n_o + Q];
+    } else if (d == 0) {
+        d0[pl.x[i]] = i;     // distinct determinants: at most one per bra row
+    }
+    key[i] = k;
+    if (k >= 0) atomicAdd((unsigned long long *)&count[k], 1ull);
+}
+
+__global__ void k_slot_scatter(int64_t n, const int32_t *__restrict__ key,
+                               const int64_t *__restrict__ start, int64_t *__restrict__ cursor,
+                               int64_t *__restrict__ sorted)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = key[i];
+    if (k < 0) return;
+    const int64_t pos = start[k] + (int64_t)atomicAdd((unsigned long long *)&cursor[k], 1ull);
+    sorted[pos] = i;
+}
+
+// rank sort inside each bucket (values are distinct pair indices)
+__global__ __launch_bounds__(256) void k_bucket_sort(const int64_t *__restrict__ start,
+                                                     const int64_t *__restrict__ count,
+                                                     int64_t *__restrict__ sorted,
+                                                     int64_t *__restrict__ tmp)
+{
+    const int k = blockIdx.x;
+    const int64_t s0 = start[k], n = count[k];
+    if (n <= 1) return;
+    for (int64_t a = threadIdx.x; a < n; a += 256) tmp[s0 + a] = sorted[s0 + a];
+    __syncthreads();
+    for (int64_t a = threadIdx.x; a < n; a += 256) {
+        const int64_t v = tmp[s0 + a];
+        int64_t r = 0;
+        for (int64_t b = 0; b < n; ++b) r += tmp[s0 + b] < v;
+        sorted[s0 + r] = v;
+    }
+}
+
+hipError_t launch_bucket(PairList pl, int64_t n, const int32_t *pqidx, int n_o, int n_slot, int M,
+                         int32_t *key, int64_t *count, int64_t *start, int64_t *cursor,
+                         int64_t *sorted, int64_t *tmp, int64_t *d0, hipStream_t st)
+{
+    hipError_t e;
+    if ((e = launch_fill_i64(count, 0, n_slot + 1, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i64(cursor, 0, n_slot + 1, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i64(d0, -1, M, st)) != hipSuccess) return e;
+    if (n > 0) {
+        const dim3 g((unsigned)((n + 255) / 256));
+        hipLaunchKernelGGL(k_slot_count, g, dim3(256), 0, st, pl, n, pqidx, n_o, key, count, d0);
+        if ((e = launch_exclusive_scan(count, start, n_slot, nullptr, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_slot_scatter, g, dim3(256), 0, st, n, key, start, cursor, sorted);
+        hipLaunchKernelGGL(k_bucket_sort, dim3(n_slot), dim3(256), 0, st, start, count, sorted, tmp);
+    } else {
+        if ((e = launch_exclusive_scan(count, start, n_slot, nullptr, st)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gamma: one workgroup per label slot k = (P, Q).
+//   J[r] = sum over degree-1 pairs with label (P,Q) of s c_a[m][n] c_b[m'][n']
+//          (+ for P == Q the degree-0 pairs weighted by the occupation of P)
+//   K[r] = the same restricted to alpha-spin excitations / alpha occupation.
+// Output Kt-major: At[k][r] = J, At[n_slot + k][r] = K.
+// ---------------------------------------------------------------------------
+constexpr int GAM_BATCH = 16;
+constexpr int GAM_RPT = 8;      // rows per thread per pass
+
+template <int W>
+__global__ __launch_bounds__(256) void k_gamma(PairList pl, const int64_t *__restrict__ start,
+                                               const int64_t *__restrict__ count,
+                                               const int64_t *__restrict__ sorted,
+                                               const int64_t *__restrict__ d0, int M0,
+                                               const int32_t *__restrict__ slotP,
+                                               const int32_t *__restrict__ slotQ, int n_slot,
+                                               const uint64_t *__restrict__ da,
+                                               const double *__restrict__ ca, int Sa,
+                                               const double *__restrict__ cb, int Sb, int nrows,
+                                               const int32_t *__restrict__ rn,
+                                               const int32_t *__restrict__ rn2,
+                                               double *__restrict__ At)
+{
+    extern __shared__ double sh[];
+    double *sa = sh;                            // [GAM_BATCH][Sa]
+    double *sb = sh + GAM_BATCH * Sa;           // [GAM_BATCH][Sb]
+    __shared__ double wj[GAM_BATCH], wk[GAM_BATCH];
+    const int k = blockIdx.x;
+    const int P = slotP[k], Q = slotQ[k];
+    const int64_t s1 = start[k], n1 = count[k];
+    const int64_t n0 = (P == Q) ? M0 : 0;
+    const int64_t ntot = n1 + n0;
+
+    for (int rbase = 0; rbase < nrows; rbase += 256 * GAM_RPT) {
+        double J[GAM_RPT], K[GAM_RPT];
+#pragma unroll
+        for (int q = 0; q < GAM_RPT; ++q) J[q] = K[q] = 0.0;
+        for (int64_t e0 = 0; e0 < ntot; e0 += GAM_BATCH) {
+            const int ne = (int)min<int64_t>(GAM_BATCH, ntot - e0);
+            __syncthreads();
+            // stage weights and CI rows of this batch
+            for (int t = threadIdx.x; t < ne; t += 256) {
+                const int64_t e = e0 + t;
+                const int64_t pidx = e < n1 ? sorted[s1 + e] : d0[e - n1];
+                double a = 0.0, b = 0.0;
+                if (pidx < 0) {
+                    // no identical ket for this bra row
+                } else if (e < n1) {
+                    const int s = pl.phase[pidx];
+                    const int sp = lab_field(pl.label[pidx], 0) & 1;
+                    a = (double)s;
+                    b = sp == 0 ? (double)s : 0.0;
+                } else {
+                    // occupation of spatial orbital P in the bra determinant
+                    const uint64_t *d = da + (size_t)pl.x[pidx] * W;
+                    const int ka = 2 * P, kb = 2 * P + 1;
+                    const int oa = (int)((d[ka >> 6] >> (ka & 63)) & 1ull);
+                    const int ob = (int)((d[kb >> 6] >> (kb & 63)) & 1ull);
+                    a = (double)(oa + ob);
+                    b = (double)oa;
+                }
+                wj[t] = a;
+                wk[t] = b;
+            }
+            for (int t = threadIdx.x; t < ne * Sa; t += 256) {
+                const int ee = t / Sa, n = t % Sa;
+                const int64_t e = e0 + ee;
+                const int64_t pidx = e < n1 ? sorted[s1 + e] : d0[e - n1];
+                sa[ee * Sa + n] = pidx < 0 ? 0.0 : ca[(size_t)pl.x[pidx] * Sa + n];
+            }
+            for (int t = threadIdx.x; t < ne * Sb; t += 256) {
+                const int ee = t / Sb, n = t % Sb;
+                const int64_t e = e0 + ee;
+                const int64_t pidx = e < n1 ? sorted[s1 + e] : d0[e - n1];
+                sb[ee * Sb + n] = pidx < 0 ? 0.0 : cb[(size_t)pl.y[pidx] * Sb + n];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < GAM_RPT; ++q) {
+                const int r = rbase + threadIdx.x + 256 * q;
+                if (r < nrows) {
+                    const int n = rn[r], n2 = rn2[r];
+                    double j = J[q], kk = K[q];
+                    for (int ee = 0; ee < ne; ++ee) {
+                        const double cc = sa[ee * Sa + n] * sb[ee * Sb + n2];
+                        j = fma(wj[ee], cc, j);
+                        kk = fma(wk[ee], cc, kk);
+                    }
+                    J[q] = j;
+                    K[q] = kk;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GAM_RPT; ++q) {
+            const int r = rbase + threadIdx.x + 256 * q;
+            if (r < nrows) {
+                At[(size_t)k * nrows + r] = J[q];
+                At[(size_t)(n_slot + k) * nrows + r] = K[q];
+            }
+        }
+    }
+}
+
+hipError_t launch_gamma(int W, PairList pl, const int64_t *start, const int64_t *count,
+                        const int64_t *sorted, const int64_t *d0, int M0, const int32_t *slotP, const int32_t *slotQ, int n_slot,
+                        const uint64_t *da, const double *ca, int Sa, const double *cb, int Sb,
+                        int nrows, const int32_t *rn, const int32_t *rn2, double *At, hipStream_t st)
+{
+    if (n_slot <= 0 || nrows <= 0) return hipSuccess;
+    const size_t shm = sizeof(double) * GAM_BATCH * (size_t)(Sa + Sb);
+    const dim3 g(n_slot), b(256);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_gamma<1>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 2: hipLaunchKernelGGL((k_gamma<2>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 3: hipLaunchKernelGGL((k_gamma<3>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 4: hipLaunchKernelGGL((k_gamma<4>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cch
