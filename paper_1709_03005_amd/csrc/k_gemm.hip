@@ -75,7 +75,7 @@ hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int 
 // Workgroup tile 64 (r) x 128 (col), 4 waves in 2 x 2, each 32 x 64 =
 // 2 x 4 MFMA tiles. K staged through LDS in slices of 16.
 // MFMA f64 16x16x4 operand layout (lane l): A[l%16][l/16], B[l/16][l%16];
-// result item v of lane l is D[4*(l/16)+v][l%16].
+// result item v of lane l is D[l/16 + 4v][l%16] (checked on gfx950).
 // ---------------------------------------------------------------------------
 typedef double dx4 __attribute__((ext_vector_type(4)));
 
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ A
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = r0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+            const int r = r0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
             if (r >= nrows) continue;
             const int n = ep.rn[r], n2 = ep.rn2[r];
             const double ht = ep.HT[r], ov = ep.O[r];
