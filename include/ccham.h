@@ -93,6 +93,9 @@ typedef struct {
     int32_t fallbacks;      /* MLP corrections replaced by the Jacobi step */
     double max_residual;
     double seconds;         /* wall time of the solve */
+    double matvec_ms;       /* device time of the H V launches (HIP events) */
+    int32_t matvec_launches;
+    int32_t reserved;
 } cch_dav_info;
 
 /* Library version string (static storage). */
@@ -194,10 +197,19 @@ cch_status cch_davidson(cch_ctx *ctx, const cch_dav_opts *opts, double *evals,
                         double *evecs, cch_dav_info *info, int32_t flags);
 
 /* Device time of the last cch_build in milliseconds (HIP events around the
- * queued work), and per-phase times (phases[8], NULL allowed):
- * 0 scans, 1 target elements + densities, 2 relayout, 3 expansion GEMM,
- * 4 class 4, 5 classes 2/8, 6 mirror + diagonal, 7 reserved. Synchronous. */
+ * queued work on the context's stream), and per-phase times (phases[8],
+ * NULL allowed): 0 excitation scans, 1 target elements + densities,
+ * 2 integral relayout, 3 expansion GEMM, 4 class 4, 5 classes 2/8,
+ * 6 mirror + diagonal, 7 reserved (0). Synchronous. */
 cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
+
+/* Work counts of the planned build, for throughput and roofline figures:
+ * out[0] lower-triangle elements (D(D+1)/2), out[1] expansion GEMM flops
+ * (2 * rows * cols * K summed over symmetry pairs), out[2] connected target
+ * pairs, out[3] connected L2 x target pairs, out[4] relayout bytes moved
+ * (read + write), out[5] class-4 outputs, out[6] L2 lower-triangle
+ * elements, out[7] number of symmetry pairs. */
+cch_status cch_work_counts(const cch_ctx *ctx, double *out8);
 
 #ifdef __cplusplus
 }

@@ -50,6 +50,8 @@ def _load():
     lib.orc_dim.argtypes = [P]
     lib.orc_build.restype = None
     lib.orc_build.argtypes = [P, C.c_int64, C.c_int64, P, P, P]
+    lib.orc_build_rows.restype = None
+    lib.orc_build_rows.argtypes = [P, C.c_int64, P, P, P, P]
     lib.orc_elements.restype = None
     lib.orc_elements.argtypes = [P, C.c_int64, P, P, P, P, P]
     lib.orc_pairs.restype = C.c_int64
@@ -132,6 +134,17 @@ class Oracle:
         K = np.zeros((r1 - r0, D), dtype=np.int32) if with_abs else None
         self.lib.orc_build(C.byref(self._st), r0, r1, _ptr(H),
                            _ptr(A) if with_abs else None, _ptr(K) if with_abs else None)
+        return (H, A, K) if with_abs else H
+
+    def build_rows(self, rows, with_abs=False):
+        """Full rows (listed, any order) of the dense contracted matrix."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        D = self.dim
+        H = np.zeros((rows.size, D))
+        A = np.zeros((rows.size, D)) if with_abs else None
+        K = np.zeros((rows.size, D), dtype=np.int32) if with_abs else None
+        self.lib.orc_build_rows(C.byref(self._st), rows.size, _ptr(rows), _ptr(H),
+                                _ptr(A) if with_abs else None, _ptr(K) if with_abs else None)
         return (H, A, K) if with_abs else H
 
     def elements(self, rows, cols):

@@ -393,78 +393,89 @@ void orc_elements(const orc_inst *I, int64_t n, const int64_t *rows, const int64
 /* full matrix                                                              */
 /* ------------------------------------------------------------------------ */
 
-/* Every element of the dense D x D contracted matrix (row-major, both
- * triangles computed independently), rows restricted to [r0, r1). The
+/* Full rows of the dense D x D contracted matrix (both triangles computed
+ * independently) for the listed rows; H is [nrows][D] in list order. The
  * continuum blocks are built per symmetry pair by looping the target pairs
  * (m, m') outside and j, j' inside, so each uncontracted element is formed
  * once and folded into all (n, n') at once (Eq. 4 as written). */
-void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Habs, int32_t *Hcnt)
+void orc_build_rows(const orc_inst *I, int64_t nrows, const int64_t *rows, double *H, double *Habs,
+                    int32_t *Hcnt)
 {
     const int64_t D = orc_dim(I);
     const int64_t Dc = sym_row0(I, I->n_sym);
     const int W = I->n_words;
-    if (r1 > D) r1 = D;
-    const int64_t nr = r1 - r0;
-    acc_t *acc = (acc_t *)calloc((size_t)(nr > 0 ? nr : 1) * (size_t)D, sizeof(acc_t));
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)D);
+    for (int64_t r = 0; r < D; ++r) slot[r] = -1;
+    for (int64_t i = 0; i < nrows; ++i) slot[rows[i]] = i;
+    acc_t *acc = (acc_t *)calloc((size_t)(nrows > 0 ? nrows : 1) * (size_t)D, sizeof(acc_t));
 
     /* continuum x continuum */
     for (int si = 0; si < I->n_sym; ++si) {
         int ai = I->sym_irrep[si] ^ I->total_irrep, nci = n_cont_of(I, si), Si = I->sym_nstate[si];
         int64_t ri0 = sym_row0(I, si);
         int j0i = I->cont_start[ai];
+        int Mi = I->sym_ndet[si];
+        /* continuum orbitals jj of this symmetry with at least one listed row */
+        int *jneed = (int *)malloc(sizeof(int) * (size_t)(nci > 0 ? nci : 1));
+        int nj = 0;
+        for (int jj = 0; jj < nci; ++jj) {
+            int any = 0;
+            for (int n = 0; n < Si; ++n) any |= slot[ri0 + (int64_t)n * nci + jj] >= 0;
+            if (any) jneed[nj++] = jj;
+        }
+        if (nj == 0) { free(jneed); continue; }
+        /* target pairs connected by at most a double substitution, per ket symmetry */
+        int **pm = (int **)malloc(sizeof(int *) * (size_t)I->n_sym);
+        int64_t *np = (int64_t *)malloc(sizeof(int64_t) * (size_t)I->n_sym);
         for (int sk = 0; sk < I->n_sym; ++sk) {
-            int ak = I->sym_irrep[sk] ^ I->total_irrep, nck = n_cont_of(I, sk), Sk = I->sym_nstate[sk];
-            int64_t rk0 = sym_row0(I, sk);
-            int j0k = I->cont_start[ak];
-            int Mi = I->sym_ndet[si], Mk = I->sym_ndet[sk];
-            /* target pairs connected by at most a double substitution */
-            int *pm = (int *)malloc(sizeof(int) * 2 * (size_t)Mi * Mk);
-            int64_t np = 0;
+            int Mk = I->sym_ndet[sk];
+            pm[sk] = (int *)malloc(sizeof(int) * 2 * ((size_t)Mi * Mk + 1));
+            np[sk] = 0;
             for (int m = 0; m < Mi; ++m) {
                 int A[MAXE], B[MAXE];
                 int na = det_occ(I->sym_dets[si] + (size_t)m * W, W, A);
                 for (int m2 = 0; m2 < Mk; ++m2) {
                     int nb = det_occ(I->sym_dets[sk] + (size_t)m2 * W, W, B);
                     if (na == nb && n_missing(A, na, B, nb) <= 2) {
-                        pm[2 * np] = m; pm[2 * np + 1] = m2; ++np;
+                        pm[sk][2 * np[sk]] = m; pm[sk][2 * np[sk] + 1] = m2; ++np[sk];
                     }
                 }
             }
-            const double *ci = I->sym_ci[si], *ck = I->sym_ci[sk];
+        }
+        const double *ci = I->sym_ci[si];
+        const int ntask = nj * I->n_sym;
 #pragma omp parallel for schedule(dynamic, 1)
-            for (int jj = 0; jj < nci; ++jj) {
-                int A[MAXE], B[MAXE];
-                /* rows (si, n, jj) */
-                int any = 0;
-                for (int n = 0; n < Si; ++n) {
-                    int64_t r = ri0 + (int64_t)n * nci + jj;
-                    if (r >= r0 && r < r1) any = 1;
-                }
-                if (!any) continue;
-                for (int64_t e = 0; e < np; ++e) {
-                    int m = pm[2 * e], m2 = pm[2 * e + 1];
-                    int na = cont_occ(I, si, m, j0i + jj, A);
-                    for (int jk = 0; jk < nck; ++jk) {
-                        cont_occ(I, sk, m2, j0k + jk, B);
-                        double ab; int nt;
-                        double v = slater_condon(&I->ints, A, B, na, &ab, &nt);
-                        if (nt == 0) continue;
-                        for (int n = 0; n < Si; ++n) {
-                            int64_t r = ri0 + (int64_t)n * nci + jj;
-                            if (r < r0 || r >= r1) continue;
-                            double wn = ci[(size_t)m * Si + n];
-                            acc_t *row = acc + (size_t)(r - r0) * D;
-                            for (int n2 = 0; n2 < Sk; ++n2) {
-                                int64_t c = rk0 + (int64_t)n2 * nck + jk;
-                                double w = wn * ck[(size_t)m2 * Sk + n2];
-                                acc_add(row + c, w * v, fabs(w) * ab, nt);
-                            }
+        for (int task = 0; task < ntask; ++task) {
+            const int jj = jneed[task / I->n_sym], sk = task % I->n_sym;
+            int ak = I->sym_irrep[sk] ^ I->total_irrep, nck = n_cont_of(I, sk), Sk = I->sym_nstate[sk];
+            int64_t rk0 = sym_row0(I, sk);
+            int j0k = I->cont_start[ak];
+            const double *ck = I->sym_ci[sk];
+            int A[MAXE], B[MAXE];
+            for (int64_t e = 0; e < np[sk]; ++e) {
+                int m = pm[sk][2 * e], m2 = pm[sk][2 * e + 1];
+                int na = cont_occ(I, si, m, j0i + jj, A);
+                for (int jk = 0; jk < nck; ++jk) {
+                    cont_occ(I, sk, m2, j0k + jk, B);
+                    double ab; int nt;
+                    double v = slater_condon(&I->ints, A, B, na, &ab, &nt);
+                    if (nt == 0) continue;
+                    for (int n = 0; n < Si; ++n) {
+                        int64_t sl = slot[ri0 + (int64_t)n * nci + jj];
+                        if (sl < 0) continue;
+                        double wn = ci[(size_t)m * Si + n];
+                        acc_t *row = acc + (size_t)sl * D;
+                        for (int n2 = 0; n2 < Sk; ++n2) {
+                            int64_t c = rk0 + (int64_t)n2 * nck + jk;
+                            double w = wn * ck[(size_t)m2 * Sk + n2];
+                            acc_add(row + c, w * v, fabs(w) * ab, nt);
                         }
                     }
                 }
             }
-            free(pm);
         }
+        for (int sk = 0; sk < I->n_sym; ++sk) free(pm[sk]);
+        free(pm); free(np); free(jneed);
     }
 
     /* continuum x L2 (Eq. 5) and L2 x continuum (its transpose, computed again) */
@@ -473,6 +484,7 @@ void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Hab
         int A[MAXE], B[MAXE];
         int nb = det_occ(I->l2_dets + (size_t)l * W, W, B);
         int64_t rl = Dc + l;
+        int64_t sll = slot[rl];
         for (int si = 0; si < I->n_sym; ++si) {
             int ai = I->sym_irrep[si] ^ I->total_irrep, nci = n_cont_of(I, si), Si = I->sym_nstate[si];
             int64_t ri0 = sym_row0(I, si);
@@ -481,6 +493,9 @@ void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Hab
                 int na0 = det_occ(I->sym_dets[si] + (size_t)m * W, W, A);
                 if (na0 + 1 != nb || n_missing(A, na0, B, nb) > 1) continue;
                 for (int jj = 0; jj < nci; ++jj) {
+                    int need = sll >= 0;
+                    for (int n = 0; n < Si && !need; ++n) need = slot[ri0 + (int64_t)n * nci + jj] >= 0;
+                    if (!need) continue;
                     int na = cont_occ(I, si, m, I->cont_start[ai] + jj, A);
                     double ab1, ab2; int nt1, nt2;
                     double v1 = slater_condon(&I->ints, A, B, na, &ab1, &nt1);   /* <cont|H|l> */
@@ -488,10 +503,10 @@ void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Hab
                     for (int n = 0; n < Si; ++n) {
                         int64_t r = ri0 + (int64_t)n * nci + jj;
                         double w = ci[(size_t)m * Si + n];
-                        if (r >= r0 && r < r1)
-                            acc_add(acc + (size_t)(r - r0) * D + rl, w * v1, fabs(w) * ab1, nt1);
-                        if (rl >= r0 && rl < r1)
-                            acc_add(acc + (size_t)(rl - r0) * D + r, w * v2, fabs(w) * ab2, nt2);
+                        if (slot[r] >= 0)
+                            acc_add(acc + (size_t)slot[r] * D + rl, w * v1, fabs(w) * ab1, nt1);
+                        if (sll >= 0)
+                            acc_add(acc + (size_t)sll * D + r, w * v2, fabs(w) * ab2, nt2);
                     }
                 }
             }
@@ -501,8 +516,8 @@ void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Hab
     /* L2 x L2 (classes 2 and 8): no contraction */
 #pragma omp parallel for schedule(dynamic, 4)
     for (int l = 0; l < I->n_l2; ++l) {
-        int64_t rl = Dc + l;
-        if (rl < r0 || rl >= r1) continue;
+        int64_t sll = slot[Dc + l];
+        if (sll < 0) continue;
         int A[MAXE], B[MAXE];
         int na = det_occ(I->l2_dets + (size_t)l * W, W, A);
         for (int l2 = 0; l2 < I->n_l2; ++l2) {
@@ -510,16 +525,29 @@ void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Hab
             if (na != nb || n_missing(A, na, B, nb) > 2) continue;
             double ab; int nt;
             double v = slater_condon(&I->ints, A, B, na, &ab, &nt);
-            acc_add(acc + (size_t)(rl - r0) * D + Dc + l2, v, ab, nt);
+            acc_add(acc + (size_t)sll * D + Dc + l2, v, ab, nt);
         }
     }
 
-    for (int64_t i = 0; i < nr * D; ++i) {
+    for (int64_t i = 0; i < nrows * D; ++i) {
         H[i] = acc[i].s + acc[i].c;
         if (Habs) Habs[i] = acc[i].a;
         if (Hcnt) Hcnt[i] = acc[i].n;
     }
     free(acc);
+    free(slot);
+}
+
+/* rows [r0, r1) */
+void orc_build(const orc_inst *I, int64_t r0, int64_t r1, double *H, double *Habs, int32_t *Hcnt)
+{
+    const int64_t D = orc_dim(I);
+    if (r1 > D) r1 = D;
+    int64_t n = r1 > r0 ? r1 - r0 : 0;
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) rows[i] = r0 + i;
+    orc_build_rows(I, n, rows, H, Habs, Hcnt);
+    free(rows);
 }
 
 /* ------------------------------------------------------------------------ */

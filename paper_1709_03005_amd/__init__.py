@@ -41,7 +41,7 @@ EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
     "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_labels",
-    "cch_davidson", "cch_build_time",
+    "cch_davidson", "cch_build_time", "cch_work_counts",
 ]
 
 if not os.path.exists(LIB_PATH):
@@ -61,7 +61,8 @@ class DavOpts(C.Structure):
 
 class DavInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
-                ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double)]
+                ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double),
+                ("matvec_ms", C.c_double), ("matvec_launches", C.c_int32), ("reserved", C.c_int32)]
 
 
 P = C.c_void_p
@@ -85,6 +86,7 @@ _SIG = {
     "cch_get_labels": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, C.POINTER(i64)]),
     "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
     "cch_build_time": (i32, [P, C.POINTER(C.c_float), P]),
+    "cch_work_counts": (i32, [P, P]),
 }
 for _n, (_r, _a) in _SIG.items():
     _f = getattr(lib, _n)
@@ -232,6 +234,13 @@ class Context:
                               C.byref(info), CCH_MEM_HOST)
         self._ck(rc, ok=(CCH_OK, CCH_E_NOT_CONVERGED))
         return ev, vec, info, rc
+
+    def work_counts(self):
+        out = np.zeros(8)
+        self._ck(lib.cch_work_counts(self.h, out.ctypes.data_as(C.c_void_p)))
+        keys = ["lower_elements", "gemm_flops", "target_pairs", "l2_target_pairs", "relayout_bytes",
+                "class4_outputs", "l2_lower_elements", "sym_pairs"]
+        return dict(zip(keys, out.tolist()))
 
     def build_time(self):
         t = C.c_float()

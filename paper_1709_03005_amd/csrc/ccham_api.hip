@@ -87,7 +87,9 @@ hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D,
                            double *R, double *part, double *norms, hipStream_t st);
 hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
                                  const int32_t *sel, int nsel, double *T, int64_t ldt, hipStream_t st);
-hipError_t launch_mgs(double *T, int64_t ldt, int b, int D, double drop_tol, int32_t *keep, hipStream_t st);
+hipError_t launch_pchol(const double *G, int ldg, int b, const double *ref, double rel, double *C, int ldc,
+                        int32_t *rank, hipStream_t st);
+hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st);
 hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
 hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
@@ -120,6 +122,7 @@ struct PairPlan {
     int32_t *d_key = nullptr;
     int64_t *d_count = nullptr, *d_start = nullptr, *d_cursor = nullptr, *d_sorted = nullptr, *d_tmp = nullptr,
             *d_d0 = nullptr;
+    double *d_B = nullptr;   // integral rows laid out for this pair's expansion
 };
 
 struct LtPlan {
@@ -158,6 +161,8 @@ struct cch_ctx {
     std::vector<PairPlan> pp;
     std::vector<LtPlan> lt;
     hipEvent_t ev[8] = {};
+    hipEvent_t mv0 = nullptr, mv1 = nullptr;
+    int64_t relayout_elems = 0;
     bool have_events = false;
 };
 
@@ -253,6 +258,10 @@ cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream)
             return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
         }
     }
+    if (hipEventCreate(&c->mv0) != hipSuccess || hipEventCreate(&c->mv1) != hipSuccess) {
+        delete c;
+        return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
+    }
     c->have_events = true;
     c->opts.precision = CCH_PREC_FP64;
     *out = c;
@@ -267,6 +276,8 @@ cch_status cch_destroy(cch_ctx *c)
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->have_events)
         for (auto &ev : c->ev) (void)hipEventDestroy(ev);
+    if (c->mv0) (void)hipEventDestroy(c->mv0);
+    if (c->mv1) (void)hipEventDestroy(c->mv1);
     delete c;
     return CCH_OK;
 }
@@ -543,7 +554,8 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
             TRY(dalloc(c, &p.d_sorted, p.pr.n));
             TRY(dalloc(c, &p.d_tmp, p.pr.n));
             TRY(dalloc(c, &p.d_d0, sa.M));
-            maxB = std::max<int64_t>(maxB, (int64_t)2 * p.n_slot * sa.nc * sb.nc);
+            TRY(dalloc(c, &p.d_B, (size_t)2 * p.n_slot * sa.nc * sb.nc));
+            maxB += (int64_t)2 * p.n_slot * sa.nc * sb.nc;
             c->pp.push_back(p);
         }
     }
@@ -554,7 +566,7 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
         TRY(alloc_pairs(c, L.pr, SCAN_LT, c->d_l2, c->n_l2, c->syms[s].d_dets, c->syms[s].M));
         c->lt.push_back(L);
     }
-    TRY(dalloc(c, &c->d_B, maxB));
+    c->relayout_elems = maxB;
     TRY(dalloc(c, &c->d_H, (size_t)c->D * c->ld));
     TRY(dalloc(c, &c->d_diag, c->D));
     c->planned = true;
@@ -595,19 +607,23 @@ cch_status cch_build(cch_ctx *c)
                               st));
     }
     HIPCK(c, hipEventRecord(c->ev[2], st));
-    // phases 2-3: relayout + expansion GEMM per symmetry pair
-    float dummy = 0;
-    (void)dummy;
+    // phase 2: integral rows laid out per symmetry pair
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
         HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
-                                 sa.nc, sb.ja0, sb.nc, c->d_B, st));
-        ExpandEpi ep{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT, p.d_O,
-                     c->d_h, c->n_o, c->n_orb};
-        HIPCK(c, launch_expand_f64(p.d_At, c->d_B, p.nrows, sa.nc * sb.nc, 2 * p.n_slot, ep, st));
+                                 sa.nc, sb.ja0, sb.nc, p.d_B, st));
     }
     HIPCK(c, hipEventRecord(c->ev[3], st));
+    // phase 3: expansion GEMM per symmetry pair
+    for (auto &p : c->pp) {
+        SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+        if (sa.nc == 0 || sb.nc == 0) continue;
+        ExpandEpi ep{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT, p.d_O,
+                     c->d_h, c->n_o, c->n_orb};
+        HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, sa.nc * sb.nc, 2 * p.n_slot, ep, st));
+    }
+    HIPCK(c, hipEventRecord(c->ev[4], st));
     // phase 4: class 4
     for (auto &L : c->lt) {
         SymInfo &s = c->syms[L.sym];
@@ -632,17 +648,17 @@ cch_status cch_build(cch_ctx *c)
         a.pairs_per_chunk = std::max(1, std::min(64, 1024 / (1 + 2 * c->n_elec)));
         HIPCK(c, launch_class4(c->W, a, c->n_l2, st));
     }
-    HIPCK(c, hipEventRecord(c->ev[4], st));
+    HIPCK(c, hipEventRecord(c->ev[5], st));
     // phase 5: classes 2 and 8
     if (c->n_l2 > 0) {
         L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
         HIPCK(c, launch_l2_block(c->W, a, st));
     }
-    HIPCK(c, hipEventRecord(c->ev[5], st));
+    HIPCK(c, hipEventRecord(c->ev[6], st));
     // phase 6: mirror the lower triangle, diagonal
     HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->D, st));
     HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->D, c->d_diag, st));
-    HIPCK(c, hipEventRecord(c->ev[6], st));
+    HIPCK(c, hipEventRecord(c->ev[7], st));
     c->built = true;
     return CCH_OK;
 }
@@ -651,20 +667,35 @@ cch_status cch_build_time(cch_ctx *c, float *total_ms, float *phases)
 {
     if (!c) return CCH_E_INVALID_ARG;
     if (!c->built) return fail(c, CCH_E_STATE, "build first");
-    HIPCK(c, hipEventSynchronize(c->ev[6]));
-    if (total_ms) HIPCK(c, hipEventElapsedTime(total_ms, c->ev[0], c->ev[6]));
+    HIPCK(c, hipEventSynchronize(c->ev[7]));
+    if (total_ms) HIPCK(c, hipEventElapsedTime(total_ms, c->ev[0], c->ev[7]));
     if (phases) {
-        float t[6];
-        for (int i = 0; i < 6; ++i) HIPCK(c, hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]));
-        phases[0] = t[0];
-        phases[1] = t[1];
-        phases[2] = 0.0f;          // relayout is timed together with the GEMM
-        phases[3] = t[2];
-        phases[4] = t[3];
-        phases[5] = t[4];
-        phases[6] = t[5];
+        for (int i = 0; i < 7; ++i) HIPCK(c, hipEventElapsedTime(&phases[i], c->ev[i], c->ev[i + 1]));
         phases[7] = 0.0f;
     }
+    return CCH_OK;
+}
+
+cch_status cch_work_counts(const cch_ctx *c, double *out)
+{
+    if (!c || !out) return CCH_E_INVALID_ARG;
+    if (!c->planned) return CCH_E_STATE;
+    double gemm = 0.0, tp = 0.0, ltp = 0.0, c4 = 0.0;
+    for (auto &p : c->pp) {
+        const SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+        gemm += 2.0 * p.nrows * (double)sa.nc * sb.nc * (2.0 * p.n_slot);
+        tp += (double)p.pr.n;
+    }
+    for (auto &L : c->lt) ltp += (double)L.pr.n;
+    for (auto &s : c->syms) c4 += (double)c->n_l2 * s.S * s.nc;
+    out[0] = (double)c->D * (c->D + 1) / 2.0;
+    out[1] = gemm;
+    out[2] = tp;
+    out[3] = ltp;
+    out[4] = 16.0 * (double)c->relayout_elems;
+    out[5] = c4;
+    out[6] = (double)c->n_l2 * (c->n_l2 + 1) / 2.0;
+    out[7] = (double)c->pp.size();
     return CCH_OK;
 }
 
@@ -776,28 +807,36 @@ cch_status cch_get_labels(cch_ctx *c, int32_t which, int32_t sym_a, int32_t sym_
 
 // ---------------------------------------------------------------------------
 // block Davidson driver
+//   basis V (m vectors) and W = H V are rotated to the Ritz basis after every
+//   Rayleigh-Ritz step, so G = V^T H V is diag(theta) plus the rows of the
+//   newest block; a thick restart keeps the lowest kr Ritz vectors.
+//   New directions: diagonal (Jacobi) corrections, orthogonalised against V
+//   by two classical Gram-Schmidt passes and inside the block by pivoted
+//   Cholesky QR, twice.
 // ---------------------------------------------------------------------------
 namespace {
 struct DavBufs {
-    double *V = nullptr, *Wv = nullptr, *G = nullptr, *theta = nullptr, *Y = nullptr, *X = nullptr, *AX = nullptr,
-           *R = nullptr, *T = nullptr, *C = nullptr, *part = nullptr, *norms = nullptr, *tmp = nullptr;
-    int32_t *keep = nullptr, *sel = nullptr, *idx = nullptr;
+    double *V = nullptr, *Wv = nullptr, *V2 = nullptr, *W2 = nullptr, *G = nullptr, *theta = nullptr,
+           *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *Gb = nullptr, *Cb = nullptr,
+           *ref = nullptr, *part = nullptr, *norms = nullptr;
+    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr;
 };
 }  // namespace
 
-cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double *evecs,
-                                   cch_dav_info *info, int32_t flags)
+cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double *evecs, cch_dav_info *info,
+                        int32_t flags)
 {
     if (!c || !o) return CCH_E_INVALID_ARG;
     if (!c->built) return fail(c, CCH_E_STATE, "build first");
     const int D = (int)c->D, k = o->k;
     if (k <= 0 || k > D) return fail(c, CCH_E_INVALID_ARG, "k out of range");
+    if (k > 16) return fail(c, CCH_E_LIMIT, "k > 16 eigenpairs per solve");
     if (!(o->tol > 0.0)) return fail(c, CCH_E_INVALID_ARG, "tol must be positive");
     if (o->precond != CCH_PRECOND_JACOBI) return fail(c, CCH_E_INVALID_ARG, "preconditioner not available");
     int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 64);
     mmax = std::min(mmax, 96);
     mmax = std::min(mmax, D);
-    const int kr = std::min(2 * k, D);         // kept at a thick restart
+    const int kr = std::min(2 * k, D);         // kept at a thick restart; also the first block
     if (kr + k > mmax && mmax < D) return fail(c, CCH_E_INVALID_ARG, "k too large for the subspace limit");
     const int max_iter = o->max_iter > 0 ? o->max_iter : 200;
     HIPCK(c, hipSetDevice(c->device));
@@ -805,6 +844,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     auto t0 = std::chrono::steady_clock::now();
 
     const int64_t ldv = ((int64_t)D + 31) / 32 * 32;
+    const int BMAX = 32;                       // block columns (<= 2k <= 32)
     std::vector<void *> tmp;
     auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
     auto A = [&](void **p, size_t bytes) -> bool {
@@ -813,15 +853,16 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         return true;
     };
     DavBufs b;
-    const int nch = (D + 4095) / 4096;
+    const int nch = (D + 1023) / 1024;
     bool ok = A((void **)&b.V, 8 * ldv * mmax) && A((void **)&b.Wv, 8 * ldv * mmax) &&
+              A((void **)&b.V2, 8 * ldv * mmax) && A((void **)&b.W2, 8 * ldv * mmax) &&
               A((void **)&b.G, 8 * (size_t)mmax * mmax) && A((void **)&b.theta, 8 * (size_t)mmax) &&
-              A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.X, 8 * ldv * std::max(kr, k)) &&
-              A((void **)&b.AX, 8 * ldv * std::max(kr, k)) && A((void **)&b.R, 8 * ldv * k) &&
-              A((void **)&b.T, 8 * ldv * std::max(kr, k)) && A((void **)&b.C, 8 * (size_t)mmax * std::max(kr, k)) &&
-              A((void **)&b.part, 8 * (size_t)nch * std::max(mmax, k) * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
-              A((void **)&b.keep, 4 * (size_t)std::max(kr, k)) && A((void **)&b.sel, 4 * (size_t)k) &&
-              A((void **)&b.idx, 4 * (size_t)kr);
+              A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.R, 8 * ldv * k) &&
+              A((void **)&b.T, 8 * ldv * BMAX) && A((void **)&b.T2, 8 * ldv * BMAX) &&
+              A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
+              A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
+              A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
+              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)k) && A((void **)&b.idx, 4 * (size_t)kr);
     if (!ok) {
         cleanup();
         return fail(c, CCH_E_OOM, "Davidson buffers");
@@ -835,7 +876,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         }                                                                                       \
     } while (0)
 
-    // initial block: unit vectors at the 2k smallest diagonal entries
+    // initial block: unit vectors at the 2k smallest diagonal entries (ties: lower index)
     std::vector<double> hdiag(D);
     DCK(hipMemcpyAsync(hdiag.data(), c->d_diag, 8 * (size_t)D, hipMemcpyDeviceToHost, st));
     DCK(hipStreamSynchronize(st));
@@ -846,44 +887,58 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)nb, hipMemcpyHostToDevice));
     DCK(launch_unit_vectors(b.T, ldv, D, b.idx, nb, st));
 
-    int m = 0, iters = 0, matvecs = 0, nconv = 0;
-    double maxres = 0.0;
+    int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0;
+    double mv_ms = 0.0, maxres = 0.0;
     std::vector<double> hres(k), htheta(mmax);
-    std::vector<int32_t> hkeep(std::max(kr, k));
     cch_status rc = CCH_E_NOT_CONVERGED;
     for (iters = 1; iters <= max_iter; ++iters) {
-        // orthogonalise the new block against V (twice) and within itself
-        for (int pass = 0; pass < 2 && m > 0; ++pass) {
-            DCK(launch_tn(b.V, ldv, m, b.T, ldv, nb, D, b.part, b.C, nb, 0, st));
-            DCK(launch_nn(b.V, ldv, m, D, b.C, nb, nb, b.T, ldv, 1.0, -1.0, b.T, ldv, st));   // T -= V C
+        // reference norms of the raw directions, for the drop test
+        DCK(launch_tn(b.T, ldv, nb, b.T, ldv, nb, D, b.part, b.Gb, BMAX, 0, st));
+        DCK(launch_diag_small(b.Gb, BMAX, nb, b.ref, st));
+        double *src = b.T, *dst = b.T2;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int cg = 0; cg < 2 && m > 0; ++cg) {     // T -= V (V^T T)
+                DCK(launch_tn(b.V, ldv, m, src, ldv, nb, D, b.part, b.C, nb, 0, st));
+                DCK(launch_nn(b.V, ldv, m, D, b.C, nb, nb, src, ldv, 1.0, -1.0, src, ldv, st));
+            }
+            DCK(launch_tn(src, ldv, nb, src, ldv, nb, D, b.part, b.Gb, BMAX, 0, st));
+            DCK(launch_pchol(b.Gb, BMAX, nb, pass == 0 ? b.ref : nullptr, pass == 0 ? 1e-7 : 1e-12, b.Cb, BMAX,
+                             b.rank, st));
+            // second pass writes the orthonormal block straight into V
+            double *o2 = pass == 0 ? dst : b.V + (int64_t)m * ldv;
+            DCK(launch_nn(src, ldv, nb, D, b.Cb, BMAX, nb, nullptr, 0, 0.0, 1.0, o2, ldv, st));
+            std::swap(src, dst);
         }
-        DCK(launch_mgs(b.T, ldv, nb, D, 1e-10, b.keep, st));
-        DCK(hipMemcpyAsync(hkeep.data(), b.keep, 4 * (size_t)nb, hipMemcpyDeviceToHost, st));
+        int32_t added = 0;
+        DCK(hipMemcpyAsync(&added, b.rank, 4, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
-        int added = 0;
-        for (int q = 0; q < nb && m + added < mmax; ++q) {
-            if (!hkeep[q]) continue;
-            DCK(hipMemcpyAsync(b.V + (int64_t)(m + added) * ldv, b.T + (int64_t)q * ldv, 8 * (size_t)D,
-                               hipMemcpyDeviceToDevice, st));
-            ++added;
-        }
-        if (added == 0) break;   // no new direction: stagnation
+        if (added <= 0) break;   // no new direction: stagnation
         // W for the new vectors and the new rows of G
+        DCK(hipEventRecord(c->mv0, st));
         DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, added, b.Wv + (int64_t)m * ldv, ldv, st));
+        DCK(hipEventRecord(c->mv1, st));
         matvecs += added;
+        mv_launches += (added + 15) / 16;
         DCK(launch_tn(b.Wv + (int64_t)m * ldv, ldv, added, b.V, ldv, m + added, D, b.part, b.G + (int64_t)m * mmax,
                       mmax, 0, st));
         DCK(launch_sym_fill(b.G, mmax, m, m + added, st));
         m += added;
         DCK(launch_jacobi_eig(b.G, mmax, m, b.theta, b.Y, mmax, st));
+        // rotate V and W to the Ritz basis; G becomes diag(theta)
+        DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.V2, ldv, st));
+        DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.W2, ldv, st));
+        std::swap(b.V, b.V2);
+        std::swap(b.Wv, b.W2);
         const int kk = std::min(k, m);
-        // Ritz vectors and residuals
-        DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, kk, nullptr, 0, 0.0, 1.0, b.X, ldv, st));
-        DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, kk, nullptr, 0, 0.0, 1.0, b.AX, ldv, st));
-        DCK(launch_residual(b.AX, b.X, ldv, D, b.theta, kk, b.R, b.part, b.norms, st));
+        DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kk, b.R, b.part, b.norms, st));
         DCK(hipMemcpyAsync(hres.data(), b.norms, 8 * (size_t)kk, hipMemcpyDeviceToHost, st));
         DCK(hipMemcpyAsync(htheta.data(), b.theta, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
+        {
+            float ms = 0.0f;
+            DCK(hipEventElapsedTime(&ms, c->mv0, c->mv1));
+            mv_ms += ms;
+        }
         std::vector<int32_t> un;
         maxres = 0.0;
         for (int e = 0; e < kk; ++e) {
@@ -895,25 +950,21 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             rc = CCH_OK;
             break;
         }
-        if (m >= D) {   // the whole space is spanned: Ritz pairs are exact
+        if (m >= D) {   // the whole space is spanned: the Ritz pairs are exact
             rc = CCH_OK;
             nconv = kk;
             break;
         }
-        // thick restart when the next block would not fit
-        if (m + (int)un.size() > mmax) {
-            const int keepn = std::min(kr, m);
-            DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, keepn, nullptr, 0, 0.0, 1.0, b.T, ldv, st));
-            DCK(hipMemcpy2DAsync(b.V, ldv * 8, b.T, ldv * 8, 8 * (size_t)D, keepn, hipMemcpyDeviceToDevice, st));
-            DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, keepn, nullptr, 0, 0.0, 1.0, b.T, ldv, st));
-            DCK(hipMemcpy2DAsync(b.Wv, ldv * 8, b.T, ldv * 8, 8 * (size_t)D, keepn, hipMemcpyDeviceToDevice, st));
+        // G in the rotated basis
+        {
             std::vector<double> g((size_t)mmax * mmax, 0.0);
-            for (int e = 0; e < keepn; ++e) g[(size_t)e * mmax + e] = htheta[e];
+            if (m + (int)un.size() > mmax) m = std::min(kr, m);   // thick restart
+            for (int e = 0; e < m; ++e) g[(size_t)e * mmax + e] = htheta[e];
             DCK(hipMemcpyAsync(b.G, g.data(), 8 * g.size(), hipMemcpyHostToDevice, st));
-            m = keepn;
         }
-        // corrections for the unconverged pairs
-        nb = (int)un.size();
+        // corrections for the unconverged pairs (never more than the basis has room for)
+        nb = std::min((int)un.size(), mmax - m);
+        if (nb <= 0) break;
         DCK(hipMemcpyAsync(b.sel, un.data(), 4 * (size_t)nb, hipMemcpyHostToDevice, st));
         DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, b.sel, nb, b.T, ldv, st));
     }
@@ -927,7 +978,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         else memcpy(evals, th.data(), 8 * (size_t)kk);
     }
     if (evecs)
-        DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.X, ldv * 8, 8 * (size_t)D, kk,
+        DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.V, ldv * 8, 8 * (size_t)D, kk,
                              (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     DCK(hipStreamSynchronize(st));
     cleanup();
@@ -938,6 +989,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->fallbacks = 0;
         info->max_residual = maxres;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->matvec_ms = mv_ms;
+        info->matvec_launches = mv_launches;
+        info->reserved = 0;
     }
     if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
     return rc;

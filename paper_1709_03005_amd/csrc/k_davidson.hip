@@ -103,7 +103,7 @@ hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, in
 // K9: out[a][c] = sum_i X[a][i] Y[c][i]  (a < na, c < nc <= 16)
 // grid (na, chunks); partials reduced in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int TN_CHUNK = 4096;
+constexpr int TN_CHUNK = 1024;
 
 __global__ __launch_bounds__(256) void k_tn_partial(const double *__restrict__ X, int64_t ldx, int D,
                                                     const double *__restrict__ Y, int64_t ldy, int nc,
@@ -166,61 +166,52 @@ hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int6
 
 // ---------------------------------------------------------------------------
 // out[e][i] = beta * base[e][i] + alpha * sum_{q<m} V[q][i] C[q*ldc + e], e < ne
+// grid (D/256, ceil(ne/4)): four outputs per thread, C slice staged in LDS
 // ---------------------------------------------------------------------------
-template <int NE>
+constexpr int NN_E = 4;
+
 __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V, int64_t ldv, int m, int D,
                                                   const double *__restrict__ Cm, int ldc, int ne,
                                                   const double *__restrict__ base, int64_t ldb, double beta,
                                                   double alpha, double *__restrict__ out, int64_t ldo)
 {
-    extern __shared__ double cs[];   // [m][NE]
-    for (int t = threadIdx.x; t < m * NE; t += 256) {
-        const int q = t / NE, e = t % NE;
+    extern __shared__ double cs[];   // [m][NN_E]
+    const int e0 = blockIdx.y * NN_E;
+    for (int t = threadIdx.x; t < m * NN_E; t += 256) {
+        const int q = t / NN_E, e = e0 + t % NN_E;
         cs[t] = e < ne ? Cm[(int64_t)q * ldc + e] : 0.0;
     }
     __syncthreads();
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= D) return;
-    double acc[NE];
+    double acc[NN_E];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+    for (int e = 0; e < NN_E; ++e) acc[e] = 0.0;
     for (int q = 0; q < m; ++q) {
         const double v = V[(int64_t)q * ldv + i];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
+        for (int e = 0; e < NN_E; ++e) acc[e] = fma(v, cs[q * NN_E + e], acc[e]);
     }
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-        if (e < ne) {
+    for (int e = 0; e < NN_E; ++e) {
+        if (e0 + e < ne) {
             double r = alpha * acc[e];
-            if (base) r += beta * base[(int64_t)e * ldb + i];
-            out[(int64_t)e * ldo + i] = r;
+            if (base) r += beta * base[(int64_t)(e0 + e) * ldb + i];
+            out[(int64_t)(e0 + e) * ldo + i] = r;
         }
     }
 }
 
+// out and base may be the same rows (in-place update of one element by one
+// thread); out must not overlap V.
 hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
                      const double *base, int64_t ldb, double beta, double alpha, double *out, int64_t ldo,
                      hipStream_t st)
 {
     if (ne <= 0 || D <= 0) return hipSuccess;
-    const dim3 g((D + 255) / 256), bl(256);
-    for (int e0 = 0; e0 < ne; e0 += 16) {
-        const int ee = min(16, ne - e0);
-        const double *b0 = base ? base + (int64_t)e0 * ldb : nullptr;
-        double *o = out + (int64_t)e0 * ldo;
-        if (m <= 0) {
-            // nothing to add: out = beta * base
-            hipLaunchKernelGGL((k_nn_small<16>), g, bl, 16 * sizeof(double), st, V, ldv, 0, D, C + e0, ldc, ee,
-                               b0, ldb, beta, alpha, o, ldo);
-        } else if (ee <= 4) {
-            hipLaunchKernelGGL((k_nn_small<4>), g, bl, (size_t)m * 4 * sizeof(double), st, V, ldv, m, D, C + e0,
-                               ldc, ee, b0, ldb, beta, alpha, o, ldo);
-        } else {
-            hipLaunchKernelGGL((k_nn_small<16>), g, bl, (size_t)m * 16 * sizeof(double), st, V, ldv, m, D,
-                               C + e0, ldc, ee, b0, ldb, beta, alpha, o, ldo);
-        }
-    }
+    const dim3 g((D + 255) / 256, (ne + NN_E - 1) / NN_E), bl(256);
+    const size_t shm = sizeof(double) * NN_E * (size_t)(m > 0 ? m : 1);
+    hipLaunchKernelGGL(k_nn_small, g, bl, shm, st, V, ldv, m, D, C, ldc, ne, base, ldb, beta, alpha, out, ldo);
     return hipGetLastError();
 }
 
@@ -291,60 +282,124 @@ hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// modified Gram-Schmidt (twice) inside a block of b vectors, one workgroup.
-// Vectors are first scaled to unit norm; a vector whose norm falls below
-// drop_tol during the sweep is marked dropped (keep[c] = 0) and left out of
-// later projections.
+// Cholesky QR of a block with column pivoting (one wave): from the Gram
+// matrix G = T^T T (b x b, b <= 32) pick columns greedily by the largest
+// remaining Schur-complement diagonal, stop when it falls below rel^2 times
+// the reference squared norm of that column (ref[j] if given, else G[j][j]),
+// and return C (b x b, column c < rank = output vector c) with
+// T C = orthonormal basis of the kept columns; columns c >= rank are zero.
 // ---------------------------------------------------------------------------
-__device__ double block_dot(const double *x, const double *y, int D, double *red)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < D; i += blockDim.x) s = fma(x[i], y[i], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    return t;
-}
+constexpr int PCH_MAX = 32;
 
-__global__ __launch_bounds__(1024) void k_mgs(double *__restrict__ T, int64_t ldt, int b, int D, double drop_tol,
-                                              int32_t *__restrict__ keep)
+__global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int ldg, int b,
+                                              const double *__restrict__ ref, double rel,
+                                              double *__restrict__ Cout, int ldc, int32_t *__restrict__ rank_out)
 {
-    __shared__ double red[16];
-    for (int c = 0; c < b; ++c) {
-        double *tc = T + (int64_t)c * ldt;
-        double n0 = sqrt(block_dot(tc, tc, D, red));
-        int ok = n0 > 0.0 && isfinite(n0);
-        if (ok)
-            for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] /= n0;
-        __syncthreads();
-        for (int pass = 0; pass < 2 && ok; ++pass) {
-            for (int q = 0; q < c; ++q) {
-                if (!keep[q]) continue;
-                const double *tq = T + (int64_t)q * ldt;
-                const double d = block_dot(tq, tc, D, red);
-                for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] -= d * tq[i];
-                __syncthreads();
+    __shared__ double A[PCH_MAX][PCH_MAX + 1];
+    __shared__ double Rq[PCH_MAX][PCH_MAX + 1];   // row i, original column q
+    __shared__ double R[PCH_MAX][PCH_MAX + 1];    // row i, pivot position j
+    __shared__ double Ri[PCH_MAX][PCH_MAX + 1];
+    __shared__ int perm[PCH_MAX];
+    __shared__ int rank_sh;
+    const int t = threadIdx.x;
+    for (int e = t; e < b * b; e += 64) {
+        const int i = e / b, j = e % b;
+        A[i][j] = 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
+    }
+    for (int e = t; e < PCH_MAX * PCH_MAX; e += 64) {
+        Rq[e / PCH_MAX][e % PCH_MAX] = 0.0;
+        R[e / PCH_MAX][e % PCH_MAX] = 0.0;
+        Ri[e / PCH_MAX][e % PCH_MAX] = 0.0;
+    }
+    if (t < PCH_MAX) perm[t] = t;
+    if (t == 0) rank_sh = -1;
+    __syncthreads();
+    int r = b;
+    for (int i = 0; i < b; ++i) {
+        if (t == 0) {
+            int jm = -1;
+            double best = -1.0;
+            for (int j = i; j < b; ++j) {
+                const int pj = perm[j];
+                const double d = A[pj][pj];
+                const double refj = ref ? ref[pj] : G[(int64_t)pj * ldg + pj];
+                if (d > rel * rel * refj && d > 0.0 && d > best) {
+                    best = d;
+                    jm = j;
+                }
+            }
+            if (jm < 0) {
+                rank_sh = i;
+            } else {
+                const int tmp = perm[i];
+                perm[i] = perm[jm];
+                perm[jm] = tmp;
             }
         }
-        if (ok) {
-            const double n1 = sqrt(block_dot(tc, tc, D, red));
-            ok = n1 > drop_tol;
-            if (ok)
-                for (int i = threadIdx.x; i < D; i += blockDim.x) tc[i] /= n1;
+        __syncthreads();
+        if (rank_sh >= 0) {
+            r = rank_sh;
+            break;
+        }
+        const int pi = perm[i];
+        const double rii = sqrt(A[pi][pi]);
+        // row i of R over the columns not yet pivoted, by original column
+        for (int j = i + t; j < b; j += 64) Rq[i][perm[j]] = (j == i) ? rii : A[pi][perm[j]] / rii;
+        __syncthreads();
+        // Schur complement update of the remaining block
+        for (int e = t; e < (b - i - 1) * (b - i - 1); e += 64) {
+            const int qj = perm[i + 1 + e / (b - i - 1)], ql = perm[i + 1 + e % (b - i - 1)];
+            A[qj][ql] -= Rq[i][qj] * Rq[i][ql];
         }
         __syncthreads();
-        if (threadIdx.x == 0) keep[c] = ok;
-        __syncthreads();
     }
+    // upper-triangular factor in final pivot order
+    for (int e = t; e < r * r; e += 64) {
+        const int i = e / r, j = e % r;
+        R[i][j] = (j >= i) ? Rq[i][perm[j]] : 0.0;
+    }
+    __syncthreads();
+    // inverse of R, column c per lane
+    if (t < r) {
+        const int c = t;
+        for (int i = c; i >= 0; --i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int j = i + 1; j <= c; ++j) s -= R[i][j] * Ri[j][c];
+            Ri[i][c] = s / R[i][i];
+        }
+    }
+    __syncthreads();
+    // C[perm[j]][c] = Ri[j][c]
+    for (int e = t; e < b * b; e += 64) {
+        const int q = e / b, c = e % b;
+        Cout[(int64_t)q * ldc + c] = 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < r * r; e += 64) {
+        const int j = e / r, c = e % r;
+        Cout[(int64_t)perm[j] * ldc + c] = Ri[j][c];
+    }
+    if (t == 0) *rank_out = r;
 }
 
-hipError_t launch_mgs(double *T, int64_t ldt, int b, int D, double drop_tol, int32_t *keep, hipStream_t st)
+hipError_t launch_pchol(const double *G, int ldg, int b, const double *ref, double rel, double *C, int ldc,
+                        int32_t *rank, hipStream_t st)
 {
-    if (b <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mgs, dim3(1), dim3(1024), 0, st, T, ldt, b, D, drop_tol, keep);
+    if (b <= 0 || b > PCH_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, st, G, ldg, b, ref, rel, C, ldc, rank);
+    return hipGetLastError();
+}
+
+// diagonal of a small matrix
+__global__ void k_diag_small(const double *__restrict__ G, int ldg, int b, double *__restrict__ out)
+{
+    const int t = threadIdx.x;
+    if (t < b) out[t] = G[(int64_t)t * ldg + t];
+}
+
+hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_small, dim3(1), dim3(64), 0, st, G, ldg, b, out);
     return hipGetLastError();
 }
 
@@ -365,19 +420,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ 
     __shared__ double Z[JAC_MAX][JAC_MAX + 1];
     __shared__ double cs[JAC_MAX / 2], sn[JAC_MAX / 2];
     __shared__ int pp[JAC_MAX / 2], qq[JAC_MAX / 2];
-    __shared__ double red[16];
+    __shared__ double red[32];
     __shared__ int perm[JAC_MAX];
+    __shared__ int nrot_sh;
     const int me = (m + 1) & ~1;     // even size (a padded index is inert)
-    for (int t = threadIdx.x; t < me * me; t += blockDim.x) {
+    const int half = me / 2;
+    const int nthr = blockDim.x;
+    for (int t = threadIdx.x; t < me * me; t += nthr) {
         const int i = t / me, j = t % me;
         A[i][j] = (i < m && j < m) ? 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]) : 0.0;
         Z[i][j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int half = me / 2;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double off = 0.0, tot = 0.0;
-        for (int t = threadIdx.x; t < me * me; t += blockDim.x) {
+        for (int t = threadIdx.x; t < me * me; t += nthr) {
             const int i = t / me, j = t % me;
             const double v = A[i][j] * A[i][j];
             tot += v;
@@ -387,32 +444,35 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ 
             off += __shfl_xor(off, o, 64);
             tot += __shfl_xor(tot, o, 64);
         }
-        __syncthreads();
         if ((threadIdx.x & 63) == 0) {
             red[threadIdx.x >> 6] = off;
+            red[16 + (threadIdx.x >> 6)] = tot;
         }
         __syncthreads();
-        double offs = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) offs += red[w];
+        double offs = 0.0, tots = 0.0;
+        for (int w = 0; w < nthr / 64; ++w) {
+            offs += red[w];
+            tots += red[16 + w];
+        }
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+        if (offs == 0.0) break;
+        if (threadIdx.x == 0) nrot_sh = 0;
         __syncthreads();
-        double tots = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tots += red[w];
-        __syncthreads();
-        if (offs <= 1e-30 * tots || offs == 0.0) break;
         for (int round = 0; round < me - 1; ++round) {
-            // round-robin pairing: index 0 fixed, others rotate
+            // round-robin pairing: index 0 fixed, the others rotate
             if (threadIdx.x < half) {
                 const int k = threadIdx.x;
-                auto pos = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + round) % (me - 1); };
-                int p = pos(k), q = pos(me - 1 - k);
-                if (p > q) { int t = p; p = q; q = t; }
+                const int s0 = k, s1 = me - 1 - k;
+                int p = s0 == 0 ? 0 : 1 + (s0 - 1 + round) % (me - 1);
+                int q = 1 + (s1 - 1 + round) % (me - 1);
+                if (p > q) { const int t = p; p = q; q = t; }
                 pp[k] = p;
                 qq[k] = q;
                 const double apq = A[p][q];
                 double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
+                // rotate only when a_pq is not negligible against the diagonal
+                if (fabs(apq) > 1e-16 * sqrt(fabs(A[p][p] * A[q][q])) && fabs(apq) > 1e-300) {
+                    nrot_sh = 1;
                     const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
@@ -422,30 +482,36 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ 
                 sn[k] = s;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int t = threadIdx.x; t < half * me; t += blockDim.x) {
-                const int k = t / me, j = t % me;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                const double ap = A[p][j], aq = A[q][j];
-                A[p][j] = c * ap - s * aq;
-                A[q][j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, Z <- Z J
-            for (int t = threadIdx.x; t < half * me; t += blockDim.x) {
-                const int k = t / me, i = t % me;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                const double ap = A[i][p], aq = A[i][q];
-                A[i][p] = c * ap - s * aq;
-                A[i][q] = s * ap + c * aq;
-                const double zp = Z[i][p], zq = Z[i][q];
-                Z[i][p] = c * zp - s * zq;
-                Z[i][q] = s * zp + c * zq;
+            // A <- J^T A J on 2x2 blocks (row pair k, column pair l), Z <- Z J
+            const int nblk = half * half;
+            for (int t = threadIdx.x; t < nblk + half * me; t += nthr) {
+                if (t < nblk) {
+                    const int k = t / half, l = t % half;
+                    const int p = pp[k], q = qq[k], r = pp[l], u = qq[l];
+                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+                    const double apr = A[p][r], apu = A[p][u], aqr = A[q][r], aqu = A[q][u];
+                    // rows: [p; q] <- [c -s; s c] [p; q]
+                    const double bpr = ck * apr - sk * aqr, bpu = ck * apu - sk * aqu;
+                    const double bqr = sk * apr + ck * aqr, bqu = sk * apu + ck * aqu;
+                    // columns: [r u] <- [r u] [c s; -s c]
+                    A[p][r] = cl * bpr - sl * bpu;
+                    A[p][u] = sl * bpr + cl * bpu;
+                    A[q][r] = cl * bqr - sl * bqu;
+                    A[q][u] = sl * bqr + cl * bqu;
+                } else {
+                    const int e = t - nblk;
+                    const int l = e / me, i = e % me;
+                    const int r = pp[l], u = qq[l];
+                    const double cl = cs[l], sl = sn[l];
+                    const double zr = Z[i][r], zu = Z[i][u];
+                    Z[i][r] = cl * zr - sl * zu;
+                    Z[i][u] = sl * zr + cl * zu;
+                }
             }
             __syncthreads();
         }
+        if (nrot_sh == 0) break;
+        __syncthreads();
     }
     // ascending order (stable), written out
     if (threadIdx.x == 0) {
@@ -461,8 +527,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ 
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m; e += blockDim.x) theta[e] = A[perm[e]][perm[e]];
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    for (int e = threadIdx.x; e < m; e += nthr) theta[e] = A[perm[e]][perm[e]];
+    for (int t = threadIdx.x; t < m * m; t += nthr) {
         const int q = t / m, e = t % m;
         Y[(int64_t)q * ldy + e] = Z[q][perm[e]];
     }
