@@ -31,6 +31,7 @@ WORKLOADS = {
     "medium": ("medium", 10, 1e-8),
     "tiny": ("tiny", 5, 1e-8),
     "small": ("small", 10, 1e-8),
+    "precision": ("precision", 10, 1e-8),
 }
 
 

@@ -375,18 +375,105 @@ static void element(const orc_inst *I, int64_t r, int64_t c, acc_t *out)
     *out = acc;
 }
 
-/* Sampled elements: val/abs/cnt may be NULL except val. */
+/* Sampled elements: val/abs/cnt may be NULL except val. Same sums as
+ * element() above (same order of m, m'), with the occupation lists and the
+ * target-pair connectivity of each symmetry pair computed once per call. */
+typedef struct { int64_t *off; int32_t *m2; } conn_t;
+
 void orc_elements(const orc_inst *I, int64_t n, const int64_t *rows, const int64_t *cols,
                   double *val, double *abss, int32_t *cnt)
 {
+    const int W = I->n_words, N = I->n_elec, ns = I->n_sym;
+    /* occupation lists of the target determinants of every symmetry */
+    int **occ = (int **)malloc(sizeof(int *) * (size_t)(ns > 0 ? ns : 1));
+    for (int s = 0; s < ns; ++s) {
+        occ[s] = (int *)malloc(sizeof(int) * (size_t)I->sym_ndet[s] * (N > 0 ? N : 1));
+        for (int m = 0; m < I->sym_ndet[s]; ++m) det_occ(I->sym_dets[s] + (size_t)m * W, W, occ[s] + (size_t)m * N);
+    }
+    /* which continuum symmetry pairs are needed */
+    conn_t *cn = (conn_t *)calloc((size_t)(ns * ns > 0 ? ns * ns : 1), sizeof(conn_t));
+    for (int64_t e = 0; e < n; ++e) {
+        rowid R = decode_row(I, rows[e]), C = decode_row(I, cols[e]);
+        if (!R.is_l2 && !C.is_l2) cn[R.sym * ns + C.sym].off = (int64_t *)1;
+    }
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            conn_t *c = &cn[a * ns + b];
+            if (!c->off) continue;
+            const int Ma = I->sym_ndet[a], Mb = I->sym_ndet[b];
+            c->off = (int64_t *)calloc((size_t)Ma + 1, sizeof(int64_t));
+            int64_t *cntr = (int64_t *)calloc((size_t)Ma, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int m = 0; m < Ma; ++m) {
+                int64_t k = 0;
+                for (int m2 = 0; m2 < Mb; ++m2)
+                    k += n_missing(occ[a] + (size_t)m * N, N, occ[b] + (size_t)m2 * N, N) <= 2;
+                cntr[m] = k;
+            }
+            for (int m = 0; m < Ma; ++m) c->off[m + 1] = c->off[m] + cntr[m];
+            c->m2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(c->off[Ma] > 0 ? c->off[Ma] : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int m = 0; m < Ma; ++m) {
+                int64_t k = c->off[m];
+                for (int m2 = 0; m2 < Mb; ++m2)
+                    if (n_missing(occ[a] + (size_t)m * N, N, occ[b] + (size_t)m2 * N, N) <= 2) c->m2[k++] = m2;
+            }
+            free(cntr);
+        }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t e = 0; e < n; ++e) {
-        acc_t a;
-        element(I, rows[e], cols[e], &a);
-        val[e] = a.s + a.c;
-        if (abss) abss[e] = a.a;
-        if (cnt) cnt[e] = a.n;
+        rowid R = decode_row(I, rows[e]), C = decode_row(I, cols[e]);
+        acc_t acc = {0, 0, 0, 0};
+        int A[MAXE], B[MAXE];
+        if (R.is_l2 && C.is_l2) {
+            element(I, rows[e], cols[e], &acc);
+        } else {
+            if (R.is_l2) { rowid t = R; R = C; C = t; }
+            const double *cr = I->sym_ci[R.sym];
+            const int Sr = I->sym_nstate[R.sym];
+            const int top = 2 * (I->ints.n_o + R.j);
+            if (C.is_l2) {
+                int nb = det_occ(I->l2_dets + (size_t)C.l * W, W, B);
+                for (int m = 0; m < I->sym_ndet[R.sym]; ++m) {
+                    memcpy(A, occ[R.sym] + (size_t)m * N, sizeof(int) * (size_t)N);
+                    A[N] = top;
+                    if (N + 1 != nb) continue;
+                    if (n_missing(A, N, B, nb) > 1) continue;
+                    double ab; int nt;
+                    double v = slater_condon(&I->ints, A, B, N + 1, &ab, &nt);
+                    double w = cr[(size_t)m * Sr + R.n];
+                    acc_add(&acc, w * v, fabs(w) * ab, nt);
+                }
+            } else {
+                const conn_t *c = &cn[R.sym * ns + C.sym];
+                const double *cc = I->sym_ci[C.sym];
+                const int Sc = I->sym_nstate[C.sym];
+                const int topc = 2 * (I->ints.n_o + C.j);
+                for (int m = 0; m < I->sym_ndet[R.sym]; ++m) {
+                    memcpy(A, occ[R.sym] + (size_t)m * N, sizeof(int) * (size_t)N);
+                    A[N] = top;
+                    for (int64_t k = c->off[m]; k < c->off[m + 1]; ++k) {
+                        const int m2 = c->m2[k];
+                        memcpy(B, occ[C.sym] + (size_t)m2 * N, sizeof(int) * (size_t)N);
+                        B[N] = topc;
+                        double ab; int nt;
+                        double v = slater_condon(&I->ints, A, B, N + 1, &ab, &nt);
+                        double w = cr[(size_t)m * Sr + R.n] * cc[(size_t)m2 * Sc + C.n];
+                        acc_add(&acc, w * v, fabs(w) * ab, nt);
+                    }
+                }
+            }
+        }
+        val[e] = acc.s + acc.c;
+        if (abss) abss[e] = acc.a;
+        if (cnt) cnt[e] = acc.n;
     }
+    for (int i = 0; i < ns * ns; ++i) {
+        if (cn[i].off) { free(cn[i].off); free(cn[i].m2); }
+    }
+    free(cn);
+    for (int s = 0; s < ns; ++s) free(occ[s]);
+    free(occ);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -77,7 +77,8 @@ hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
 hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
 // Davidson
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
-                         int64_t ldw, hipStream_t st);
+                         int64_t ldw, double *Wp, hipStream_t st);
+int matvec_splits(int D);
 hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
                      double *part, double *out, int64_t ldo, int transpose, hipStream_t st);
 hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
@@ -818,7 +819,7 @@ namespace {
 struct DavBufs {
     double *V = nullptr, *Wv = nullptr, *V2 = nullptr, *W2 = nullptr, *G = nullptr, *theta = nullptr,
            *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *Gb = nullptr, *Cb = nullptr,
-           *ref = nullptr, *part = nullptr, *norms = nullptr;
+           *ref = nullptr, *part = nullptr, *norms = nullptr, *Wp = nullptr;
     int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr;
 };
 }  // namespace
@@ -862,7 +863,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
               A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
-              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)k) && A((void **)&b.idx, 4 * (size_t)kr);
+              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)k) && A((void **)&b.idx, 4 * (size_t)kr) &&
+              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1));
     if (!ok) {
         cleanup();
         return fail(c, CCH_E_OOM, "Davidson buffers");
@@ -915,7 +917,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         if (added <= 0) break;   // no new direction: stagnation
         // W for the new vectors and the new rows of G
         DCK(hipEventRecord(c->mv0, st));
-        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, added, b.Wv + (int64_t)m * ldv, ldv, st));
+        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, added, b.Wv + (int64_t)m * ldv, ldv, b.Wp,
+                          st));
         DCK(hipEventRecord(c->mv1, st));
         matvecs += added;
         mv_launches += (added + 15) / 16;

@@ -8,6 +8,8 @@
 //       eigenproblem solved by cyclic Jacobi rotations in parallel
 //       (round-robin) order inside one workgroup, all in LDS.
 // Vectors are stored one per row: V[q][i], leading dimension ldv.
+#include <algorithm>
+
 #include "ccham_internal.h"
 
 namespace cch {
@@ -79,22 +81,106 @@ __global__ __launch_bounds__(256) void k_matvec(const double *__restrict__ H, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// K8 on the matrix cores: W^T = V^T H (H symmetric), FP64 MFMA 16x16x4.
+// Each wave owns a 16-column strip of H and a range of rows of H (split-K
+// across blockIdx.y); the B operand is 4 rows x 16 columns of H (four 128-byte
+// row segments per instruction), the A operand 16 vectors x 4 rows of V
+// (zero rows for q >= b). Partial sums per split go to Wp[ks][q][r] and are
+// reduced in a fixed order.
+// ---------------------------------------------------------------------------
+typedef double dx4m __attribute__((ext_vector_type(4)));
+constexpr int MVM_UNROLL = 8;      // MFMA k-steps per register block (32 rows)
+constexpr int MVM_NS = 4;          // 16-column strips per wave (share the V fragment)
+
+__global__ __launch_bounds__(256) void k_matvec_mfma(const double *__restrict__ H, int64_t ld, int D,
+                                                     const double *__restrict__ V, int64_t ldv, int b,
+                                                     int rows_per_split, double *__restrict__ Wp)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 4 + wv) * (16 * MVM_NS);
+    const int q = lane & 15;                    // vector of the A operand
+    const int kq = lane >> 4;                   // k within a 4-step
+    const int cb = blockIdx.y * rows_per_split;
+    const int ce = min(D, cb + rows_per_split);
+    const bool qok = q < b;
+    const double *vrow = V + (int64_t)(qok ? q : 0) * ldv;
+    const double *hcol[MVM_NS];
+    bool colok[MVM_NS];
+#pragma unroll
+    for (int t = 0; t < MVM_NS; ++t) {
+        const int col = r0 + 16 * t + (lane & 15);
+        colok[t] = col < D;
+        hcol[t] = H + (colok[t] ? col : 0);
+    }
+    dx4m acc[MVM_NS];
+#pragma unroll
+    for (int t = 0; t < MVM_NS; ++t) acc[t] = (dx4m){0.0, 0.0, 0.0, 0.0};
+    for (int c0 = cb; c0 < ce; c0 += 4 * MVM_UNROLL) {
+        double bv[MVM_UNROLL][MVM_NS], av[MVM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < MVM_UNROLL; ++u) {
+            const int c = c0 + 4 * u + kq;
+            const bool ok = c < ce;
+            av[u] = (ok && qok) ? vrow[c] : 0.0;
+#pragma unroll
+            for (int t = 0; t < MVM_NS; ++t)
+                bv[u][t] = (ok && colok[t]) ? __builtin_nontemporal_load(hcol[t] + (int64_t)c * ld) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < MVM_UNROLL; ++u)
+#pragma unroll
+            for (int t = 0; t < MVM_NS; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][t], acc[t], 0, 0, 0);
+    }
+    // item v of lane l: row (vector) l/16 + 4v, column (r) l%16 of the strip
+#pragma unroll
+    for (int t = 0; t < MVM_NS; ++t) {
+        const int col = r0 + 16 * t + (lane & 15);
+        if (colok[t]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int qq = (lane >> 4) + 4 * v;
+                Wp[((int64_t)blockIdx.y * 16 + qq) * D + col] = acc[t][v];
+            }
+        }
+    }
+}
+
+__global__ void k_matvec_reduce(const double *__restrict__ Wp, int ks, int D, int b, double *__restrict__ Wo,
+                                int64_t ldw)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (r >= D || q >= b) return;
+    double s = 0.0;
+    for (int k = 0; k < ks; ++k) s += Wp[((int64_t)k * 16 + q) * D + r];
+    Wo[(int64_t)q * ldw + r] = s;
+}
+
+// number of row splits for the MFMA mat-vec (enough waves to cover HBM latency)
+int matvec_splits(int D)
+{
+    const int waves = (D + 16 * MVM_NS - 1) / (16 * MVM_NS);
+    int ks = (4096 + waves - 1) / waves;
+    ks = std::max(1, std::min(ks, 64));
+    return ks;
+}
+
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
-                         int64_t ldw, hipStream_t st)
+                         int64_t ldw, double *Wp, hipStream_t st)
 {
     if (D <= 0 || b <= 0) return hipSuccess;
-    const int rows_per_wg = 4 * MV_ROWS_PER_WAVE;
-    const dim3 g((D + rows_per_wg - 1) / rows_per_wg), bl(256);
+    const int ks = matvec_splits(D);
+    int rps = (D + ks - 1) / ks;
+    rps = (rps + 4 * MVM_UNROLL - 1) / (4 * MVM_UNROLL) * (4 * MVM_UNROLL);
+    const int ksu = (D + rps - 1) / rps;
     for (int q0 = 0; q0 < b; q0 += 16) {
-        const int bb = min(16, b - q0);
-        const double *Vq = V + (int64_t)q0 * ldv;
-        double *Wq = W + (int64_t)q0 * ldw;
-        if (bb <= 4)
-            hipLaunchKernelGGL((k_matvec<4>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
-        else if (bb <= 8)
-            hipLaunchKernelGGL((k_matvec<8>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
-        else
-            hipLaunchKernelGGL((k_matvec<16>), g, bl, 0, st, H, ld, D, Vq, ldv, bb, Wq, ldw);
+        const int bb = std::min(16, b - q0);
+        hipLaunchKernelGGL(k_matvec_mfma, dim3((D + 64 * MVM_NS - 1) / (64 * MVM_NS), ksu), dim3(256), 0, st, H, ld, D,
+                           V + (int64_t)q0 * ldv, ldv, bb, rps, Wp);
+        hipLaunchKernelGGL(k_matvec_reduce, dim3((D + 255) / 256, bb), dim3(256), 0, st, Wp, ksu, D, bb,
+                           W + (int64_t)q0 * ldw, ldw);
     }
     return hipGetLastError();
 }
