@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64",
+                    help="expansion GEMM form: fp64, fp32, or bf16xS (split-BF16 with S slices)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -104,9 +106,17 @@ def main():
 
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
+    if args.precision == "fp64":
+        prec, slices = cc.CCH_PREC_FP64, 0
+    elif args.precision == "fp32":
+        prec, slices = cc.CCH_PREC_FP32, 0
+    elif args.precision.startswith("bf16x"):
+        prec, slices = cc.CCH_PREC_SPLIT_BF16, int(args.precision[5:])
+    else:
+        raise SystemExit(f"unknown --precision {args.precision}")
     ctx = cc.from_instance(inst, device=0, stream=stream, plan=False)
     t = time.perf_counter()
-    ctx.plan()
+    ctx.plan(precision=prec, split_slices=slices)
     ctx.sync()
     plan_s = time.perf_counter() - t
     work = ctx.work_counts()
@@ -196,6 +206,24 @@ def main():
         "plan_s": plan_s,
         "roofline": roof,
     }
+    if prec != cc.CCH_PREC_FP64:
+        # error of this form against the FP64 build (itself checked against the oracle)
+        G = ctx.get_matrix()
+        ev_lo = np.array(ev)
+        ref = cc.from_instance(inst, device=0, stream=stream)
+        ref.build()
+        H64 = ref.get_matrix()
+        ev64, _, _, _ = ref.davidson(k, tol=tol, want_vectors=False)
+        ref.close()
+        out["precision_error"] = {
+            "mode": args.precision,
+            "max_abs_element_error": float(np.abs(G - H64).max()),
+            "max_abs_element": float(np.abs(H64).max()),
+            "max_abs_eigenvalue_error": float(np.abs(ev_lo - ev64).max()),
+            "reference": "FP64 build of the same inputs (parity-checked against the oracle)",
+        }
+        del G, H64
+    out["precision"] = args.precision
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)
     ctx.close()

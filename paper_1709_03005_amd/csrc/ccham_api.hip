@@ -47,6 +47,13 @@ struct ExpandEpi {
 };
 hipError_t launch_expand_f64(const double *At, const double *B, int nrows, int N, int K, const ExpandEpi &ep,
                              hipStream_t st);
+hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t st);
+hipError_t launch_expand_f32(const float *At, const float *B, int nrows, int N, int K, const ExpandEpi &ep,
+                             hipStream_t st);
+hipError_t launch_slices(const double *At, int nrows, const double *B, int K, int N, int s, int ldk,
+                         double *sigA, __bf16 *SA, double *sigB, __bf16 *SB, hipStream_t st);
+hipError_t launch_expand_bf16split(const __bf16 *SA, const __bf16 *SB, const double *sigA, const double *sigB,
+                                   int s, int nrows, int N, int ldk, const ExpandEpi &ep, hipStream_t st);
 struct Class4Args {
     const uint64_t *tdets;
     const double *ci;
@@ -124,6 +131,11 @@ struct PairPlan {
     int64_t *d_count = nullptr, *d_start = nullptr, *d_cursor = nullptr, *d_sorted = nullptr, *d_tmp = nullptr,
             *d_d0 = nullptr;
     double *d_B = nullptr;   // integral rows laid out for this pair's expansion
+    // reduced-precision operands of the expansion product
+    float *d_At32 = nullptr, *d_B32 = nullptr;
+    double *d_sigA = nullptr, *d_sigB = nullptr;
+    __bf16 *d_SA = nullptr, *d_SB = nullptr;
+    int ldk = 0;
 };
 
 struct LtPlan {
@@ -492,7 +504,12 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     if (c->syms.empty() && c->n_l2 == 0) return fail(c, CCH_E_STATE, "no basis functions");
     if (c->planned) return fail(c, CCH_E_STATE, "already planned");
     if (opts) {
-        if (opts->precision != CCH_PREC_FP64) return fail(c, CCH_E_INVALID_ARG, "precision mode not available");
+        if (opts->precision != CCH_PREC_FP64 && opts->precision != CCH_PREC_FP32 &&
+            opts->precision != CCH_PREC_SPLIT_BF16)
+            return fail(c, CCH_E_INVALID_ARG, "unknown precision mode %d", opts->precision);
+        if (opts->precision == CCH_PREC_SPLIT_BF16 && (opts->split_slices < 1 || opts->split_slices > 8))
+            return fail(c, CCH_E_INVALID_ARG, "split_slices must be 1..8");
+        if (opts->max_device_bytes < 0) return fail(c, CCH_E_INVALID_ARG, "negative memory budget");
         c->opts = *opts;
     }
     HIPCK(c, hipSetDevice(c->device));
@@ -557,6 +574,21 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
             TRY(dalloc(c, &p.d_d0, sa.M));
             TRY(dalloc(c, &p.d_B, (size_t)2 * p.n_slot * sa.nc * sb.nc));
             maxB += (int64_t)2 * p.n_slot * sa.nc * sb.nc;
+            {
+                const size_t K = (size_t)2 * p.n_slot, N = (size_t)sa.nc * sb.nc;
+                if (c->opts.precision == CCH_PREC_FP32) {
+                    TRY(dalloc(c, &p.d_At32, K * p.nrows));
+                    TRY(dalloc(c, &p.d_B32, K * N));
+                } else if (c->opts.precision == CCH_PREC_SPLIT_BF16) {
+                    const int sl = c->opts.split_slices;
+                    p.ldk = (int)((K + 63) / 64 * 64);
+                    if (p.ldk == 0) p.ldk = 64;
+                    TRY(dalloc(c, &p.d_sigA, p.nrows));
+                    TRY(dalloc(c, &p.d_sigB, N));
+                    TRY(dalloc(c, &p.d_SA, (size_t)sl * p.nrows * p.ldk));
+                    TRY(dalloc(c, &p.d_SB, (size_t)sl * N * p.ldk));
+                }
+            }
             c->pp.push_back(p);
         }
     }
@@ -614,6 +646,14 @@ cch_status cch_build(cch_ctx *c)
         if (sa.nc == 0 || sb.nc == 0) continue;
         HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
                                  sa.nc, sb.ja0, sb.nc, p.d_B, st));
+        const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
+        if (c->opts.precision == CCH_PREC_FP32) {
+            HIPCK(c, launch_to_f32(p.d_At, p.d_At32, (int64_t)K * p.nrows, st));
+            HIPCK(c, launch_to_f32(p.d_B, p.d_B32, (int64_t)K * N, st));
+        } else if (c->opts.precision == CCH_PREC_SPLIT_BF16) {
+            HIPCK(c, launch_slices(p.d_At, p.nrows, p.d_B, K, N, c->opts.split_slices, p.ldk, p.d_sigA, p.d_SA,
+                                   p.d_sigB, p.d_SB, st));
+        }
     }
     HIPCK(c, hipEventRecord(c->ev[3], st));
     // phase 3: expansion GEMM per symmetry pair
@@ -622,7 +662,14 @@ cch_status cch_build(cch_ctx *c)
         if (sa.nc == 0 || sb.nc == 0) continue;
         ExpandEpi ep{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT, p.d_O,
                      c->d_h, c->n_o, c->n_orb};
-        HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, sa.nc * sb.nc, 2 * p.n_slot, ep, st));
+        const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
+        if (c->opts.precision == CCH_PREC_FP32)
+            HIPCK(c, launch_expand_f32(p.d_At32, p.d_B32, p.nrows, N, K, ep, st));
+        else if (c->opts.precision == CCH_PREC_SPLIT_BF16)
+            HIPCK(c, launch_expand_bf16split(p.d_SA, p.d_SB, p.d_sigA, p.d_sigB, c->opts.split_slices, p.nrows, N,
+                                             p.ldk, ep, st));
+        else
+            HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, N, K, ep, st));
     }
     HIPCK(c, hipEventRecord(c->ev[4], st));
     // phase 4: class 4
