@@ -76,12 +76,72 @@ def cpu_baseline(inst, budget_s=20.0):
             "seconds": t_total}
 
 
+def bench_batch(args):
+    """64 seeded instances (D ~ U[500, 6000]) built one after another with
+    cch_build (plain) and together with cch_batch_build (persistent launches
+    in one hipGraph, autotuned); elements/s of both on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_1709_03005_amd as cc
+    import synth
+    t = time.perf_counter()
+    insts = [synth.batch_instance(i) for i in range(args.instances)]
+    print(f"[bench] batch of {len(insts)} generated in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.init()
+    ctxs = [cc.from_instance(I) for I in insts]
+    lower = sum(c.work_counts()["lower_elements"] for c in ctxs)
+    # plain: one cch_build per instance, back to back
+    for c in ctxs:
+        c.build()
+    for c in ctxs:
+        c.sync()
+    plain = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        for c in ctxs:
+            c.build()
+        for c in ctxs:
+            c.sync()
+        plain.append(time.perf_counter() - t0)
+    t = time.perf_counter()
+    b = cc.Batch(ctxs, autotune=True)
+    tune_s = time.perf_counter() - t
+    for _ in range(args.warmup):
+        b.build()
+    batched, dev = [], []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        b.build()
+        batched.append(time.perf_counter() - t0)
+        dev.append(b.time_ms())
+    info = b.info()
+    ms = float(np.median(batched)) * 1e3
+    out = {
+        "metric": METRIC, "value": lower / (ms * 1e-3), "unit": "elements/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (64 seeded instances)",
+        "config": {"workload": "batch", "instances": len(insts), "dims": [I.dim() for I in insts],
+                   "total_lower_elements": lower},
+        "batched_device_ms": float(np.median(dev)),
+        "plain_ms": float(np.median(plain)) * 1e3,
+        "plain_elements_per_s": lower / float(np.median(plain)),
+        "speedup_vs_plain": float(np.median(plain)) / float(np.median(batched)),
+        "batch_info": info, "autotune_and_capture_s": tune_s,
+    }
+    b.close()
+    for c in ctxs:
+        c.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64",
                     help="expansion GEMM form: fp64, fp32, or bf16xS (split-BF16 with S slices)")
@@ -97,6 +157,8 @@ def main():
     import paper_1709_03005_amd as cc
     import synth
 
+    if args.workload == "batch":
+        return bench_batch(args)
     gen, k, tol = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     inst = synth.CONFIGS[gen]()

@@ -211,6 +211,36 @@ cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
  * elements, out[7] number of symmetry pairs. */
 cch_status cch_work_counts(const cch_ctx *ctx, double *out8);
 
+/* ------------------------------------------------------------------------
+ * Batched build: many instances of uneven size built together. Every context
+ * must be planned with the FP64 form, on the same device. The build phases of
+ * all instances are queued on one internal stream; the expansion products of
+ * all (instance, symmetry pair), all class-4 rows and all L2 tiles each run as
+ * one persistent launch walking a tile list, and the whole sequence is
+ * captured once in a hipGraph and replayed on every cch_batch_build.
+ * With CCH_BATCH_AUTOTUNE, cch_batch_create times candidate tile heights of
+ * the expansion product and grid sizes of the persistent launches on the
+ * device and keeps the fastest (cached per batch shape for the process).
+ * Results are bit-identical to building each context alone.
+ * ------------------------------------------------------------------------ */
+typedef struct cch_batch cch_batch;
+
+#define CCH_BATCH_AUTOTUNE 1
+
+/* ctxs[n]: planned contexts (caller keeps ownership; they must outlive the
+ * batch). Synchronous: waits for the contexts' streams. */
+cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, int32_t flags);
+/* Build every context's matrix (graph replay); synchronous. Afterwards each
+ * context is built: cch_get_matrix / cch_davidson work on it as usual. */
+cch_status cch_batch_build(cch_batch *b);
+/* Device time of the last cch_batch_build in ms (HIP events around the graph). */
+cch_status cch_batch_time(const cch_batch *b, float *ms);
+/* out[8]: expansion tile height, expansion grid, class-4 grid, L2 grid,
+ * autotuned (0/1), taken from the cache (0/1), graph nodes, instances. */
+cch_status cch_batch_info(const cch_batch *b, int32_t *out8);
+cch_status cch_batch_destroy(cch_batch *b);
+const char *cch_batch_last_error(const cch_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

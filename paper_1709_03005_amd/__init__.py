@@ -41,8 +41,10 @@ EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
     "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_labels",
-    "cch_davidson", "cch_build_time", "cch_work_counts",
+    "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
+    "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
 ]
+CCH_BATCH_AUTOTUNE = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run paper_1709_03005_amd/build.py (hipcc, gfx950)")
@@ -87,6 +89,12 @@ _SIG = {
     "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
     "cch_build_time": (i32, [P, C.POINTER(C.c_float), P]),
     "cch_work_counts": (i32, [P, P]),
+    "cch_batch_create": (i32, [C.POINTER(P), P, i32, i32]),
+    "cch_batch_build": (i32, [P]),
+    "cch_batch_time": (i32, [P, C.POINTER(C.c_float)]),
+    "cch_batch_info": (i32, [P, P]),
+    "cch_batch_destroy": (i32, [P]),
+    "cch_batch_last_error": (C.c_char_p, [P]),
 }
 for _n, (_r, _a) in _SIG.items():
     _f = getattr(lib, _n)
@@ -247,6 +255,48 @@ class Context:
         ph = (C.c_float * 8)()
         self._ck(lib.cch_build_time(self.h, C.byref(t), C.cast(ph, C.c_void_p)))
         return t.value, list(ph)
+
+
+class Batch:
+    """cch_batch over planned contexts (kept alive by this object)."""
+
+    def __init__(self, contexts, autotune=True):
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        rc = lib.cch_batch_create(C.byref(h), C.cast(arr, C.c_void_p), len(self.contexts),
+                                  CCH_BATCH_AUTOTUNE if autotune else 0)
+        if rc != CCH_OK:
+            raise CchError(rc, lib.cch_batch_last_error(None).decode())
+        self.h = h
+
+    def build(self):
+        rc = lib.cch_batch_build(self.h)
+        if rc != CCH_OK:
+            raise CchError(rc, lib.cch_batch_last_error(self.h).decode())
+
+    def time_ms(self) -> float:
+        t = C.c_float()
+        lib.cch_batch_time(self.h, C.byref(t))
+        return t.value
+
+    def info(self) -> dict:
+        o = np.zeros(8, np.int32)
+        lib.cch_batch_info(self.h, o.ctypes.data_as(C.c_void_p))
+        keys = ["tile_rows", "grid_expand", "grid_class4", "grid_l2", "autotuned", "from_cache",
+                "graph_nodes", "instances"]
+        return dict(zip(keys, [int(x) for x in o]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.cch_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_instance(inst, device=0, stream=None, plan=True, **plan_kw) -> Context:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -80,6 +81,29 @@ struct L2Args {
     int64_t row0;
 };
 hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st);
+struct GemmTask {
+    const double *At;
+    const double *B;
+    int nrows, N, K;
+    int tiles_m, tiles_n;
+    int64_t first;
+    ExpandEpi ep;
+};
+struct L2Task {
+    L2Args a;
+    int64_t first;
+};
+struct C4Task {
+    Class4Args a;
+    int n_l2, jtiles;
+    int64_t first;
+};
+int expand_tiles(int nrows, int N, int bm);
+int64_t l2_tiles(int n_l2);
+hipError_t launch_expand_f64_batched(const GemmTask *tasks, int ntask, int64_t total, int bm, int grid,
+                                     hipStream_t st);
+hipError_t launch_l2_batched(int W, const L2Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
+hipError_t launch_class4_batched(int W, const C4Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
 hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
 hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
 // Davidson
@@ -176,6 +200,7 @@ struct cch_ctx {
     hipEvent_t ev[8] = {};
     hipEvent_t mv0 = nullptr, mv1 = nullptr;
     int64_t relayout_elems = 0;
+    bool timed = false;     // the phase events belong to the last build
     bool have_events = false;
 };
 
@@ -606,15 +631,51 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     return CCH_OK;
 }
 
-cch_status cch_build(cch_ctx *c)
+// ---------------------------------------------------------------------------
+// build phases; `ev` records the phase events on the stream
+// ---------------------------------------------------------------------------
+#define EVREC(i)                                                 \
+    do {                                                         \
+        if (ev) HIPCK(c, hipEventRecord(c->ev[(i)], st));        \
+    } while (0)
+
+static Class4Args class4_args(cch_ctx *c, const LtPlan &L)
 {
-    if (!c) return CCH_E_INVALID_ARG;
-    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
-    HIPCK(c, hipSetDevice(c->device));
-    hipStream_t st = c->stream;
+    const SymInfo &s = c->syms[L.sym];
+    Class4Args a{};
+    a.tdets = s.d_dets;
+    a.ci = s.d_ci;
+    a.S = s.S;
+    a.h = c->d_h;
+    a.tttc = c->d_tttc;
+    a.n_o = c->n_o;
+    a.n_orb = c->n_orb;
+    a.n_cont = c->n_cont;
+    a.ja0 = s.ja0;
+    a.nc = s.nc;
+    a.row_off = L.pr.row_off;
+    a.row_cnt = L.pr.row_cnt;
+    a.pl = L.pr.pl;
+    a.H = c->d_H;
+    a.ld = c->ld;
+    a.row_l2 = c->Dc;
+    a.col0 = s.row0;
+    a.pairs_per_chunk = std::max(1, std::min(64, 1024 / (1 + 2 * c->n_elec)));
+    return a;
+}
+
+static ExpandEpi expand_epi(cch_ctx *c, const PairPlan &p)
+{
+    const SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+    return ExpandEpi{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT,
+                     p.d_O, c->d_h, c->n_o, c->n_orb};
+}
+
+// phases 0-2: scans, target elements and densities, relayout
+static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev)
+{
     const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
-    HIPCK(c, hipEventRecord(c->ev[0], st));
-    // phase 0: excitation scans (emit)
+    EVREC(0);
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         HIPCK(c, launch_scan(SCAN_TT, c->W, sa.d_dets, sa.M, sb.d_dets, sb.M, 2 * c->n_o, p.pr.row_off,
@@ -625,8 +686,7 @@ cch_status cch_build(cch_ctx *c)
         HIPCK(c, launch_scan(SCAN_LT, c->W, c->d_l2, c->n_l2, s.d_dets, s.M, 2 * c->n_o, L.pr.row_off,
                              L.pr.row_cnt, L.pr.pl, st));
     }
-    HIPCK(c, hipEventRecord(c->ev[1], st));
-    // phase 1: target elements, projection, densities
+    EVREC(1);
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         HIPCK(c, launch_pair_values(c->W, I, sa.d_dets, sb.d_dets, p.pr.pl, p.pr.n, p.d_hv, st));
@@ -639,8 +699,7 @@ cch_status cch_build(cch_ctx *c)
                               p.n_slot, sa.d_dets, sa.d_ci, sa.S, sb.d_ci, sb.S, p.nrows, p.d_rn, p.d_rn2, p.d_At,
                               st));
     }
-    HIPCK(c, hipEventRecord(c->ev[2], st));
-    // phase 2: integral rows laid out per symmetry pair
+    EVREC(2);
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
@@ -655,13 +714,17 @@ cch_status cch_build(cch_ctx *c)
                                    p.d_sigB, p.d_SB, st));
         }
     }
-    HIPCK(c, hipEventRecord(c->ev[3], st));
-    // phase 3: expansion GEMM per symmetry pair
+    EVREC(3);
+    return CCH_OK;
+}
+
+// phase 3: expansion product per symmetry pair
+static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st)
+{
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
-        ExpandEpi ep{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT, p.d_O,
-                     c->d_h, c->n_o, c->n_orb};
+        const ExpandEpi ep = expand_epi(c, p);
         const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
         if (c->opts.precision == CCH_PREC_FP32)
             HIPCK(c, launch_expand_f32(p.d_At32, p.d_B32, p.nrows, N, K, ep, st));
@@ -671,50 +734,57 @@ cch_status cch_build(cch_ctx *c)
         else
             HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, N, K, ep, st));
     }
-    HIPCK(c, hipEventRecord(c->ev[4], st));
-    // phase 4: class 4
-    for (auto &L : c->lt) {
-        SymInfo &s = c->syms[L.sym];
-        Class4Args a{};
-        a.tdets = s.d_dets;
-        a.ci = s.d_ci;
-        a.S = s.S;
-        a.h = c->d_h;
-        a.tttc = c->d_tttc;
-        a.n_o = c->n_o;
-        a.n_orb = c->n_orb;
-        a.n_cont = c->n_cont;
-        a.ja0 = s.ja0;
-        a.nc = s.nc;
-        a.row_off = L.pr.row_off;
-        a.row_cnt = L.pr.row_cnt;
-        a.pl = L.pr.pl;
-        a.H = c->d_H;
-        a.ld = c->ld;
-        a.row_l2 = c->Dc;
-        a.col0 = s.row0;
-        a.pairs_per_chunk = std::max(1, std::min(64, 1024 / (1 + 2 * c->n_elec)));
-        HIPCK(c, launch_class4(c->W, a, c->n_l2, st));
-    }
-    HIPCK(c, hipEventRecord(c->ev[5], st));
-    // phase 5: classes 2 and 8
+    return CCH_OK;
+}
+
+static cch_status enqueue_class4(cch_ctx *c, hipStream_t st)
+{
+    for (auto &L : c->lt) HIPCK(c, launch_class4(c->W, class4_args(c, L), c->n_l2, st));
+    return CCH_OK;
+}
+
+static cch_status enqueue_l2(cch_ctx *c, hipStream_t st)
+{
     if (c->n_l2 > 0) {
+        const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
         L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
         HIPCK(c, launch_l2_block(c->W, a, st));
     }
-    HIPCK(c, hipEventRecord(c->ev[6], st));
-    // phase 6: mirror the lower triangle, diagonal
+    return CCH_OK;
+}
+
+static cch_status enqueue_post(cch_ctx *c, hipStream_t st)
+{
     HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->D, st));
     HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->D, c->d_diag, st));
-    HIPCK(c, hipEventRecord(c->ev[7], st));
+    return CCH_OK;
+}
+
+cch_status cch_build(cch_ctx *c)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    HIPCK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const bool ev = true;
+    TRY(enqueue_pre(c, st, ev));
+    TRY(enqueue_gemm(c, st));
+    EVREC(4);
+    TRY(enqueue_class4(c, st));
+    EVREC(5);
+    TRY(enqueue_l2(c, st));
+    EVREC(6);
+    TRY(enqueue_post(c, st));
+    EVREC(7);
     c->built = true;
+    c->timed = true;
     return CCH_OK;
 }
 
 cch_status cch_build_time(cch_ctx *c, float *total_ms, float *phases)
 {
     if (!c) return CCH_E_INVALID_ARG;
-    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    if (!c->built || !c->timed) return fail(c, CCH_E_STATE, "no timed build (cch_build) yet");
     HIPCK(c, hipEventSynchronize(c->ev[7]));
     if (total_ms) HIPCK(c, hipEventElapsedTime(total_ms, c->ev[0], c->ev[7]));
     if (phases) {
@@ -852,6 +922,321 @@ cch_status cch_get_labels(cch_ctx *c, int32_t which, int32_t sym_a, int32_t sym_
     return CCH_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// batched build
+// ---------------------------------------------------------------------------
+#include <map>
+
+struct cch_batch {
+    std::vector<cch_ctx *> cs;
+    int device = 0;
+    hipStream_t st = nullptr;
+    std::string err;
+    std::vector<void *> allocs;
+    GemmTask *d_gemm[2] = {nullptr, nullptr};   // tile height 32 / 64
+    int n_gemm = 0;
+    int64_t gemm_total[2] = {0, 0};
+    struct Group {
+        int W;
+        void *d_tasks;
+        int n;
+        int64_t total;
+    };
+    std::vector<Group> l2g, c4g;
+    int bm = 64, g_gemm = 1024, g_c4 = 2048, g_l2 = 2048;
+    int tuned = 0, cached = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    size_t nodes = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float last_ms = 0.0f;
+};
+
+static std::map<std::string, std::array<int, 4>> g_tune_cache;
+
+static cch_status bfail(cch_batch *b, cch_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+#define BCK(b, x)                                                                                \
+    do {                                                                                         \
+        hipError_t e_ = (x);                                                                     \
+        if (e_ != hipSuccess) return bfail((b), CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+static cch_status bupload(cch_batch *b, T **d, const std::vector<T> &h)
+{
+    void *p = nullptr;
+    BCK(b, hipMalloc(&p, sizeof(T) * (h.empty() ? 1 : h.size())));
+    b->allocs.push_back(p);
+    if (!h.empty()) BCK(b, hipMemcpy(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    *d = (T *)p;
+    return CCH_OK;
+}
+
+static cch_status ctx_status(cch_batch *b, cch_ctx *c, cch_status rc)
+{
+    if (rc != CCH_OK) b->err = c->err;
+    return rc;
+}
+
+static cch_status batch_gemm(cch_batch *b, int bm, int grid)
+{
+    const int v = bm == 32 ? 0 : 1;
+    BCK(b, launch_expand_f64_batched(b->d_gemm[v], b->n_gemm, b->gemm_total[v], bm, grid, b->st));
+    return CCH_OK;
+}
+
+static cch_status batch_c4(cch_batch *b, int grid)
+{
+    for (auto &g : b->c4g) BCK(b, launch_class4_batched(g.W, (const C4Task *)g.d_tasks, g.n, g.total, grid, b->st));
+    return CCH_OK;
+}
+
+static cch_status batch_l2(cch_batch *b, int grid)
+{
+    for (auto &g : b->l2g) BCK(b, launch_l2_batched(g.W, (const L2Task *)g.d_tasks, g.n, g.total, grid, b->st));
+    return CCH_OK;
+}
+
+static cch_status enqueue_batch(cch_batch *b)
+{
+    for (cch_ctx *c : b->cs) TRY(ctx_status(b, c, enqueue_pre(c, b->st, false)));
+    TRY(batch_gemm(b, b->bm, b->g_gemm));
+    TRY(batch_c4(b, b->g_c4));
+    TRY(batch_l2(b, b->g_l2));
+    for (cch_ctx *c : b->cs) TRY(ctx_status(b, c, enqueue_post(c, b->st)));
+    return CCH_OK;
+}
+
+template <class F>
+static cch_status time_it(cch_batch *b, F &&f, float *ms)
+{
+    BCK(b, hipEventRecord(b->e0, b->st));
+    TRY(f());
+    BCK(b, hipEventRecord(b->e1, b->st));
+    BCK(b, hipEventSynchronize(b->e1));
+    BCK(b, hipEventElapsedTime(ms, b->e0, b->e1));
+    return CCH_OK;
+}
+
+cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, int32_t flags)
+{
+    if (!out || !ctxs || n <= 0) return bfail(nullptr, CCH_E_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return bfail(nullptr, CCH_E_INVALID_ARG, "context %d is NULL", i);
+        if (!ctxs[i]->planned) return bfail(nullptr, CCH_E_STATE, "context %d is not planned", i);
+        if (ctxs[i]->opts.precision != CCH_PREC_FP64)
+            return bfail(nullptr, CCH_E_INVALID_ARG, "context %d: batched builds use the FP64 form", i);
+        if (ctxs[i]->device != ctxs[0]->device) return bfail(nullptr, CCH_E_INVALID_ARG, "contexts on two devices");
+    }
+    cch_batch *b = new (std::nothrow) cch_batch();
+    if (!b) return bfail(nullptr, CCH_E_OOM, "batch allocation failed");
+    b->cs.assign(ctxs, ctxs + n);
+    b->device = ctxs[0]->device;
+    auto cleanup_fail = [&](cch_status rc) {
+        g_create_err = b->err;
+        cch_batch_destroy(b);
+        return rc;
+    };
+    if (hipSetDevice(b->device) != hipSuccess || hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
+        return cleanup_fail(bfail(b, CCH_E_HIP, "stream/event creation failed"));
+    for (cch_ctx *c : b->cs)
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup_fail(bfail(b, CCH_E_HIP, "sync failed"));
+    // task tables
+    std::vector<GemmTask> g32, g64;
+    int64_t t32 = 0, t64 = 0;
+    std::map<int, std::vector<L2Task>> l2;
+    std::map<int, std::vector<C4Task>> c4;
+    std::map<int, int64_t> l2t, c4t;
+    for (cch_ctx *c : b->cs) {
+        for (auto &p : c->pp) {
+            SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+            if (sa.nc == 0 || sb.nc == 0 || p.nrows == 0) continue;
+            GemmTask g{p.d_At, p.d_B, p.nrows, sa.nc * sb.nc, 2 * p.n_slot, 0, 0, 0, expand_epi(c, p)};
+            g.tiles_m = (p.nrows + 31) / 32;
+            g.tiles_n = expand_tiles(1, g.N, 32);
+            g.first = t32;
+            t32 += (int64_t)g.tiles_m * g.tiles_n;
+            g32.push_back(g);
+            g.tiles_m = (p.nrows + 63) / 64;
+            g.first = t64;
+            t64 += (int64_t)g.tiles_m * g.tiles_n;
+            g64.push_back(g);
+        }
+        for (auto &L : c->lt) {
+            const SymInfo &s = c->syms[L.sym];
+            if (s.nc == 0 || c->n_l2 == 0) continue;
+            C4Task k{class4_args(c, L), c->n_l2, (s.nc + 63) / 64, c4t[c->W]};
+            c4t[c->W] += (int64_t)k.n_l2 * k.jtiles;
+            c4[c->W].push_back(k);
+        }
+        if (c->n_l2 > 0) {
+            const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
+            L2Task t{L2Args{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc}, l2t[c->W]};
+            l2t[c->W] += l2_tiles(c->n_l2);
+            l2[c->W].push_back(t);
+        }
+    }
+    b->n_gemm = (int)g64.size();
+    b->gemm_total[0] = t32;
+    b->gemm_total[1] = t64;
+    cch_status rc;
+    if ((rc = bupload(b, &b->d_gemm[0], g32)) != CCH_OK) return cleanup_fail(rc);
+    if ((rc = bupload(b, &b->d_gemm[1], g64)) != CCH_OK) return cleanup_fail(rc);
+    for (auto &kv : l2) {
+        L2Task *d = nullptr;
+        if ((rc = bupload(b, &d, kv.second)) != CCH_OK) return cleanup_fail(rc);
+        b->l2g.push_back({kv.first, d, (int)kv.second.size(), l2t[kv.first]});
+    }
+    for (auto &kv : c4) {
+        C4Task *d = nullptr;
+        if ((rc = bupload(b, &d, kv.second)) != CCH_OK) return cleanup_fail(rc);
+        b->c4g.push_back({kv.first, d, (int)kv.second.size(), c4t[kv.first]});
+    }
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    b->g_gemm = 4 * cus;
+    b->g_c4 = 8 * cus;
+    b->g_l2 = 8 * cus;
+    if (flags & CCH_BATCH_AUTOTUNE) {
+        int64_t c4tot = 0, l2tot = 0;
+        for (auto &g : b->c4g) c4tot += g.total;
+        for (auto &g : b->l2g) l2tot += g.total;
+        char key[256];
+        snprintf(key, sizeof key, "n%zu:g%d:%lld:%lld:c%lld:l%lld", b->cs.size(), b->n_gemm, (long long)t32,
+                 (long long)t64, (long long)c4tot, (long long)l2tot);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            b->bm = it->second[0];
+            b->g_gemm = it->second[1];
+            b->g_c4 = it->second[2];
+            b->g_l2 = it->second[3];
+            b->cached = 1;
+        } else {
+            // inputs of the persistent phases
+            for (cch_ctx *c : b->cs)
+                if ((rc = ctx_status(b, c, enqueue_pre(c, b->st, false))) != CCH_OK) return cleanup_fail(rc);
+            float best = 1e30f, ms = 0.0f;
+            for (int bm : {64, 32})
+                for (int mult : {1, 2, 4, 8}) {
+                    if ((rc = time_it(b, [&] { return batch_gemm(b, bm, mult * cus); }, &ms)) != CCH_OK)
+                        return cleanup_fail(rc);
+                    if (ms < best) {
+                        best = ms;
+                        b->bm = bm;
+                        b->g_gemm = mult * cus;
+                    }
+                }
+            best = 1e30f;
+            for (int mult : {2, 4, 8, 16}) {
+                if ((rc = time_it(b, [&] { return batch_c4(b, mult * cus); }, &ms)) != CCH_OK) return cleanup_fail(rc);
+                if (ms < best) {
+                    best = ms;
+                    b->g_c4 = mult * cus;
+                }
+            }
+            best = 1e30f;
+            for (int mult : {2, 4, 8, 16}) {
+                if ((rc = time_it(b, [&] { return batch_l2(b, mult * cus); }, &ms)) != CCH_OK) return cleanup_fail(rc);
+                if (ms < best) {
+                    best = ms;
+                    b->g_l2 = mult * cus;
+                }
+            }
+            g_tune_cache[key] = {b->bm, b->g_gemm, b->g_c4, b->g_l2};
+        }
+        b->tuned = 1;
+    }
+    // capture the whole batched build once
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return cleanup_fail(bfail(b, CCH_E_HIP, "hipStreamBeginCapture failed"));
+    rc = enqueue_batch(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->st, &g);
+    if (rc != CCH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return cleanup_fail(rc);
+    }
+    if (ce != hipSuccess || !g) return cleanup_fail(bfail(b, CCH_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce)));
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return cleanup_fail(bfail(b, CCH_E_HIP, "hipGraphInstantiate failed"));
+    (void)hipGraphGetNodes(b->graph, nullptr, &b->nodes);
+    *out = b;
+    return CCH_OK;
+}
+
+cch_status cch_batch_build(cch_batch *b)
+{
+    if (!b || !b->exec) return CCH_E_INVALID_ARG;
+    BCK(b, hipSetDevice(b->device));
+    for (cch_ctx *c : b->cs) BCK(b, hipStreamSynchronize(c->stream));
+    BCK(b, hipEventRecord(b->e0, b->st));
+    BCK(b, hipGraphLaunch(b->exec, b->st));
+    BCK(b, hipEventRecord(b->e1, b->st));
+    BCK(b, hipEventSynchronize(b->e1));
+    BCK(b, hipEventElapsedTime(&b->last_ms, b->e0, b->e1));
+    for (cch_ctx *c : b->cs) {
+        c->built = true;
+        c->timed = false;
+    }
+    return CCH_OK;
+}
+
+cch_status cch_batch_time(const cch_batch *b, float *ms)
+{
+    if (!b || !ms) return CCH_E_INVALID_ARG;
+    *ms = b->last_ms;
+    return CCH_OK;
+}
+
+cch_status cch_batch_info(const cch_batch *b, int32_t *o)
+{
+    if (!b || !o) return CCH_E_INVALID_ARG;
+    o[0] = b->bm;
+    o[1] = b->g_gemm;
+    o[2] = b->g_c4;
+    o[3] = b->g_l2;
+    o[4] = b->tuned;
+    o[5] = b->cached;
+    o[6] = (int32_t)b->nodes;
+    o[7] = (int32_t)b->cs.size();
+    return CCH_OK;
+}
+
+cch_status cch_batch_destroy(cch_batch *b)
+{
+    if (!b) return CCH_OK;
+    (void)hipSetDevice(b->device);
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : b->allocs) (void)hipFree(p);
+    if (b->e0) (void)hipEventDestroy(b->e0);
+    if (b->e1) (void)hipEventDestroy(b->e1);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+    return CCH_OK;
+}
+
+const char *cch_batch_last_error(const cch_batch *b) { return b ? b->err.c_str() : g_create_err.c_str(); }
 
 // ---------------------------------------------------------------------------
 // block Davidson driver

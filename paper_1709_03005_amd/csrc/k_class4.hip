@@ -15,6 +15,8 @@
 //       s [ (P H1|H2 j) d(sp,sh1) d(alpha,sh2) - (P H2|H1 j) d(sp,sh2) d(alpha,sh1) ]
 // One workgroup per (l, tile of 64 j); pairs are turned into terms in
 // order, so the accumulation order is fixed.
+#include <algorithm>
+
 #include "ccham_internal.h"
 
 namespace cch {
@@ -39,16 +41,23 @@ struct Class4Args {
 constexpr int C4_TERMS = 1024;
 constexpr int C4_NQ = 16;          // states per thread: S <= 64 per pass
 
+struct C4Shared {
+    const double *trow[C4_TERMS];
+    double tcoef[C4_TERMS];
+    int32_t tm[C4_TERMS];
+    int32_t pcount[64], poff[65];
+};
+
+// one L2 row l and one tile of 64 continuum orbitals
 template <int W>
-__global__ __launch_bounds__(256) void k_class4(Class4Args a, int n_l2)
+__device__ __forceinline__ void class4_row(const Class4Args &a, int l, int jtile, C4Shared &sh)
 {
-    __shared__ const double *trow[C4_TERMS];
-    __shared__ double tcoef[C4_TERMS];
-    __shared__ int32_t tm[C4_TERMS];
-    __shared__ int32_t pcount[64], poff[65];
-    const int l = blockIdx.x;
-    const int jj0 = blockIdx.y * 64;
-    if (l >= n_l2) return;
+    const double **trow = sh.trow;
+    double *tcoef = sh.tcoef;
+    int32_t *tm = sh.tm;
+    int32_t *pcount = sh.pcount, *poff = sh.poff;
+    const int jj0 = jtile * 64;
+    __syncthreads();   // the LDS term lists are reused by the next row of a persistent loop
     const int jl = threadIdx.x & 63;          // j within the tile
     const int nq0 = threadIdx.x >> 6;         // first state of this thread
     const int64_t p0 = a.row_off[l], np = a.row_cnt[l];
@@ -170,6 +179,14 @@ __global__ __launch_bounds__(256) void k_class4(Class4Args a, int n_l2)
     }
 }
 
+template <int W>
+__global__ __launch_bounds__(256) void k_class4(Class4Args a, int n_l2)
+{
+    __shared__ C4Shared sh;
+    if ((int)blockIdx.x >= n_l2) return;
+    class4_row<W>(a, blockIdx.x, blockIdx.y, sh);
+}
+
 hipError_t launch_class4(int W, const Class4Args &a, int n_l2, hipStream_t st)
 {
     if (n_l2 <= 0 || a.nc <= 0 || a.S <= 0) return hipSuccess;
@@ -179,6 +196,44 @@ hipError_t launch_class4(int W, const Class4Args &a, int n_l2, hipStream_t st)
     case 2: hipLaunchKernelGGL((k_class4<2>), g, b, 0, st, a, n_l2); break;
     case 3: hipLaunchKernelGGL((k_class4<3>), g, b, 0, st, a, n_l2); break;
     case 4: hipLaunchKernelGGL((k_class4<4>), g, b, 0, st, a, n_l2); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// persistent form over many (instance, symmetry) blocks with the same word count
+struct C4Task {
+    Class4Args a;
+    int n_l2, jtiles;
+    int64_t first;
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_class4_batched(const C4Task *__restrict__ tasks, int ntask, int64_t total)
+{
+    __shared__ C4Shared sh;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = ntask - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].first <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const C4Task &k = tasks[lo];
+        const int64_t local = t - k.first;
+        class4_row<W>(k.a, (int)(local / k.jtiles), (int)(local % k.jtiles), sh);
+    }
+}
+
+hipError_t launch_class4_batched(int W, const C4Task *tasks, int ntask, int64_t total, int grid, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    const dim3 g((unsigned)std::min<int64_t>(total, grid)), bl(256);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_class4_batched<1>), g, bl, 0, st, tasks, ntask, total); break;
+    case 2: hipLaunchKernelGGL((k_class4_batched<2>), g, bl, 0, st, tasks, ntask, total); break;
+    case 3: hipLaunchKernelGGL((k_class4_batched<3>), g, bl, 0, st, tasks, ntask, total); break;
+    case 4: hipLaunchKernelGGL((k_class4_batched<4>), g, bl, 0, st, tasks, ntask, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

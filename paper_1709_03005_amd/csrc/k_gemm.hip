@@ -9,6 +9,8 @@
 // K0 lays the integral rows out as B[(PQ)][(j,j')]; K5 multiplies with FP64
 // MFMA (v_mfma_f64_16x16x4) and scatters each (n,n',j,j') to its row
 // (i,n,j) / column (i',n',j') of the contracted matrix (lower triangle).
+#include <algorithm>
+
 #include "ccham_internal.h"
 
 namespace cch {
@@ -91,7 +93,7 @@ struct ExpandEpi {
     int n_o, n_orb;
 };
 
-constexpr int GBM = 64, GBN = 128, GBK = 16;
+constexpr int GBN = 128, GBK = 16;
 
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
@@ -102,38 +104,38 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return (b % 8) * per + b / 8;
 }
 
-__global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ At, const double *__restrict__ B,
-                                                    int nrows, int N, int K, ExpandEpi ep)
+// One output tile (BM rows x 128 columns) of the expansion product; 4 waves,
+// BM/32 x (4/(BM/32)) of them, each 32 rows x (128 / waves_n) columns.
+template <int BM>
+__device__ __forceinline__ void expand_tile_f64(const double *__restrict__ At, const double *__restrict__ B,
+                                                int nrows, int N, int K, const ExpandEpi &ep, int tm, int tn,
+                                                double (*As)[BM], double (*Bs)[GBN])
 {
-    __shared__ double As[GBK][GBM];
-    __shared__ double Bs[GBK][GBN];
-    const int tiles_m = (nrows + GBM - 1) / GBM;
-    const int tiles_n = (N + GBN - 1) / GBN;
-    const int nb = tiles_m * tiles_n;
-    const int lb = xcd_remap(blockIdx.x, nb);
-    const int tm = lb % tiles_m, tn = lb / tiles_m;
-    const int r0 = tm * GBM, c0 = tn * GBN;
+    constexpr int WAVES_M = BM / 32, WAVES_N = 4 / WAVES_M;
+    constexpr int WCOLS = GBN / WAVES_N, NT = WCOLS / 16;   // MFMA tiles along N per wave
+    constexpr int AQ = BM * GBK / 256, BQ = GBN * GBK / 256;
+    const int r0 = tm * BM, c0 = tn * GBN;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wm = wv & 1, wn = wv >> 1;
+    const int wm = wv % WAVES_M, wn = wv / WAVES_M;
 
-    dx4 acc[2][4];
+    dx4 acc[2][NT];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (dx4){0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < NT; ++b) acc[a][b] = (dx4){0.0, 0.0, 0.0, 0.0};
 
-    double ra[4], rb[8];
+    double ra[AQ], rb[BQ];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = threadIdx.x + 256 * q;     // 0..1023
-            const int kk = e / GBM, rr = e % GBM;
+        for (int q = 0; q < AQ; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int kk = e / BM, rr = e % BM;
             const int k = k0 + kk, r = r0 + rr;
             ra[q] = (k < K && r < nrows) ? At[(size_t)k * nrows + r] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = threadIdx.x + 256 * q;     // 0..2047
+        for (int q = 0; q < BQ; ++q) {
+            const int e = threadIdx.x + 256 * q;
             const int kk = e / GBN, cc = e % GBN;
             const int k = k0 + kk, c = c0 + cc;
             rb[q] = (k < K && c < N) ? B[(size_t)k * N + c] : 0.0;
@@ -143,12 +145,12 @@ __global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ A
     for (int k0 = 0; k0 < K; k0 += GBK) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < AQ; ++q) {
             const int e = threadIdx.x + 256 * q;
-            As[e / GBM][e % GBM] = ra[q];
+            As[e / BM][e % BM] = ra[q];
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < BQ; ++q) {
             const int e = threadIdx.x + 256 * q;
             Bs[e / GBN][e % GBN] = rb[q];
         }
@@ -157,18 +159,19 @@ __global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ A
 #pragma unroll
         for (int ks = 0; ks < GBK; ks += 4) {
             const int kk = ks + (lane >> 4);
-            double af[2], bf[4];
+            double af[2], bf[NT];
 #pragma unroll
             for (int a = 0; a < 2; ++a) af[a] = As[kk][wm * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bf[b] = Bs[kk][wn * 64 + b * 16 + (lane & 15)];
+            for (int b = 0; b < NT; ++b) bf[b] = Bs[kk][wn * WCOLS + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < NT; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
     }
+    __syncthreads();   // the LDS tiles are reused by the next tile of a persistent loop
 
     // epilogue: scatter into the contracted matrix (lower triangle only)
 #pragma unroll
@@ -180,8 +183,8 @@ __global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ A
             const int n = ep.rn[r], n2 = ep.rn2[r];
             const double ht = ep.HT[r], ov = ep.O[r];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = c0 + wn * 64 + b * 16 + (lane & 15);
+            for (int b = 0; b < NT; ++b) {
+                const int c = c0 + wn * WCOLS + b * 16 + (lane & 15);
                 if (c >= N) continue;
                 const int jj = c / ep.ncb, jp = c - jj * ep.ncb;
                 const int64_t R = ep.row0a + (int64_t)n * ep.nca + jj;
@@ -197,12 +200,71 @@ __global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ A
     }
 }
 
+__global__ __launch_bounds__(256) void k_expand_f64(const double *__restrict__ At, const double *__restrict__ B,
+                                                    int nrows, int N, int K, ExpandEpi ep)
+{
+    __shared__ double As[GBK][64];
+    __shared__ double Bs[GBK][GBN];
+    const int tiles_m = (nrows + 63) / 64;
+    const int tiles_n = (N + GBN - 1) / GBN;
+    const int lb = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    expand_tile_f64<64>(At, B, nrows, N, K, ep, lb % tiles_m, lb / tiles_m, As, Bs);
+}
+
 hipError_t launch_expand_f64(const double *At, const double *B, int nrows, int N, int K, const ExpandEpi &ep,
                              hipStream_t st)
 {
     if (nrows <= 0 || N <= 0) return hipSuccess;
-    const int tiles = ((nrows + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+    const int tiles = ((nrows + 63) / 64) * ((N + GBN - 1) / GBN);
     hipLaunchKernelGGL(k_expand_f64, dim3(tiles), dim3(256), 0, st, At, B, nrows, N, K, ep);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form over many (instance, symmetry pair) products: a fixed grid
+// walks the concatenated tile list (static round-robin); descriptor d owns
+// tiles [first[d], first[d] + tiles_m * tiles_n).
+// ---------------------------------------------------------------------------
+struct GemmTask {
+    const double *At;
+    const double *B;
+    int nrows, N, K;
+    int tiles_m, tiles_n;
+    int64_t first;
+    ExpandEpi ep;
+};
+
+template <int BM>
+__global__ __launch_bounds__(256) void k_expand_f64_batched(const GemmTask *__restrict__ tasks, int ntask,
+                                                            int64_t total)
+{
+    __shared__ double As[GBK][BM];
+    __shared__ double Bs[GBK][GBN];
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = ntask - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].first <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmTask &g = tasks[lo];
+        const int64_t local = t - g.first;
+        expand_tile_f64<BM>(g.At, g.B, g.nrows, g.N, g.K, g.ep, (int)(local % g.tiles_m),
+                            (int)(local / g.tiles_m), As, Bs);
+    }
+}
+
+int expand_tiles(int nrows, int N, int bm) { return ((nrows + bm - 1) / bm) * ((N + GBN - 1) / GBN); }
+
+hipError_t launch_expand_f64_batched(const GemmTask *tasks, int ntask, int64_t total, int bm, int grid,
+                                     hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(total, grid);
+    if (bm == 32)
+        hipLaunchKernelGGL((k_expand_f64_batched<32>), dim3(g), dim3(256), 0, st, tasks, ntask, total);
+    else
+        hipLaunchKernelGGL((k_expand_f64_batched<64>), dim3(g), dim3(256), 0, st, tasks, ntask, total);
     return hipGetLastError();
 }
 

@@ -4,6 +4,8 @@
 // loop; here each workgroup takes one 64 x 64 tile of the flattened lower
 // triangle). The scan and the element evaluation are fused: every tile
 // element is written (zero when more than a double substitution apart).
+#include <algorithm>
+
 #include "ccham_internal.h"
 
 namespace cch {
@@ -17,17 +19,23 @@ struct L2Args {
     int64_t row0;           // first L2 row / column of the matrix
 };
 
-template <int W>
-__global__ __launch_bounds__(256) void k_l2_block(L2Args a)
+__device__ __forceinline__ void tri_decode(int64_t b, int64_t *ti, int64_t *tj)
 {
-    __shared__ uint64_t bra[64][W], ket[64][W];
     // flattened lower-triangular tile index -> (ti >= tj)
-    const int64_t b = blockIdx.x;
-    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > b) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-    const int64_t tj = b - ti * (ti + 1) / 2;
+    int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > b) --i;
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    *ti = i;
+    *tj = b - i * (i + 1) / 2;
+}
+
+template <int W>
+__device__ __forceinline__ void l2_tile(const L2Args &a, int64_t b, uint64_t (*bra)[W], uint64_t (*ket)[W])
+{
+    int64_t ti, tj;
+    tri_decode(b, &ti, &tj);
     const int l0 = (int)(ti * 64), k0 = (int)(tj * 64);
+    __syncthreads();   // the LDS dets are reused by the next tile of a persistent loop
     for (int t = threadIdx.x; t < 64 * W; t += 256) {
         const int r = t / W, w = t % W;
         bra[r][w] = (l0 + r < a.n_l2) ? a.dets[(size_t)(l0 + r) * W + w] : 0ull;
@@ -53,6 +61,13 @@ __global__ __launch_bounds__(256) void k_l2_block(L2Args a)
     }
 }
 
+template <int W>
+__global__ __launch_bounds__(256) void k_l2_block(L2Args a)
+{
+    __shared__ uint64_t bra[64][W], ket[64][W];
+    l2_tile<W>(a, blockIdx.x, bra, ket);
+}
+
 hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st)
 {
     if (a.n_l2 <= 0) return hipSuccess;
@@ -64,6 +79,47 @@ hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st)
     case 2: hipLaunchKernelGGL((k_l2_block<2>), g, bl, 0, st, a); break;
     case 3: hipLaunchKernelGGL((k_l2_block<3>), g, bl, 0, st, a); break;
     case 4: hipLaunchKernelGGL((k_l2_block<4>), g, bl, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// persistent form over many instances with the same word count
+struct L2Task {
+    L2Args a;
+    int64_t first;   // first global tile of this instance
+};
+
+int64_t l2_tiles(int n_l2)
+{
+    const int64_t T = (n_l2 + 63) / 64;
+    return T * (T + 1) / 2;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_l2_batched(const L2Task *__restrict__ tasks, int ntask, int64_t total)
+{
+    __shared__ uint64_t bra[64][W], ket[64][W];
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = ntask - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].first <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        l2_tile<W>(tasks[lo].a, t - tasks[lo].first, bra, ket);
+    }
+}
+
+hipError_t launch_l2_batched(int W, const L2Task *tasks, int ntask, int64_t total, int grid, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    const dim3 g((unsigned)std::min<int64_t>(total, grid)), bl(256);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_l2_batched<1>), g, bl, 0, st, tasks, ntask, total); break;
+    case 2: hipLaunchKernelGGL((k_l2_batched<2>), g, bl, 0, st, tasks, ntask, total); break;
+    case 3: hipLaunchKernelGGL((k_l2_batched<3>), g, bl, 0, st, tasks, ntask, total); break;
+    case 4: hipLaunchKernelGGL((k_l2_batched<4>), g, bl, 0, st, tasks, ntask, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

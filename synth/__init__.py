@@ -338,7 +338,11 @@ def learned_test(seed=999):
                          name="learned_test")
 
 
-def _batch_like(rng, seed, d_lo, d_hi, name):
+def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
+    """Draw (D, n_o, symmetries, states, continuum, N) from the batch ranges;
+    draws whose dense (tt|cc) + (tc|tc) storage would exceed max_int_bytes,
+    whose L2 count would be negative, or whose L2 space is too small are
+    redrawn."""
     while True:
         d = int(rng.integers(d_lo, d_hi + 1))
         n_o = int(rng.integers(12, 41))
@@ -348,8 +352,13 @@ def _batch_like(rng, seed, d_lo, d_hi, name):
         nc = int(rng.integers(50, 201))
         n_elec = int(rng.choice([4, 6, 8, 10, 12]))
         n_l2 = d - n_sym * s * nc
-        if n_l2 >= 0:
-            break
+        n_cont = n_sym * nc
+        if n_l2 < 0 or 16 * n_o * n_o * n_cont * n_cont > max_int_bytes:
+            continue
+        na = n_elec // 2
+        if n_l2 > math.comb(n_o, na + 1) * math.comb(n_o, na) // (4 * n_irrep):
+            continue
+        break
     m = max(s, int(rng.integers(2 * s, 8 * s + 1)))
     return make_instance(n_o, n_elec, n_irrep, nc, list(range(n_sym)), m, s, n_l2,
                          seed, name=name)
