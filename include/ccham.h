@@ -212,6 +212,42 @@ cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
 cch_status cch_work_counts(const cch_ctx *ctx, double *out8);
 
 /* ------------------------------------------------------------------------
+ * Learned Davidson preconditioner (not in the paper): a 3-layer perceptron
+ * 4 -> 128 -> 128 -> 1 (ReLU) maps per-row features of a Ritz pair (theta,
+ * H_ii, off-diagonal row norm, row class) to g and the correction becomes
+ * exp(clamp(g, -4, 4)) r_i / (theta - H_ii); the diagonal (Jacobi) step is the
+ * fallback. Weights are an FP32 blob of cch_mlp_num_params() floats:
+ * W1[128][4], b1[128], W2[128][128], b2[128], w3[128], b3. The 128 x 128 layer
+ * runs on BF16 matrix cores with FP32 accumulation; training uses Adam in FP32.
+ * Training rows: features X[n][4] (see cch_mlp_features), the Jacobi step tj,
+ * the target correction e and a weight w per row; loss = sum w (exp(g) tj - e)^2.
+ * Array arguments are host pointers unless flags & CCH_MEM_DEVICE.
+ * ------------------------------------------------------------------------ */
+typedef struct cch_mlp cch_mlp;
+
+int32_t cch_mlp_num_params(void);
+/* He-initialised weights from `seed`, output layer near zero (starts as Jacobi). */
+cch_status cch_mlp_create(cch_mlp **out, int32_t device, void *hip_stream, uint64_t seed);
+cch_status cch_mlp_destroy(cch_mlp *m);
+const char *cch_mlp_last_error(const cch_mlp *m);
+cch_status cch_mlp_set_weights(cch_mlp *m, const float *w, int64_t n, int32_t flags);
+cch_status cch_mlp_get_weights(cch_mlp *m, float *w, int64_t n, int32_t flags);
+/* g[n] = network(X[n][4]). Synchronous. */
+cch_status cch_mlp_forward(cch_mlp *m, const float *X, int64_t n, float *g, int32_t flags);
+/* loss and its gradient grad[num_params] (FP32) for the rows. Synchronous. */
+cch_status cch_mlp_grad(cch_mlp *m, const float *X, const float *tj, const float *e, const float *w, int64_t n,
+                        double *loss, float *grad, int32_t flags);
+/* one Adam step (lr) on the rows; *loss = loss before the step. Synchronous. */
+cch_status cch_mlp_train_step(cch_mlp *m, const float *X, const float *tj, const float *e, const float *w,
+                              int64_t n, float lr, double *loss, int32_t flags);
+/* Feature rows of the built matrix for one Ritz value theta: X[D][4]
+ * (asinh(d), asinh(rho), asinh(rho/|d|), L2-row flag; d = theta - H_ii
+ * floored at 1e-8, rho = off-diagonal row norm). Synchronous. */
+cch_status cch_mlp_features(cch_ctx *ctx, double theta, float *X, int32_t flags);
+/* Attach (or detach with NULL) the network used by CCH_PRECOND_MLP. */
+cch_status cch_davidson_set_mlp(cch_ctx *ctx, cch_mlp *m);
+
+/* ------------------------------------------------------------------------
  * Batched build: many instances of uneven size built together. Every context
  * must be planned with the FP64 form, on the same device. The build phases of
  * all instances are queued on one internal stream; the expansion products of

@@ -43,6 +43,9 @@ EXPORTS = [
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
+    "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
+    "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
+    "cch_davidson_set_mlp",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -95,6 +98,17 @@ _SIG = {
     "cch_batch_info": (i32, [P, P]),
     "cch_batch_destroy": (i32, [P]),
     "cch_batch_last_error": (C.c_char_p, [P]),
+    "cch_mlp_num_params": (i32, []),
+    "cch_mlp_create": (i32, [C.POINTER(P), i32, P, C.c_uint64]),
+    "cch_mlp_destroy": (i32, [P]),
+    "cch_mlp_last_error": (C.c_char_p, [P]),
+    "cch_mlp_set_weights": (i32, [P, P, i64, i32]),
+    "cch_mlp_get_weights": (i32, [P, P, i64, i32]),
+    "cch_mlp_forward": (i32, [P, P, i64, P, i32]),
+    "cch_mlp_grad": (i32, [P, P, P, P, P, i64, C.POINTER(C.c_double), P, i32]),
+    "cch_mlp_train_step": (i32, [P, P, P, P, P, i64, C.c_float, C.POINTER(C.c_double), i32]),
+    "cch_mlp_features": (i32, [P, C.c_double, P, i32]),
+    "cch_davidson_set_mlp": (i32, [P, P]),
 }
 for _n, (_r, _a) in _SIG.items():
     _f = getattr(lib, _n)
@@ -250,11 +264,92 @@ class Context:
                 "class4_outputs", "l2_lower_elements", "sym_pairs"]
         return dict(zip(keys, out.tolist()))
 
+    def mlp_features(self, theta):
+        D, _ = self.dim()
+        X = np.zeros((D, 4), np.float32)
+        self._ck(lib.cch_mlp_features(self.h, float(theta), X.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
+        return X
+
+    def set_mlp(self, mlp):
+        self._ck(lib.cch_davidson_set_mlp(self.h, mlp.h if mlp is not None else None))
+        self._mlp = mlp
+
     def build_time(self):
         t = C.c_float()
         ph = (C.c_float * 8)()
         self._ck(lib.cch_build_time(self.h, C.byref(t), C.cast(ph, C.c_void_p)))
         return t.value, list(ph)
+
+
+class Mlp:
+    """cch_mlp: the learned Davidson preconditioner's network."""
+
+    def __init__(self, device=0, stream=None, seed=0):
+        h = C.c_void_p()
+        rc = lib.cch_mlp_create(C.byref(h), device, C.c_void_p(stream or 0), seed)
+        if rc != CCH_OK:
+            raise CchError(rc, lib.cch_mlp_last_error(None).decode())
+        self.h = h
+        self.n_params = lib.cch_mlp_num_params()
+
+    def _ck(self, rc):
+        if rc != CCH_OK:
+            raise CchError(rc, lib.cch_mlp_last_error(self.h).decode())
+
+    def weights(self):
+        w = np.zeros(self.n_params, np.float32)
+        self._ck(lib.cch_mlp_get_weights(self.h, w.ctypes.data_as(C.c_void_p), self.n_params, CCH_MEM_HOST))
+        return w
+
+    def set_weights(self, w):
+        p, f, k = _arr(w, np.float32)
+        self._ck(lib.cch_mlp_set_weights(self.h, p, int(k.size if hasattr(k, "size") else k.numel()), f))
+
+    def forward(self, X):
+        p, f, k = _arr(X, np.float32)
+        n = k.shape[0]
+        if f == CCH_MEM_DEVICE:
+            import torch
+            g = torch.empty(n, dtype=torch.float32, device=k.device)
+            self._ck(lib.cch_mlp_forward(self.h, p, n, C.c_void_p(g.data_ptr()), f))
+            return g
+        g = np.zeros(n, np.float32)
+        self._ck(lib.cch_mlp_forward(self.h, p, n, g.ctypes.data_as(C.c_void_p), f))
+        return g
+
+    def grad(self, X, tj, e, w):
+        args = [_arr(a, np.float32) for a in (X, tj, e, w)]
+        f = args[0][1]
+        n = args[0][2].shape[0]
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        if f == CCH_MEM_DEVICE:
+            import torch
+            gd = torch.empty(self.n_params, dtype=torch.float32, device=args[0][2].device)
+            self._ck(lib.cch_mlp_grad(self.h, *[a[0] for a in args], n, C.byref(loss),
+                                      C.c_void_p(gd.data_ptr()), f))
+            return loss.value, gd.cpu().numpy()
+        self._ck(lib.cch_mlp_grad(self.h, *[a[0] for a in args], n, C.byref(loss),
+                                  g.ctypes.data_as(C.c_void_p), f))
+        return loss.value, g
+
+    def train_step(self, X, tj, e, w, lr=1e-3):
+        args = [_arr(a, np.float32) for a in (X, tj, e, w)]
+        loss = C.c_double()
+        self._ck(lib.cch_mlp_train_step(self.h, *[a[0] for a in args], args[0][2].shape[0], float(lr),
+                                        C.byref(loss), args[0][1]))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.cch_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

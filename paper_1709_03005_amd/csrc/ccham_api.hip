@@ -125,7 +125,23 @@ hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipSt
 hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
 hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
+// learned preconditioner
+int mlp_num_params();
+int mlp_grid(int64_t n);
+hipError_t launch_mlp_pack(const float *w, __bf16 *w2, __bf16 *w2t, hipStream_t st);
+hipError_t launch_mlp_forward(const float *w, const __bf16 *w2, const __bf16 *w2t, const float *X, int64_t n,
+                              float *g, hipStream_t st);
+hipError_t launch_mlp_grad(const float *w, const __bf16 *w2, const __bf16 *w2t, const float *X, const float *tj,
+                           const float *ev, const float *wr, int64_t n, float *part, double *lpart, float *grad,
+                           double *loss, hipStream_t st);
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, float lr, int step, hipStream_t st);
+hipError_t launch_row_norms(const double *H, int64_t ld, int D, double *rho, hipStream_t st);
+hipError_t launch_mlp_dav(const float *w, const __bf16 *w2, const __bf16 *w2t, const double *R, int64_t ld, int D,
+                          int Dc, const double *diag, const double *rho, const double *theta, const int32_t *sel,
+                          int nsel, float *X, float *g, double *T, int64_t ldt, int32_t *nfallback, hipStream_t st);
 }  // namespace cch
+
+struct cch_mlp;
 
 using namespace cch;
 
@@ -201,6 +217,7 @@ struct cch_ctx {
     hipEvent_t mv0 = nullptr, mv1 = nullptr;
     int64_t relayout_elems = 0;
     bool timed = false;     // the phase events belong to the last build
+    cch_mlp *mlp = nullptr; // network used by CCH_PRECOND_MLP
     bool have_events = false;
 };
 
@@ -924,6 +941,258 @@ cch_status cch_get_labels(cch_ctx *c, int32_t which, int32_t sym_a, int32_t sym_
 
 
 // ---------------------------------------------------------------------------
+// learned preconditioner object
+// ---------------------------------------------------------------------------
+#include <random>
+
+struct cch_mlp {
+    int device = 0;
+    hipStream_t st = nullptr;
+    std::string err;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    __bf16 *w2 = nullptr, *w2t = nullptr;
+    double *loss = nullptr;
+    int step = 0;
+    // scratch for rows (grown on demand)
+    float *part = nullptr;
+    double *lpart = nullptr;
+    int part_blocks = 0;
+    float *xin = nullptr, *tin = nullptr, *ein = nullptr, *win = nullptr, *gout = nullptr;
+    int64_t cap = 0;
+};
+
+static cch_status mfail(cch_mlp *m, cch_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (m) m->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+#define MCK(m, x)                                                                                \
+    do {                                                                                         \
+        hipError_t e_ = (x);                                                                     \
+        if (e_ != hipSuccess) return mfail((m), CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+int32_t cch_mlp_num_params(void) { return mlp_num_params(); }
+
+cch_status cch_mlp_destroy(cch_mlp *m)
+{
+    if (!m) return CCH_OK;
+    (void)hipSetDevice(m->device);
+    (void)hipStreamSynchronize(m->st);
+    for (void *p : {(void *)m->w, (void *)m->m, (void *)m->v, (void *)m->grad, (void *)m->w2, (void *)m->w2t,
+                    (void *)m->loss, (void *)m->part, (void *)m->lpart, (void *)m->xin, (void *)m->tin,
+                    (void *)m->ein, (void *)m->win, (void *)m->gout})
+        if (p) (void)hipFree(p);
+    delete m;
+    return CCH_OK;
+}
+
+const char *cch_mlp_last_error(const cch_mlp *m) { return m ? m->err.c_str() : g_create_err.c_str(); }
+
+cch_status cch_mlp_create(cch_mlp **out, int32_t device, void *hip_stream, uint64_t seed)
+{
+    if (!out) return mfail(nullptr, CCH_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return mfail(nullptr, CCH_E_HIP, "hipSetDevice failed");
+    cch_mlp *m = new (std::nothrow) cch_mlp();
+    if (!m) return mfail(nullptr, CCH_E_OOM, "allocation failed");
+    m->device = device;
+    m->st = (hipStream_t)hip_stream;
+    const int P = mlp_num_params();
+    bool ok = hipMalloc(&m->w, 4 * (size_t)P) == hipSuccess && hipMalloc(&m->m, 4 * (size_t)P) == hipSuccess &&
+              hipMalloc(&m->v, 4 * (size_t)P) == hipSuccess && hipMalloc(&m->grad, 4 * (size_t)P) == hipSuccess &&
+              hipMalloc(&m->w2, 2 * 128 * 128) == hipSuccess && hipMalloc(&m->w2t, 2 * 128 * 128) == hipSuccess &&
+              hipMalloc(&m->loss, 8) == hipSuccess;
+    if (!ok) {
+        cch_mlp_destroy(m);
+        return mfail(nullptr, CCH_E_OOM, "MLP buffers");
+    }
+    // He initialisation; output layer near zero so the network starts as Jacobi
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    std::vector<float> w(P, 0.f);
+    for (int i = 0; i < 128 * 4; ++i) w[i] = nd(rng) * std::sqrt(2.f / 4.f);
+    for (int i = 0; i < 128 * 128; ++i) w[128 * 4 + 128 + i] = nd(rng) * std::sqrt(2.f / 128.f);
+    for (int i = 0; i < 128; ++i) w[128 * 4 + 128 + 128 * 128 + 128 + i] = nd(rng) * 1e-3f;
+    std::vector<float> z(P, 0.f);
+    ok = hipMemcpy(m->w, w.data(), 4 * (size_t)P, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->m, z.data(), 4 * (size_t)P, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->v, z.data(), 4 * (size_t)P, hipMemcpyHostToDevice) == hipSuccess &&
+         launch_mlp_pack(m->w, m->w2, m->w2t, m->st) == hipSuccess && hipStreamSynchronize(m->st) == hipSuccess;
+    if (!ok) {
+        cch_mlp_destroy(m);
+        return mfail(nullptr, CCH_E_HIP, "MLP initialisation");
+    }
+    *out = m;
+    return CCH_OK;
+}
+
+cch_status cch_mlp_set_weights(cch_mlp *m, const float *w, int64_t n, int32_t flags)
+{
+    if (!m || !w) return CCH_E_INVALID_ARG;
+    if (n != mlp_num_params()) return mfail(m, CCH_E_INVALID_ARG, "expected %d weights", mlp_num_params());
+    MCK(m, hipSetDevice(m->device));
+    MCK(m, hipMemcpyAsync(m->w, w, 4 * (size_t)n, (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice
+                                                                            : hipMemcpyHostToDevice, m->st));
+    MCK(m, launch_mlp_pack(m->w, m->w2, m->w2t, m->st));
+    MCK(m, hipStreamSynchronize(m->st));
+    m->step = 0;
+    return CCH_OK;
+}
+
+cch_status cch_mlp_get_weights(cch_mlp *m, float *w, int64_t n, int32_t flags)
+{
+    if (!m || !w) return CCH_E_INVALID_ARG;
+    if (n != mlp_num_params()) return mfail(m, CCH_E_INVALID_ARG, "expected %d weights", mlp_num_params());
+    MCK(m, hipMemcpyAsync(w, m->w, 4 * (size_t)n, (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice
+                                                                            : hipMemcpyDeviceToHost, m->st));
+    MCK(m, hipStreamSynchronize(m->st));
+    return CCH_OK;
+}
+
+// rows staged on the device (copied when host pointers are passed)
+static cch_status mlp_rows(cch_mlp *m, int64_t n, const float *X, const float *tj, const float *e, const float *w,
+                           int32_t flags, const float **dX, const float **dt, const float **de, const float **dw)
+{
+    if (n <= 0) return mfail(m, CCH_E_INVALID_ARG, "no rows");
+    if (!(flags & CCH_MEM_DEVICE) && n > m->cap) {
+        for (float *p : {m->xin, m->tin, m->ein, m->win}) if (p) (void)hipFree(p);
+        m->xin = m->tin = m->ein = m->win = nullptr;
+        if (hipMalloc(&m->xin, 16 * (size_t)n) != hipSuccess || hipMalloc(&m->tin, 4 * (size_t)n) != hipSuccess ||
+            hipMalloc(&m->ein, 4 * (size_t)n) != hipSuccess || hipMalloc(&m->win, 4 * (size_t)n) != hipSuccess)
+            return mfail(m, CCH_E_OOM, "row buffers");
+        m->cap = n;
+    }
+    if (flags & CCH_MEM_DEVICE) {
+        *dX = X; *dt = tj; *de = e; *dw = w;
+        return CCH_OK;
+    }
+    MCK(m, hipMemcpyAsync(m->xin, X, 16 * (size_t)n, hipMemcpyHostToDevice, m->st));
+    if (tj) MCK(m, hipMemcpyAsync(m->tin, tj, 4 * (size_t)n, hipMemcpyHostToDevice, m->st));
+    if (e) MCK(m, hipMemcpyAsync(m->ein, e, 4 * (size_t)n, hipMemcpyHostToDevice, m->st));
+    if (w) MCK(m, hipMemcpyAsync(m->win, w, 4 * (size_t)n, hipMemcpyHostToDevice, m->st));
+    *dX = m->xin; *dt = m->tin; *de = m->ein; *dw = m->win;
+    return CCH_OK;
+}
+
+static cch_status mlp_part(cch_mlp *m, int64_t n)
+{
+    const int blocks = mlp_grid(n);
+    if (blocks > m->part_blocks) {
+        if (m->part) (void)hipFree(m->part);
+        if (m->lpart) (void)hipFree(m->lpart);
+        m->part = nullptr;
+        m->lpart = nullptr;
+        if (hipMalloc(&m->part, 4 * (size_t)blocks * mlp_num_params()) != hipSuccess ||
+            hipMalloc(&m->lpart, 8 * (size_t)blocks) != hipSuccess)
+            return mfail(m, CCH_E_OOM, "gradient partials");
+        m->part_blocks = blocks;
+    }
+    return CCH_OK;
+}
+
+cch_status cch_mlp_forward(cch_mlp *m, const float *X, int64_t n, float *g, int32_t flags)
+{
+    if (!m || !X || !g) return CCH_E_INVALID_ARG;
+    MCK(m, hipSetDevice(m->device));
+    const float *dX, *dt, *de, *dw;
+    TRY(mlp_rows(m, n, X, nullptr, nullptr, nullptr, flags, &dX, &dt, &de, &dw));
+    float *dg = g;
+    if (!(flags & CCH_MEM_DEVICE)) {
+        if (m->gout) (void)hipFree(m->gout);
+        m->gout = nullptr;
+        if (hipMalloc(&m->gout, 4 * (size_t)n) != hipSuccess) return mfail(m, CCH_E_OOM, "output buffer");
+        dg = m->gout;
+    }
+    MCK(m, launch_mlp_forward(m->w, m->w2, m->w2t, dX, n, dg, m->st));
+    if (!(flags & CCH_MEM_DEVICE)) MCK(m, hipMemcpyAsync(g, dg, 4 * (size_t)n, hipMemcpyDeviceToHost, m->st));
+    MCK(m, hipStreamSynchronize(m->st));
+    return CCH_OK;
+}
+
+cch_status cch_mlp_grad(cch_mlp *m, const float *X, const float *tj, const float *e, const float *w, int64_t n,
+                        double *loss, float *grad, int32_t flags)
+{
+    if (!m || !X || !tj || !e || !w) return CCH_E_INVALID_ARG;
+    MCK(m, hipSetDevice(m->device));
+    const float *dX, *dt, *de, *dw;
+    TRY(mlp_rows(m, n, X, tj, e, w, flags, &dX, &dt, &de, &dw));
+    TRY(mlp_part(m, n));
+    MCK(m, launch_mlp_grad(m->w, m->w2, m->w2t, dX, dt, de, dw, n, m->part, m->lpart, m->grad, m->loss, m->st));
+    if (grad)
+        MCK(m, hipMemcpyAsync(grad, m->grad, 4 * (size_t)mlp_num_params(),
+                              (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, m->st));
+    if (loss) MCK(m, hipMemcpyAsync(loss, m->loss, 8, hipMemcpyDeviceToHost, m->st));
+    MCK(m, hipStreamSynchronize(m->st));
+    return CCH_OK;
+}
+
+cch_status cch_mlp_train_step(cch_mlp *m, const float *X, const float *tj, const float *e, const float *w,
+                              int64_t n, float lr, double *loss, int32_t flags)
+{
+    if (!m || !X || !tj || !e || !w || !(lr > 0.f)) return CCH_E_INVALID_ARG;
+    MCK(m, hipSetDevice(m->device));
+    const float *dX, *dt, *de, *dw;
+    TRY(mlp_rows(m, n, X, tj, e, w, flags, &dX, &dt, &de, &dw));
+    TRY(mlp_part(m, n));
+    MCK(m, launch_mlp_grad(m->w, m->w2, m->w2t, dX, dt, de, dw, n, m->part, m->lpart, m->grad, m->loss, m->st));
+    MCK(m, launch_adam(m->w, m->m, m->v, m->grad, lr, ++m->step, m->st));
+    MCK(m, launch_mlp_pack(m->w, m->w2, m->w2t, m->st));
+    if (loss) MCK(m, hipMemcpyAsync(loss, m->loss, 8, hipMemcpyDeviceToHost, m->st));
+    MCK(m, hipStreamSynchronize(m->st));
+    return CCH_OK;
+}
+
+namespace cch {
+hipError_t launch_mlp_features_theta(const double *diag, const double *rho, int D, int Dc, double theta, float *X,
+                                     hipStream_t st);
+}
+
+cch_status cch_mlp_features(cch_ctx *c, double theta, float *X, int32_t flags)
+{
+    if (!c || !X) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    HIPCK(c, hipSetDevice(c->device));
+    const int D = (int)c->D;
+    double *rho = nullptr, *th = nullptr;
+    float *dX = X;
+    int32_t *sel = nullptr;
+    bool ok = hipMalloc(&rho, 8 * (size_t)D) == hipSuccess && hipMalloc(&th, 8) == hipSuccess &&
+              hipMalloc(&sel, 4) == hipSuccess;
+    if (ok && !(flags & CCH_MEM_DEVICE)) ok = hipMalloc(&dX, 16 * (size_t)D) == hipSuccess;
+    const int32_t zero = 0;
+    hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpy(th, &theta, 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sel, &zero, 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_row_norms(c->d_H, c->ld, D, rho, c->stream);
+    if (e == hipSuccess) e = launch_mlp_features_theta(c->d_diag, rho, D, (int)c->Dc, theta, dX, c->stream);
+    if (e == hipSuccess && !(flags & CCH_MEM_DEVICE))
+        e = hipMemcpyAsync(X, dX, 16 * (size_t)D, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (rho) (void)hipFree(rho);
+    if (th) (void)hipFree(th);
+    if (sel) (void)hipFree(sel);
+    if (dX && dX != X) (void)hipFree(dX);
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "features: %s", hipGetErrorString(e));
+    return CCH_OK;
+}
+
+cch_status cch_davidson_set_mlp(cch_ctx *c, cch_mlp *m)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (m && m->device != c->device) return fail(c, CCH_E_INVALID_ARG, "network on another device");
+    c->mlp = m;
+    return CCH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batched build
 // ---------------------------------------------------------------------------
 #include <map>
@@ -1251,8 +1520,9 @@ namespace {
 struct DavBufs {
     double *V = nullptr, *Wv = nullptr, *V2 = nullptr, *W2 = nullptr, *G = nullptr, *theta = nullptr,
            *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *Gb = nullptr, *Cb = nullptr,
-           *ref = nullptr, *part = nullptr, *norms = nullptr, *Wp = nullptr;
-    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr;
+           *ref = nullptr, *part = nullptr, *norms = nullptr, *Wp = nullptr, *rho = nullptr;
+    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr, *nfb = nullptr;
+    float *mx = nullptr, *mg = nullptr;
 };
 }  // namespace
 
@@ -1265,7 +1535,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     if (k <= 0 || k > D) return fail(c, CCH_E_INVALID_ARG, "k out of range");
     if (k > 16) return fail(c, CCH_E_LIMIT, "k > 16 eigenpairs per solve");
     if (!(o->tol > 0.0)) return fail(c, CCH_E_INVALID_ARG, "tol must be positive");
-    if (o->precond != CCH_PRECOND_JACOBI) return fail(c, CCH_E_INVALID_ARG, "preconditioner not available");
+    if (o->precond != CCH_PRECOND_JACOBI && o->precond != CCH_PRECOND_MLP)
+        return fail(c, CCH_E_INVALID_ARG, "unknown preconditioner %d", o->precond);
+    if (o->precond == CCH_PRECOND_MLP && !c->mlp) return fail(c, CCH_E_STATE, "no network attached (cch_davidson_set_mlp)");
     int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 64);
     mmax = std::min(mmax, 96);
     mmax = std::min(mmax, D);
@@ -1296,7 +1568,11 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
               A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
               A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)k) && A((void **)&b.idx, 4 * (size_t)kr) &&
-              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1));
+              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4);
+    const bool want_mlp = o->precond == CCH_PRECOND_MLP;
+    if (ok && want_mlp)
+        ok = A((void **)&b.rho, 8 * (size_t)D) && A((void **)&b.mx, 16 * (size_t)D * k) &&
+             A((void **)&b.mg, 4 * (size_t)D * k);
     if (!ok) {
         cleanup();
         return fail(c, CCH_E_OOM, "Davidson buffers");
@@ -1321,8 +1597,13 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)nb, hipMemcpyHostToDevice));
     DCK(launch_unit_vectors(b.T, ldv, D, b.idx, nb, st));
 
-    int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0;
-    double mv_ms = 0.0, maxres = 0.0;
+    int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0, fallbacks = 0;
+    double mv_ms = 0.0, maxres = 0.0, best_res = 1e300;
+    bool use_mlp = want_mlp;
+    if (want_mlp) {
+        DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
+        DCK(hipMemsetAsync(b.nfb, 0, 4, st));
+    }
     std::vector<double> hres(k), htheta(mmax);
     cch_status rc = CCH_E_NOT_CONVERGED;
     for (iters = 1; iters <= max_iter; ++iters) {
@@ -1381,6 +1662,13 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             if (!(hres[e] <= o->tol)) un.push_back(e);
         }
         nconv = kk - (int)un.size();
+        // judge of the learned step: a residual that grows tenfold over the best so far
+        // switches the rest of the solve to the diagonal step
+        if (use_mlp && iters > 3 && maxres > 10.0 * best_res) {
+            use_mlp = false;
+            ++fallbacks;
+        }
+        best_res = std::min(best_res, maxres);
         if (kk == k && un.empty()) {
             rc = CCH_OK;
             break;
@@ -1401,7 +1689,13 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         nb = std::min((int)un.size(), mmax - m);
         if (nb <= 0) break;
         DCK(hipMemcpyAsync(b.sel, un.data(), 4 * (size_t)nb, hipMemcpyHostToDevice, st));
-        DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, b.sel, nb, b.T, ldv, st));
+        if (use_mlp) {
+            const cch_mlp *net = c->mlp;
+            DCK(launch_mlp_dav(net->w, net->w2, net->w2t, b.R, ldv, D, (int)c->Dc, c->d_diag, b.rho, b.theta, b.sel, nb,
+                               b.mx, b.mg, b.T, ldv, b.nfb, st));
+        } else {
+            DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, b.sel, nb, b.T, ldv, st));
+        }
     }
     if (iters > max_iter) iters = max_iter;
     const int kk = std::min(k, m);
@@ -1412,6 +1706,11 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         if (flags & CCH_MEM_DEVICE) DCK(hipMemcpy(evals, th.data(), 8 * (size_t)kk, hipMemcpyHostToDevice));
         else memcpy(evals, th.data(), 8 * (size_t)kk);
     }
+    int32_t elem_fb = 0;
+    if (want_mlp) {
+        DCK(hipMemcpyAsync(&elem_fb, b.nfb, 4, hipMemcpyDeviceToHost, st));
+        DCK(hipStreamSynchronize(st));
+    }
     if (evecs)
         DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.V, ldv * 8, 8 * (size_t)D, kk,
                              (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
@@ -1421,7 +1720,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->iterations = iters;
         info->matvecs = matvecs;
         info->converged = nconv;
-        info->fallbacks = 0;
+        info->fallbacks = fallbacks + (elem_fb > 0 ? 1 : 0);
         info->max_residual = maxres;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->matvec_ms = mv_ms;
