@@ -53,6 +53,7 @@ typedef int32_t cch_status;
 
 #define CCH_MEM_HOST 0
 #define CCH_MEM_DEVICE 1
+#define CCH_DAV_RESIDUALS 2   /* cch_davidson: evecs holds 2k rows, residuals after the vectors */
 
 /* precision of the CI-contraction / expansion GEMMs (cch_plan_opts) */
 #define CCH_PREC_FP64 0
@@ -191,8 +192,10 @@ cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sy
 
 /* Lowest opts->k eigenpairs of the built matrix by block Davidson in FP64 on
  * the device. evals[k]; evecs[k][D] (row-major: eigenvector e at evecs + e*D);
- * either may be NULL. Returns CCH_E_NOT_CONVERGED (with the best pairs) when
- * max_iter is reached. Synchronous. */
+ * either may be NULL. With flags & CCH_DAV_RESIDUALS, evecs has 2k rows and
+ * rows k..2k-1 receive the residuals H x - theta x. Returns
+ * CCH_E_NOT_CONVERGED (with the best pairs) when max_iter is reached.
+ * Synchronous. */
 cch_status cch_davidson(cch_ctx *ctx, const cch_dav_opts *opts, double *evals,
                         double *evecs, cch_dav_info *info, int32_t flags);
 

@@ -28,6 +28,7 @@ CCH_E_HIP = -6
 CCH_E_NOT_CONVERGED = -7
 CCH_MEM_HOST = 0
 CCH_MEM_DEVICE = 1
+CCH_DAV_RESIDUALS = 2
 CCH_PREC_FP64 = 0
 CCH_PREC_FP32 = 1
 CCH_PREC_SPLIT_BF16 = 2
@@ -51,6 +52,12 @@ CCH_BATCH_AUTOTUNE = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run paper_1709_03005_amd/build.py (hipcc, gfx950)")
+# torch ships its own HIP runtime (soname libamdhip64.so.7, loaded by the
+# unversioned name). Loading torch first lets this library bind to that same
+# runtime; loading it first would put two HIP/HSA runtimes in one process,
+# after which the second one to initialise finds no device.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 
@@ -245,15 +252,17 @@ class Context:
         return dict(x=x, y=y, deg=d, label=lab, phase=ph)
 
     def davidson(self, k, tol=1e-8, max_iter=200, max_subspace=0, precond=CCH_PRECOND_JACOBI,
-                 want_vectors=True):
+                 want_vectors=True, residuals=False):
+        """(eigenvalues, vectors or None, info, status); with residuals=True the
+        vectors array has 2k rows, residuals H x - theta x after the vectors."""
         D, _ = self.dim()
         ev = np.zeros(k)
-        vec = np.zeros((k, D)) if want_vectors else None
+        vec = np.zeros((2 * k if residuals else k, D)) if (want_vectors or residuals) else None
         info = DavInfo()
         o = DavOpts(k, max_iter, max_subspace, precond, tol)
         rc = lib.cch_davidson(self.h, C.byref(o), ev.ctypes.data_as(C.c_void_p),
-                              vec.ctypes.data_as(C.c_void_p) if want_vectors else None,
-                              C.byref(info), CCH_MEM_HOST)
+                              vec.ctypes.data_as(C.c_void_p) if vec is not None else None,
+                              C.byref(info), CCH_MEM_HOST | (CCH_DAV_RESIDUALS if residuals else 0))
         self._ck(rc, ok=(CCH_OK, CCH_E_NOT_CONVERGED))
         return ev, vec, info, rc
 

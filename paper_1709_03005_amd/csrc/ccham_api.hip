@@ -1000,7 +1000,12 @@ cch_status cch_mlp_create(cch_mlp **out, int32_t device, void *hip_stream, uint6
 {
     if (!out) return mfail(nullptr, CCH_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (hipSetDevice(device) != hipSuccess) return mfail(nullptr, CCH_E_HIP, "hipSetDevice failed");
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || ndev <= 0) return mfail(nullptr, CCH_E_HIP, "no HIP device: %s", hipGetErrorString(he));
+    if (device < 0 || device >= ndev) return mfail(nullptr, CCH_E_INVALID_ARG, "device %d out of range", device);
+    he = hipSetDevice(device);
+    if (he != hipSuccess) return mfail(nullptr, CCH_E_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(he));
     cch_mlp *m = new (std::nothrow) cch_mlp();
     if (!m) return mfail(nullptr, CCH_E_OOM, "allocation failed");
     m->device = device;
@@ -1711,9 +1716,15 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(hipMemcpyAsync(&elem_fb, b.nfb, 4, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
     }
-    if (evecs)
-        DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.V, ldv * 8, 8 * (size_t)D, kk,
-                             (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (evecs) {
+        const hipMemcpyKind kind = (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.V, ldv * 8, 8 * (size_t)D, kk, kind, st));
+        if (flags & CCH_DAV_RESIDUALS) {
+            // residuals of the returned Ritz pairs (b.R holds those of the last Rayleigh-Ritz step)
+            DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kk, b.R, b.part, b.norms, st));
+            DCK(hipMemcpy2DAsync(evecs + (size_t)k * D, 8 * (size_t)D, b.R, ldv * 8, 8 * (size_t)D, kk, kind, st));
+        }
+    }
     DCK(hipStreamSynchronize(st));
     cleanup();
     if (info) {
