@@ -7,6 +7,11 @@ FP64 MFMA expansion, class 4, classes 2/8, mirror) followed by cch_davidson
 configuration (30 target orbitals, N = 10, 4 symmetries x 500 dets x 5 states,
 150 continuum orbitals per irrep, 5000 L2; D = 8000; lowest 10 to 1e-8).
 
+Workloads: medium (default), tiny, small, precision (D = 40000), learned
+(D = 60000; --precond mlp solves with the trained network and reports the
+Jacobi solve of the same matrix beside it), batch (64 instances, batched vs
+one after another).
+
 Prints ONE JSON line. `value` = lower-triangle Hamiltonian elements per second
 of the whole step (build + solve); the build-only rate and the
 time-to-eigenpairs are separate fields.
@@ -27,28 +32,72 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
-    # name: (generator, k, tol)
-    "medium": ("medium", 10, 1e-8),
-    "tiny": ("tiny", 5, 1e-8),
-    "small": ("small", 10, 1e-8),
-    "precision": ("precision", 10, 1e-8),
+    # name: (generator, k, tol, CPU-baseline mode)
+    "medium": ("medium", 10, 1e-8, "rows"),
+    "tiny": ("tiny", 5, 1e-8, "rows"),
+    "small": ("small", 10, 1e-8, "rows"),
+    "precision": ("precision", 10, 1e-8, "elements"),
+    "learned": ("learned_test", 10, 1e-8, "elements"),
 }
 
 
-def cpu_baseline(inst, budget_s=20.0):
-    """The CPU oracle on a stratified sample of rows of the same matrix:
-    for each target symmetry the rows of one continuum orbital (all states),
-    and L2 rows in the matrix's continuum : L2 proportion. Returns
-    elements/s (full rows, both triangles, as the oracle computes them)."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(inst, mode="rows", budget_s=20.0):
+    """The CPU oracle, timed on a bounded sample of the same matrix.
+
+    mode "rows": stratified groups of full rows, each group the rows of one
+    continuum orbital (all states) per target symmetry plus L2 rows in the
+    matrix's continuum : L2 proportion; elements/s over full rows (both
+    triangles, as the oracle computes them).
+
+    mode "elements": for matrices where one continuum row alone takes the
+    oracle minutes (thousands of target determinants), the oracle's
+    per-element path on a seeded sample of each block class of the lower
+    triangle (continuum-continuum, L2-continuum, L2-L2); the per-class
+    times per element are weighted by the class sizes into one rate for the
+    whole lower triangle."""
     import numpy as np
 
     import oracle
     O = oracle.Oracle(inst)
     D = inst.dim()
-    n_cont_rows = inst.n_cont_rows()
-    rows_c = []
-    r0 = 0
+    Dc = inst.n_cont_rows()
     rng = np.random.default_rng(7)
+    if mode == "elements":
+        counts = {"cont_cont": Dc * (Dc + 1) / 2, "l2_cont": float(inst.n_l2) * Dc,
+                  "l2_l2": inst.n_l2 * (inst.n_l2 + 1) / 2}
+        per_el, n_tot, t_tot = {}, 0, 0.0
+        for cls, cnt in counts.items():
+            if cnt == 0:
+                continue
+            n_s, t_c, n_c = 16, 0.0, 0
+            while t_c < budget_s / 6 and n_c < (1 << 17):
+                if cls == "cont_cont":
+                    r = rng.integers(0, Dc, n_s); c = rng.integers(0, Dc, n_s)
+                elif cls == "l2_cont":
+                    r = rng.integers(Dc, D, n_s); c = rng.integers(0, Dc, n_s)
+                else:
+                    r = rng.integers(Dc, D, n_s); c = rng.integers(Dc, D, n_s)
+                r, c = np.maximum(r, c), np.minimum(r, c)
+                t = time.perf_counter()
+                O.elements(r, c)
+                t_c += time.perf_counter() - t
+                n_c += n_s
+                n_s *= 2
+            per_el[cls] = t_c / n_c
+            n_tot += n_c
+            t_tot += t_c
+            log(f"cpu baseline {cls}: {n_c} elements in {t_c:.1f} s")
+        total = sum(counts.values())
+        est = sum(counts[c] * per_el[c] for c in per_el)
+        return {"value": total / est, "unit": "elements/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{n_tot} seeded lower-triangle elements of the same matrix, drawn per block class "
+                          f"({', '.join(f'{c}: {per_el[c] * 1e6:.1f} us/element' for c in per_el)}), "
+                          f"weighted by the class sizes; {t_tot:.1f} s of oracle time",
+                "seconds": t_tot}
     groups = 0
     t_total = 0.0
     n_el = 0
@@ -62,14 +111,15 @@ def cpu_baseline(inst, budget_s=20.0):
                 jj = int(rng.integers(nc))
                 rows_c += [r0 + n * nc + jj for n in range(S)]
             r0 += S * nc
-        n_l2_rows = max(1, int(round(len(rows_c) * inst.n_l2 / max(n_cont_rows, 1))))
-        rows_l = list(n_cont_rows + rng.choice(inst.n_l2, size=min(n_l2_rows, inst.n_l2), replace=False))
+        n_l2_rows = max(1, int(round(len(rows_c) * inst.n_l2 / max(Dc, 1))))
+        rows_l = list(Dc + rng.choice(inst.n_l2, size=min(n_l2_rows, inst.n_l2), replace=False))
         rows = np.array(rows_c + rows_l, dtype=np.int64)
         t = time.perf_counter()
         O.build_rows(rows)
         t_total += time.perf_counter() - t
         n_el += rows.size * D
         groups += 1
+        log(f"cpu baseline group {groups}: {rows.size} rows, {t_total:.1f} s")
     return {"value": n_el / t_total, "unit": "elements/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{groups} stratified row groups of the same matrix ({n_el // D} full rows: one continuum "
                       f"orbital x all states per symmetry + L2 rows in proportion), {t_total:.1f} s",
@@ -145,6 +195,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64",
                     help="expansion GEMM form: fp64, fp32, or bf16xS (split-BF16 with S slices)")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mlp"],
+                    help="Davidson correction: diagonal (Jacobi) or the trained network "
+                         "(paper_1709_03005_amd/mlp_weights.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -159,12 +212,11 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
-    gen, k, tol = WORKLOADS[args.workload]
+    gen, k, tol, cpu_mode = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     inst = synth.CONFIGS[gen]()
     t_gen = time.perf_counter() - t_gen
-    print(f"[bench] workload {args.workload}: D={inst.dim()} generated in {t_gen:.1f} s", file=sys.stderr,
-          flush=True)
+    log(f"workload {args.workload}: D={inst.dim()} generated in {t_gen:.1f} s")
 
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
@@ -181,17 +233,25 @@ def main():
     ctx.plan(precision=prec, split_slices=slices)
     ctx.sync()
     plan_s = time.perf_counter() - t
+    log(f"planned in {plan_s:.1f} s")
     work = ctx.work_counts()
     lower = work["lower_elements"]
+    net = None
+    if args.precond == "mlp":
+        net = cc.Mlp(device=0, stream=stream)
+        net.set_weights(np.load(os.path.join(ROOT, "paper_1709_03005_amd", "mlp_weights.npy")))
+        ctx.set_mlp(net)
+    pc = cc.CCH_PRECOND_MLP if net is not None else cc.CCH_PRECOND_JACOBI
 
     def step():
         ctx.build()
-        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False)
+        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, precond=pc)
         return ev, info, rc
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("warmup done")
     builds, phases, dav_s, dav_it, mv_ms, mv_n, resid, rcs = [], [], [], [], [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -207,6 +267,7 @@ def main():
         rcs.append(rc)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"{args.steps} timed steps in {wall:.2f} s")
     ms_step = wall / args.steps * 1e3
     build_ms = float(np.median(builds))
     ph = np.median(np.array(phases), axis=0)
@@ -286,8 +347,22 @@ def main():
         }
         del G, H64
     out["precision"] = args.precision
+    out["precond"] = args.precond
+    if net is not None:
+        # the plain (Jacobi) solve of the same matrix, outside the timed region
+        ev_j, _, inf_j, rc_j = ctx.davidson(k, tol=tol, want_vectors=False)
+        out["precond_ab"] = {
+            "mlp_ms": out["davidson_ms"], "mlp_iterations": out["davidson_iterations"],
+            "mlp_fallbacks": int(info.fallbacks),
+            "jacobi_ms": inf_j.seconds * 1e3, "jacobi_iterations": int(inf_j.iterations),
+            "jacobi_status": int(rc_j),
+            "time_gain": inf_j.seconds * 1e3 / out["davidson_ms"],
+            "max_abs_eigenvalue_difference": float(np.abs(np.array(ev) - ev_j).max()),
+        }
+        ctx.set_mlp(None)
+        net.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst)
+        out["cpu_baseline"] = cpu_baseline(inst, cpu_mode)
     ctx.close()
     print(json.dumps(out))
 

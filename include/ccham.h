@@ -85,6 +85,11 @@ typedef struct {
     int32_t max_subspace;   /* basis size before a thick restart (0: max(8k, 64)) */
     int32_t precond;        /* CCH_PRECOND_* */
     double tol;             /* converged when ||H x - theta x||_2 <= tol, ||x|| = 1 */
+    int32_t block;          /* Ritz pairs given a correction each iteration, k..16
+                               (0: k); pairs k..block-1 are guards: corrected
+                               while any wanted pair is unconverged, never
+                               tested for convergence */
+    int32_t reserved;       /* 0 */
 } cch_dav_opts;
 
 typedef struct {

@@ -68,7 +68,7 @@ class PlanOpts(C.Structure):
 
 class DavOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_subspace", C.c_int32),
-                ("precond", C.c_int32), ("tol", C.c_double)]
+                ("precond", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("reserved", C.c_int32)]
 
 
 class DavInfo(C.Structure):
@@ -252,14 +252,14 @@ class Context:
         return dict(x=x, y=y, deg=d, label=lab, phase=ph)
 
     def davidson(self, k, tol=1e-8, max_iter=200, max_subspace=0, precond=CCH_PRECOND_JACOBI,
-                 want_vectors=True, residuals=False):
+                 want_vectors=True, residuals=False, block=0):
         """(eigenvalues, vectors or None, info, status); with residuals=True the
         vectors array has 2k rows, residuals H x - theta x after the vectors."""
         D, _ = self.dim()
         ev = np.zeros(k)
         vec = np.zeros((2 * k if residuals else k, D)) if (want_vectors or residuals) else None
         info = DavInfo()
-        o = DavOpts(k, max_iter, max_subspace, precond, tol)
+        o = DavOpts(k, max_iter, max_subspace, precond, tol, block, 0)
         rc = lib.cch_davidson(self.h, C.byref(o), ev.ctypes.data_as(C.c_void_p),
                               vec.ctypes.data_as(C.c_void_p) if vec is not None else None,
                               C.byref(info), CCH_MEM_HOST | (CCH_DAV_RESIDUALS if residuals else 0))

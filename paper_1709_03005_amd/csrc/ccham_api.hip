@@ -1548,6 +1548,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     mmax = std::min(mmax, D);
     const int kr = std::min(2 * k, D);         // kept at a thick restart; also the first block
     if (kr + k > mmax && mmax < D) return fail(c, CCH_E_INVALID_ARG, "k too large for the subspace limit");
+    const int blk = o->block > 0 ? o->block : k;   // wanted + guard pairs corrected per iteration
+    if (blk < k || blk > 16) return fail(c, CCH_E_INVALID_ARG, "block must lie in [k, 16]");
     const int max_iter = o->max_iter > 0 ? o->max_iter : 200;
     HIPCK(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
@@ -1567,17 +1569,17 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     bool ok = A((void **)&b.V, 8 * ldv * mmax) && A((void **)&b.Wv, 8 * ldv * mmax) &&
               A((void **)&b.V2, 8 * ldv * mmax) && A((void **)&b.W2, 8 * ldv * mmax) &&
               A((void **)&b.G, 8 * (size_t)mmax * mmax) && A((void **)&b.theta, 8 * (size_t)mmax) &&
-              A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.R, 8 * ldv * k) &&
+              A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.R, 8 * ldv * blk) &&
               A((void **)&b.T, 8 * ldv * BMAX) && A((void **)&b.T2, 8 * ldv * BMAX) &&
               A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
-              A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)k) &&
-              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)k) && A((void **)&b.idx, 4 * (size_t)kr) &&
+              A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)blk) &&
+              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)kr) &&
               A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4);
     const bool want_mlp = o->precond == CCH_PRECOND_MLP;
     if (ok && want_mlp)
-        ok = A((void **)&b.rho, 8 * (size_t)D) && A((void **)&b.mx, 16 * (size_t)D * k) &&
-             A((void **)&b.mg, 4 * (size_t)D * k);
+        ok = A((void **)&b.rho, 8 * (size_t)D) && A((void **)&b.mx, 16 * (size_t)D * blk) &&
+             A((void **)&b.mg, 4 * (size_t)D * blk);
     if (!ok) {
         cleanup();
         return fail(c, CCH_E_OOM, "Davidson buffers");
@@ -1609,7 +1611,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
         DCK(hipMemsetAsync(b.nfb, 0, 4, st));
     }
-    std::vector<double> hres(k), htheta(mmax);
+    std::vector<double> hres(blk), htheta(mmax);
     cch_status rc = CCH_E_NOT_CONVERGED;
     for (iters = 1; iters <= max_iter; ++iters) {
         // reference norms of the raw directions, for the drop test
@@ -1650,9 +1652,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.W2, ldv, st));
         std::swap(b.V, b.V2);
         std::swap(b.Wv, b.W2);
-        const int kk = std::min(k, m);
-        DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kk, b.R, b.part, b.norms, st));
-        DCK(hipMemcpyAsync(hres.data(), b.norms, 8 * (size_t)kk, hipMemcpyDeviceToHost, st));
+        const int kk = std::min(k, m), kg = std::min(blk, m);
+        DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kg, b.R, b.part, b.norms, st));
+        DCK(hipMemcpyAsync(hres.data(), b.norms, 8 * (size_t)kg, hipMemcpyDeviceToHost, st));
         DCK(hipMemcpyAsync(htheta.data(), b.theta, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
         {
@@ -1667,6 +1669,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             if (!(hres[e] <= o->tol)) un.push_back(e);
         }
         nconv = kk - (int)un.size();
+        if (!un.empty())   // guard pairs ride along in the same mat-vec pass
+            for (int e = kk; e < kg; ++e)
+                if (!(hres[e] <= o->tol)) un.push_back(e);
         // judge of the learned step: a residual that grows tenfold over the best so far
         // switches the rest of the solve to the diagonal step
         if (use_mlp && iters > 3 && maxres > 10.0 * best_res) {
