@@ -64,6 +64,10 @@ typedef int32_t cch_status;
 #define CCH_PRECOND_JACOBI 0
 #define CCH_PRECOND_MLP 1
 
+/* cch_subspace_eig methods */
+#define CCH_EIG_AUTO 0
+#define CCH_EIG_JACOBI 1
+
 /* which determinant-pair list cch_get_labels returns */
 #define CCH_PAIRS_TARGET 0   /* target x target, one symmetry pair */
 #define CCH_PAIRS_L2 1       /* L2 x L2, lower triangle */
@@ -101,7 +105,7 @@ typedef struct {
     double seconds;         /* wall time of the solve */
     double matvec_ms;       /* device time of the H V launches (HIP events) */
     int32_t matvec_launches;
-    int32_t reserved;
+    int32_t rr_fallbacks;   /* Rayleigh-Ritz solves rerun by cyclic Jacobi */
 } cch_dav_info;
 
 /* Library version string (static storage). */
@@ -203,6 +207,22 @@ cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sy
  * Synchronous. */
 cch_status cch_davidson(cch_ctx *ctx, const cch_dav_opts *opts, double *evals,
                         double *evecs, cch_dav_info *info, int32_t flags);
+
+/* The Rayleigh-Ritz eigenproblem of cch_davidson, exposed for testing and
+ * reuse: every eigenpair of a small dense symmetric matrix in FP64 on the
+ * context's device and stream (the context needs no build). G is m x m,
+ * 1 <= m <= 96, row-major with leading dimension ldg >= m; (G + G^T)/2 is
+ * used. theta[m] receives the eigenvalues ascending; Y (m rows, leading
+ * dimension ldy >= m) the orthonormal eigenvectors, eigenvector e in column
+ * e (Y[q*ldy + e]). method CCH_EIG_AUTO: Householder tridiagonalisation,
+ * eigenvalues by Sturm multisection, eigenvectors by twisted factorisation,
+ * re-orthogonalised, with cyclic Jacobi when a check fails (*fallback, which
+ * may be NULL, receives 1 then); CCH_EIG_JACOBI: cyclic Jacobi alone. Arrays
+ * are host memory, or device memory with flags & CCH_MEM_DEVICE.
+ * Synchronous. */
+cch_status cch_subspace_eig(cch_ctx *ctx, const double *G, int32_t ldg, int32_t m,
+                            double *theta, double *Y, int32_t ldy, int32_t method,
+                            int32_t *fallback, int32_t flags);
 
 /* Device time of the last cch_build in milliseconds (HIP events around the
  * queued work on the context's stream), and per-phase times (phases[8],

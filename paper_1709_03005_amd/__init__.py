@@ -34,6 +34,8 @@ CCH_PREC_FP32 = 1
 CCH_PREC_SPLIT_BF16 = 2
 CCH_PRECOND_JACOBI = 0
 CCH_PRECOND_MLP = 1
+CCH_EIG_AUTO = 0
+CCH_EIG_JACOBI = 1
 CCH_PAIRS_TARGET = 0
 CCH_PAIRS_L2 = 1
 CCH_PAIRS_L2_TARGET = 2
@@ -46,7 +48,7 @@ EXPORTS = [
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
     "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
-    "cch_davidson_set_mlp",
+    "cch_davidson_set_mlp", "cch_subspace_eig",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -74,7 +76,7 @@ class DavOpts(C.Structure):
 class DavInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
                 ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double),
-                ("matvec_ms", C.c_double), ("matvec_launches", C.c_int32), ("reserved", C.c_int32)]
+                ("matvec_ms", C.c_double), ("matvec_launches", C.c_int32), ("rr_fallbacks", C.c_int32)]
 
 
 P = C.c_void_p
@@ -116,6 +118,7 @@ _SIG = {
     "cch_mlp_train_step": (i32, [P, P, P, P, P, i64, C.c_float, C.POINTER(C.c_double), i32]),
     "cch_mlp_features": (i32, [P, C.c_double, P, i32]),
     "cch_davidson_set_mlp": (i32, [P, P]),
+    "cch_subspace_eig": (i32, [P, P, i32, i32, P, P, i32, i32, C.POINTER(i32), i32]),
 }
 for _n, (_r, _a) in _SIG.items():
     _f = getattr(lib, _n)
@@ -272,6 +275,19 @@ class Context:
         keys = ["lower_elements", "gemm_flops", "target_pairs", "l2_target_pairs", "relayout_bytes",
                 "class4_outputs", "l2_lower_elements", "sym_pairs"]
         return dict(zip(keys, out.tolist()))
+
+    def subspace_eig(self, G, method=CCH_EIG_AUTO):
+        """(theta ascending, Y with eigenvectors in columns, fell_back) for a
+        small symmetric host matrix G (m <= 96), solved on the device."""
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        m = G.shape[0]
+        theta = np.zeros(m)
+        Y = np.zeros((m, m))
+        fb = C.c_int32()
+        self._ck(lib.cch_subspace_eig(self.h, G.ctypes.data_as(C.c_void_p), G.shape[1], m,
+                                      theta.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p), m, method,
+                                      C.byref(fb), CCH_MEM_HOST))
+        return theta, Y, bool(fb.value)
 
     def mlp_features(self, theta):
         D, _ = self.dim()

@@ -123,6 +123,8 @@ hipError_t launch_pchol(const double *G, int ldg, int b, const double *ref, doub
                         int32_t *rank, hipStream_t st);
 hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st);
 hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
+hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, int32_t *nfallback,
+                         hipStream_t st);
 hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
 // learned preconditioner
@@ -873,6 +875,61 @@ cch_status cch_get_diagonal(cch_ctx *c, double *out, int32_t flags)
     return CCH_OK;
 }
 
+cch_status cch_subspace_eig(cch_ctx *c, const double *G, int32_t ldg, int32_t m, double *theta, double *Y,
+                            int32_t ldy, int32_t method, int32_t *fallback, int32_t flags)
+{
+    if (!c || !G || !theta || !Y) return CCH_E_INVALID_ARG;
+    if (m < 1 || m > 96) return fail(c, CCH_E_INVALID_ARG, "m must lie in [1, 96]");
+    if (ldg < m || ldy < m) return fail(c, CCH_E_INVALID_ARG, "leading dimension below m");
+    if (method != CCH_EIG_AUTO && method != CCH_EIG_JACOBI) return fail(c, CCH_E_INVALID_ARG, "unknown method");
+    HIPCK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const bool dev = flags & CCH_MEM_DEVICE;
+    double *dG = nullptr, *dT = nullptr, *dY = nullptr;
+    int32_t *dF = nullptr;
+    auto cleanup = [&]() {
+        if (!dev) {
+            (void)hipFree(dG);
+            (void)hipFree(dT);
+            (void)hipFree(dY);
+        }
+        (void)hipFree(dF);
+    };
+#define ECK(x)                                                                                  \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) {                                                                 \
+            cleanup();                                                                          \
+            return fail(c, CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_));                    \
+        }                                                                                       \
+    } while (0)
+    if (dev) {
+        dG = const_cast<double *>(G);
+        dT = theta;
+        dY = Y;
+    } else {
+        ECK(hipMalloc((void **)&dG, 8 * (size_t)m * ldg));
+        ECK(hipMalloc((void **)&dT, 8 * (size_t)m));
+        ECK(hipMalloc((void **)&dY, 8 * (size_t)m * ldy));
+        ECK(hipMemcpyAsync(dG, G, 8 * (size_t)m * ldg, hipMemcpyHostToDevice, st));
+    }
+    ECK(hipMalloc((void **)&dF, 4));
+    ECK(hipMemsetAsync(dF, 0, 4, st));
+    if (method == CCH_EIG_JACOBI) ECK(launch_jacobi_eig(dG, ldg, m, dT, dY, ldy, st));
+    else ECK(launch_rr_eig(dG, ldg, m, dT, dY, ldy, dF, st));
+    int32_t hf = 0;
+    ECK(hipMemcpyAsync(&hf, dF, 4, hipMemcpyDeviceToHost, st));
+    if (!dev) {
+        ECK(hipMemcpyAsync(theta, dT, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+        ECK(hipMemcpyAsync(Y, dY, 8 * (size_t)m * ldy, hipMemcpyDeviceToHost, st));
+    }
+    ECK(hipStreamSynchronize(st));
+#undef ECK
+    cleanup();
+    if (fallback) *fallback = hf;
+    return CCH_OK;
+}
+
 cch_status cch_get_labels(cch_ctx *c, int32_t which, int32_t sym_a, int32_t sym_b, int32_t *x, int32_t *y,
                           int8_t *degree, uint64_t *label, int8_t *phase, int64_t cap, int64_t *n)
 {
@@ -1526,7 +1583,7 @@ struct DavBufs {
     double *V = nullptr, *Wv = nullptr, *V2 = nullptr, *W2 = nullptr, *G = nullptr, *theta = nullptr,
            *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *Gb = nullptr, *Cb = nullptr,
            *ref = nullptr, *part = nullptr, *norms = nullptr, *Wp = nullptr, *rho = nullptr;
-    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr, *nfb = nullptr;
+    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr, *nfb = nullptr, *rrfb = nullptr;
     float *mx = nullptr, *mg = nullptr;
 };
 }  // namespace
@@ -1575,7 +1632,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
               A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)blk) &&
               A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)kr) &&
-              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4);
+              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4) &&
+              A((void **)&b.rrfb, 4);
     const bool want_mlp = o->precond == CCH_PRECOND_MLP;
     if (ok && want_mlp)
         ok = A((void **)&b.rho, 8 * (size_t)D) && A((void **)&b.mx, 16 * (size_t)D * blk) &&
@@ -1611,6 +1669,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
         DCK(hipMemsetAsync(b.nfb, 0, 4, st));
     }
+    DCK(hipMemsetAsync(b.rrfb, 0, 4, st));
     std::vector<double> hres(blk), htheta(mmax);
     cch_status rc = CCH_E_NOT_CONVERGED;
     for (iters = 1; iters <= max_iter; ++iters) {
@@ -1646,7 +1705,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
                       mmax, 0, st));
         DCK(launch_sym_fill(b.G, mmax, m, m + added, st));
         m += added;
-        DCK(launch_jacobi_eig(b.G, mmax, m, b.theta, b.Y, mmax, st));
+        DCK(launch_rr_eig(b.G, mmax, m, b.theta, b.Y, mmax, b.rrfb, st));
         // rotate V and W to the Ritz basis; G becomes diag(theta)
         DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.V2, ldv, st));
         DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.W2, ldv, st));
@@ -1716,11 +1775,10 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         if (flags & CCH_MEM_DEVICE) DCK(hipMemcpy(evals, th.data(), 8 * (size_t)kk, hipMemcpyHostToDevice));
         else memcpy(evals, th.data(), 8 * (size_t)kk);
     }
-    int32_t elem_fb = 0;
-    if (want_mlp) {
-        DCK(hipMemcpyAsync(&elem_fb, b.nfb, 4, hipMemcpyDeviceToHost, st));
-        DCK(hipStreamSynchronize(st));
-    }
+    int32_t elem_fb = 0, rr_fb = 0;
+    if (want_mlp) DCK(hipMemcpyAsync(&elem_fb, b.nfb, 4, hipMemcpyDeviceToHost, st));
+    DCK(hipMemcpyAsync(&rr_fb, b.rrfb, 4, hipMemcpyDeviceToHost, st));
+    DCK(hipStreamSynchronize(st));
     if (evecs) {
         const hipMemcpyKind kind = (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         DCK(hipMemcpy2DAsync(evecs, 8 * (size_t)D, b.V, ldv * 8, 8 * (size_t)D, kk, kind, st));
@@ -1741,7 +1799,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->matvec_ms = mv_ms;
         info->matvec_launches = mv_launches;
-        info->reserved = 0;
+        info->rr_fallbacks = rr_fb;
     }
     if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
     return rc;

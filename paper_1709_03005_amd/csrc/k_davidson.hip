@@ -4,9 +4,8 @@
 //   K8  W = H V for a block of b vectors (dense H streamed once: HBM-bound)
 //   K9  tall-skinny products X^T Y (Gram blocks, projections) and V C
 //       updates; modified Gram-Schmidt of a block in one workgroup
-//   K10 residuals, the diagonal (Jacobi) correction, and the Rayleigh-Ritz
-//       eigenproblem solved by cyclic Jacobi rotations in parallel
-//       (round-robin) order inside one workgroup, all in LDS.
+//   K10 residuals and the diagonal (Jacobi) correction (the Rayleigh-Ritz
+//       eigenproblem is in k_rr.hip).
 // Vectors are stored one per row: V[q][i], leading dimension ldv.
 #include <algorithm>
 
@@ -486,144 +485,6 @@ __global__ void k_diag_small(const double *__restrict__ G, int ldg, int b, doubl
 hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_diag_small, dim3(1), dim3(64), 0, st, G, ldg, b, out);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Rayleigh-Ritz eigenproblem: G (m x m, symmetric) -> ascending theta and
-// eigenvectors Y (column e of Y at Y[q*ldy + e]). Cyclic Jacobi, parallel
-// (round-robin tournament) ordering: m/2 disjoint rotations per round,
-// m-1 rounds per sweep, sweeps until the off-diagonal mass is below
-// (1e-15 ||G||_F)^2.
-// ---------------------------------------------------------------------------
-constexpr int JAC_MAX = 96;
-
-__global__ __launch_bounds__(1024) void k_jacobi_eig(const double *__restrict__ G, int ldg, int m,
-                                                     double *__restrict__ theta, double *__restrict__ Y, int ldy,
-                                                     int max_sweeps)
-{
-    __shared__ double A[JAC_MAX][JAC_MAX + 1];
-    __shared__ double Z[JAC_MAX][JAC_MAX + 1];
-    __shared__ double cs[JAC_MAX / 2], sn[JAC_MAX / 2];
-    __shared__ int pp[JAC_MAX / 2], qq[JAC_MAX / 2];
-    __shared__ double red[32];
-    __shared__ int perm[JAC_MAX];
-    __shared__ int nrot_sh;
-    const int me = (m + 1) & ~1;     // even size (a padded index is inert)
-    const int half = me / 2;
-    const int nthr = blockDim.x;
-    for (int t = threadIdx.x; t < me * me; t += nthr) {
-        const int i = t / me, j = t % me;
-        A[i][j] = (i < m && j < m) ? 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]) : 0.0;
-        Z[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int t = threadIdx.x; t < me * me; t += nthr) {
-            const int i = t / me, j = t % me;
-            const double v = A[i][j] * A[i][j];
-            tot += v;
-            if (i != j) off += v;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_xor(off, o, 64);
-            tot += __shfl_xor(tot, o, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            red[threadIdx.x >> 6] = off;
-            red[16 + (threadIdx.x >> 6)] = tot;
-        }
-        __syncthreads();
-        double offs = 0.0, tots = 0.0;
-        for (int w = 0; w < nthr / 64; ++w) {
-            offs += red[w];
-            tots += red[16 + w];
-        }
-        __syncthreads();
-        if (offs == 0.0) break;
-        if (threadIdx.x == 0) nrot_sh = 0;
-        __syncthreads();
-        for (int round = 0; round < me - 1; ++round) {
-            // round-robin pairing: index 0 fixed, the others rotate
-            if (threadIdx.x < half) {
-                const int k = threadIdx.x;
-                const int s0 = k, s1 = me - 1 - k;
-                int p = s0 == 0 ? 0 : 1 + (s0 - 1 + round) % (me - 1);
-                int q = 1 + (s1 - 1 + round) % (me - 1);
-                if (p > q) { const int t = p; p = q; q = t; }
-                pp[k] = p;
-                qq[k] = q;
-                const double apq = A[p][q];
-                double c = 1.0, s = 0.0;
-                // rotate only when a_pq is not negligible against the diagonal
-                if (fabs(apq) > 1e-16 * sqrt(fabs(A[p][p] * A[q][q])) && fabs(apq) > 1e-300) {
-                    nrot_sh = 1;
-                    const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                cs[k] = c;
-                sn[k] = s;
-            }
-            __syncthreads();
-            // A <- J^T A J on 2x2 blocks (row pair k, column pair l), Z <- Z J
-            const int nblk = half * half;
-            for (int t = threadIdx.x; t < nblk + half * me; t += nthr) {
-                if (t < nblk) {
-                    const int k = t / half, l = t % half;
-                    const int p = pp[k], q = qq[k], r = pp[l], u = qq[l];
-                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-                    const double apr = A[p][r], apu = A[p][u], aqr = A[q][r], aqu = A[q][u];
-                    // rows: [p; q] <- [c -s; s c] [p; q]
-                    const double bpr = ck * apr - sk * aqr, bpu = ck * apu - sk * aqu;
-                    const double bqr = sk * apr + ck * aqr, bqu = sk * apu + ck * aqu;
-                    // columns: [r u] <- [r u] [c s; -s c]
-                    A[p][r] = cl * bpr - sl * bpu;
-                    A[p][u] = sl * bpr + cl * bpu;
-                    A[q][r] = cl * bqr - sl * bqu;
-                    A[q][u] = sl * bqr + cl * bqu;
-                } else {
-                    const int e = t - nblk;
-                    const int l = e / me, i = e % me;
-                    const int r = pp[l], u = qq[l];
-                    const double cl = cs[l], sl = sn[l];
-                    const double zr = Z[i][r], zu = Z[i][u];
-                    Z[i][r] = cl * zr - sl * zu;
-                    Z[i][u] = sl * zr + cl * zu;
-                }
-            }
-            __syncthreads();
-        }
-        if (nrot_sh == 0) break;
-        __syncthreads();
-    }
-    // ascending order (stable), written out
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < m; ++i) perm[i] = i;
-        for (int i = 1; i < m; ++i) {
-            const int v = perm[i];
-            int j = i - 1;
-            while (j >= 0 && A[perm[j]][perm[j]] > A[v][v]) {
-                perm[j + 1] = perm[j];
-                --j;
-            }
-            perm[j + 1] = v;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m; e += nthr) theta[e] = A[perm[e]][perm[e]];
-    for (int t = threadIdx.x; t < m * m; t += nthr) {
-        const int q = t / m, e = t % m;
-        Y[(int64_t)q * ldy + e] = Z[q][perm[e]];
-    }
-}
-
-hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st)
-{
-    if (m <= 0 || m > JAC_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, st, G, ldg, m, theta, Y, ldy, 40);
     return hipGetLastError();
 }
 

@@ -1,0 +1,629 @@
+// Rayleigh-Ritz eigenproblem of the Davidson solver (Sec. 3.2 lists
+// Davidson among the diagonalisers): G (m x m, symmetric, m <= 96) ->
+// ascending theta and orthonormal eigenvectors Y (column e at Y[q*ldy + e]),
+// FP64, one workgroup, all of it in LDS.
+//
+// k_rr_eig, the main path:
+//   1. G is scaled by a power of two and reduced to tridiagonal form
+//      T = Q^T G Q by Householder reflectors (kept below the subdiagonal);
+//   2. every eigenvalue of T by multisection: Sturm counts from the
+//      leading-minor recurrence (rescaled by powers of two) at many shifts
+//      at once, one thread per shift;
+//   3. one eigenvector of T per thread from the twisted factorisation of
+//      T - lambda I at the twist index of smallest |gamma|;
+//   4. modified Gram-Schmidt (two passes) inside clusters of eigenvalues
+//      closer than 1e-3 ||T||, then the reflectors applied to the vectors;
+//   5. one Newton-Schulz step Y <- Y (3I - Y^T Y) / 2 on FP64 MFMA, which
+//      takes the orthogonality defect from ~1e-13 to rounding level.
+// A failed check (a non-finite value, a twisted residual above 1e-10 ||T||,
+// a cluster vector that loses 99% of its norm to the projections, or a
+// defect above 1e-8 before the Newton-Schulz step, as with exactly
+// repeated eigenvalues) reruns the problem by cyclic Jacobi in the same
+// launch and counts the event. k_jacobi_eig is the Jacobi path alone.
+#include <cfloat>
+
+#include "ccham_internal.h"
+
+namespace cch {
+
+constexpr int RR_MAX = 96, RR_LD = RR_MAX + 1, RR_NT = 1024, RR_NW = RR_NT / 64;
+typedef double rr_dx4 __attribute__((ext_vector_type(4)));
+
+constexpr int RR_SL = 8;     // row slices of the Householder products (x 2 column halves = 16 waves)
+constexpr int RR_BSL = 6;    // row slices of the back-transformation
+
+struct RRShared {
+    double A[RR_MAX][RR_LD];
+    double Z[RR_MAX][RR_LD];
+    double d[RR_MAX], e[RR_MAX], lam[RR_MAX], tau[RR_MAX], hinv[RR_MAX];
+    double sc[6][RR_MAX];        // per-phase scratch vectors
+    double red[2][32];           // alternating reduction buffers
+    union {
+        int cnt[RR_NT];                  // Sturm counts; Jacobi pairing tables
+        double part[RR_BSL][RR_MAX];     // back-transformation partial products
+    } u;
+    int flag, nrot;
+};
+static_assert(sizeof(RRShared) <= 160 * 1024, "LDS budget");
+
+__device__ __forceinline__ double rr_wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double rr_wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block reductions with one barrier: consecutive calls must alternate the
+// buffer, so that a buffer is written again only after a later barrier.
+__device__ __forceinline__ double rr_block_sum(double v, double *red)
+{
+    v = rr_wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+__device__ __forceinline__ double rr_block_max(double v, double *red)
+{
+    v = rr_wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, red[w]);
+    return s;
+}
+
+// Cross-lane helpers on doubles as two 32-bit halves: DPP moves (row shifts
+// and row broadcasts) and readlane with a wave-uniform lane index.
+struct RrI2 {
+    int x, y;
+};
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double rr_dpp(double v)
+{
+    RrI2 a = __builtin_bit_cast(RrI2, v);
+    a.x = __builtin_amdgcn_update_dpp(0, a.x, CTRL, ROW_MASK, BANK_MASK, true);
+    a.y = __builtin_amdgcn_update_dpp(0, a.y, CTRL, ROW_MASK, BANK_MASK, true);
+    return __builtin_bit_cast(double, a);
+}
+
+__device__ __forceinline__ double rr_rl(double v, int lane)
+{
+    RrI2 a = __builtin_bit_cast(RrI2, v);
+    a.x = __builtin_amdgcn_readlane(a.x, lane);
+    a.y = __builtin_amdgcn_readlane(a.y, lane);
+    return __builtin_bit_cast(double, a);
+}
+
+// sum over the 64 lanes, returned to every lane: partial sums of 4 within
+// each row of 16 (row_shr 1..3), of 8 and 16 (row_shr 4, 8 on the upper
+// banks), then rows 0+1 and 2+3 (row_bcast15) and all four (row_bcast31)
+// collect in lane 63. Fixed order, so every wave gets the same bits.
+__device__ __forceinline__ double rr_wsum(double v)
+{
+    double s = v + rr_dpp<0x111, 0xf, 0xf>(v);
+    s += rr_dpp<0x112, 0xf, 0xf>(v);
+    s += rr_dpp<0x113, 0xf, 0xf>(v);
+    s += rr_dpp<0x114, 0xf, 0xe>(s);
+    s += rr_dpp<0x118, 0xf, 0xc>(s);
+    s += rr_dpp<0x142, 0xa, 0xf>(s);
+    s += rr_dpp<0x143, 0xc, 0xf>(s);
+    return rr_rl(s, 63);
+}
+
+// element i (wave-uniform, < 128) of a vector held as lo = x[lane], hi = x[lane + 64]
+__device__ __forceinline__ double rr_get(double lo, double hi, int i)
+{
+    return i < 64 ? rr_rl(lo, i) : rr_rl(hi, i - 64);
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi, parallel (round-robin tournament) ordering: m/2 disjoint
+// rotations per round, m-1 rounds per sweep; a rotation is skipped when
+// |a_pq| <= 1e-16 sqrt(|a_pp a_qq|), and the sweeps stop after one with no
+// rotation. Reads G itself (unscaled) and writes theta and Y.
+// ---------------------------------------------------------------------------
+__device__ void rr_jacobi(RRShared &sh, const double *__restrict__ G, int ldg, int m, double *__restrict__ theta,
+                          double *__restrict__ Y, int ldy, int max_sweeps)
+{
+    double(*A)[RR_LD] = sh.A;
+    double(*Z)[RR_LD] = sh.Z;
+    double *cs = sh.sc[3], *sn = sh.sc[4];
+    int *pp = sh.u.cnt, *qq = sh.u.cnt + RR_MAX / 2, *perm = sh.u.cnt + RR_MAX;
+    const int me = (m + 1) & ~1;     // even size (a padded index is inert)
+    const int half = me / 2;
+    const int nthr = blockDim.x;
+    __syncthreads();
+    for (int t = threadIdx.x; t < me * me; t += nthr) {
+        const int i = t / me, j = t % me;
+        A[i][j] = (i < m && j < m) ? 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]) : 0.0;
+        Z[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) sh.nrot = 0;
+        __syncthreads();
+        for (int round = 0; round < me - 1; ++round) {
+            if (threadIdx.x < half) {
+                const int k = threadIdx.x;
+                const int s0 = k, s1 = me - 1 - k;
+                int p = s0 == 0 ? 0 : 1 + (s0 - 1 + round) % (me - 1);
+                int q = 1 + (s1 - 1 + round) % (me - 1);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                pp[k] = p;
+                qq[k] = q;
+                const double apq = A[p][q];
+                double c = 1.0, s = 0.0;
+                if (fabs(apq) > 1e-16 * sqrt(fabs(A[p][p] * A[q][q])) && fabs(apq) > 1e-300) {
+                    sh.nrot = 1;
+                    const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                cs[k] = c;
+                sn[k] = s;
+            }
+            __syncthreads();
+            // A <- J^T A J on 2x2 blocks (row pair k, column pair l), Z <- Z J
+            const int nblk = half * half;
+            for (int t = threadIdx.x; t < nblk + half * me; t += nthr) {
+                if (t < nblk) {
+                    const int k = t / half, l = t % half;
+                    const int p = pp[k], q = qq[k], r = pp[l], u = qq[l];
+                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+                    const double apr = A[p][r], apu = A[p][u], aqr = A[q][r], aqu = A[q][u];
+                    const double bpr = ck * apr - sk * aqr, bpu = ck * apu - sk * aqu;
+                    const double bqr = sk * apr + ck * aqr, bqu = sk * apu + ck * aqu;
+                    A[p][r] = cl * bpr - sl * bpu;
+                    A[p][u] = sl * bpr + cl * bpu;
+                    A[q][r] = cl * bqr - sl * bqu;
+                    A[q][u] = sl * bqr + cl * bqu;
+                } else {
+                    const int e = t - nblk;
+                    const int l = e / me, i = e % me;
+                    const int r = pp[l], u = qq[l];
+                    const double cl = cs[l], sl = sn[l];
+                    const double zr = Z[i][r], zu = Z[i][u];
+                    Z[i][r] = cl * zr - sl * zu;
+                    Z[i][u] = sl * zr + cl * zu;
+                }
+            }
+            __syncthreads();
+        }
+        if (sh.nrot == 0) break;
+        __syncthreads();
+    }
+    // ascending order (stable), written out
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < m; ++i) perm[i] = i;
+        for (int i = 1; i < m; ++i) {
+            const int v = perm[i];
+            int j = i - 1;
+            while (j >= 0 && A[perm[j]][perm[j]] > A[v][v]) {
+                perm[j + 1] = perm[j];
+                --j;
+            }
+            perm[j + 1] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += nthr) theta[e] = A[perm[e]][perm[e]];
+    for (int t = threadIdx.x; t < m * m; t += nthr) {
+        const int q = t / m, e = t % m;
+        Y[(int64_t)q * ldy + e] = Z[q][perm[e]];
+    }
+}
+
+__global__ __launch_bounds__(RR_NT) void k_jacobi_eig(const double *__restrict__ G, int ldg, int m,
+                                                      double *__restrict__ theta, double *__restrict__ Y, int ldy,
+                                                      int max_sweeps)
+{
+    __shared__ RRShared sh;
+    rr_jacobi(sh, G, ldg, m, theta, Y, ldy, max_sweeps);
+}
+
+// Sturm count: eigenvalues of T below x, from the signs of the leading
+// principal minors of T - xI (p_{i+1} = (d_i - x) p_i - e_{i-1}^2 p_{i-1});
+// an exact zero minor counts as negative. d and e^2 come from registers
+// (d_i in lane i of dl0 / dl1, e_i^2 in lane i of ql0 / ql1). The pair
+// (p_i, p_{i-1}) is rescaled by 2^-+500 every fourth step: T is scaled to
+// entries below 2 and couplings below eps (|d_i| + |d_{i+1}|) are zeroed,
+// so four steps can neither overflow nor underflow from [2^-500, 2^500].
+__device__ __forceinline__ int rr_sturm(double dl0, double dl1, double ql0, double ql1, int n, double x)
+{
+    double pp = 1.0, p = rr_rl(dl0, 0) - x;
+    p = (p == 0.0) ? -DBL_MIN : p;
+    int c = p < 0.0;
+    for (int i = 1; i < n; ++i) {
+        const double di = rr_get(dl0, dl1, i), qi = rr_get(ql0, ql1, i - 1);
+        double q = fma(di - x, p, -(qi * pp));
+        q = (q == 0.0) ? (p > 0.0 ? -DBL_MIN : DBL_MIN) : q;
+        c += (q < 0.0) != (p < 0.0);
+        pp = p;
+        p = q;
+        if ((i & 3) == 0) {
+            const double mx = fmax(fabs(p), fabs(pp));
+            const double f = mx > 0x1p+500 ? 0x1p-500 : (mx < 0x1p-500 ? 0x1p+500 : 1.0);
+            p *= f;
+            pp *= f;
+        }
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, int ldg, int m,
+                                                  double *__restrict__ theta, double *__restrict__ Y, int ldy,
+                                                  int32_t *__restrict__ nfallback)
+{
+    __shared__ RRShared sh;
+    double(*A)[RR_LD] = sh.A;
+    double(*Z)[RR_LD] = sh.Z;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = m;
+    int rp = 0;
+    auto bmax = [&](double v) {
+        const double r = rr_block_max(v, sh.red[rp]);
+        rp ^= 1;
+        return r;
+    };
+
+    // ---- load, symmetrise, scale by a power of two --------------------------
+    if (tid == 0) sh.flag = 0;
+    double amax = 0.0;
+    for (int t = tid; t < RR_MAX * RR_MAX; t += RR_NT) {
+        const int i = t / RR_MAX, j = t % RR_MAX;
+        double v = 0.0;
+        if (i < n && j < n) v = 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
+        A[i][j] = v;
+        Z[i][j] = 0.0;
+        amax = fmax(amax, fabs(v));
+    }
+    amax = bmax(amax);
+    if (amax == 0.0) {
+        for (int e = tid; e < n; e += RR_NT) theta[e] = 0.0;
+        for (int t = tid; t < n * n; t += RR_NT) Y[(int64_t)(t / n) * ldy + t % n] = (t / n == t % n) ? 1.0 : 0.0;
+        return;
+    }
+    bool bad = !isfinite(amax);
+    const double scale = bad ? 1.0 : ldexp(1.0, -ilogb(amax));
+    for (int t = tid; t < n * RR_MAX; t += RR_NT) {
+        const int i = t / RR_MAX, j = t % RR_MAX;
+        A[i][j] *= scale;
+    }
+    __syncthreads();
+
+    if (!bad) {
+        // ---- Householder reduction to tridiagonal form ------------------------
+        // Step k: x = row k of the trailing matrix, H_k = I - tau v v^T with
+        // v_{k+1} = 1 and v_r = x_r * hinv[k] below; row k keeps x afterwards.
+        // Thread (wave w, lane l) owns column lane + 64 (w & 1) over the rows
+        // k+1+s, k+1+s+8, ... of slice s = w >> 1. Every wave holds x, v and
+        // w in registers and forms sigma and K itself (identical bits).
+        {
+            const int half = wv & 1, slice = wv >> 1;
+            const int col = lane + 64 * half;
+            for (int k = 0; k + 2 < n; ++k) {
+                const double x0 = lane < n ? A[k][lane] : 0.0;
+                const double x1 = lane + 64 < n ? A[k][lane + 64] : 0.0;
+                const double sig =
+                    rr_wsum((lane >= k + 2 ? x0 * x0 : 0.0) + (lane + 64 >= k + 2 ? x1 * x1 : 0.0));
+                const double alpha = rr_get(x0, x1, k + 1);
+                if (sig == 0.0) {   // the same in every wave
+                    if (tid == 0) {
+                        sh.tau[k] = 0.0;
+                        sh.e[k] = alpha;
+                    }
+                    continue;
+                }
+                const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+                const double t = (beta - alpha) / beta;
+                const double inv = 1.0 / (alpha - beta);
+                if (tid == 0) {
+                    sh.tau[k] = t;
+                    sh.e[k] = beta;
+                    sh.hinv[k] = inv;
+                }
+                const double v0 = lane == k + 1 ? 1.0 : (lane >= k + 2 ? x0 * inv : 0.0);
+                const double v1 = lane + 64 == k + 1 ? 1.0 : (lane + 64 >= k + 2 ? x1 * inv : 0.0);
+                // partial p_col = sum over this slice's rows of A[r][col] v_r (into Z).
+                // Loops that read lanes run with the whole wave active: a lane that
+                // sits out a branch may not hold the value another lane reads.
+                const bool act = col < n && col >= k + 1;
+                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
+                double acc = 0.0;
+                for (int r = k + 1 + slice; r < n; r += RR_SL) acc = fma(A[r][cc], rr_get(v0, v1, r), acc);
+                if (col < RR_MAX) Z[slice][col] = act ? acc : 0.0;
+                __syncthreads();
+                double p0 = 0.0, p1 = 0.0;
+                for (int q = 0; q < RR_SL; ++q) {
+                    p0 += Z[q][lane];
+                    if (lane + 64 < RR_MAX) p1 += Z[q][lane + 64];
+                }
+                p0 *= t;
+                p1 *= t;
+                const double K = 0.5 * t * rr_wsum(p0 * v0 + p1 * v1);
+                const double w0 = p0 - K * v0, w1 = p1 - K * v1;
+                // A' -= v w^T + w v^T on this thread's column and slice
+                {
+                    const double vc = half ? v1 : v0, wc = half ? w1 : w0;
+                    for (int r = k + 1 + slice; r < n; r += RR_SL) {
+                        const double nv = A[r][cc] - (rr_get(v0, v1, r) * wc + rr_get(w0, w1, r) * vc);
+                        if (act) A[r][col] = nv;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < n; i += RR_NT) sh.d[i] = A[i][i];
+        if (tid == 0 && n >= 2) sh.e[n - 2] = A[n - 2][n - 1];
+        __syncthreads();
+        for (int t = tid; t < RR_MAX * RR_MAX; t += RR_NT) Z[t / RR_MAX][t % RR_MAX] = 0.0;
+        // negligible couplings split T into independent blocks
+        double *e2 = sh.sc[2];
+        for (int i = tid; i + 1 < n; i += RR_NT) {
+            double ei = sh.e[i];
+            if (fabs(ei) <= DBL_EPSILON * (fabs(sh.d[i]) + fabs(sh.d[i + 1]))) ei = 0.0;
+            sh.e[i] = ei;
+            e2[i] = ei * ei;
+        }
+        __syncthreads();
+        // d and e^2 in registers of every wave (element i in lane i / i - 64)
+        const double dl0 = lane < n ? sh.d[lane] : 0.0, dl1 = lane + 64 < n ? sh.d[lane + 64] : 0.0;
+        const double ql0 = lane + 1 < n ? e2[lane] : 0.0, ql1 = lane + 65 < n ? e2[lane + 64] : 0.0;
+
+        // ---- eigenvalues by multisection ---------------------------------------
+        double glo = INFINITY, ghi = -INFINITY;
+        for (int i = tid; i < n; i += RR_NT) {
+            const double r = (i > 0 ? fabs(sh.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(sh.e[i]) : 0.0);
+            glo = fmin(glo, sh.d[i] - r);
+            ghi = fmax(ghi, sh.d[i] + r);
+        }
+        double gl = -bmax(-glo);
+        double gu = bmax(ghi);
+        const double tnorm = fmax(fabs(gl), fabs(gu));
+        gl -= 2.0 * n * DBL_EPSILON * tnorm + 2.0 * DBL_MIN;
+        gu += 2.0 * n * DBL_EPSILON * tnorm + 2.0 * DBL_MIN;
+        const double tolabs = 2.0 * DBL_EPSILON * tnorm;
+        double *lo = sh.sc[0], *hi = sh.sc[1];
+        int *cnt = sh.u.cnt;
+        {
+            const double fr = (double)(tid + 1) / (double)(RR_NT + 1);
+            cnt[tid] = rr_sturm(dl0, dl1, ql0, ql1, n, fma(gu - gl, fr, gl));
+        }
+        __syncthreads();
+        if (tid < n) {
+            // a transition cnt[a] <= j < cnt[b] (virtual ends gl, gu) by bisection on
+            // the index; it holds even where rounding makes the counts non-monotone
+            int a = -1, b = RR_NT;
+            while (b - a > 1) {
+                const int mid = (a + b) >> 1;
+                if (cnt[mid] <= tid) a = mid;
+                else b = mid;
+            }
+            const double l = a < 0 ? gl : fma(gu - gl, (double)(a + 1) / (double)(RR_NT + 1), gl);
+            const double h = b >= RR_NT ? gu : fma(gu - gl, (double)(b + 1) / (double)(RR_NT + 1), gl);
+            if (!(l < h)) sh.flag = 1;
+            lo[tid] = l;
+            hi[tid] = h;
+        }
+        const int per = RR_NT / n;                  // >= 10 shifts per eigenvalue
+        const int myj = tid / per, mys = tid % per;
+        for (int pass = 0; pass < 64; ++pass) {
+            __syncthreads();
+            {   // every lane counts (readlane inside); only real shifts are kept
+                const int jj = myj < n ? myj : 0;
+                const double fr = (double)(mys + 1) / (double)(per + 1);
+                const int c = rr_sturm(dl0, dl1, ql0, ql1, n, fma(hi[jj] - lo[jj], fr, lo[jj]));
+                if (myj < n) cnt[tid] = c;
+            }
+            __syncthreads();
+            int active = 0;
+            if (tid < n) {
+                const double l0 = lo[tid], h0 = hi[tid];
+                double l = l0, h = h0;
+                for (int s = 0; s < per; ++s) {
+                    const double x = fma(h0 - l0, (double)(s + 1) / (double)(per + 1), l0);
+                    if (cnt[tid * per + s] <= tid) l = fmax(l, x);
+                    else h = fmin(h, x);
+                }
+                lo[tid] = l;
+                hi[tid] = h;
+                active = (h - l) > fmax(tolabs, 2.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)));
+            }
+            if (!__syncthreads_or(active)) break;
+        }
+        if (tid < n) sh.lam[tid] = 0.5 * (lo[tid] + hi[tid]);
+        __syncthreads();
+
+        // ---- eigenvectors of T: twisted factorisations, one per thread ------
+        if (wv < 2) {   // d, e, e^2 by readlane: the loops below are wave-uniform
+            const int j = tid, jc = j < n ? j : 0;   // jc: in-bounds column for idle lanes
+            const double lj = sh.lam[jc];
+            // top-down pivots delta+ kept in column j
+            double dp = rr_rl(dl0, 0) - lj;
+            if (dp == 0.0) dp = -DBL_MIN;
+            if (j < n) Z[0][j] = dp;
+            for (int i = 1; i < n; ++i) {
+                double x = (rr_get(dl0, dl1, i) - lj) - rr_get(ql0, ql1, i - 1) / dp;
+                if (x == 0.0) x = -DBL_MIN;
+                dp = x;
+                if (j < n) Z[i][j] = x;
+            }
+            // bottom-up pivots delta-, twist index of smallest |gamma|
+            double dm = rr_get(dl0, dl1, n - 1) - lj;
+            if (dm == 0.0) dm = -DBL_MIN;
+            double best = fabs(Z[n - 1][jc]);
+            int r = n - 1;
+            for (int i = n - 2; i >= 0; --i) {
+                const double di = rr_get(dl0, dl1, i) - lj;
+                dm = di - rr_get(ql0, ql1, i) / dm;
+                if (dm == 0.0) dm = -DBL_MIN;
+                const double g = fabs(Z[i][jc] + dm - di);
+                if (g < best) {
+                    best = g;
+                    r = i;
+                }
+            }
+            if (j < n) {
+                // ratios below the twist: z_{i+1} / z_i = -e_i / delta-_{i+1}
+                dm = rr_get(dl0, dl1, n - 1) - lj;
+                if (dm == 0.0) dm = -DBL_MIN;
+                for (int i = n - 2; i >= r; --i) {
+                    const double ei = sh.e[i];
+                    const double rho = -ei / dm;
+                    Z[i + 1][j] = rho;
+                    dm = (sh.d[i] - lj) + ei * rho;
+                    if (dm == 0.0) dm = -DBL_MIN;
+                }
+                Z[r][j] = 1.0;
+                for (int i = r; i + 1 < n; ++i) Z[i + 1][j] *= Z[i][j];
+                // above the twist: z_i = -(e_i / delta+_i) z_{i+1}
+                for (int i = r - 1; i >= 0; --i) Z[i][j] = -(sh.e[i] / Z[i][j]) * Z[i + 1][j];
+                double nn = 0.0;
+                for (int i = 0; i < n; ++i) nn += Z[i][j] * Z[i][j];
+                const double inv = 1.0 / sqrt(nn);
+                for (int i = 0; i < n; ++i) Z[i][j] *= inv;
+                if (!(nn > 0.0) || !isfinite(nn) || !(best * inv <= 1e-10 * tnorm)) sh.flag = 1;
+            }
+        }
+        {
+            // ---- clusters: modified Gram-Schmidt, two passes (one wave) ------
+            const int close = tid + 1 < n && sh.lam[tid + 1] - sh.lam[tid] < 1e-3 * tnorm;
+            if (__syncthreads_or(close) && wv == 0) {
+                int j0 = 0;
+                while (j0 < n) {
+                    int j1 = j0;
+                    while (j1 + 1 < n && sh.lam[j1 + 1] - sh.lam[j1] < 1e-3 * tnorm) ++j1;
+                    for (int a = j0 + 1; a <= j1; ++a) {
+                        for (int rep = 0; rep < 2; ++rep)
+                            for (int b = j0; b < a; ++b) {
+                                double s = 0.0;
+                                for (int i = lane; i < n; i += 64) s += Z[i][b] * Z[i][a];
+                                s = rr_wsum(s);
+                                for (int i = lane; i < n; i += 64) Z[i][a] -= s * Z[i][b];
+                            }
+                        double nn = 0.0;
+                        for (int i = lane; i < n; i += 64) nn += Z[i][a] * Z[i][a];
+                        nn = rr_wsum(nn);
+                        if (!(nn >= 1e-4)) {
+                            if (lane == 0) sh.flag = 1;
+                            nn = 1.0;
+                        }
+                        const double inv = 1.0 / sqrt(nn);
+                        for (int i = lane; i < n; i += 64) Z[i][a] *= inv;
+                    }
+                    j0 = j1 + 1;
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- back-transformation Z <- H_0 H_1 ... H_{n-3} Z --------------------
+        // thread (wave w < 12, lane l): column l + 64 (w & 1), row slice w >> 1
+        {
+            const int col = lane + 64 * (wv & 1), bs = wv >> 1;
+            for (int k = n - 3; k >= 0; --k) {
+                const double t = sh.tau[k];
+                if (t == 0.0) continue;
+                const double inv = sh.hinv[k];
+                const double r0 = lane == k + 1 ? 1.0 : (lane >= k + 2 && lane < n ? A[k][lane] * inv : 0.0);
+                const double r1 =
+                    lane + 64 == k + 1 ? 1.0 : (lane + 64 >= k + 2 && lane + 64 < n ? A[k][lane + 64] * inv : 0.0);
+                const bool act = col < n;
+                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
+                if (bs < RR_BSL) {   // wave-uniform
+                    double acc = 0.0;
+                    for (int r = k + 1 + bs; r < n; r += RR_BSL) acc = fma(rr_get(r0, r1, r), Z[r][cc], acc);
+                    if (col < RR_MAX) sh.u.part[bs][col] = act ? acc : 0.0;
+                }
+                __syncthreads();
+                if (bs < RR_BSL) {
+                    double wc = 0.0;
+                    for (int q = 0; q < RR_BSL; ++q) wc += sh.u.part[q][cc];
+                    wc *= t;
+                    for (int r = k + 1 + bs; r < n; r += RR_BSL) {
+                        const double nz = Z[r][cc] - rr_get(r0, r1, r) * wc;
+                        if (act) Z[r][col] = nz;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // ---- Newton-Schulz: S = Z^T Z into A, then Y = Z (3I - S) / 2 ---------
+        const int nt = (n + 15) / 16, kq = (n + 3) / 4;
+        for (int tile = wv; tile < nt * nt; tile += RR_NW) {
+            const int a0 = (tile / nt) * 16, b0 = (tile % nt) * 16;
+            rr_dx4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < kq; ++kk) {
+                const int i = kk * 4 + (lane >> 4);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Z[i][a0 + (lane & 15)], Z[i][b0 + (lane & 15)], acc, 0,
+                                                           0, 0);
+            }
+            for (int q = 0; q < 4; ++q) A[a0 + (lane >> 4) + 4 * q][b0 + (lane & 15)] = acc[q];
+        }
+        __syncthreads();
+        double defect = 0.0;
+        for (int t = tid; t < n * RR_MAX; t += RR_NT) {
+            const int a = t / RR_MAX, b = t % RR_MAX;
+            if (b < n) defect = fmax(defect, fabs(A[a][b] - (a == b ? 1.0 : 0.0)));
+        }
+        defect = bmax(defect);
+        if (!(defect <= 1e-8)) sh.flag = 1;
+        for (int t = tid; t < RR_MAX * RR_MAX; t += RR_NT) {
+            const int a = t / RR_MAX, b = t % RR_MAX;
+            A[a][b] = (a == b ? 1.5 : 0.0) - 0.5 * A[a][b];
+        }
+        __syncthreads();
+        if (!sh.flag) {
+            for (int tile = wv; tile < nt * nt; tile += RR_NW) {
+                const int i0 = (tile / nt) * 16, b0 = (tile % nt) * 16;
+                rr_dx4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int kk = 0; kk < kq; ++kk) {
+                    const int a = kk * 4 + (lane >> 4);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Z[i0 + (lane & 15)][a], A[a][b0 + (lane & 15)], acc,
+                                                               0, 0, 0);
+                }
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + (lane >> 4) + 4 * q, b = b0 + (lane & 15);
+                    if (i < n && b < n) Y[(int64_t)i * ldy + b] = acc[q];
+                }
+            }
+            for (int e = tid; e < n; e += RR_NT) theta[e] = sh.lam[e] / scale;
+            return;
+        }
+    }
+    // ---- fallback: cyclic Jacobi on G ------------------------------------------
+    if (tid == 0 && nfallback) atomicAdd(nfallback, 1);
+    rr_jacobi(sh, G, ldg, m, theta, Y, ldy, 40);
+}
+
+hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st)
+{
+    if (m <= 0 || m > RR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(RR_NT), 0, st, G, ldg, m, theta, Y, ldy, 40);
+    return hipGetLastError();
+}
+
+hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, int32_t *nfallback,
+                         hipStream_t st)
+{
+    if (m <= 0 || m > RR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(RR_NT), 0, st, G, ldg, m, theta, Y, ldy, nfallback);
+    return hipGetLastError();
+}
+
+}  // namespace cch
