@@ -110,6 +110,7 @@ hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStrea
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
                          int64_t ldw, double *Wp, hipStream_t st);
 int matvec_splits(int D);
+int64_t tn_part_doubles();
 hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
                      double *part, double *out, int64_t ldo, int transpose, hipStream_t st);
 hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
@@ -1630,7 +1631,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.T, 8 * ldv * BMAX) && A((void **)&b.T2, 8 * ldv * BMAX) &&
               A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
-              A((void **)&b.part, 8 * (size_t)nch * mmax * 16) && A((void **)&b.norms, 8 * (size_t)blk) &&
+              A((void **)&b.part, 8 * (size_t)std::max<int64_t>((int64_t)nch * mmax * 16, tn_part_doubles())) && A((void **)&b.norms, 8 * (size_t)blk) &&
               A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)kr) &&
               A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4) &&
               A((void **)&b.rrfb, 4);

@@ -185,67 +185,103 @@ hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, in
 }
 
 // ---------------------------------------------------------------------------
-// K9: out[a][c] = sum_i X[a][i] Y[c][i]  (a < na, c < nc <= 16)
-// grid (na, chunks); partials reduced in a fixed order.
+// K9: tall-skinny products out[a][c] = sum_i X[a][i] Y[c][i]
 // ---------------------------------------------------------------------------
-constexpr int TN_CHUNK = 1024;
+constexpr int TN_CHUNK = 1024;   // row chunk of the residual norms
 
-__global__ __launch_bounds__(256) void k_tn_partial(const double *__restrict__ X, int64_t ldx, int D,
-                                                    const double *__restrict__ Y, int64_t ldy, int nc,
-                                                    double *__restrict__ part)
+// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c], a < na,
+// c < nc <= 96, on FP64 MFMA: one wave per 16 x 16 output tile and slice of
+// the long dimension, 4 waves per workgroup share a split and sum their tiles
+// in LDS; the splits are summed in order by k_tn_sum (deterministic).
+// A lane loads 4 consecutive doubles of one X row and one Y row per 16-row
+// step (32-byte pieces, 128 contiguous bytes per row); the four MFMAs of a
+// step take k = 4 (l / 16) + j for lane l and j = 0..3 in both operands.
+typedef double tnx4 __attribute__((ext_vector_type(4)));
+constexpr int TN_SPLIT_MAX = 64, TN_LD = 96;
+
+int tn_splits(int D)
 {
-    const int a = blockIdx.x, ch = blockIdx.y;
-    const int i0 = ch * TN_CHUNK, i1 = min(D, i0 + TN_CHUNK);
-    double acc[16];
+    return std::max(1, std::min(TN_SPLIT_MAX, (D + 1023) / 1024));
+}
+
+int64_t tn_part_doubles()
+{
+    return (int64_t)TN_SPLIT_MAX * TN_LD * TN_LD;
+}
+
+__device__ __forceinline__ void tn_load4(const double *row, int k, int D, bool ok, double *v)
+{
+    if (ok && k + 3 < D) {
+        const double4 q = *reinterpret_cast<const double4 *>(row + k);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double x = X[(int64_t)a * ldx + i];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < nc) acc[c] = fma(x, Y[(int64_t)c * ldy + i], acc[c]);
-    }
-    __shared__ double red[4][16];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        double v = acc[c];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wv][c] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < nc) {
-        const int c = threadIdx.x;
-        part[((int64_t)ch * gridDim.x + a) * 16 + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        for (int j = 0; j < 4; ++j) v[j] = (ok && k + j < D) ? row[k + j] : 0.0;
     }
 }
 
-__global__ void k_tn_reduce(const double *__restrict__ part, int nchunks, int na, int nc,
-                            double *__restrict__ out, int64_t ldo, int transpose)
+__global__ __launch_bounds__(256) void k_tn_mfma(const double *__restrict__ X, int64_t ldx, int na,
+                                                 const double *__restrict__ Y, int64_t ldy, int nc, int D,
+                                                 int rows_per_split, double *__restrict__ part)
+{
+    __shared__ double red[4][16][17];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nct = (nc + 15) / 16;
+    const int a0 = (blockIdx.x / nct) * 16, c0 = (blockIdx.x % nct) * 16;
+    const int split = blockIdx.y;
+    const int kb = split * rows_per_split, ke = min(D, kb + rows_per_split);
+    const int ra = a0 + (lane & 15), rc = c0 + (lane & 15);
+    const bool oka = ra < na, okc = rc < nc;
+    const double *xr = X + (int64_t)(oka ? ra : 0) * ldx;
+    const double *yr = Y + (int64_t)(okc ? rc : 0) * ldy;
+    tnx4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = kb + 16 * wv; k0 < ke; k0 += 64) {
+        const int k = k0 + 4 * (lane >> 4);
+        double xv[4], yv[4];
+        tn_load4(xr, k, ke, oka, xv);
+        tn_load4(yr, k, ke, okc, yv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[j], yv[j], acc, 0, 0, 0);
+    }
+    // item v of lane l: row (a) l/16 + 4v, column (c) l%16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][(lane >> 4) + 4 * v][lane & 15] = acc[v];
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    if (a0 + r < na && c0 + c < nc)
+        part[((int64_t)split * TN_LD + a0 + r) * TN_LD + c0 + c] = red[0][r][c] + red[1][r][c] + red[2][r][c] +
+                                                                   red[3][r][c];
+}
+
+__global__ void k_tn_sum(const double *__restrict__ part, int nsplit, int na, int nc, double *__restrict__ out,
+                         int64_t ldo, int transpose)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= na * nc) return;
     const int a = t / nc, c = t % nc;
     double s = 0.0;
-    for (int ch = 0; ch < nchunks; ++ch) s += part[((int64_t)ch * na + a) * 16 + c];
+    for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * TN_LD + a) * TN_LD + c];
     if (transpose) out[(int64_t)c * ldo + a] = s;
     else out[(int64_t)a * ldo + c] = s;
 }
 
-// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c]
+// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c]; na, nc <= 96,
+// X and Y rows 32-byte aligned (leading dimensions multiples of 4)
 hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
                      double *part, double *out, int64_t ldo, int transpose, hipStream_t st)
 {
     if (na <= 0 || nc <= 0) return hipSuccess;
-    const int nch = (D + TN_CHUNK - 1) / TN_CHUNK;
-    for (int c0 = 0; c0 < nc; c0 += 16) {
-        const int cc = min(16, nc - c0);
-        hipLaunchKernelGGL(k_tn_partial, dim3(na, nch), dim3(256), 0, st, X, ldx, D, Y + (int64_t)c0 * ldy,
-                           ldy, cc, part);
-        double *o = transpose ? out + (int64_t)c0 * ldo : out + c0;
-        hipLaunchKernelGGL(k_tn_reduce, dim3((na * cc + 255) / 256), dim3(256), 0, st, part, nch, na, cc, o,
-                           ldo, transpose);
-    }
+    if (na > TN_LD || nc > TN_LD || (ldx & 3) || (ldy & 3) || ((uintptr_t)X & 31) || ((uintptr_t)Y & 31))
+        return hipErrorInvalidValue;
+    const int ns = tn_splits(D);
+    const int rps = ((D + ns - 1) / ns + 15) / 16 * 16;
+    const int tiles = ((na + 15) / 16) * ((nc + 15) / 16);
+    hipLaunchKernelGGL(k_tn_mfma, dim3(tiles, ns), dim3(256), 0, st, X, ldx, na, Y, ldy, nc, D, rps, part);
+    hipLaunchKernelGGL(k_tn_sum, dim3((na * nc + 255) / 256), dim3(256), 0, st, part, ns, na, nc, out, ldo,
+                       transpose);
     return hipGetLastError();
 }
 
