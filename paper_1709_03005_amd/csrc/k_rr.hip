@@ -31,6 +31,7 @@ typedef double rr_dx4 __attribute__((ext_vector_type(4)));
 
 constexpr int RR_SL = 8;     // row slices of the Householder products (x 2 column halves = 16 waves)
 constexpr int RR_BSL = 6;    // row slices of the back-transformation
+constexpr int RR_G = 512;    // shifts of the first multisection pass
 
 struct RRShared {
     double A[RR_MAX][RR_LD];
@@ -247,8 +248,7 @@ __device__ __forceinline__ int rr_sturm(double dl0, double dl1, double ql0, doub
     double pp = 1.0, p = rr_rl(dl0, 0) - x;
     p = (p == 0.0) ? -DBL_MIN : p;
     int c = p < 0.0;
-    for (int i = 1; i < n; ++i) {
-        const double di = rr_get(dl0, dl1, i), qi = rr_get(ql0, ql1, i - 1);
+    auto step = [&](int i, double di, double qi) {
         double q = fma(di - x, p, -(qi * pp));
         q = (q == 0.0) ? (p > 0.0 ? -DBL_MIN : DBL_MIN) : q;
         c += (q < 0.0) != (p < 0.0);
@@ -260,6 +260,13 @@ __device__ __forceinline__ int rr_sturm(double dl0, double dl1, double ql0, doub
             p *= f;
             pp *= f;
         }
+    };
+    const int n0 = n < 64 ? n : 64;
+    int i = 1;
+    for (; i < n0; ++i) step(i, rr_rl(dl0, i), rr_rl(ql0, i - 1));
+    if (i < n) {
+        step(i, rr_rl(dl1, 0), rr_rl(ql0, 63));
+        for (++i; i < n; ++i) step(i, rr_rl(dl1, i - 64), rr_rl(ql1, i - 65));
     }
     return c;
 }
@@ -271,7 +278,10 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
     __shared__ RRShared sh;
     double(*A)[RR_LD] = sh.A;
     double(*Z)[RR_LD] = sh.Z;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave index as a scalar: loops over row slices are then uniform, so
+    // readlane takes its index from an SGPR and the loops can be pipelined
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = m;
     int rp = 0;
     auto bmax = [&](double v) {
@@ -344,7 +354,11 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 const bool act = col < n && col >= k + 1;
                 const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
                 double acc = 0.0;
-                for (int r = k + 1 + slice; r < n; r += RR_SL) acc = fma(A[r][cc], rr_get(v0, v1, r), acc);
+                int r = k + 1 + slice;
+                #pragma unroll 4
+                for (; r < n && r < 64; r += RR_SL) acc = fma(A[r][cc], rr_rl(v0, r), acc);
+                #pragma unroll 4
+                for (; r < n; r += RR_SL) acc = fma(A[r][cc], rr_rl(v1, r - 64), acc);
                 if (col < RR_MAX) Z[slice][col] = act ? acc : 0.0;
                 __syncthreads();
                 double p0 = 0.0, p1 = 0.0;
@@ -359,8 +373,15 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 // A' -= v w^T + w v^T on this thread's column and slice
                 {
                     const double vc = half ? v1 : v0, wc = half ? w1 : w0;
-                    for (int r = k + 1 + slice; r < n; r += RR_SL) {
-                        const double nv = A[r][cc] - (rr_get(v0, v1, r) * wc + rr_get(w0, w1, r) * vc);
+                    int r = k + 1 + slice;
+                    #pragma unroll 4
+                    for (; r < n && r < 64; r += RR_SL) {
+                        const double nv = A[r][cc] - (rr_rl(v0, r) * wc + rr_rl(w0, r) * vc);
+                        if (act) A[r][col] = nv;
+                    }
+                    #pragma unroll 4
+                    for (; r < n; r += RR_SL) {
+                        const double nv = A[r][cc] - (rr_rl(v1, r - 64) * wc + rr_rl(w1, r - 64) * vc);
                         if (act) A[r][col] = nv;
                     }
                 }
@@ -399,31 +420,33 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
         const double tolabs = 2.0 * DBL_EPSILON * tnorm;
         double *lo = sh.sc[0], *hi = sh.sc[1];
         int *cnt = sh.u.cnt;
-        {
-            const double fr = (double)(tid + 1) / (double)(RR_NT + 1);
+        if (tid < RR_G) {   // RR_G shifts over the Gershgorin interval (whole waves)
+            const double fr = (double)(tid + 1) / (double)(RR_G + 1);
             cnt[tid] = rr_sturm(dl0, dl1, ql0, ql1, n, fma(gu - gl, fr, gl));
         }
         __syncthreads();
         if (tid < n) {
             // a transition cnt[a] <= j < cnt[b] (virtual ends gl, gu) by bisection on
             // the index; it holds even where rounding makes the counts non-monotone
-            int a = -1, b = RR_NT;
+            int a = -1, b = RR_G;
             while (b - a > 1) {
                 const int mid = (a + b) >> 1;
                 if (cnt[mid] <= tid) a = mid;
                 else b = mid;
             }
-            const double l = a < 0 ? gl : fma(gu - gl, (double)(a + 1) / (double)(RR_NT + 1), gl);
-            const double h = b >= RR_NT ? gu : fma(gu - gl, (double)(b + 1) / (double)(RR_NT + 1), gl);
+            const double l = a < 0 ? gl : fma(gu - gl, (double)(a + 1) / (double)(RR_G + 1), gl);
+            const double h = b >= RR_G ? gu : fma(gu - gl, (double)(b + 1) / (double)(RR_G + 1), gl);
             if (!(l < h)) sh.flag = 1;
             lo[tid] = l;
             hi[tid] = h;
         }
-        const int per = RR_NT / n;                  // >= 10 shifts per eigenvalue
+        // the counts are VALU-bound: few shifts per eigenvalue (2..8, at most 512
+        // lanes) cost less in total than many, at the price of more passes
+        const int per = max(2, min(8, RR_G / n));
         const int myj = tid / per, mys = tid % per;
-        for (int pass = 0; pass < 64; ++pass) {
+        for (int pass = 0; pass < 96; ++pass) {
             __syncthreads();
-            {   // every lane counts (readlane inside); only real shifts are kept
+            if (wv * 64 < n * per) {   // whole waves; every lane counts (readlane inside)
                 const int jj = myj < n ? myj : 0;
                 const double fr = (double)(mys + 1) / (double)(per + 1);
                 const int c = rr_sturm(dl0, dl1, ql0, ql1, n, fma(hi[jj] - lo[jj], fr, lo[jj]));
@@ -456,26 +479,37 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
             double dp = rr_rl(dl0, 0) - lj;
             if (dp == 0.0) dp = -DBL_MIN;
             if (j < n) Z[0][j] = dp;
-            for (int i = 1; i < n; ++i) {
-                double x = (rr_get(dl0, dl1, i) - lj) - rr_get(ql0, ql1, i - 1) / dp;
+            auto fwd = [&](int i, double di, double qi) {
+                double x = (di - lj) - qi / dp;
                 if (x == 0.0) x = -DBL_MIN;
                 dp = x;
                 if (j < n) Z[i][j] = x;
+            };
+            {
+                int i = 1;
+                for (; i < n && i < 64; ++i) fwd(i, rr_rl(dl0, i), rr_rl(ql0, i - 1));
+                if (i < n) fwd(i, rr_rl(dl1, 0), rr_rl(ql0, 63));
+                for (++i; i < n; ++i) fwd(i, rr_rl(dl1, i - 64), rr_rl(ql1, i - 65));
             }
             // bottom-up pivots delta-, twist index of smallest |gamma|
             double dm = rr_get(dl0, dl1, n - 1) - lj;
             if (dm == 0.0) dm = -DBL_MIN;
             double best = fabs(Z[n - 1][jc]);
             int r = n - 1;
-            for (int i = n - 2; i >= 0; --i) {
-                const double di = rr_get(dl0, dl1, i) - lj;
-                dm = di - rr_get(ql0, ql1, i) / dm;
+            auto bwd = [&](int i, double dv, double qi) {
+                const double di = dv - lj;
+                dm = di - qi / dm;
                 if (dm == 0.0) dm = -DBL_MIN;
                 const double g = fabs(Z[i][jc] + dm - di);
                 if (g < best) {
                     best = g;
                     r = i;
                 }
+            };
+            {
+                int i = n - 2;
+                for (; i >= 64; --i) bwd(i, rr_rl(dl1, i - 64), rr_rl(ql1, i - 64));
+                for (; i >= 0; --i) bwd(i, rr_rl(dl0, i), rr_rl(ql0, i));
             }
             if (j < n) {
                 // ratios below the twist: z_{i+1} / z_i = -e_i / delta-_{i+1}
@@ -546,7 +580,11 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
                 if (bs < RR_BSL) {   // wave-uniform
                     double acc = 0.0;
-                    for (int r = k + 1 + bs; r < n; r += RR_BSL) acc = fma(rr_get(r0, r1, r), Z[r][cc], acc);
+                    int r = k + 1 + bs;
+                    #pragma unroll 4
+                    for (; r < n && r < 64; r += RR_BSL) acc = fma(rr_rl(r0, r), Z[r][cc], acc);
+                    #pragma unroll 4
+                    for (; r < n; r += RR_BSL) acc = fma(rr_rl(r1, r - 64), Z[r][cc], acc);
                     if (col < RR_MAX) sh.u.part[bs][col] = act ? acc : 0.0;
                 }
                 __syncthreads();
@@ -554,8 +592,15 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                     double wc = 0.0;
                     for (int q = 0; q < RR_BSL; ++q) wc += sh.u.part[q][cc];
                     wc *= t;
-                    for (int r = k + 1 + bs; r < n; r += RR_BSL) {
-                        const double nz = Z[r][cc] - rr_get(r0, r1, r) * wc;
+                    int r = k + 1 + bs;
+                    #pragma unroll 4
+                    for (; r < n && r < 64; r += RR_BSL) {
+                        const double nz = Z[r][cc] - rr_rl(r0, r) * wc;
+                        if (act) Z[r][col] = nz;
+                    }
+                    #pragma unroll 4
+                    for (; r < n; r += RR_BSL) {
+                        const double nz = Z[r][cc] - rr_rl(r1, r - 64) * wc;
                         if (act) Z[r][col] = nz;
                     }
                 }
