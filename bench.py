@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Hamiltonian elements/s + Davidson time-to-eigenpairs, plain vs chosen form"
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# FP64 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (one FMA per lane per cycle) x 2.4 GHz = 78.6 TFLOP/s
+FP64_VALU_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
     # name: (generator, k, tol, CPU-baseline mode)
@@ -253,6 +256,7 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
     builds, phases, dav_s, dav_it, mv_ms, mv_n, resid, rcs = [], [], [], [], [], [], [], []
+    rr_ms, rr_fl, rr_n, rr_fb = [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ev, info, rc = step()
@@ -263,6 +267,10 @@ def main():
         dav_it.append(info.iterations)
         mv_ms.append(info.matvec_ms)
         mv_n.append(info.matvec_launches)
+        rr_ms.append(info.rr_ms)
+        rr_fl.append(info.rr_flops)
+        rr_n.append(info.rr_calls)
+        rr_fb.append(info.rr_fallbacks)
         resid.append(info.max_residual)
         rcs.append(rc)
     torch.cuda.synchronize()
@@ -292,6 +300,13 @@ def main():
         "relayout": {"bound": "hbm", "achieved": work["relayout_bytes"] / max(phase_ms["relayout"], 1e-9) / 1e6,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "total_ms_per_step": phase_ms["relayout"]},
     }
+    rr_avg_ms = float(np.sum(rr_ms) / max(np.sum(rr_n), 1))
+    kernels["rayleigh_ritz"] = {
+        "bound": "alu", "achieved": float(np.sum(rr_fl)) / max(float(np.sum(rr_ms)) * 1e-3, 1e-12) / 1e12,
+        "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "avg_ms": rr_avg_ms,
+        "launches_per_step": float(np.mean(rr_n)), "total_ms_per_step": float(np.mean(rr_ms)),
+        "fallbacks_per_step": float(np.mean(rr_fb)),
+        "note": "one workgroup per solve (m <= 96): latency-bound; flops = (10/3) m^3 per solve"}
     for v in kernels.values():
         v["frac"] = v["achieved"] / v["peak"]
     dom = max(kernels, key=lambda n: kernels[n]["total_ms_per_step"])

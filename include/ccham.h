@@ -106,6 +106,10 @@ typedef struct {
     double matvec_ms;       /* device time of the H V launches (HIP events) */
     int32_t matvec_launches;
     int32_t rr_fallbacks;   /* Rayleigh-Ritz solves rerun by cyclic Jacobi */
+    double rr_ms;           /* device time of the Rayleigh-Ritz launches (HIP events) */
+    double rr_flops;        /* sum over those solves of (10/3) m^3 */
+    int32_t rr_calls;       /* Rayleigh-Ritz solves */
+    int32_t reserved;
 } cch_dav_info;
 
 /* Library version string (static storage). */

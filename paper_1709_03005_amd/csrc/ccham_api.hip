@@ -217,7 +217,7 @@ struct cch_ctx {
     std::vector<PairPlan> pp;
     std::vector<LtPlan> lt;
     hipEvent_t ev[8] = {};
-    hipEvent_t mv0 = nullptr, mv1 = nullptr;
+    hipEvent_t mv0 = nullptr, mv1 = nullptr, rr0 = nullptr, rr1 = nullptr;
     int64_t relayout_elems = 0;
     bool timed = false;     // the phase events belong to the last build
     cch_mlp *mlp = nullptr; // network used by CCH_PRECOND_MLP
@@ -316,7 +316,8 @@ cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream)
             return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
         }
     }
-    if (hipEventCreate(&c->mv0) != hipSuccess || hipEventCreate(&c->mv1) != hipSuccess) {
+    if (hipEventCreate(&c->mv0) != hipSuccess || hipEventCreate(&c->mv1) != hipSuccess ||
+        hipEventCreate(&c->rr0) != hipSuccess || hipEventCreate(&c->rr1) != hipSuccess) {
         delete c;
         return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
     }
@@ -336,6 +337,8 @@ cch_status cch_destroy(cch_ctx *c)
         for (auto &ev : c->ev) (void)hipEventDestroy(ev);
     if (c->mv0) (void)hipEventDestroy(c->mv0);
     if (c->mv1) (void)hipEventDestroy(c->mv1);
+    if (c->rr0) (void)hipEventDestroy(c->rr0);
+    if (c->rr1) (void)hipEventDestroy(c->rr1);
     delete c;
     return CCH_OK;
 }
@@ -1664,7 +1667,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     DCK(launch_unit_vectors(b.T, ldv, D, b.idx, nb, st));
 
     int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0, fallbacks = 0;
-    double mv_ms = 0.0, maxres = 0.0, best_res = 1e300;
+    double mv_ms = 0.0, maxres = 0.0, best_res = 1e300, rr_ms = 0.0, rr_flops = 0.0;
+    int rr_calls = 0;
     bool use_mlp = want_mlp;
     if (want_mlp) {
         DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
@@ -1706,7 +1710,11 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
                       mmax, 0, st));
         DCK(launch_sym_fill(b.G, mmax, m, m + added, st));
         m += added;
+        DCK(hipEventRecord(c->rr0, st));
         DCK(launch_rr_eig(b.G, mmax, m, b.theta, b.Y, mmax, b.rrfb, st));
+        DCK(hipEventRecord(c->rr1, st));
+        ++rr_calls;
+        rr_flops += (10.0 / 3.0) * (double)m * m * m;   // tridiagonalisation + back-transformation
         // rotate V and W to the Ritz basis; G becomes diag(theta)
         DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.V2, ldv, st));
         DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.W2, ldv, st));
@@ -1721,6 +1729,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             float ms = 0.0f;
             DCK(hipEventElapsedTime(&ms, c->mv0, c->mv1));
             mv_ms += ms;
+            DCK(hipEventElapsedTime(&ms, c->rr0, c->rr1));
+            rr_ms += ms;
         }
         std::vector<int32_t> un;
         maxres = 0.0;
@@ -1801,6 +1811,10 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->matvec_ms = mv_ms;
         info->matvec_launches = mv_launches;
         info->rr_fallbacks = rr_fb;
+        info->rr_ms = rr_ms;
+        info->rr_flops = rr_flops;
+        info->rr_calls = rr_calls;
+        info->reserved = 0;
     }
     if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
     return rc;

@@ -43,6 +43,7 @@ struct RRShared {
         int cnt[RR_NT];                  // Sturm counts; Jacobi pairing tables
         double part[RR_BSL][RR_MAX];     // back-transformation partial products
     } u;
+    unsigned long long open_mask[2];   // eigenvalues still bracketed (multisection)
     int flag, nrot;
 };
 static_assert(sizeof(RRShared) <= 160 * 1024, "LDS budget");
@@ -328,6 +329,22 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
             for (int k = 0; k + 2 < n; ++k) {
                 const double x0 = lane < n ? A[k][lane] : 0.0;
                 const double x1 = lane + 64 < n ? A[k][lane + 64] : 0.0;
+                // row k+1 too, before the first barrier: other waves update it afterwards
+                const double y0 = lane < n ? A[k + 1][lane] : 0.0;
+                const double y1 = lane + 64 < n ? A[k + 1][lane + 64] : 0.0;
+                // partial S_col = sum over this slice's rows r >= k+2 of A[r][col] x_r (into
+                // Z); it needs only x, so it overlaps the scalar chain below. Loops that read
+                // lanes run with the whole wave active: a lane that sits out a branch may not
+                // hold the value another lane reads.
+                const bool act = col < n && col >= k + 1;
+                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
+                {
+                    double acc = 0.0;
+                    int r = k + 2 + slice;
+                    for (; r < n && r < 64; r += RR_SL) acc = fma(A[r][cc], rr_rl(x0, r), acc);
+                    for (; r < n; r += RR_SL) acc = fma(A[r][cc], rr_rl(x1, r - 64), acc);
+                    if (col < RR_MAX) Z[slice][col] = act ? acc : 0.0;
+                }
                 const double sig =
                     rr_wsum((lane >= k + 2 ? x0 * x0 : 0.0) + (lane + 64 >= k + 2 ? x1 * x1 : 0.0));
                 const double alpha = rr_get(x0, x1, k + 1);
@@ -336,6 +353,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                         sh.tau[k] = 0.0;
                         sh.e[k] = alpha;
                     }
+                    __syncthreads();   // Z is rewritten by the next step
                     continue;
                 }
                 const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
@@ -348,26 +366,15 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 }
                 const double v0 = lane == k + 1 ? 1.0 : (lane >= k + 2 ? x0 * inv : 0.0);
                 const double v1 = lane + 64 == k + 1 ? 1.0 : (lane + 64 >= k + 2 ? x1 * inv : 0.0);
-                // partial p_col = sum over this slice's rows of A[r][col] v_r (into Z).
-                // Loops that read lanes run with the whole wave active: a lane that
-                // sits out a branch may not hold the value another lane reads.
-                const bool act = col < n && col >= k + 1;
-                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
-                double acc = 0.0;
-                int r = k + 1 + slice;
-                #pragma unroll 4
-                for (; r < n && r < 64; r += RR_SL) acc = fma(A[r][cc], rr_rl(v0, r), acc);
-                #pragma unroll 4
-                for (; r < n; r += RR_SL) acc = fma(A[r][cc], rr_rl(v1, r - 64), acc);
-                if (col < RR_MAX) Z[slice][col] = act ? acc : 0.0;
                 __syncthreads();
+                // p_c = t (A[k+1][c] + inv S_c): v_{k+1} = 1, v_r = x_r inv below
                 double p0 = 0.0, p1 = 0.0;
                 for (int q = 0; q < RR_SL; ++q) {
                     p0 += Z[q][lane];
                     if (lane + 64 < RR_MAX) p1 += Z[q][lane + 64];
                 }
-                p0 *= t;
-                p1 *= t;
+                p0 = lane < n ? t * fma(inv, p0, y0) : 0.0;
+                p1 = lane + 64 < n ? t * fma(inv, p1, y1) : 0.0;
                 const double K = 0.5 * t * rr_wsum(p0 * v0 + p1 * v1);
                 const double w0 = p0 - K * v0, w1 = p1 - K * v1;
                 // A' -= v w^T + w v^T on this thread's column and slice
@@ -439,34 +446,111 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
             if (!(l < h)) sh.flag = 1;
             lo[tid] = l;
             hi[tid] = h;
+            // start of the Laguerre iteration: the idx-th of the k eigenvalues in
+            // the interval starts at fraction (idx + 1/2) / k of it
+            const int cl = a < 0 ? 0 : cnt[a], ch = b >= RR_G ? n : cnt[b];
+            sh.sc[3][tid] = (tid - cl + 0.5) / (double)max(ch - cl, 1);
         }
-        // the counts are VALU-bound: few shifts per eigenvalue (2..8, at most 512
-        // lanes) cost less in total than many, at the price of more passes
-        const int per = max(2, min(8, RR_G / n));
-        const int myj = tid / per, mys = tid % per;
+        __syncthreads();
+        // Laguerre's method on det(T - xI) from the middle of each isolating
+        // interval (waves 0-1, one eigenvalue per lane): G = P'/P and
+        // H = G^2 - P''/P from the pivot recurrences q_i = d_i - x - e_{i-1}^2 / q_{i-1}
+        // and their first two derivatives; cubic convergence at simple roots.
+        // A step leaving the interval, a non-finite value or no convergence in
+        // 16 steps, or a result whose Sturm counts do not bracket index j,
+        // leaves the interval to the multisection below.
+        if (wv < 2) {
+            const int j = tid, jc = j < n ? j : 0;
+            const double l0 = lo[jc], h0 = hi[jc], nd = (double)n;
+            double x = fma(h0 - l0, fmin(fmax(sh.sc[3][jc], 0.0), 1.0), l0);
+            bool conv = j >= n, ok = false;
+            for (int it = 0; it < 16; ++it) {
+                if (__all(conv)) break;
+                double q = rr_rl(dl0, 0) - x;
+                q = (q == 0.0) ? -DBL_MIN : q;
+                double qp = -1.0, qpp = 0.0, rq = 1.0 / q;
+                double Gs = qp * rq, Hs = Gs * Gs;
+                auto lag = [&](double di, double e2p) {
+                    const double qn = (di - x) - e2p * rq;
+                    const double qpn = -1.0 + e2p * qp * rq * rq;
+                    const double qppn = e2p * (qpp - 2.0 * qp * qp * rq) * rq * rq;
+                    q = (qn == 0.0) ? -DBL_MIN : qn;
+                    qp = qpn;
+                    qpp = qppn;
+                    rq = 1.0 / q;
+                    const double t = qp * rq;
+                    Gs += t;
+                    Hs += t * t - qpp * rq;
+                };
+                {
+                    int i = 1;
+                    for (; i < n && i < 64; ++i) lag(rr_rl(dl0, i), rr_rl(ql0, i - 1));
+                    if (i < n) lag(rr_rl(dl1, 0), rr_rl(ql0, 63));
+                    for (++i; i < n; ++i) lag(rr_rl(dl1, i - 64), rr_rl(ql1, i - 65));
+                }
+                if (!conv) {
+                    const double sq = sqrt(fmax((nd - 1.0) * (nd * Hs - Gs * Gs), 0.0));
+                    const double den = fabs(Gs + sq) >= fabs(Gs - sq) ? Gs + sq : Gs - sq;
+                    const double a = nd / den;
+                    const double xn = x - a;
+                    if (!(den != 0.0) || !isfinite(xn) || !(xn >= l0 && xn <= h0)) {
+                        conv = true;
+                    } else {
+                        x = xn;
+                        if (fabs(a) <= 2.0 * DBL_EPSILON * tnorm) {
+                            conv = true;
+                            ok = true;
+                        }
+                    }
+                }
+            }
+            const double dl = 4.0 * DBL_EPSILON * tnorm;
+            const int c1 = rr_sturm(dl0, dl1, ql0, ql1, n, x - dl);
+            const int c2 = rr_sturm(dl0, dl1, ql0, ql1, n, x + dl);
+            if (j < n && ok && c1 <= j && j < c2) {
+                lo[j] = x;
+                hi[j] = x;
+            }
+        }
+        // multisection for what Laguerre left: the open eigenvalues (ballot of
+        // waves 0-1) share the RR_G shifts, up to 64 each
+        auto open = [&](int j) {
+            return (hi[j] - lo[j]) > fmax(tolabs, 2.0 * DBL_EPSILON * fmax(fabs(lo[j]), fabs(hi[j])));
+        };
         for (int pass = 0; pass < 96; ++pass) {
             __syncthreads();
-            if (wv * 64 < n * per) {   // whole waves; every lane counts (readlane inside)
-                const int jj = myj < n ? myj : 0;
-                const double fr = (double)(mys + 1) / (double)(per + 1);
-                const int c = rr_sturm(dl0, dl1, ql0, ql1, n, fma(hi[jj] - lo[jj], fr, lo[jj]));
-                if (myj < n) cnt[tid] = c;
+            if (wv < 2) {
+                const unsigned long long mk = __ballot(tid < n && open(tid));
+                if (lane == 0) sh.open_mask[wv] = mk;
             }
             __syncthreads();
-            int active = 0;
-            if (tid < n) {
+            const unsigned long long m0 = sh.open_mask[0], m1 = sh.open_mask[1];
+            const int c0 = __popcll(m0), na = c0 + __popcll(m1);
+            if (na == 0) break;
+            const int per = max(2, min(64, RR_G / na));
+            const int slot = tid / per, sft = tid % per;
+            if (slot < na) {
+                // eigenvalue of this slot: the slot-th set bit of (m0, m1)
+                unsigned long long mk = slot < c0 ? m0 : m1;
+                for (int q = slot < c0 ? slot : slot - c0; q > 0; --q) mk &= mk - 1;
+                const int j = __builtin_ctzll(mk) + (slot < c0 ? 0 : 64);
+                const double fr = (double)(sft + 1) / (double)(per + 1);
+                cnt[tid] = rr_sturm(dl0, dl1, ql0, ql1, n, fma(hi[j] - lo[j], fr, lo[j]));
+            }
+            __syncthreads();
+            if (tid < n && ((tid < 64 ? m0 >> tid : m1 >> (tid - 64)) & 1ull)) {
+                const int myslot = tid < 64 ? __popcll(m0 & ((1ull << tid) - 1ull))
+                                            : c0 + __popcll(m1 & ((1ull << (tid - 64)) - 1ull));
                 const double l0 = lo[tid], h0 = hi[tid];
                 double l = l0, h = h0;
-                for (int s = 0; s < per; ++s) {
-                    const double x = fma(h0 - l0, (double)(s + 1) / (double)(per + 1), l0);
-                    if (cnt[tid * per + s] <= tid) l = fmax(l, x);
+                for (int q = 0; q < per; ++q) {
+                    const double x = fma(h0 - l0, (double)(q + 1) / (double)(per + 1), l0);
+                    if (cnt[myslot * per + q] <= tid) l = fmax(l, x);
                     else h = fmin(h, x);
                 }
                 lo[tid] = l;
                 hi[tid] = h;
-                active = (h - l) > fmax(tolabs, 2.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)));
             }
-            if (!__syncthreads_or(active)) break;
         }
         if (tid < n) sh.lam[tid] = 0.5 * (lo[tid] + hi[tid]);
         __syncthreads();
