@@ -34,6 +34,34 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # (one FMA per lane per cycle) x 2.4 GHz = 78.6 TFLOP/s
 FP64_VALU_PEAK_TFLOPS = 78.6
 
+# HBM bytes per launch of the medium workload's kernels: rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes (KiB per dispatch, averaged over one step), scaled by
+# what the same counters read for a plain 512 MiB device copy (bench.py
+# --workload copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them).
+# Keyed by the source file of the kernel and its hash when counted: a kernel
+# changed since reports null.
+COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+TRAFFIC = {
+    # name: (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    "rayleigh_ritz": ("k_rr.hip", "0e38bc910ded4b1f", 40.766, 27.408),
+    "matvec": ("k_davidson.hip", "ffa94cff9d5d7a67", 252081.06, 32000.0),
+    "expansion_gemm": ("k_gemm.hip", "f888765de180c807", 40278.58, 3533.66),
+    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22068.06, 98765.28),
+}
+
+
+def traffic_bytes(kernel, workload):
+    """Counter-measured HBM bytes per launch, or None."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None or workload != "medium":
+        return None
+    src = os.path.join(ROOT, "paper_1709_03005_amd", "csrc", t[0])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != t[1]:
+        return None
+    return 1024.0 * (t[2] * COUNTER_SCALE["FETCH_SIZE"] + t[3] * COUNTER_SCALE["WRITE_SIZE"])
+
+
 WORKLOADS = {
     # name: (generator, k, tol, CPU-baseline mode)
     "medium": ("medium", 10, 1e-8, "rows"),
@@ -193,7 +221,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["batch", "copy"],
+                    help="copy: three plain 512 MiB device copies, the calibration run for HBM counters")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64",
@@ -215,6 +244,15 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "copy":
+        n = 64 << 20
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_per_copy": n * 8, "copies": 3}))
+        return None
     gen, k, tol, cpu_mode = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     inst = synth.CONFIGS[gen]()
@@ -231,7 +269,10 @@ def main():
         prec, slices = cc.CCH_PREC_SPLIT_BF16, int(args.precision[5:])
     else:
         raise SystemExit(f"unknown --precision {args.precision}")
-    ctx = cc.from_instance(inst, device=0, stream=stream, plan=False)
+    t_up = time.perf_counter()
+    ctx = cc.from_instance(inst, device=0, stream=stream, plan=False)   # inputs host -> HBM
+    ctx.sync()
+    upload_s = time.perf_counter() - t_up
     t = time.perf_counter()
     ctx.plan(precision=prec, split_slices=slices)
     ctx.sync()
@@ -311,8 +352,10 @@ def main():
         v["frac"] = v["achieved"] / v["peak"]
     dom = max(kernels, key=lambda n: kernels[n]["total_ms_per_step"])
     roof = dict(kernels[dom])
+    for name, v in kernels.items():
+        v["traffic"] = traffic_bytes(name, args.workload)
     roof = {"kernel": dom, "bound": roof["bound"], "achieved": roof["achieved"], "peak": roof["peak"],
-            "unit": roof["unit"], "frac": roof["frac"], "traffic": None}
+            "unit": roof["unit"], "frac": roof["frac"], "traffic": kernels[dom]["traffic"]}
 
     out = {
         "metric": METRIC,
@@ -342,6 +385,9 @@ def main():
         "kernels": kernels,
         "work": work,
         "plan_s": plan_s,
+        "upload_s": upload_s,
+        # whole job with the host -> HBM upload of the inputs counted once (not `value`)
+        "pcie_inclusive_elements_per_s": lower / (upload_s + plan_s + ms_step * 1e-3),
         "roofline": roof,
     }
     if prec != cc.CCH_PREC_FP64:

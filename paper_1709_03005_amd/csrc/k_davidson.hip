@@ -201,7 +201,7 @@ constexpr int TN_SPLIT_MAX = 64, TN_LD = 96;
 
 int tn_splits(int D)
 {
-    return std::max(1, std::min(TN_SPLIT_MAX, (D + 1023) / 1024));
+    return std::max(1, std::min(TN_SPLIT_MAX, (D + 255) / 256));
 }
 
 int64_t tn_part_doubles()
