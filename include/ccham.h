@@ -80,7 +80,15 @@ typedef struct {
     int32_t split_slices;   /* slices per operand for CCH_PREC_SPLIT_BF16 (2..8) */
     int32_t autotune;       /* 1: time candidate tile shapes on the device */
     int32_t reserved;
-    int64_t max_device_bytes; /* 0: no limit; else fail with CCH_E_OOM above it */
+    int64_t max_device_bytes; /* 0: no limit. Else the plan's device memory stays
+                                 within it: in FP64 mode the integral rows of the
+                                 expansion product are laid out and multiplied in
+                                 passes over the continuum orbitals, as many per
+                                 pass as fit (same result, bit for bit; the
+                                 relayout time then counts in phase 3);
+                                 CCH_E_OOM when the rest alone, or one orbital
+                                 per pass, does not fit, or in FP32 / split-BF16
+                                 mode when the whole plan does not */
 } cch_plan_opts;
 
 typedef struct {
@@ -242,6 +250,12 @@ cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
  * (read + write), out[5] class-4 outputs, out[6] L2 lower-triangle
  * elements, out[7] number of symmetry pairs. */
 cch_status cch_work_counts(const cch_ctx *ctx, double *out8);
+
+/* Device memory held by the planned context (bytes) and the number of passes
+ * the expansion product takes under cch_plan_opts.max_device_bytes (1 when
+ * unsplit). Contexts planned in several passes cannot join a batch
+ * (cch_batch_create returns CCH_E_STATE). Either pointer may be NULL. */
+cch_status cch_plan_info(cch_ctx *ctx, int64_t *device_bytes, int32_t *expansion_passes);
 
 /* ------------------------------------------------------------------------
  * Learned Davidson preconditioner (not in the paper): a 3-layer perceptron

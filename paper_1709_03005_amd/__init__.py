@@ -48,7 +48,7 @@ EXPORTS = [
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
     "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
-    "cch_davidson_set_mlp", "cch_subspace_eig",
+    "cch_davidson_set_mlp", "cch_subspace_eig", "cch_plan_info",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -120,6 +120,7 @@ _SIG = {
     "cch_mlp_features": (i32, [P, C.c_double, P, i32]),
     "cch_davidson_set_mlp": (i32, [P, P]),
     "cch_subspace_eig": (i32, [P, P, i32, i32, P, P, i32, i32, C.POINTER(i32), i32]),
+    "cch_plan_info": (i32, [P, C.POINTER(i64), C.POINTER(i32)]),
 }
 for _n, (_r, _a) in _SIG.items():
     _f = getattr(lib, _n)
@@ -276,6 +277,13 @@ class Context:
         keys = ["lower_elements", "gemm_flops", "target_pairs", "l2_target_pairs", "relayout_bytes",
                 "class4_outputs", "l2_lower_elements", "sym_pairs"]
         return dict(zip(keys, out.tolist()))
+
+    def plan_info(self):
+        """(device bytes held, expansion passes)."""
+        b = C.c_int64()
+        n = C.c_int32()
+        self._ck(lib.cch_plan_info(self.h, C.byref(b), C.byref(n)))
+        return b.value, n.value
 
     def subspace_eig(self, G, method=CCH_EIG_AUTO):
         """(theta ascending, Y with eigenvectors in columns, fell_back) for a

@@ -174,6 +174,7 @@ struct PairPlan {
     int64_t *d_count = nullptr, *d_start = nullptr, *d_cursor = nullptr, *d_sorted = nullptr, *d_tmp = nullptr,
             *d_d0 = nullptr;
     double *d_B = nullptr;   // integral rows laid out for this pair's expansion
+    int jj_chunk = 0;        // continuum orbitals (rows j) per expansion pass; < nca: passes share d_B
     // reduced-precision operands of the expansion product
     float *d_At32 = nullptr, *d_B32 = nullptr;
     double *d_sigA = nullptr, *d_sigB = nullptr;
@@ -219,6 +220,8 @@ struct cch_ctx {
     hipEvent_t ev[8] = {};
     hipEvent_t mv0 = nullptr, mv1 = nullptr, rr0 = nullptr, rr1 = nullptr;
     int64_t relayout_elems = 0;
+    int expansion_passes = 1;   // > 1: the budget split the expansion into column passes
+    bool b_shared = false;      // all pairs use one integral-row buffer, laid out just before each product
     bool timed = false;     // the phase events belong to the last build
     cch_mlp *mlp = nullptr; // network used by CCH_PRECOND_MLP
     bool have_events = false;
@@ -620,7 +623,11 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
             TRY(dalloc(c, &p.d_sorted, p.pr.n));
             TRY(dalloc(c, &p.d_tmp, p.pr.n));
             TRY(dalloc(c, &p.d_d0, sa.M));
-            TRY(dalloc(c, &p.d_B, (size_t)2 * p.n_slot * sa.nc * sb.nc));
+            // FP64 integral rows are placed after everything else (below), where a
+            // memory budget may split them into passes; the reduced-precision
+            // operands are derived from a full copy
+            if (c->opts.precision != CCH_PREC_FP64) TRY(dalloc(c, &p.d_B, (size_t)2 * p.n_slot * sa.nc * sb.nc));
+            p.jj_chunk = sa.nc;
             maxB += (int64_t)2 * p.n_slot * sa.nc * sb.nc;
             {
                 const size_t K = (size_t)2 * p.n_slot, N = (size_t)sa.nc * sb.nc;
@@ -650,6 +657,35 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     c->relayout_elems = maxB;
     TRY(dalloc(c, &c->d_H, (size_t)c->D * c->ld));
     TRY(dalloc(c, &c->d_diag, c->D));
+    if (c->opts.precision == CCH_PREC_FP64) {
+        const int64_t budget = c->opts.max_device_bytes;
+        if (budget == 0 || c->bytes + 8 * maxB <= budget) {
+            for (auto &p : c->pp)   // one pass: every pair keeps its integral rows
+                TRY(dalloc(c, &p.d_B, (size_t)2 * p.n_slot * c->syms[p.a].nc * c->syms[p.b].nc));
+        } else {
+            // the budget left after everything else holds one shared buffer; each pair
+            // relays and multiplies as many continuum rows j per pass as fit
+            const int64_t left = (budget - c->bytes) / 8;
+            int64_t need = 0;
+            c->expansion_passes = 1;
+            for (auto &p : c->pp) {
+                const SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+                const int64_t row = (int64_t)2 * p.n_slot * sb.nc;   // one j of B
+                if (row == 0 || sa.nc == 0) continue;
+                const int64_t fit = std::min<int64_t>(sa.nc, left / row);
+                if (fit < 1)
+                    return fail(c, CCH_E_OOM, "device budget of %lld bytes too small for one continuum orbital "
+                                              "of the expansion", (long long)budget);
+                p.jj_chunk = (int)fit;
+                need = std::max(need, fit * row);
+                c->expansion_passes = std::max(c->expansion_passes, (int)((sa.nc + fit - 1) / fit));
+            }
+            double *shared = nullptr;
+            TRY(dalloc(c, &shared, (size_t)need));
+            for (auto &p : c->pp) p.d_B = shared;
+            c->b_shared = true;
+        }
+    }
     c->planned = true;
     return CCH_OK;
 }
@@ -726,6 +762,7 @@ static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev)
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
+        if (c->b_shared) continue;   // one shared buffer: rows are laid out pass by pass in phase 3
         HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
                                  sa.nc, sb.ja0, sb.nc, p.d_B, st));
         const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
@@ -754,8 +791,21 @@ static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st)
         else if (c->opts.precision == CCH_PREC_SPLIT_BF16)
             HIPCK(c, launch_expand_bf16split(p.d_SA, p.d_SB, p.d_sigA, p.d_sigB, c->opts.split_slices, p.nrows, N,
                                              p.ldk, ep, st));
-        else
+        else if (!c->b_shared)
             HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, N, K, ep, st));
+        else {
+            // passes over ranges of j: the rows j0..j0+nj-1 of the integral layout, then
+            // the product's columns (j, j') of those rows; each output keeps its sum over K
+            for (int j0 = 0; j0 < sa.nc; j0 += p.jj_chunk) {
+                const int nj = std::min(p.jj_chunk, sa.nc - j0);
+                HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot,
+                                         sa.ja0 + j0, nj, sb.ja0, sb.nc, p.d_B, st));
+                ExpandEpi e2 = ep;
+                e2.row0a += j0;
+                e2.ja0 += j0;
+                HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, nj * sb.nc, K, e2, st));
+            }
+        }
     }
     return CCH_OK;
 }
@@ -814,6 +864,15 @@ cch_status cch_build_time(cch_ctx *c, float *total_ms, float *phases)
         for (int i = 0; i < 7; ++i) HIPCK(c, hipEventElapsedTime(&phases[i], c->ev[i], c->ev[i + 1]));
         phases[7] = 0.0f;
     }
+    return CCH_OK;
+}
+
+cch_status cch_plan_info(cch_ctx *c, int64_t *device_bytes, int32_t *expansion_passes)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    if (device_bytes) *device_bytes = c->bytes;
+    if (expansion_passes) *expansion_passes = c->expansion_passes;
     return CCH_OK;
 }
 
@@ -1372,6 +1431,8 @@ cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, in
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, CCH_E_INVALID_ARG, "context %d is NULL", i);
         if (!ctxs[i]->planned) return bfail(nullptr, CCH_E_STATE, "context %d is not planned", i);
+        if (ctxs[i]->b_shared)
+            return bfail(nullptr, CCH_E_STATE, "context %d was planned in several expansion passes", i);
         if (ctxs[i]->opts.precision != CCH_PREC_FP64)
             return bfail(nullptr, CCH_E_INVALID_ARG, "context %d: batched builds use the FP64 form", i);
         if (ctxs[i]->device != ctxs[0]->device) return bfail(nullptr, CCH_E_INVALID_ARG, "contexts on two devices");
