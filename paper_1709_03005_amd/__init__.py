@@ -202,6 +202,9 @@ class Context:
         pd, fd, kd = _arr(dets, np.uint64)
         pc, fc, kc = _arr(ci, np.float64)
         n_det, n_words = kd.shape
+        if kc.ndim != 2 or kc.shape[0] != n_det:
+            # the library reads n_det rows of ci: refuse a shorter array here
+            raise CchError(CCH_E_INVALID_ARG, f"ci has shape {tuple(kc.shape)}, expected ({n_det}, n_states)")
         sid = i32()
         self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
                                              int(kc.shape[1]), pc, fd, C.byref(sid)))

@@ -120,3 +120,42 @@ def test_input_validation(cc):
         ctx.set_orbitals(40000, np.zeros(40000, np.uint8), 1, [0], 0)
     assert e.value.code == cc.CCH_E_LIMIT
     ctx.close()
+
+
+def test_input_validation_spin_irrep_words(cc):
+    """Alpha/beta imbalance, a determinant of another irrep, an electron
+    beyond the target spin-orbitals and a word-count mismatch are refused
+    with CCH_E_INPUT / CCH_E_INVALID_ARG; the context stays usable."""
+    inst = synth.small()                     # 12 orbitals, two symmetries of different irreps
+    s0, s1 = inst.syms[0], inst.syms[1]
+    ctx = cc.Context(0)
+    ctx.set_orbitals(inst.n_o, inst.tgt_irrep, inst.n_irrep, inst.n_c, inst.total_irrep)
+    ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc)
+
+    def refused(irrep, dets, ci, codes=(cc.CCH_E_INPUT,)):
+        with pytest.raises(cc.CchError) as e:
+            ctx.add_target_symmetry(irrep, dets, ci)
+        assert e.value.code in codes, e.value
+
+    # move one alpha electron to a beta spin-orbital: N unchanged, n_alpha off by one
+    bad = s0.dets.copy()
+    d = int(bad[0, 0])
+    a = next(k for k in range(0, 2 * inst.n_o, 2) if d >> k & 1)
+    b = next(k for k in range(1, 2 * inst.n_o, 2) if not d >> k & 1)
+    bad[0, 0] = np.uint64(d ^ (1 << a) ^ (1 << b))
+    refused(s0.irrep, bad, s0.ci)
+    # determinants of symmetry 1 declared with the irrep of symmetry 0
+    assert s0.irrep != s1.irrep
+    refused(s0.irrep, s1.dets, s1.ci)
+    # an electron in a spin-orbital >= 2 n_o
+    bad = s0.dets.copy()
+    bad[0, 0] = np.uint64(int(bad[0, 0]) | (1 << (2 * inst.n_o)))
+    refused(s0.irrep, bad, s0.ci)
+    # two words per determinant for a one-word orbital set
+    wide = np.concatenate([s0.dets, np.zeros_like(s0.dets)], axis=1)
+    refused(s0.irrep, wide, s0.ci, (cc.CCH_E_INPUT, cc.CCH_E_INVALID_ARG))
+    # CI rows that do not match the determinants
+    refused(s0.irrep, s0.dets, s0.ci[:-1], (cc.CCH_E_INPUT, cc.CCH_E_INVALID_ARG))
+    # the valid symmetry is still accepted afterwards
+    assert ctx.add_target_symmetry(s0.irrep, s0.dets, s0.ci) == 0
+    ctx.close()
