@@ -1744,7 +1744,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(launch_diag_small(b.Gb, BMAX, nb, b.ref, st));
         double *src = b.T, *dst = b.T2;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int cg = 0; cg < 2 && m > 0; ++cg) {     // T -= V (V^T T)
+            for (int cg = 0; cg < (pass == 0 ? 2 : 1) && m > 0; ++cg) {   // T -= V (V^T T): twice, then once
                 DCK(launch_tn(b.V, ldv, m, src, ldv, nb, D, b.part, b.C, nb, 0, st));
                 DCK(launch_nn(b.V, ldv, m, D, b.C, nb, nb, src, ldv, 1.0, -1.0, src, ldv, st));
             }
