@@ -127,6 +127,7 @@ hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, dou
 hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, int32_t *nfallback,
                          hipStream_t st);
 hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
+hipError_t launch_g_ritz(double *G, int ldg, int m, const double *theta, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
 // learned preconditioner
 int mlp_num_params();
@@ -1680,7 +1681,12 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     const int64_t ldv = ((int64_t)D + 31) / 32 * 32;
     const int BMAX = 32;                       // block columns (<= 2k <= 32)
     std::vector<void *> tmp;
-    auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
+    void *tmp_host = nullptr;
+    auto cleanup = [&]() {
+        for (void *p : tmp) (void)hipFree(p);
+        if (tmp_host) (void)hipHostFree(tmp_host);
+        tmp_host = nullptr;
+    };
     auto A = [&](void **p, size_t bytes) -> bool {
         if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) return false;
         tmp.push_back(*p);
@@ -1736,7 +1742,20 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(hipMemsetAsync(b.nfb, 0, 4, st));
     }
     DCK(hipMemsetAsync(b.rrfb, 0, 4, st));
-    std::vector<double> hres(blk), htheta(mmax);
+    // pinned host block for the per-iteration transfers (rank, residual norms,
+    // selected pairs): asynchronous copies, no staging
+    struct HostIO {
+        int32_t rank;
+        int32_t sel[16];
+        double res[16];
+    };
+    HostIO *hio = nullptr;
+    if (hipHostMalloc((void **)&hio, sizeof(HostIO)) != hipSuccess) {
+        cleanup();
+        return fail(c, CCH_E_OOM, "pinned host buffer");
+    }
+    tmp_host = hio;
+    double *hres = hio->res;
     cch_status rc = CCH_E_NOT_CONVERGED;
     for (iters = 1; iters <= max_iter; ++iters) {
         // reference norms of the raw directions, for the drop test
@@ -1756,9 +1775,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             DCK(launch_nn(src, ldv, nb, D, b.Cb, BMAX, nb, nullptr, 0, 0.0, 1.0, o2, ldv, st));
             std::swap(src, dst);
         }
-        int32_t added = 0;
-        DCK(hipMemcpyAsync(&added, b.rank, 4, hipMemcpyDeviceToHost, st));
+        DCK(hipMemcpyAsync(&hio->rank, b.rank, 4, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
+        const int32_t added = hio->rank;
         if (added <= 0) break;   // no new direction: stagnation
         // W for the new vectors and the new rows of G
         DCK(hipEventRecord(c->mv0, st));
@@ -1783,8 +1802,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         std::swap(b.Wv, b.W2);
         const int kk = std::min(k, m), kg = std::min(blk, m);
         DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kg, b.R, b.part, b.norms, st));
-        DCK(hipMemcpyAsync(hres.data(), b.norms, 8 * (size_t)kg, hipMemcpyDeviceToHost, st));
-        DCK(hipMemcpyAsync(htheta.data(), b.theta, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+        DCK(hipMemcpyAsync(hres, b.norms, 8 * (size_t)kg, hipMemcpyDeviceToHost, st));
         DCK(hipStreamSynchronize(st));
         {
             float ms = 0.0f;
@@ -1820,16 +1838,13 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             break;
         }
         // G in the rotated basis
-        {
-            std::vector<double> g((size_t)mmax * mmax, 0.0);
-            if (m + (int)un.size() > mmax) m = std::min(kr, m);   // thick restart
-            for (int e = 0; e < m; ++e) g[(size_t)e * mmax + e] = htheta[e];
-            DCK(hipMemcpyAsync(b.G, g.data(), 8 * g.size(), hipMemcpyHostToDevice, st));
-        }
+        if (m + (int)un.size() > mmax) m = std::min(kr, m);   // thick restart
+        DCK(launch_g_ritz(b.G, mmax, m, b.theta, st));
         // corrections for the unconverged pairs (never more than the basis has room for)
         nb = std::min((int)un.size(), mmax - m);
         if (nb <= 0) break;
-        DCK(hipMemcpyAsync(b.sel, un.data(), 4 * (size_t)nb, hipMemcpyHostToDevice, st));
+        for (int e = 0; e < nb; ++e) hio->sel[e] = un[e];
+        DCK(hipMemcpyAsync(b.sel, hio->sel, 4 * (size_t)nb, hipMemcpyHostToDevice, st));
         if (use_mlp) {
             const cch_mlp *net = c->mlp;
             DCK(launch_mlp_dav(net->w, net->w2, net->w2t, b.R, ldv, D, (int)c->Dc, c->d_diag, b.rho, b.theta, b.sel, nb,

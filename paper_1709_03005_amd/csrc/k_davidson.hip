@@ -524,6 +524,23 @@ hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipSt
     return hipGetLastError();
 }
 
+// G = diag(theta) on its leading m x m block (the projected matrix in the
+// Ritz basis after a rotation or a thick restart)
+__global__ void k_g_ritz(double *G, int ldg, int m, const double *__restrict__ theta)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * m) return;
+    const int r = t / m, c = t % m;
+    G[(int64_t)r * ldg + c] = (r == c) ? theta[r] : 0.0;
+}
+
+hipError_t launch_g_ritz(double *G, int ldg, int m, const double *theta, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_g_ritz, dim3((m * m + 255) / 256), dim3(256), 0, st, G, ldg, m, theta);
+    return hipGetLastError();
+}
+
 // G[a][b] symmetric fill of a new column block from computed rows
 __global__ void k_sym_fill(double *G, int ldg, int m0, int m1)
 {
