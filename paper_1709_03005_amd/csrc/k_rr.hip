@@ -26,11 +26,11 @@
 
 namespace cch {
 
-constexpr int RR_MAX = 96, RR_LD = RR_MAX + 1, RR_NT = 1024, RR_NW = RR_NT / 64;
+constexpr int RR_MAX = 96, RR_LD = RR_MAX + 1, RR_NT = 512, RR_NW = RR_NT / 64;
 typedef double rr_dx4 __attribute__((ext_vector_type(4)));
 
-constexpr int RR_SL = 8;     // row slices of the Householder products (x 2 column halves = 16 waves)
-constexpr int RR_BSL = 6;    // row slices of the back-transformation
+constexpr int RR_SL = 4;     // row slices of the Householder products (x 2 column halves = 8 waves)
+constexpr int RR_BSL = 4;    // row slices of the back-transformation (x 2 column halves)
 constexpr int RR_G = 512;    // shifts of the first multisection pass
 
 struct RRShared {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
         // Step k: x = row k of the trailing matrix, H_k = I - tau v v^T with
         // v_{k+1} = 1 and v_r = x_r * hinv[k] below; row k keeps x afterwards.
         // Thread (wave w, lane l) owns column lane + 64 (w & 1) over the rows
-        // k+1+s, k+1+s+8, ... of slice s = w >> 1. Every wave holds x, v and
+        // k+1+s, k+1+s+RR_SL, ... of slice s = w >> 1. Every wave holds x, v and
         // w in registers and forms sigma and K itself (identical bits).
         {
             const int half = wv & 1, slice = wv >> 1;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
         }
 
         // ---- back-transformation Z <- H_0 H_1 ... H_{n-3} Z --------------------
-        // thread (wave w < 12, lane l): column l + 64 (w & 1), row slice w >> 1
+        // thread (wave w, lane l): column l + 64 (w & 1), row slice w >> 1
         {
             const int col = lane + 64 * (wv & 1), bs = wv >> 1;
             for (int k = n - 3; k >= 0; --k) {
