@@ -53,25 +53,38 @@ hipError_t launch_pair_values(int W, TgtInts I, const uint64_t *da, const uint64
 // Y[m][n'] = sum_{pairs (m, m')} H_T[m,m'] c'[m'][n'],  Yo = same over
 // degree-0 pairs with weight 1. One wave per bra row, pairs in order.
 // ---------------------------------------------------------------------------
+// Y[m][n] = sum over the connected pairs p of row m of hv[p] cb[y_p][n]
+// (Yo likewise with weight 1 on degree-0 pairs): one wave per row m, its lanes
+// split into G pair groups x (64 / G) states; the G partial sums of a state
+// are combined by xor-shuffles over the group bits (fixed order).
 __global__ __launch_bounds__(256) void k_spmm_rows(int M, const int64_t *__restrict__ row_off,
                                                    const int64_t *__restrict__ row_cnt, PairList pl,
                                                    const double *__restrict__ hv,
-                                                   const double *__restrict__ cb, int Sb,
+                                                   const double *__restrict__ cb, int Sb, int lg_states,
                                                    double *__restrict__ Y, double *__restrict__ Yo)
 {
     const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (m >= M) return;
+    if (m >= M) return;   // whole waves
+    const int ns = 1 << lg_states;              // state lanes (power of two, <= 64)
+    const int ng = 64 >> lg_states;             // pair groups
+    const int nl = lane & (ns - 1), g = lane >> lg_states;
     const int64_t p0 = row_off[m], p1 = p0 + row_cnt[m];
-    for (int n0 = 0; n0 < Sb; n0 += 64) {
-        const int n = n0 + lane;
+    for (int n0 = 0; n0 < Sb; n0 += ns) {
+        const int n = n0 + nl;
         double acc = 0.0, acco = 0.0;
         if (n < Sb) {
-            for (int64_t p = p0; p < p1; ++p) {
+            for (int64_t p = p0 + g; p < p1; p += ng) {
                 const double c = cb[(size_t)pl.y[p] * Sb + n];
                 acc = fma(hv[p], c, acc);
                 if (pl.deg[p] == 0) acco += c;
             }
+        }
+        for (int o = ns; o < 64; o <<= 1) {
+            acc += __shfl_xor(acc, o, 64);
+            acco += __shfl_xor(acco, o, 64);
+        }
+        if (g == 0 && n < Sb) {
             Y[(size_t)m * Sb + n] = acc;
             Yo[(size_t)m * Sb + n] = acco;
         }
@@ -117,8 +130,10 @@ hipError_t launch_projection(int M, const int64_t *row_off, const int64_t *row_c
                              double *HT, double *O, hipStream_t st)
 {
     if (M > 0) {
+        int lg = 0;   // state lanes: the power of two >= Sb, at most 64
+        while ((1 << lg) < Sb && lg < 6) ++lg;
         hipLaunchKernelGGL(k_spmm_rows, dim3((M + 3) / 4), dim3(256), 0, st, M, row_off, row_cnt, pl,
-                           hv, cb, Sb, Y, Yo);
+                           hv, cb, Sb, lg, Y, Yo);
     }
     hipLaunchKernelGGL(k_project, dim3(nrows), dim3(256), 0, st, M, ca, Sa, Y, Yo, Sb, rn, rn2, HT, O);
     return hipGetLastError();
