@@ -262,8 +262,19 @@ __global__ void k_tn_sum(const double *__restrict__ part, int nsplit, int na, in
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= na * nc) return;
     const int a = t / nc, c = t % nc;
-    double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * TN_LD + a) * TN_LD + c];
+    // four interleaved partial sums (loads in flight), added in a fixed order
+    const double *pp = part + (int64_t)a * TN_LD + c;
+    const int64_t st = (int64_t)TN_LD * TN_LD;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 3 < nsplit; q += 4) {
+        s0 += pp[q * st];
+        s1 += pp[(q + 1) * st];
+        s2 += pp[(q + 2) * st];
+        s3 += pp[(q + 3) * st];
+    }
+    for (; q < nsplit; ++q) s0 += pp[q * st];
+    const double s = (s0 + s1) + (s2 + s3);
     if (transpose) out[(int64_t)c * ldo + a] = s;
     else out[(int64_t)a * ldo + c] = s;
 }
@@ -421,12 +432,15 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int 
     __shared__ double R[PCH_MAX][PCH_MAX + 1];    // row i, pivot position j
     __shared__ double Ri[PCH_MAX][PCH_MAX + 1];
     __shared__ int perm[PCH_MAX];
+    __shared__ double refd[PCH_MAX];
     __shared__ int rank_sh;
     const int t = threadIdx.x;
     for (int e = t; e < b * b; e += 64) {
         const int i = e / b, j = e % b;
         A[i][j] = 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
     }
+    // drop threshold per original column: rel^2 times the reference norm^2
+    if (t < b) refd[t] = rel * rel * (ref ? ref[t] : G[(int64_t)t * ldg + t]);
     for (int e = t; e < PCH_MAX * PCH_MAX; e += 64) {
         Rq[e / PCH_MAX][e % PCH_MAX] = 0.0;
         R[e / PCH_MAX][e % PCH_MAX] = 0.0;
@@ -437,24 +451,36 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int 
     __syncthreads();
     int r = b;
     for (int i = 0; i < b; ++i) {
-        if (t == 0) {
-            int jm = -1;
-            double best = -1.0;
-            for (int j = i; j < b; ++j) {
-                const int pj = perm[j];
+        {
+            // pivot: the largest admissible remaining diagonal, ties to the first
+            // position (wave-wide argmax; every lane ends with the same pair)
+            double bd = -1.0;
+            int bj = b;
+            if (t >= i && t < b) {
+                const int pj = perm[t];
                 const double d = A[pj][pj];
-                const double refj = ref ? ref[pj] : G[(int64_t)pj * ldg + pj];
-                if (d > rel * rel * refj && d > 0.0 && d > best) {
-                    best = d;
-                    jm = j;
+                if (d > refd[pj] && d > 0.0) {
+                    bd = d;
+                    bj = t;
                 }
             }
-            if (jm < 0) {
-                rank_sh = i;
-            } else {
-                const int tmp = perm[i];
-                perm[i] = perm[jm];
-                perm[jm] = tmp;
+            for (int o = 32; o > 0; o >>= 1) {
+                const double od = __shfl_xor(bd, o, 64);
+                const int oj = __shfl_xor(bj, o, 64);
+                if (od > bd || (od == bd && oj < bj)) {
+                    bd = od;
+                    bj = oj;
+                }
+            }
+            __syncthreads();
+            if (t == 0) {
+                if (bd < 0.0) {
+                    rank_sh = i;
+                } else {
+                    const int tmp = perm[i];
+                    perm[i] = perm[bj];
+                    perm[bj] = tmp;
+                }
             }
         }
         __syncthreads();
