@@ -129,6 +129,10 @@ hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double 
 hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
 hipError_t launch_g_ritz(double *G, int ldg, int m, const double *theta, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
+hipError_t launch_gather_principal(const double *H, int64_t ld, const int32_t *idx, int ns, double *G, int ldg,
+                                   hipStream_t st);
+hipError_t launch_seed_scatter(double *V, int64_t ldv, const int32_t *idx, const double *Y, int ldy, int ns, int b,
+                               hipStream_t st);
 // learned preconditioner
 int mlp_num_params();
 int mlp_grid(int64_t n);
@@ -1702,7 +1706,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
               A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
               A((void **)&b.part, 8 * (size_t)std::max<int64_t>((int64_t)nch * mmax * 16, tn_part_doubles())) && A((void **)&b.norms, 8 * (size_t)blk) &&
-              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)kr) &&
+              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)mmax) &&
               A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4) &&
               A((void **)&b.rrfb, 4);
     const bool want_mlp = o->precond == CCH_PRECOND_MLP;
@@ -1722,7 +1726,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         }                                                                                       \
     } while (0)
 
-    // initial block: unit vectors at the 2k smallest diagonal entries (ties: lower index)
+    // initial block: the lowest 2k Ritz vectors of the principal submatrix on the
+    // mmax smallest diagonal entries (ties: lower index)
     std::vector<double> hdiag(D);
     DCK(hipMemcpyAsync(hdiag.data(), c->d_diag, 8 * (size_t)D, hipMemcpyDeviceToHost, st));
     DCK(hipStreamSynchronize(st));
@@ -1730,8 +1735,12 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     for (int i = 0; i < D; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return hdiag[a] < hdiag[bb]; });
     int nb = kr;
-    DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)nb, hipMemcpyHostToDevice));
-    DCK(launch_unit_vectors(b.T, ldv, D, b.idx, nb, st));
+    const int ns = std::min(mmax, D);
+    DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
+    DCK(launch_gather_principal(c->d_H, c->ld, b.idx, ns, b.G, mmax, st));
+    DCK(launch_rr_eig(b.G, mmax, ns, b.theta, b.Y, mmax, b.rrfb, st));
+    DCK(launch_fill_f64(b.T, 0.0, (int64_t)nb * ldv, st));
+    DCK(launch_seed_scatter(b.T, ldv, b.idx, b.Y, mmax, ns, nb, st));
 
     int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0, fallbacks = 0;
     double mv_ms = 0.0, maxres = 0.0, best_res = 1e300, rr_ms = 0.0, rr_flops = 0.0;

@@ -586,6 +586,42 @@ hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st)
     return hipGetLastError();
 }
 
+// G0[r][c] = H[idx[r]][idx[c]], r, c < ns: a principal submatrix of H
+__global__ void k_gather_principal(const double *__restrict__ H, int64_t ld, const int32_t *__restrict__ idx, int ns,
+                                   double *__restrict__ G, int ldg)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns * ns) return;
+    const int r = t / ns, c = t % ns;
+    G[(int64_t)r * ldg + c] = H[(int64_t)idx[r] * ld + idx[c]];
+}
+
+hipError_t launch_gather_principal(const double *H, int64_t ld, const int32_t *idx, int ns, double *G, int ldg,
+                                   hipStream_t st)
+{
+    if (ns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_principal, dim3((ns * ns + 255) / 256), dim3(256), 0, st, H, ld, idx, ns, G, ldg);
+    return hipGetLastError();
+}
+
+// V[c][idx[r]] = Y[r][c] for r < ns, c < b (the rest of V's rows already zero)
+__global__ void k_seed_scatter(double *V, int64_t ldv, const int32_t *__restrict__ idx, const double *__restrict__ Y,
+                               int ldy, int ns, int b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns * b) return;
+    const int r = t / b, c = t % b;
+    V[(int64_t)c * ldv + idx[r]] = Y[(int64_t)r * ldy + c];
+}
+
+hipError_t launch_seed_scatter(double *V, int64_t ldv, const int32_t *idx, const double *Y, int ldy, int ns, int b,
+                               hipStream_t st)
+{
+    if (ns <= 0 || b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seed_scatter, dim3((ns * b + 255) / 256), dim3(256), 0, st, V, ldv, idx, Y, ldy, ns, b);
+    return hipGetLastError();
+}
+
 __global__ void k_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
