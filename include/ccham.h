@@ -117,7 +117,9 @@ typedef struct {
     double rr_ms;           /* device time of the Rayleigh-Ritz launches (HIP events) */
     double rr_flops;        /* sum over those solves of (10/3) m^3 */
     int32_t rr_calls;       /* Rayleigh-Ritz solves */
-    int32_t reserved;
+    int32_t dropped;        /* correction directions dropped by the rank test
+                               (nearly inside the basis); each iteration with a
+                               drop repeats its Rayleigh-Ritz step */
 } cch_dav_info;
 
 /* Library version string (static storage). */

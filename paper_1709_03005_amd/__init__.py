@@ -77,7 +77,7 @@ class DavInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
                 ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double),
                 ("matvec_ms", C.c_double), ("matvec_launches", C.c_int32), ("rr_fallbacks", C.c_int32),
-                ("rr_ms", C.c_double), ("rr_flops", C.c_double), ("rr_calls", C.c_int32), ("reserved", C.c_int32)]
+                ("rr_ms", C.c_double), ("rr_flops", C.c_double), ("rr_calls", C.c_int32), ("dropped", C.c_int32)]
 
 
 P = C.c_void_p

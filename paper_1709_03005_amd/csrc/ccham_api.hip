@@ -111,18 +111,18 @@ hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, in
                          int64_t ldw, double *Wp, hipStream_t st);
 int matvec_splits(int D);
 int64_t tn_part_doubles();
-hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
-                     double *part, double *out, int64_t ldo, int transpose, hipStream_t st);
-hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
-                     const double *base, int64_t ldb, double beta, double alpha, double *out, int64_t ldo,
-                     hipStream_t st);
+hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, int64_t ldx2, int na,
+                     const double *Y, int64_t ldy, int nc, int D, double *part, double *out, int64_t ldo,
+                     int transpose, hipStream_t st);
+hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, int64_t ldv2, int m, int D,
+                     const double *C, int ldc, int ne, const double *base, int64_t ldb, double beta, double alpha,
+                     double *out, int64_t ldo, hipStream_t st);
 hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D, const double *theta, int k,
                            double *R, double *part, double *norms, hipStream_t st);
 hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
-                                 const int32_t *sel, int nsel, double *T, int64_t ldt, hipStream_t st);
-hipError_t launch_pchol(const double *G, int ldg, int b, const double *ref, double rel, double *C, int ldc,
-                        int32_t *rank, hipStream_t st);
-hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st);
+                                 const DavSel &sel, int nsel, double *T, int64_t ldt, hipStream_t st);
+hipError_t launch_pchol(const double *G, int ldg, int b, const double *S, int lds, int m, const double *ref,
+                        int ref_stride, double rel, double *C, int ldc, int32_t *rank, hipStream_t st);
 hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
 hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, int32_t *nfallback,
                          hipStream_t st);
@@ -145,7 +145,7 @@ hipError_t launch_mlp_grad(const float *w, const __bf16 *w2, const __bf16 *w2t, 
 hipError_t launch_adam(float *w, float *m, float *v, const float *g, float lr, int step, hipStream_t st);
 hipError_t launch_row_norms(const double *H, int64_t ld, int D, double *rho, hipStream_t st);
 hipError_t launch_mlp_dav(const float *w, const __bf16 *w2, const __bf16 *w2t, const double *R, int64_t ld, int D,
-                          int Dc, const double *diag, const double *rho, const double *theta, const int32_t *sel,
+                          int Dc, const double *diag, const double *rho, const double *theta, const DavSel &sel,
                           int nsel, float *X, float *g, double *T, int64_t ldt, int32_t *nfallback, hipStream_t st);
 }  // namespace cch
 
@@ -1651,9 +1651,9 @@ const char *cch_batch_last_error(const cch_batch *b) { return b ? b->err.c_str()
 namespace {
 struct DavBufs {
     double *V = nullptr, *Wv = nullptr, *V2 = nullptr, *W2 = nullptr, *G = nullptr, *theta = nullptr,
-           *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *Gb = nullptr, *Cb = nullptr,
-           *ref = nullptr, *part = nullptr, *norms = nullptr, *Wp = nullptr, *rho = nullptr;
-    int32_t *rank = nullptr, *sel = nullptr, *idx = nullptr, *nfb = nullptr, *rrfb = nullptr;
+           *Y = nullptr, *R = nullptr, *T = nullptr, *T2 = nullptr, *C = nullptr, *P0 = nullptr, *P1 = nullptr,
+           *part = nullptr, *norms = nullptr, *Wp = nullptr, *rho = nullptr;
+    int32_t *idx = nullptr, *nfb = nullptr, *rrfb = nullptr;
     float *mx = nullptr, *mg = nullptr;
 };
 }  // namespace
@@ -1703,10 +1703,10 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.G, 8 * (size_t)mmax * mmax) && A((void **)&b.theta, 8 * (size_t)mmax) &&
               A((void **)&b.Y, 8 * (size_t)mmax * mmax) && A((void **)&b.R, 8 * ldv * blk) &&
               A((void **)&b.T, 8 * ldv * BMAX) && A((void **)&b.T2, 8 * ldv * BMAX) &&
-              A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.Gb, 8 * (size_t)BMAX * BMAX) &&
-              A((void **)&b.Cb, 8 * (size_t)BMAX * BMAX) && A((void **)&b.ref, 8 * (size_t)BMAX) &&
+              A((void **)&b.C, 8 * (size_t)mmax * BMAX) && A((void **)&b.P0, 8 * (size_t)mmax * BMAX) &&
+              A((void **)&b.P1, 8 * (size_t)mmax * BMAX) &&
               A((void **)&b.part, 8 * (size_t)std::max<int64_t>((int64_t)nch * mmax * 16, tn_part_doubles())) && A((void **)&b.norms, 8 * (size_t)blk) &&
-              A((void **)&b.rank, 8) && A((void **)&b.sel, 4 * (size_t)blk) && A((void **)&b.idx, 4 * (size_t)mmax) &&
+              A((void **)&b.idx, 4 * (size_t)mmax) &&
               A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4) &&
               A((void **)&b.rrfb, 4);
     const bool want_mlp = o->precond == CCH_PRECOND_MLP;
@@ -1744,74 +1744,88 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
 
     int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0, fallbacks = 0;
     double mv_ms = 0.0, maxres = 0.0, best_res = 1e300, rr_ms = 0.0, rr_flops = 0.0;
-    int rr_calls = 0;
+    int rr_calls = 0, dropped = 0;
     bool use_mlp = want_mlp;
     if (want_mlp) {
         DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
         DCK(hipMemsetAsync(b.nfb, 0, 4, st));
     }
     DCK(hipMemsetAsync(b.rrfb, 0, 4, st));
-    // pinned host block for the per-iteration transfers (rank, residual norms,
-    // selected pairs): asynchronous copies, no staging
+    // pinned, host-coherent block that the kernels write directly (the rank of
+    // the new block, the residual norms): one synchronisation per iteration
     struct HostIO {
         int32_t rank;
-        int32_t sel[16];
+        int32_t pad;
         double res[16];
     };
     HostIO *hio = nullptr;
-    if (hipHostMalloc((void **)&hio, sizeof(HostIO)) != hipSuccess) {
+    if (hipHostMalloc((void **)&hio, sizeof(HostIO), hipHostMallocCoherent) != hipSuccess) {
         cleanup();
         return fail(c, CCH_E_OOM, "pinned host buffer");
     }
     tmp_host = hio;
     double *hres = hio->res;
+    DavSel sel{};
     cch_status rc = CCH_E_NOT_CONVERGED;
-    for (iters = 1; iters <= max_iter; ++iters) {
-        // reference norms of the raw directions, for the drop test
-        DCK(launch_tn(b.T, ldv, nb, b.T, ldv, nb, D, b.part, b.Gb, BMAX, 0, st));
-        DCK(launch_diag_small(b.Gb, BMAX, nb, b.ref, st));
-        double *src = b.T, *dst = b.T2;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int cg = 0; cg < (pass == 0 ? 2 : 1) && m > 0; ++cg) {   // T -= V (V^T T): twice, then once
-                DCK(launch_tn(b.V, ldv, m, src, ldv, nb, D, b.part, b.C, nb, 0, st));
-                DCK(launch_nn(b.V, ldv, m, D, b.C, nb, nb, src, ldv, 1.0, -1.0, src, ldv, st));
-            }
-            DCK(launch_tn(src, ldv, nb, src, ldv, nb, D, b.part, b.Gb, BMAX, 0, st));
-            DCK(launch_pchol(b.Gb, BMAX, nb, pass == 0 ? b.ref : nullptr, pass == 0 ? 1e-7 : 1e-12, b.Cb, BMAX,
-                             b.rank, st));
-            // second pass writes the orthonormal block straight into V
-            double *o2 = pass == 0 ? dst : b.V + (int64_t)m * ldv;
-            DCK(launch_nn(src, ldv, nb, D, b.Cb, BMAX, nb, nullptr, 0, 0.0, 1.0, o2, ldv, st));
-            std::swap(src, dst);
-        }
-        DCK(hipMemcpyAsync(&hio->rank, b.rank, 4, hipMemcpyDeviceToHost, st));
-        DCK(hipStreamSynchronize(st));
-        const int32_t added = hio->rank;
-        if (added <= 0) break;   // no new direction: stagnation
-        // W for the new vectors and the new rows of G
-        DCK(hipEventRecord(c->mv0, st));
-        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, added, b.Wv + (int64_t)m * ldv, ldv, b.Wp,
-                          st));
-        DCK(hipEventRecord(c->mv1, st));
-        matvecs += added;
-        mv_launches += (added + 15) / 16;
-        DCK(launch_tn(b.Wv + (int64_t)m * ldv, ldv, added, b.V, ldv, m + added, D, b.part, b.G + (int64_t)m * mmax,
-                      mmax, 0, st));
-        DCK(launch_sym_fill(b.G, mmax, m, m + added, st));
-        m += added;
-        DCK(hipEventRecord(c->rr0, st));
-        DCK(launch_rr_eig(b.G, mmax, m, b.theta, b.Y, mmax, b.rrfb, st));
-        DCK(hipEventRecord(c->rr1, st));
+    // Rayleigh-Ritz on the leading m x m block of G, rotation of V and W to the
+    // Ritz basis, residuals of the first kg pairs (norms to the host block)
+    auto rayleigh_ritz = [&](int mm) -> hipError_t {
+        hipError_t e;
+        if ((e = hipEventRecord(c->rr0, st)) != hipSuccess) return e;
+        if ((e = launch_rr_eig(b.G, mmax, mm, b.theta, b.Y, mmax, b.rrfb, st)) != hipSuccess) return e;
+        if ((e = hipEventRecord(c->rr1, st)) != hipSuccess) return e;
         ++rr_calls;
-        rr_flops += (10.0 / 3.0) * (double)m * m * m;   // tridiagonalisation + back-transformation
-        // rotate V and W to the Ritz basis; G becomes diag(theta)
-        DCK(launch_nn(b.V, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.V2, ldv, st));
-        DCK(launch_nn(b.Wv, ldv, m, D, b.Y, mmax, m, nullptr, 0, 0.0, 1.0, b.W2, ldv, st));
+        rr_flops += (10.0 / 3.0) * (double)mm * mm * mm;   // tridiagonalisation + back-transformation
+        if ((e = launch_nn(b.V, ldv, mm, nullptr, 0, mm, D, b.Y, mmax, mm, nullptr, 0, 0.0, 1.0, b.V2, ldv, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_nn(b.Wv, ldv, mm, nullptr, 0, mm, D, b.Y, mmax, mm, nullptr, 0, 0.0, 1.0, b.W2, ldv, st)) !=
+            hipSuccess)
+            return e;
         std::swap(b.V, b.V2);
         std::swap(b.Wv, b.W2);
-        const int kk = std::min(k, m), kg = std::min(blk, m);
-        DCK(launch_residual(b.Wv, b.V, ldv, D, b.theta, kg, b.R, b.part, b.norms, st));
-        DCK(hipMemcpyAsync(hres, b.norms, 8 * (size_t)kg, hipMemcpyDeviceToHost, st));
+        return launch_residual(b.Wv, b.V, ldv, D, b.theta, std::min(blk, mm), b.R, b.part, hres, st);
+    };
+    for (iters = 1; iters <= max_iter; ++iters) {
+        // Orthogonalisation of the new block T against V and within itself:
+        // [V | T]^T T in one product gives both the projection S = V^T T and the
+        // Gram matrix T^T T; the pivoted Cholesky step then takes the Gram matrix
+        // of T - V S as T^T T - S^T S and returns [-S B; B], so projection and
+        // normalisation are one product [V | T] [-S B; B] = (T - V S) B.
+        // First pass: project once explicitly, then once more folded into the
+        // normalisation, with the drop test against the raw norms; the second
+        // pass repeats project + normalise once (CholQR2 with re-projection).
+        const double *ref = b.P0 + (int64_t)m * BMAX;   // diag of the raw T^T T, stride BMAX + 1
+        DCK(launch_tn(b.V, ldv, m, b.T, ldv, m + nb, b.T, ldv, nb, D, b.part, b.P0, BMAX, 0, st));
+        const double *P = b.P0;
+        if (m > 0) {
+            DCK(launch_nn(b.V, ldv, m, nullptr, 0, m, D, b.P0, BMAX, nb, b.T, ldv, 1.0, -1.0, b.T, ldv, st));
+            DCK(launch_tn(b.V, ldv, m, b.T, ldv, m + nb, b.T, ldv, nb, D, b.part, b.P1, BMAX, 0, st));
+            P = b.P1;
+        }
+        DCK(launch_pchol(P + (int64_t)m * BMAX, BMAX, nb, P, BMAX, m, ref, BMAX + 1, 1e-7, b.C, BMAX, &hio->rank,
+                         st));
+        DCK(launch_nn(b.V, ldv, m, b.T, ldv, m + nb, D, b.C, BMAX, nb, nullptr, 0, 0.0, 1.0, b.T2, ldv, st));
+        DCK(launch_tn(b.V, ldv, m, b.T2, ldv, m + nb, b.T2, ldv, nb, D, b.part, b.P1, BMAX, 0, st));
+        DCK(launch_pchol(b.P1 + (int64_t)m * BMAX, BMAX, nb, b.P1, BMAX, m, nullptr, 0, 1e-12, b.C, BMAX,
+                         &hio->rank, st));
+        // the orthonormal block goes straight into V; columns past the rank are zero
+        DCK(launch_nn(b.V, ldv, m, b.T2, ldv, m + nb, D, b.C, BMAX, nb, nullptr, 0, 0.0, 1.0, b.V + (int64_t)m * ldv,
+                      ldv, st));
+        // W for the new vectors and the new rows of G, taking all nb directions as
+        // kept; the rank is read with the residual norms below
+        const int m0 = m;
+        DCK(hipEventRecord(c->mv0, st));
+        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp,
+                          st));
+        DCK(hipEventRecord(c->mv1, st));
+        matvecs += nb;
+        mv_launches += (nb + 15) / 16;
+        DCK(launch_tn(b.Wv + (int64_t)m * ldv, ldv, nb, nullptr, 0, nb, b.V, ldv, m + nb, D, b.part,
+                      b.G + (int64_t)m * mmax, mmax, 0, st));
+        DCK(launch_sym_fill(b.G, mmax, m, m + nb, st));
+        m = m0 + nb;
+        DCK(rayleigh_ritz(m));
         DCK(hipStreamSynchronize(st));
         {
             float ms = 0.0f;
@@ -1820,6 +1834,26 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             DCK(hipEventElapsedTime(&ms, c->rr0, c->rr1));
             rr_ms += ms;
         }
+        const int added = hio->rank;
+        if (added < nb) {
+            dropped += nb - std::max(added, 0);
+            // dropped directions: V holds zero columns past the rank. Back to the
+            // basis before the rotation; the leading m0 + added block of G is
+            // exact (G was diag(theta) on the first m0), so Rayleigh-Ritz is redone
+            // on it. No new direction at all: stagnation, stop there.
+            std::swap(b.V, b.V2);
+            std::swap(b.Wv, b.W2);
+            m = m0 + std::max(added, 0);
+            if (m > 0) {
+                DCK(rayleigh_ritz(m));
+                DCK(hipStreamSynchronize(st));
+                float ms = 0.0f;
+                DCK(hipEventElapsedTime(&ms, c->rr0, c->rr1));
+                rr_ms += ms;
+            }
+            if (added <= 0) break;
+        }
+        const int kk = std::min(k, m), kg = std::min(blk, m);
         std::vector<int32_t> un;
         maxres = 0.0;
         for (int e = 0; e < kk; ++e) {
@@ -1852,14 +1886,13 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         // corrections for the unconverged pairs (never more than the basis has room for)
         nb = std::min((int)un.size(), mmax - m);
         if (nb <= 0) break;
-        for (int e = 0; e < nb; ++e) hio->sel[e] = un[e];
-        DCK(hipMemcpyAsync(b.sel, hio->sel, 4 * (size_t)nb, hipMemcpyHostToDevice, st));
+        for (int e = 0; e < nb; ++e) sel.e[e] = un[e];
         if (use_mlp) {
             const cch_mlp *net = c->mlp;
-            DCK(launch_mlp_dav(net->w, net->w2, net->w2t, b.R, ldv, D, (int)c->Dc, c->d_diag, b.rho, b.theta, b.sel, nb,
+            DCK(launch_mlp_dav(net->w, net->w2, net->w2t, b.R, ldv, D, (int)c->Dc, c->d_diag, b.rho, b.theta, sel, nb,
                                b.mx, b.mg, b.T, ldv, b.nfb, st));
         } else {
-            DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, b.sel, nb, b.T, ldv, st));
+            DCK(launch_jacobi_correct(b.R, ldv, D, c->d_diag, b.theta, sel, nb, b.T, ldv, st));
         }
     }
     if (iters > max_iter) iters = max_iter;
@@ -1899,7 +1932,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->rr_ms = rr_ms;
         info->rr_flops = rr_flops;
         info->rr_calls = rr_calls;
-        info->reserved = 0;
+        info->dropped = dropped;
     }
     if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
     return rc;

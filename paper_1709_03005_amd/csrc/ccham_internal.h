@@ -211,6 +211,12 @@ enum ScanMode { SCAN_TT = 0, SCAN_LL = 1, SCAN_LT = 2 };
 // kernel launchers (host side, defined in the .hip files)
 // ---------------------------------------------------------------------------
 namespace cch {
+// the Ritz pairs whose corrections a Davidson step forms (output c uses pair
+// e[c]), passed to the kernels by value
+struct DavSel {
+    int32_t e[32];
+};
+
 struct GemmDesc;
 hipError_t launch_scan(int mode, int W, const uint64_t *A, int nA, const uint64_t *B, int nB,
                        int top, const int64_t *row_off, int64_t *row_cnt, PairList out,

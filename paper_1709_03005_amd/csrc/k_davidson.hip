@@ -197,7 +197,7 @@ constexpr int TN_CHUNK = 1024;   // row chunk of the residual norms
 // step (32-byte pieces, 128 contiguous bytes per row); the four MFMAs of a
 // step take k = 4 (l / 16) + j for lane l and j = 0..3 in both operands.
 typedef double tnx4 __attribute__((ext_vector_type(4)));
-constexpr int TN_SPLIT_MAX = 64, TN_LD = 96;
+constexpr int TN_SPLIT_MAX = 64, TN_LD = 96, TN_U = 4;
 
 int tn_splits(int D)
 {
@@ -223,7 +223,8 @@ __device__ __forceinline__ void tn_load4(const double *row, int k, int D, bool o
     }
 }
 
-__global__ __launch_bounds__(256) void k_tn_mfma(const double *__restrict__ X, int64_t ldx, int na,
+__global__ __launch_bounds__(256) void k_tn_mfma(const double *__restrict__ X1, int64_t ldx1, int na1,
+                                                 const double *__restrict__ X2, int64_t ldx2, int na,
                                                  const double *__restrict__ Y, int64_t ldy, int nc, int D,
                                                  int rows_per_split, double *__restrict__ part)
 {
@@ -235,16 +236,24 @@ __global__ __launch_bounds__(256) void k_tn_mfma(const double *__restrict__ X, i
     const int kb = split * rows_per_split, ke = min(D, kb + rows_per_split);
     const int ra = a0 + (lane & 15), rc = c0 + (lane & 15);
     const bool oka = ra < na, okc = rc < nc;
-    const double *xr = X + (int64_t)(oka ? ra : 0) * ldx;
+    // rows a < na1 of X come from X1, the rest from X2
+    const double *xr = !oka ? X1 : (ra < na1 ? X1 + (int64_t)ra * ldx1 : X2 + (int64_t)(ra - na1) * ldx2);
     const double *yr = Y + (int64_t)(okc ? rc : 0) * ldy;
     tnx4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = kb + 16 * wv; k0 < ke; k0 += 64) {
-        const int k = k0 + 4 * (lane >> 4);
-        double xv[4], yv[4];
-        tn_load4(xr, k, ke, oka, xv);
-        tn_load4(yr, k, ke, okc, yv);
+    // TN_U steps of 16 rows per trip: every load of the trip is issued before
+    // its MFMAs (steps past the end of the split load zeros)
+    for (int k0 = kb + 16 * wv; k0 < ke; k0 += 64 * TN_U) {
+        double xv[TN_U][4], yv[TN_U][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[j], yv[j], acc, 0, 0, 0);
+        for (int u = 0; u < TN_U; ++u) {
+            const int k = k0 + 64 * u + 4 * (lane >> 4);
+            tn_load4(xr, k, ke, oka, xv[u]);
+            tn_load4(yr, k, ke, okc, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < TN_U; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][j], yv[u][j], acc, 0, 0, 0);
     }
     // item v of lane l: row (a) l/16 + 4v, column (c) l%16
 #pragma unroll
@@ -279,30 +288,37 @@ __global__ void k_tn_sum(const double *__restrict__ part, int nsplit, int na, in
     else out[(int64_t)a * ldo + c] = s;
 }
 
-// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c]; na, nc <= 96,
-// X and Y rows 32-byte aligned (leading dimensions multiples of 4)
-hipError_t launch_tn(const double *X, int64_t ldx, int na, const double *Y, int64_t ldy, int nc, int D,
-                     double *part, double *out, int64_t ldo, int transpose, hipStream_t st)
+// out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c], where
+// X[a] = X1[a] for a < na1 and X2[a - na1] for na1 <= a < na; na, nc <= 96,
+// every row 32-byte aligned (leading dimensions multiples of 4)
+hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, int64_t ldx2, int na,
+                     const double *Y, int64_t ldy, int nc, int D, double *part, double *out, int64_t ldo,
+                     int transpose, hipStream_t st)
 {
     if (na <= 0 || nc <= 0) return hipSuccess;
-    if (na > TN_LD || nc > TN_LD || (ldx & 3) || (ldy & 3) || ((uintptr_t)X & 31) || ((uintptr_t)Y & 31))
+    if (na1 < 0 || na1 > na || na > TN_LD || nc > TN_LD || (ldx1 & 3) || (ldy & 3) || ((uintptr_t)X1 & 31) ||
+        ((uintptr_t)Y & 31))
         return hipErrorInvalidValue;
+    if (na1 < na && (X2 == nullptr || (ldx2 & 3) || ((uintptr_t)X2 & 31))) return hipErrorInvalidValue;
     const int ns = tn_splits(D);
     const int rps = ((D + ns - 1) / ns + 15) / 16 * 16;
     const int tiles = ((na + 15) / 16) * ((nc + 15) / 16);
-    hipLaunchKernelGGL(k_tn_mfma, dim3(tiles, ns), dim3(256), 0, st, X, ldx, na, Y, ldy, nc, D, rps, part);
+    hipLaunchKernelGGL(k_tn_mfma, dim3(tiles, ns), dim3(256), 0, st, X1, ldx1, na1, X2, ldx2, na, Y, ldy, nc, D, rps,
+                       part);
     hipLaunchKernelGGL(k_tn_sum, dim3((na * nc + 255) / 256), dim3(256), 0, st, part, ns, na, nc, out, ldo,
                        transpose);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// out[e][i] = beta * base[e][i] + alpha * sum_{q<m} V[q][i] C[q*ldc + e], e < ne
+// out[e][i] = beta * base[e][i] + alpha * sum_{q<m} V[q][i] C[q*ldc + e], e < ne,
+// where V[q] = V1[q] for q < m1 and V2[q - m1] for m1 <= q < m
 // grid (D/256, ceil(ne/4)): four outputs per thread, C slice staged in LDS
 // ---------------------------------------------------------------------------
 constexpr int NN_E = 4;
 
-__global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V, int64_t ldv, int m, int D,
+__global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1, int64_t ldv1, int m1,
+                                                  const double *__restrict__ V2, int64_t ldv2, int m, int D,
                                                   const double *__restrict__ Cm, int ldc, int ne,
                                                   const double *__restrict__ base, int64_t ldb, double beta,
                                                   double alpha, double *__restrict__ out, int64_t ldo)
@@ -319,8 +335,13 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V, 
     double acc[NN_E];
 #pragma unroll
     for (int e = 0; e < NN_E; ++e) acc[e] = 0.0;
-    for (int q = 0; q < m; ++q) {
-        const double v = V[(int64_t)q * ldv + i];
+    for (int q = 0; q < m1; ++q) {
+        const double v = V1[(int64_t)q * ldv1 + i];
+#pragma unroll
+        for (int e = 0; e < NN_E; ++e) acc[e] = fma(v, cs[q * NN_E + e], acc[e]);
+    }
+    for (int q = m1; q < m; ++q) {
+        const double v = V2[(int64_t)(q - m1) * ldv2 + i];
 #pragma unroll
         for (int e = 0; e < NN_E; ++e) acc[e] = fma(v, cs[q * NN_E + e], acc[e]);
     }
@@ -335,15 +356,17 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V, 
 }
 
 // out and base may be the same rows (in-place update of one element by one
-// thread); out must not overlap V.
-hipError_t launch_nn(const double *V, int64_t ldv, int m, int D, const double *C, int ldc, int ne,
-                     const double *base, int64_t ldb, double beta, double alpha, double *out, int64_t ldo,
-                     hipStream_t st)
+// thread); out must not overlap the rows read from V1 or V2.
+hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, int64_t ldv2, int m, int D,
+                     const double *C, int ldc, int ne, const double *base, int64_t ldb, double beta, double alpha,
+                     double *out, int64_t ldo, hipStream_t st)
 {
     if (ne <= 0 || D <= 0) return hipSuccess;
+    if (m1 < 0 || m1 > m || (m1 < m && V2 == nullptr)) return hipErrorInvalidValue;
     const dim3 g((D + 255) / 256, (ne + NN_E - 1) / NN_E), bl(256);
     const size_t shm = sizeof(double) * NN_E * (size_t)(m > 0 ? m : 1);
-    hipLaunchKernelGGL(k_nn_small, g, bl, shm, st, V, ldv, m, D, C, ldc, ne, base, ldb, beta, alpha, out, ldo);
+    hipLaunchKernelGGL(k_nn_small, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta, alpha,
+                       out, ldo);
     return hipGetLastError();
 }
 
@@ -389,121 +412,150 @@ hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D,
 }
 
 // diagonal (Jacobi) correction t = r / (theta - H_ii), |den| floored at 1e-8
-// with its sign kept; sel[c] picks the residual row of output c
+// with its sign kept; sel.e[c] picks the residual row of output c
 __global__ void k_jacobi_correct(const double *__restrict__ R, int64_t ld, int D,
-                                 const double *__restrict__ diag, const double *__restrict__ theta,
-                                 const int32_t *__restrict__ sel, int nsel, double *__restrict__ T,
-                                 int64_t ldt)
+                                 const double *__restrict__ diag, const double *__restrict__ theta, DavSel sel,
+                                 int nsel, double *__restrict__ T, int64_t ldt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= D || c >= nsel) return;
-    const int e = sel[c];
+    const int e = sel.e[c];
     double den = theta[e] - diag[i];
     if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
     T[(int64_t)c * ldt + i] = R[(int64_t)e * ld + i] / den;
 }
 
 hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
-                                 const int32_t *sel, int nsel, double *T, int64_t ldt, hipStream_t st)
+                                 const DavSel &sel, int nsel, double *T, int64_t ldt, hipStream_t st)
 {
     if (nsel <= 0) return hipSuccess;
+    if (nsel > 32) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_jacobi_correct, dim3((D + 255) / 256, nsel), dim3(256), 0, st, R, ld, D, diag, theta,
                        sel, nsel, T, ldt);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky QR of a block with column pivoting (one wave): from the Gram
-// matrix G = T^T T (b x b, b <= 32) pick columns greedily by the largest
-// remaining Schur-complement diagonal, stop when it falls below rel^2 times
-// the reference squared norm of that column (ref[j] if given, else G[j][j]),
-// and return C (b x b, column c < rank = output vector c) with
-// T C = orthonormal basis of the kept columns; columns c >= rank are zero.
+// Cholesky QR of a projected block with column pivoting (one wave).
+// The block is T' = T - V S with S = V^T T (m x b, row q = V column q); its
+// Gram matrix is taken as G - S^T S with G = T^T T (b x b, b <= 32), which
+// equals T'^T T' up to S^T (V^T V - I) S. Columns are picked greedily by the
+// largest remaining Schur-complement diagonal and kept while it exceeds rel^2
+// times the reference squared norm of that column (ref[j * ref_stride] if
+// given, else the projected Gram diagonal). With R the Cholesky factor of the
+// kept columns in pivot order and B = P R^-1 (b x b, column c < rank), the
+// output is the (m + b) x b matrix M = [-S B; B], so that [V | T] M = T' B is
+// an orthonormal basis of the kept directions; columns c >= rank are zero.
 // ---------------------------------------------------------------------------
-constexpr int PCH_MAX = 32;
+constexpr int PCH_MAX = 32, PCH_M = 96;
+
+struct PchI2 {
+    int x, y;
+};
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double pch_dpp(double v)
+{
+    PchI2 a = __builtin_bit_cast(PchI2, v);
+    a.x = __builtin_amdgcn_update_dpp(0, a.x, CTRL, ROW_MASK, BANK_MASK, true);
+    a.y = __builtin_amdgcn_update_dpp(0, a.y, CTRL, ROW_MASK, BANK_MASK, true);
+    return __builtin_bit_cast(double, a);
+}
+
+__device__ __forceinline__ double pch_rl(double v, int lane)
+{
+    PchI2 a = __builtin_bit_cast(PchI2, v);
+    a.x = __builtin_amdgcn_readlane(a.x, lane);
+    a.y = __builtin_amdgcn_readlane(a.y, lane);
+    return __builtin_bit_cast(double, a);
+}
+
+// maximum over the 64 lanes of values >= 0 (lanes without a DPP source read
+// 0): within rows of 16 by row shifts, then across rows by row broadcasts;
+// the result collects in lane 63 and is read from there
+__device__ __forceinline__ double pch_wmax(double v)
+{
+    double s = fmax(v, pch_dpp<0x111, 0xf, 0xf>(v));
+    s = fmax(s, pch_dpp<0x112, 0xf, 0xf>(v));
+    s = fmax(s, pch_dpp<0x113, 0xf, 0xf>(v));
+    s = fmax(s, pch_dpp<0x114, 0xf, 0xe>(s));
+    s = fmax(s, pch_dpp<0x118, 0xf, 0xc>(s));
+    s = fmax(s, pch_dpp<0x142, 0xa, 0xf>(s));
+    s = fmax(s, pch_dpp<0x143, 0xc, 0xf>(s));
+    return pch_rl(s, 63);
+}
 
 __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int ldg, int b,
-                                              const double *__restrict__ ref, double rel,
+                                              const double *__restrict__ S, int lds, int m,
+                                              const double *__restrict__ ref, int ref_stride, double rel,
                                               double *__restrict__ Cout, int ldc, int32_t *__restrict__ rank_out)
 {
-    __shared__ double A[PCH_MAX][PCH_MAX + 1];
-    __shared__ double Rq[PCH_MAX][PCH_MAX + 1];   // row i, original column q
-    __shared__ double R[PCH_MAX][PCH_MAX + 1];    // row i, pivot position j
-    __shared__ double Ri[PCH_MAX][PCH_MAX + 1];
-    __shared__ int perm[PCH_MAX];
-    __shared__ double refd[PCH_MAX];
-    __shared__ int rank_sh;
+    __shared__ double A[PCH_MAX][PCH_MAX + 1];    // lane l owns column l
+    __shared__ double Ss[PCH_M][PCH_MAX + 1];
+    __shared__ double Rq[PCH_MAX][PCH_MAX + 1];   // row i of R by original column
+    __shared__ double R[PCH_MAX][PCH_MAX + 1];    // R in pivot order
+    __shared__ double Ri[PCH_MAX][PCH_MAX + 1];   // its inverse
+    __shared__ double Bq[PCH_MAX][PCH_MAX + 1];   // B by original column
+    __shared__ int piv[PCH_MAX];
     const int t = threadIdx.x;
+    const int tc = t < PCH_MAX ? t : PCH_MAX - 1;   // in-bounds column for idle lanes
+    for (int e = t; e < m * b; e += 64) Ss[e / b][e % b] = S[(int64_t)(e / b) * lds + e % b];
     for (int e = t; e < b * b; e += 64) {
         const int i = e / b, j = e % b;
         A[i][j] = 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
     }
-    // drop threshold per original column: rel^2 times the reference norm^2
-    if (t < b) refd[t] = rel * rel * (ref ? ref[t] : G[(int64_t)t * ldg + t]);
     for (int e = t; e < PCH_MAX * PCH_MAX; e += 64) {
         Rq[e / PCH_MAX][e % PCH_MAX] = 0.0;
-        R[e / PCH_MAX][e % PCH_MAX] = 0.0;
-        Ri[e / PCH_MAX][e % PCH_MAX] = 0.0;
+        Bq[e / PCH_MAX][e % PCH_MAX] = 0.0;
     }
-    if (t < PCH_MAX) perm[t] = t;
-    if (t == 0) rank_sh = -1;
     __syncthreads();
+    // A -= S^T S (the same products in the same order for (i, j) and (j, i))
+    for (int e = t; e < b * b; e += 64) {
+        const int i = e / b, j = e % b;
+        double g = A[i][j];
+        for (int q = 0; q < m; ++q) g = fma(-Ss[q][i], Ss[q][j], g);
+        A[i][j] = g;
+    }
+    __syncthreads();
+    const bool mine = t < b;
+    const double refd = mine ? rel * rel * (ref ? ref[(int64_t)t * ref_stride] : A[t][t]) : 0.0;
+    // Every value that another lane reads (key through DPP, the R row through
+    // LDS) is formed by selects with the whole wave active, so no lane holds a
+    // stale register; only the stores are masked.
+    bool used = !mine;
     int r = b;
     for (int i = 0; i < b; ++i) {
-        {
-            // pivot: the largest admissible remaining diagonal, ties to the first
-            // position (wave-wide argmax; every lane ends with the same pair)
-            double bd = -1.0;
-            int bj = b;
-            if (t >= i && t < b) {
-                const int pj = perm[t];
-                const double d = A[pj][pj];
-                if (d > refd[pj] && d > 0.0) {
-                    bd = d;
-                    bj = t;
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double od = __shfl_xor(bd, o, 64);
-                const int oj = __shfl_xor(bj, o, 64);
-                if (od > bd || (od == bd && oj < bj)) {
-                    bd = od;
-                    bj = oj;
-                }
-            }
-            __syncthreads();
-            if (t == 0) {
-                if (bd < 0.0) {
-                    rank_sh = i;
-                } else {
-                    const int tmp = perm[i];
-                    perm[i] = perm[bj];
-                    perm[bj] = tmp;
-                }
-            }
-        }
-        __syncthreads();
-        if (rank_sh >= 0) {
-            r = rank_sh;
+        // pivot: the largest admissible remaining diagonal (ties: lowest column)
+        const double d = A[tc][tc];
+        const bool cand = !used && d > refd && d > 0.0;
+        const double key = cand ? d : 0.0;
+        const double mx = pch_wmax(key);
+        if (!(mx > 0.0)) {
+            r = i;
             break;
         }
-        const int pi = perm[i];
-        const double rii = sqrt(A[pi][pi]);
-        // row i of R over the columns not yet pivoted, by original column
-        for (int j = i + t; j < b; j += 64) Rq[i][perm[j]] = (j == i) ? rii : A[pi][perm[j]] / rii;
+        const int p = __ffsll((unsigned long long)__ballot(key == mx)) - 1;
+        const double rpp = sqrt(mx);
+        const double quo = A[p][tc] / rpp;
+        const double rl = used ? 0.0 : (t == p ? rpp : quo);
+        used = used || t == p;
+        if (mine) Rq[i][t] = rl;
+        if (t == 0) piv[i] = p;
         __syncthreads();
-        // Schur complement update of the remaining block
-        for (int e = t; e < (b - i - 1) * (b - i - 1); e += 64) {
-            const int qj = perm[i + 1 + e / (b - i - 1)], ql = perm[i + 1 + e % (b - i - 1)];
-            A[qj][ql] -= Rq[i][qj] * Rq[i][ql];
+        // Schur complement on the columns still free: lane l updates its column
+        // with the R row read back from LDS
+        const unsigned long long freem = __ballot(!used);
+        for (int q = 0; q < b; ++q) {
+            const double rq = Rq[i][q];
+            const double a = A[q][tc];
+            if (!used && ((freem >> q) & 1ull)) A[q][tc] = fma(-rq, rl, a);
         }
-        __syncthreads();
     }
-    // upper-triangular factor in final pivot order
+    __syncthreads();
     for (int e = t; e < r * r; e += 64) {
         const int i = e / r, j = e % r;
-        R[i][j] = (j >= i) ? Rq[i][perm[j]] : 0.0;
+        R[i][j] = (j >= i) ? Rq[i][piv[j]] : 0.0;
     }
     __syncthreads();
     // inverse of R, column c per lane
@@ -516,37 +568,32 @@ __global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int 
         }
     }
     __syncthreads();
-    // C[perm[j]][c] = Ri[j][c]
-    for (int e = t; e < b * b; e += 64) {
-        const int q = e / b, c = e % b;
-        Cout[(int64_t)q * ldc + c] = 0.0;
-    }
-    __syncthreads();
+    // B[perm[j]][c] = (R^-1)[j][c]: upper triangular, only j <= c was formed
     for (int e = t; e < r * r; e += 64) {
         const int j = e / r, c = e % r;
-        Cout[(int64_t)perm[j] * ldc + c] = Ri[j][c];
+        Bq[piv[j]][c] = j <= c ? Ri[j][c] : 0.0;
+    }
+    __syncthreads();
+    // M = [-S B; B]
+    for (int e = t; e < (m + b) * b; e += 64) {
+        const int q = e / b, c = e % b;
+        double v;
+        if (q < m) {
+            v = 0.0;
+            for (int j = 0; j < b; ++j) v = fma(-Ss[q][j], Bq[j][c], v);
+        } else {
+            v = Bq[q - m][c];
+        }
+        Cout[(int64_t)q * ldc + c] = v;
     }
     if (t == 0) *rank_out = r;
 }
 
-hipError_t launch_pchol(const double *G, int ldg, int b, const double *ref, double rel, double *C, int ldc,
-                        int32_t *rank, hipStream_t st)
+hipError_t launch_pchol(const double *G, int ldg, int b, const double *S, int lds, int m, const double *ref,
+                        int ref_stride, double rel, double *C, int ldc, int32_t *rank, hipStream_t st)
 {
-    if (b <= 0 || b > PCH_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, st, G, ldg, b, ref, rel, C, ldc, rank);
-    return hipGetLastError();
-}
-
-// diagonal of a small matrix
-__global__ void k_diag_small(const double *__restrict__ G, int ldg, int b, double *__restrict__ out)
-{
-    const int t = threadIdx.x;
-    if (t < b) out[t] = G[(int64_t)t * ldg + t];
-}
-
-hipError_t launch_diag_small(const double *G, int ldg, int b, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_diag_small, dim3(1), dim3(64), 0, st, G, ldg, b, out);
+    if (b <= 0 || b > PCH_MAX || m < 0 || m > PCH_M || (m > 0 && S == nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, st, G, ldg, b, S, lds, m, ref, ref_stride, rel, C, ldc, rank);
     return hipGetLastError();
 }
 

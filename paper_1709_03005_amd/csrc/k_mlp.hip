@@ -342,27 +342,25 @@ __device__ __forceinline__ void mlp_features(double th, double hii, double rho, 
 }
 
 __global__ void k_mlp_dav_features(const double *__restrict__ diag, const double *__restrict__ rho, int D, int Dc,
-                                   const double *__restrict__ theta, const int32_t *__restrict__ sel, int nsel,
-                                   float *__restrict__ X)
+                                   const double *__restrict__ theta, DavSel sel, int nsel, float *__restrict__ X)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= D || c >= nsel) return;
     float f[MLP_IN];
-    mlp_features(theta[sel[c]], diag[i], rho[i], i >= Dc, f);
+    mlp_features(theta[sel.e[c]], diag[i], rho[i], i >= Dc, f);
     for (int q = 0; q < MLP_IN; ++q) X[((int64_t)c * D + i) * MLP_IN + q] = f[q];
 }
 
 // t = exp(clamp(g)) r / den; a non-finite value falls back to the Jacobi step
 __global__ void k_mlp_dav_correct(const double *__restrict__ R, int64_t ld, int D, const double *__restrict__ diag,
-                                  const double *__restrict__ theta, const int32_t *__restrict__ sel, int nsel,
-                                  const float *__restrict__ g, double *__restrict__ T, int64_t ldt,
+                                  const double *__restrict__ theta, DavSel sel, int nsel, const float *__restrict__ g, double *__restrict__ T, int64_t ldt,
                                   int32_t *__restrict__ nfallback)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= D || c >= nsel) return;
-    const int e = sel[c];
+    const int e = sel.e[c];
     double den = theta[e] - diag[i];
     if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
     const double tj = R[(int64_t)e * ld + i] / den;
@@ -400,10 +398,11 @@ hipError_t launch_row_norms(const double *H, int64_t ld, int D, double *rho, hip
 }
 
 hipError_t launch_mlp_dav(const float *w, const __bf16 *w2, const __bf16 *w2t, const double *R, int64_t ld, int D,
-                          int Dc, const double *diag, const double *rho, const double *theta, const int32_t *sel,
+                          int Dc, const double *diag, const double *rho, const double *theta, const DavSel &sel,
                           int nsel, float *X, float *g, double *T, int64_t ldt, int32_t *nfallback, hipStream_t st)
 {
     if (nsel <= 0) return hipSuccess;
+    if (nsel > 32) return hipErrorInvalidValue;
     const dim3 gr((D + 255) / 256, nsel);
     hipLaunchKernelGGL(k_mlp_dav_features, gr, dim3(256), 0, st, diag, rho, D, Dc, theta, sel, nsel, X);
     hipError_t e = launch_mlp_forward(w, w2, w2t, X, (int64_t)D * nsel, g, st);

@@ -92,6 +92,28 @@ def test_davidson_eigenpairs(cc, name, k):
     assert np.linalg.norm(r, axis=0).max() < 1e-8
 
 
+def test_davidson_dropped_directions(cc):
+    """A tolerance below what FP64 reaches keeps the solve going until the
+    corrections lie inside the basis: the rank test drops them and the
+    iteration repeats its Rayleigh-Ritz step on the kept directions. The
+    pairs stay exact (oracle matrix, LAPACK) and orthonormal."""
+    inst, (H, _, _) = _oracle("tiny")
+    k = 5
+    w, _ = oracle.lowest_eigenpairs(H, k)
+    with cc.from_instance(inst) as ctx:
+        ctx.build()
+        ev, vec, info, rc = ctx.davidson(k, tol=1e-14, max_iter=80)
+    print(f"[dropped] rc={rc} iterations={info.iterations} dropped={info.dropped} "
+          f"rayleigh_ritz={info.rr_calls}", flush=True)
+    assert info.dropped > 0
+    assert info.rr_calls > info.iterations          # the repeated Rayleigh-Ritz steps
+    scale = max(np.abs(w).max(), 1.0)
+    assert np.all(np.abs(ev - w) <= 1e-10 * np.maximum(np.abs(w), scale)), (ev - w)
+    assert np.abs(vec @ vec.T - np.eye(k)).max() < 1e-12
+    r = H @ vec.T - vec.T * ev[None, :]
+    assert np.linalg.norm(r, axis=0).max() < 1e-10
+
+
 def test_input_validation(cc):
     inst = synth.tiny()
     ctx = cc.Context(0)
