@@ -132,6 +132,15 @@ __device__ __forceinline__ double rr_get(double lo, double hi, int i)
 // rotations per round, m-1 rounds per sweep; a rotation is skipped when
 // |a_pq| <= 1e-16 sqrt(|a_pp a_qq|), and the sweeps stop after one with no
 // rotation. Reads G itself (unscaled) and writes theta and Y.
+// a value every lane holds alike (read from LDS), as a wave-uniform scalar
+__device__ __forceinline__ double rr_uni(double v)
+{
+    RrI2 a = __builtin_bit_cast(RrI2, v);
+    a.x = __builtin_amdgcn_readfirstlane(a.x);
+    a.y = __builtin_amdgcn_readfirstlane(a.y);
+    return __builtin_bit_cast(double, a);
+}
+
 // ---------------------------------------------------------------------------
 __device__ void rr_jacobi(RRShared &sh, const double *__restrict__ G, int ldg, int m, double *__restrict__ theta,
                           double *__restrict__ Y, int ldy, int max_sweeps)
@@ -320,77 +329,85 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
         // ---- Householder reduction to tridiagonal form ------------------------
         // Step k: x = row k of the trailing matrix, H_k = I - tau v v^T with
         // v_{k+1} = 1 and v_r = x_r * hinv[k] below; row k keeps x afterwards.
-        // Thread (wave w, lane l) owns column lane + 64 (w & 1) over the rows
-        // k+1+s, k+1+s+RR_SL, ... of slice s = w >> 1. Every wave holds x, v and
-        // w in registers and forms sigma and K itself (identical bits).
+        // Thread (wave w, lane l) owns column c = l + 64 (w & 1) over the rows
+        // k+1+s, k+1+s+RR_SL, ... of slice s = w >> 1. Broadcast operands (x_r,
+        // v_r, w_r) are LDS reads at one address per wave, not lane reads; wave 0
+        // alone forms sigma, beta, tau and hinv, which the others read after the
+        // barrier; each wave keeps its own copy of v and w (rows of Z, free here),
+        // so no barrier separates writing them from reading them. A lane whose
+        // column is not updated stores into the padding column RR_MAX. Up to 64
+        // columns the 8 waves are 8 row slices over one column half.
         {
-            const int half = wv & 1, slice = wv >> 1;
+            const int nsl = n <= 64 ? 2 * RR_SL : RR_SL;
+            const int half = n <= 64 ? 0 : wv & 1, slice = n <= 64 ? wv : wv >> 1;
             const int col = lane + 64 * half;
+            const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds column for loads
+            double *vw = &Z[2 * RR_SL + 2 * wv][0];             // this wave's v (then w at +RR_LD)
             for (int k = 0; k + 2 < n; ++k) {
                 const double x0 = lane < n ? A[k][lane] : 0.0;
                 const double x1 = lane + 64 < n ? A[k][lane + 64] : 0.0;
-                // row k+1 too, before the first barrier: other waves update it afterwards
+                // row k+1 before the barrier: other waves update it afterwards
                 const double y0 = lane < n ? A[k + 1][lane] : 0.0;
                 const double y1 = lane + 64 < n ? A[k + 1][lane + 64] : 0.0;
-                // partial S_col = sum over this slice's rows r >= k+2 of A[r][col] x_r (into
-                // Z); it needs only x, so it overlaps the scalar chain below. Loops that read
-                // lanes run with the whole wave active: a lane that sits out a branch may not
-                // hold the value another lane reads.
                 const bool act = col < n && col >= k + 1;
-                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
+                const int cst = act ? col : RR_MAX;   // store column
+                // partial S_c = sum over this slice's rows r >= k+2 of A[r][c] x_r
                 {
-                    double acc = 0.0;
+                    double s0 = 0.0, s1 = 0.0;
                     int r = k + 2 + slice;
-                    for (; r < n && r < 64; r += RR_SL) acc = fma(A[r][cc], rr_rl(x0, r), acc);
-                    for (; r < n; r += RR_SL) acc = fma(A[r][cc], rr_rl(x1, r - 64), acc);
-                    if (col < RR_MAX) Z[slice][col] = act ? acc : 0.0;
-                }
-                const double sig =
-                    rr_wsum((lane >= k + 2 ? x0 * x0 : 0.0) + (lane + 64 >= k + 2 ? x1 * x1 : 0.0));
-                const double alpha = rr_get(x0, x1, k + 1);
-                if (sig == 0.0) {   // the same in every wave
-                    if (tid == 0) {
-                        sh.tau[k] = 0.0;
-                        sh.e[k] = alpha;
+                    for (; r + nsl < n; r += 2 * nsl) {
+                        s0 = fma(A[r][cc], A[k][r], s0);
+                        s1 = fma(A[r + nsl][cc], A[k][r + nsl], s1);
                     }
-                    __syncthreads();   // Z is rewritten by the next step
+                    if (r < n) s0 = fma(A[r][cc], A[k][r], s0);
+                    Z[slice][col < RR_MAX ? col : RR_MAX] = act ? s0 + s1 : 0.0;
+                }
+                if (wv == 0) {
+                    const double sig =
+                        rr_wsum((lane >= k + 2 ? x0 * x0 : 0.0) + (lane + 64 >= k + 2 ? x1 * x1 : 0.0));
+                    const double alpha = rr_get(x0, x1, k + 1);
+                    if (lane == 0) {
+                        if (sig == 0.0) {
+                            sh.tau[k] = 0.0;
+                            sh.e[k] = alpha;
+                            sh.hinv[k] = 0.0;
+                        } else {
+                            const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+                            sh.tau[k] = (beta - alpha) / beta;
+                            sh.e[k] = beta;
+                            sh.hinv[k] = 1.0 / (alpha - beta);
+                        }
+                    }
+                }
+                __syncthreads();
+                const double t = rr_uni(sh.tau[k]);
+                if (t == 0.0) {   // no reflection: row k+1 stays; nothing read Z
                     continue;
                 }
-                const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-                const double t = (beta - alpha) / beta;
-                const double inv = 1.0 / (alpha - beta);
-                if (tid == 0) {
-                    sh.tau[k] = t;
-                    sh.e[k] = beta;
-                    sh.hinv[k] = inv;
-                }
+                const double inv = rr_uni(sh.hinv[k]);
                 const double v0 = lane == k + 1 ? 1.0 : (lane >= k + 2 ? x0 * inv : 0.0);
                 const double v1 = lane + 64 == k + 1 ? 1.0 : (lane + 64 >= k + 2 ? x1 * inv : 0.0);
-                __syncthreads();
                 // p_c = t (A[k+1][c] + inv S_c): v_{k+1} = 1, v_r = x_r inv below
                 double p0 = 0.0, p1 = 0.0;
-                for (int q = 0; q < RR_SL; ++q) {
+                for (int q = 0; q < nsl; ++q) {
                     p0 += Z[q][lane];
-                    if (lane + 64 < RR_MAX) p1 += Z[q][lane + 64];
+                    p1 += Z[q][lane + 64 < RR_MAX ? lane + 64 : RR_MAX];
                 }
                 p0 = lane < n ? t * fma(inv, p0, y0) : 0.0;
                 p1 = lane + 64 < n ? t * fma(inv, p1, y1) : 0.0;
                 const double K = 0.5 * t * rr_wsum(p0 * v0 + p1 * v1);
                 const double w0 = p0 - K * v0, w1 = p1 - K * v1;
+                vw[lane] = v0;
+                vw[RR_LD + lane] = w0;
+                if (lane + 64 < RR_MAX) {
+                    vw[lane + 64] = v1;
+                    vw[RR_LD + lane + 64] = w1;
+                }
                 // A' -= v w^T + w v^T on this thread's column and slice
                 {
                     const double vc = half ? v1 : v0, wc = half ? w1 : w0;
-                    int r = k + 1 + slice;
-                    #pragma unroll 4
-                    for (; r < n && r < 64; r += RR_SL) {
-                        const double nv = A[r][cc] - (rr_rl(v0, r) * wc + rr_rl(w0, r) * vc);
-                        if (act) A[r][col] = nv;
-                    }
-                    #pragma unroll 4
-                    for (; r < n; r += RR_SL) {
-                        const double nv = A[r][cc] - (rr_rl(v1, r - 64) * wc + rr_rl(w1, r - 64) * vc);
-                        if (act) A[r][col] = nv;
-                    }
+                    for (int r = k + 1 + slice; r < n; r += nsl)
+                        A[r][cst] = A[r][cc] - (vw[r] * wc + vw[RR_LD + r] * vc);
                 }
                 __syncthreads();
             }
@@ -650,44 +667,40 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
         }
 
         // ---- back-transformation Z <- H_0 H_1 ... H_{n-3} Z --------------------
-        // thread (wave w, lane l): column l + 64 (w & 1), row slice w >> 1
+        // the reflector rows first become the vectors themselves (v_{k+1} = 1,
+        // v_r = x_r hinv below), read as broadcasts; thread (wave w, lane l):
+        // column l + 64 (w & 1), row slice w >> 1 (up to 64 columns: column l,
+        // row slice w; the partials of slices 4..7 go to sc[0..3], free here)
+        for (int t = tid; t < n * n; t += RR_NT) {
+            const int k = t / n, r = t % n;
+            if (k + 2 < n && r >= k + 1 && sh.tau[k] != 0.0) A[k][r] = r == k + 1 ? 1.0 : A[k][r] * sh.hinv[k];
+        }
+        __syncthreads();
         {
-            const int col = lane + 64 * (wv & 1), bs = wv >> 1;
+            const int nbs = n <= 64 ? 2 * RR_BSL : RR_BSL;
+            const int col = n <= 64 ? lane : lane + 64 * (wv & 1), bs = n <= 64 ? wv : wv >> 1;
+            double *mypart = bs < RR_BSL ? &sh.u.part[bs][0] : &sh.sc[bs - RR_BSL][0];
+            const bool act = col < n;
+            const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds column for loads
+            const int cst = act ? col : RR_MAX;               // store column (padding when idle)
             for (int k = n - 3; k >= 0; --k) {
-                const double t = sh.tau[k];
+                const double t = rr_uni(sh.tau[k]);
                 if (t == 0.0) continue;
-                const double inv = sh.hinv[k];
-                const double r0 = lane == k + 1 ? 1.0 : (lane >= k + 2 && lane < n ? A[k][lane] * inv : 0.0);
-                const double r1 =
-                    lane + 64 == k + 1 ? 1.0 : (lane + 64 >= k + 2 && lane + 64 < n ? A[k][lane + 64] * inv : 0.0);
-                const bool act = col < n;
-                const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds address when masked
-                if (bs < RR_BSL) {   // wave-uniform
-                    double acc = 0.0;
+                {
+                    double s0 = 0.0, s1 = 0.0;
                     int r = k + 1 + bs;
-                    #pragma unroll 4
-                    for (; r < n && r < 64; r += RR_BSL) acc = fma(rr_rl(r0, r), Z[r][cc], acc);
-                    #pragma unroll 4
-                    for (; r < n; r += RR_BSL) acc = fma(rr_rl(r1, r - 64), Z[r][cc], acc);
-                    if (col < RR_MAX) sh.u.part[bs][col] = act ? acc : 0.0;
+                    for (; r + nbs < n; r += 2 * nbs) {
+                        s0 = fma(A[k][r], Z[r][cc], s0);
+                        s1 = fma(A[k][r + nbs], Z[r + nbs][cc], s1);
+                    }
+                    if (r < n) s0 = fma(A[k][r], Z[r][cc], s0);
+                    if (col < RR_MAX) mypart[col] = act ? s0 + s1 : 0.0;
                 }
                 __syncthreads();
-                if (bs < RR_BSL) {
-                    double wc = 0.0;
-                    for (int q = 0; q < RR_BSL; ++q) wc += sh.u.part[q][cc];
-                    wc *= t;
-                    int r = k + 1 + bs;
-                    #pragma unroll 4
-                    for (; r < n && r < 64; r += RR_BSL) {
-                        const double nz = Z[r][cc] - rr_rl(r0, r) * wc;
-                        if (act) Z[r][col] = nz;
-                    }
-                    #pragma unroll 4
-                    for (; r < n; r += RR_BSL) {
-                        const double nz = Z[r][cc] - rr_rl(r1, r - 64) * wc;
-                        if (act) Z[r][col] = nz;
-                    }
-                }
+                double wc = 0.0;
+                for (int q = 0; q < nbs; ++q) wc += q < RR_BSL ? sh.u.part[q][cc] : sh.sc[q - RR_BSL][cc];
+                wc *= t;
+                for (int r = k + 1 + bs; r < n; r += nbs) Z[r][cst] = Z[r][cc] - A[k][r] * wc;
                 __syncthreads();
             }
         }
