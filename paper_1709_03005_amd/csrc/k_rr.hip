@@ -132,6 +132,18 @@ __device__ __forceinline__ double rr_get(double lo, double hi, int i)
 // rotations per round, m-1 rounds per sweep; a rotation is skipped when
 // |a_pq| <= 1e-16 sqrt(|a_pp a_qq|), and the sweeps stop after one with no
 // rotation. Reads G itself (unscaled) and writes theta and Y.
+// 1/q from the hardware estimate and two Newton-Raphson corrections
+// r <- r + r (1 - q r), each squaring the relative error: a short dependent
+// chain for the recurrences below, within about one ulp of the quotient
+__device__ __forceinline__ double rr_recip(double q)
+{
+    double r = __builtin_amdgcn_rcp(q);
+    double e = fma(-q, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-q, r, 1.0);
+    return fma(r, e, r);
+}
+
 // a value every lane holds alike (read from LDS), as a wave-uniform scalar
 __device__ __forceinline__ double rr_uni(double v)
 {
@@ -485,7 +497,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 if (__all(conv)) break;
                 double q = rr_rl(dl0, 0) - x;
                 q = (q == 0.0) ? -DBL_MIN : q;
-                double qp = -1.0, qpp = 0.0, rq = 1.0 / q;
+                double qp = -1.0, qpp = 0.0, rq = rr_recip(q);
                 double Gs = qp * rq, Hs = Gs * Gs;
                 auto lag = [&](double di, double e2p) {
                     const double qn = (di - x) - e2p * rq;
@@ -494,7 +506,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                     q = (qn == 0.0) ? -DBL_MIN : qn;
                     qp = qpn;
                     qpp = qppn;
-                    rq = 1.0 / q;
+                    rq = rr_recip(q);
                     const double t = qp * rq;
                     Gs += t;
                     Hs += t * t - qpp * rq;
@@ -581,7 +593,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
             if (dp == 0.0) dp = -DBL_MIN;
             if (j < n) Z[0][j] = dp;
             auto fwd = [&](int i, double di, double qi) {
-                double x = (di - lj) - qi / dp;
+                double x = (di - lj) - qi * rr_recip(dp);
                 if (x == 0.0) x = -DBL_MIN;
                 dp = x;
                 if (j < n) Z[i][j] = x;
@@ -599,7 +611,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
             int r = n - 1;
             auto bwd = [&](int i, double dv, double qi) {
                 const double di = dv - lj;
-                dm = di - qi / dm;
+                dm = di - qi * rr_recip(dm);
                 if (dm == 0.0) dm = -DBL_MIN;
                 const double g = fabs(Z[i][jc] + dm - di);
                 if (g < best) {
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 if (dm == 0.0) dm = -DBL_MIN;
                 for (int i = n - 2; i >= r; --i) {
                     const double ei = sh.e[i];
-                    const double rho = -ei / dm;
+                    const double rho = -ei * rr_recip(dm);
                     Z[i + 1][j] = rho;
                     dm = (sh.d[i] - lj) + ei * rho;
                     if (dm == 0.0) dm = -DBL_MIN;
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 Z[r][j] = 1.0;
                 for (int i = r; i + 1 < n; ++i) Z[i + 1][j] *= Z[i][j];
                 // above the twist: z_i = -(e_i / delta+_i) z_{i+1}
-                for (int i = r - 1; i >= 0; --i) Z[i][j] = -(sh.e[i] / Z[i][j]) * Z[i + 1][j];
+                for (int i = r - 1; i >= 0; --i) Z[i][j] = -(sh.e[i] * rr_recip(Z[i][j])) * Z[i + 1][j];
                 double nn = 0.0;
                 for (int i = 0; i < n; ++i) nn += Z[i][j] * Z[i][j];
                 const double inv = 1.0 / sqrt(nn);
