@@ -94,7 +94,8 @@ typedef struct {
 typedef struct {
     int32_t k;              /* eigenpairs wanted (lowest) */
     int32_t max_iter;       /* Davidson iterations */
-    int32_t max_subspace;   /* basis size before a thick restart (0: max(8k, 64)) */
+    int32_t max_subspace;   /* basis size before a thick restart (0: max(8k, 64), or 96
+                               from D = 20000 on; at most 96 and D) */
     int32_t precond;        /* CCH_PRECOND_* */
     double tol;             /* converged when ||H x - theta x||_2 <= tol, ||x|| = 1 */
     int32_t block;          /* Ritz pairs given a correction each iteration, k..16

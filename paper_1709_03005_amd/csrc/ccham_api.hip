@@ -1670,7 +1670,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     if (o->precond != CCH_PRECOND_JACOBI && o->precond != CCH_PRECOND_MLP)
         return fail(c, CCH_E_INVALID_ARG, "unknown preconditioner %d", o->precond);
     if (o->precond == CCH_PRECOND_MLP && !c->mlp) return fail(c, CCH_E_STATE, "no network attached (cch_davidson_set_mlp)");
-    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 64);
+    // default basis limit: max(8k, 64); from D = 20000 on the mat-vec outweighs
+    // the Rayleigh-Ritz step, and the largest basis (fewer restarts) wins
+    int mmax = o->max_subspace > 0 ? o->max_subspace : (D >= 20000 ? 96 : std::max(8 * k, 64));
     mmax = std::min(mmax, 96);
     mmax = std::min(mmax, D);
     const int kr = std::min(2 * k, D);         // kept at a thick restart; also the first block

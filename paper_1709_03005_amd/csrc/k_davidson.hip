@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const double *__restrict__ 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int qq = (lane >> 4) + 4 * v;
-                Wp[((int64_t)blockIdx.y * 16 + qq) * D + col] = acc[t][v];
+                if (qq < b) Wp[((int64_t)blockIdx.y * 16 + qq) * D + col] = acc[t][v];
             }
         }
     }
