@@ -194,6 +194,8 @@ struct LtPlan {
 
 }  // namespace
 
+constexpr int CCH_NAUX = 4;   // auxiliary streams of a build
+
 struct cch_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -224,6 +226,11 @@ struct cch_ctx {
     std::vector<LtPlan> lt;
     hipEvent_t ev[8] = {};
     hipEvent_t mv0 = nullptr, mv1 = nullptr, rr0 = nullptr, rr1 = nullptr;
+    // auxiliary streams (default priority) over which a build phase spreads its
+    // independent per-pair work; joined back into `stream` before the phase ends
+    hipStream_t aux[CCH_NAUX] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[CCH_NAUX] = {};
+    bool have_aux = false;
     int64_t relayout_elems = 0;
     int expansion_passes = 1;   // > 1: the budget split the expansion into column passes
     bool b_shared = false;      // all pairs use one integral-row buffer, laid out just before each product
@@ -330,6 +337,11 @@ cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream)
         return fail(nullptr, CCH_E_HIP, "hipEventCreate failed");
     }
     c->have_events = true;
+    bool aux_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < CCH_NAUX && aux_ok; ++i)
+        aux_ok = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    c->have_aux = aux_ok;   // without them every phase runs on the context stream
     c->opts.precision = CCH_PREC_FP64;
     *out = c;
     return CCH_OK;
@@ -347,6 +359,14 @@ cch_status cch_destroy(cch_ctx *c)
     if (c->mv1) (void)hipEventDestroy(c->mv1);
     if (c->rr0) (void)hipEventDestroy(c->rr0);
     if (c->rr1) (void)hipEventDestroy(c->rr1);
+    for (int i = 0; i < CCH_NAUX; ++i) {
+        if (c->aux[i]) {
+            (void)hipStreamSynchronize(c->aux[i]);
+            (void)hipStreamDestroy(c->aux[i]);
+        }
+        if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     delete c;
     return CCH_OK;
 }
@@ -735,69 +755,116 @@ static ExpandEpi expand_epi(cch_ctx *c, const PairPlan &p)
                      p.d_O, c->d_h, c->n_o, c->n_orb};
 }
 
-// phases 0-2: scans, target elements and densities, relayout
-static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev)
+// Independent launches of one phase spread round-robin over the auxiliary
+// streams: begin() makes them wait for what the stream has queued, end() makes
+// the stream wait for all of them. Off (batch capture, no streams): all on st.
+struct Fan {
+    cch_ctx *c;
+    hipStream_t st;
+    bool on;
+    hipError_t begin() const
+    {
+        if (!on) return hipSuccess;
+        hipError_t e = hipEventRecord(c->fork_ev, st);
+        for (int i = 0; i < CCH_NAUX && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->aux[i], c->fork_ev, 0);
+        return e;
+    }
+    hipStream_t operator()(int i) const { return on ? c->aux[i % CCH_NAUX] : st; }
+    hipError_t end() const
+    {
+        if (!on) return hipSuccess;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < CCH_NAUX && e == hipSuccess; ++i) {
+            e = hipEventRecord(c->join_ev[i], c->aux[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, c->join_ev[i], 0);
+        }
+        return e;
+    }
+};
+
+// phases 0-2: scans, target elements and densities, relayout; every symmetry
+// pair (and L2-target group) writes only its own buffers, so with `fan` they
+// run on the auxiliary streams side by side
+static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan)
 {
     const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
+    const Fan f{c, st, fan && c->have_aux};
     EVREC(0);
+    HIPCK(c, f.begin());
+    int w = 0;
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         HIPCK(c, launch_scan(SCAN_TT, c->W, sa.d_dets, sa.M, sb.d_dets, sb.M, 2 * c->n_o, p.pr.row_off,
-                             p.pr.row_cnt, p.pr.pl, st));
+                             p.pr.row_cnt, p.pr.pl, f(w++)));
     }
     for (auto &L : c->lt) {
         SymInfo &s = c->syms[L.sym];
         HIPCK(c, launch_scan(SCAN_LT, c->W, c->d_l2, c->n_l2, s.d_dets, s.M, 2 * c->n_o, L.pr.row_off,
-                             L.pr.row_cnt, L.pr.pl, st));
+                             L.pr.row_cnt, L.pr.pl, f(w++)));
     }
+    HIPCK(c, f.end());
     EVREC(1);
+    HIPCK(c, f.begin());
+    w = 0;
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
-        HIPCK(c, launch_pair_values(c->W, I, sa.d_dets, sb.d_dets, p.pr.pl, p.pr.n, p.d_hv, st));
+        const hipStream_t s = f(w++);
+        HIPCK(c, launch_pair_values(c->W, I, sa.d_dets, sb.d_dets, p.pr.pl, p.pr.n, p.d_hv, s));
         HIPCK(c, launch_projection(sa.M, p.pr.row_off, p.pr.row_cnt, p.pr.pl, p.d_hv, sa.d_ci, sa.S, sb.d_ci, sb.S,
-                                   p.nrows, p.d_rn, p.d_rn2, p.d_Y, p.d_Yo, p.d_HT, p.d_O, st));
+                                   p.nrows, p.d_rn, p.d_rn2, p.d_Y, p.d_Yo, p.d_HT, p.d_O, s));
         HIPCK(c, launch_bucket(p.pr.pl, p.pr.n, p.d_pqidx, c->n_o, p.n_slot, sa.M, p.d_key, p.d_count, p.d_start,
-                               p.d_cursor, p.d_sorted, p.d_tmp, p.d_d0, st));
+                               p.d_cursor, p.d_sorted, p.d_tmp, p.d_d0, s));
         const int M0 = (sa.irrep == sb.irrep) ? sa.M : 0;
         HIPCK(c, launch_gamma(c->W, p.pr.pl, p.d_start, p.d_count, p.d_sorted, p.d_d0, M0, p.d_slotP, p.d_slotQ,
                               p.n_slot, sa.d_dets, sa.d_ci, sa.S, sb.d_ci, sb.S, p.nrows, p.d_rn, p.d_rn2, p.d_At,
-                              st));
+                              s));
     }
+    HIPCK(c, f.end());
     EVREC(2);
+    HIPCK(c, f.begin());
+    w = 0;
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
         if (c->b_shared) continue;   // one shared buffer: rows are laid out pass by pass in phase 3
+        const hipStream_t s = f(w++);
         HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
-                                 sa.nc, sb.ja0, sb.nc, p.d_B, st));
+                                 sa.nc, sb.ja0, sb.nc, p.d_B, s));
         const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
         if (c->opts.precision == CCH_PREC_FP32) {
-            HIPCK(c, launch_to_f32(p.d_At, p.d_At32, (int64_t)K * p.nrows, st));
-            HIPCK(c, launch_to_f32(p.d_B, p.d_B32, (int64_t)K * N, st));
+            HIPCK(c, launch_to_f32(p.d_At, p.d_At32, (int64_t)K * p.nrows, s));
+            HIPCK(c, launch_to_f32(p.d_B, p.d_B32, (int64_t)K * N, s));
         } else if (c->opts.precision == CCH_PREC_SPLIT_BF16) {
             HIPCK(c, launch_slices(p.d_At, p.nrows, p.d_B, K, N, c->opts.split_slices, p.ldk, p.d_sigA, p.d_SA,
-                                   p.d_sigB, p.d_SB, st));
+                                   p.d_sigB, p.d_SB, s));
         }
     }
+    HIPCK(c, f.end());
     EVREC(3);
     return CCH_OK;
 }
 
 // phase 3: expansion product per symmetry pair
-static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st)
+static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st, bool fan)
 {
+    // one product per pair, side by side (not with the shared integral buffer,
+    // which the pairs use one after another)
+    const Fan f{c, st, fan && c->have_aux && !c->b_shared};
+    HIPCK(c, f.begin());
+    int w = 0;
     for (auto &p : c->pp) {
         SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
         if (sa.nc == 0 || sb.nc == 0) continue;
         const ExpandEpi ep = expand_epi(c, p);
         const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
+        const hipStream_t s = f(w++);
         if (c->opts.precision == CCH_PREC_FP32)
-            HIPCK(c, launch_expand_f32(p.d_At32, p.d_B32, p.nrows, N, K, ep, st));
+            HIPCK(c, launch_expand_f32(p.d_At32, p.d_B32, p.nrows, N, K, ep, s));
         else if (c->opts.precision == CCH_PREC_SPLIT_BF16)
             HIPCK(c, launch_expand_bf16split(p.d_SA, p.d_SB, p.d_sigA, p.d_sigB, c->opts.split_slices, p.nrows, N,
-                                             p.ldk, ep, st));
+                                             p.ldk, ep, s));
         else if (!c->b_shared)
-            HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, N, K, ep, st));
+            HIPCK(c, launch_expand_f64(p.d_At, p.d_B, p.nrows, N, K, ep, s));
         else {
             // passes over ranges of j: the rows j0..j0+nj-1 of the integral layout, then
             // the product's columns (j, j') of those rows; each output keeps its sum over K
@@ -812,12 +879,17 @@ static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st)
             }
         }
     }
+    HIPCK(c, f.end());
     return CCH_OK;
 }
 
-static cch_status enqueue_class4(cch_ctx *c, hipStream_t st)
+static cch_status enqueue_class4(cch_ctx *c, hipStream_t st, bool fan)
 {
-    for (auto &L : c->lt) HIPCK(c, launch_class4(c->W, class4_args(c, L), c->n_l2, st));
+    const Fan f{c, st, fan && c->have_aux};
+    HIPCK(c, f.begin());
+    int w = 0;
+    for (auto &L : c->lt) HIPCK(c, launch_class4(c->W, class4_args(c, L), c->n_l2, f(w++)));
+    HIPCK(c, f.end());
     return CCH_OK;
 }
 
@@ -845,10 +917,10 @@ cch_status cch_build(cch_ctx *c)
     HIPCK(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
     const bool ev = true;
-    TRY(enqueue_pre(c, st, ev));
-    TRY(enqueue_gemm(c, st));
+    TRY(enqueue_pre(c, st, ev, true));
+    TRY(enqueue_gemm(c, st, true));
     EVREC(4);
-    TRY(enqueue_class4(c, st));
+    TRY(enqueue_class4(c, st, true));
     EVREC(5);
     TRY(enqueue_l2(c, st));
     EVREC(6);
@@ -1410,7 +1482,7 @@ static cch_status batch_l2(cch_batch *b, int grid)
 
 static cch_status enqueue_batch(cch_batch *b)
 {
-    for (cch_ctx *c : b->cs) TRY(ctx_status(b, c, enqueue_pre(c, b->st, false)));
+    for (cch_ctx *c : b->cs) TRY(ctx_status(b, c, enqueue_pre(c, b->st, false, false)));
     TRY(batch_gemm(b, b->bm, b->g_gemm));
     TRY(batch_c4(b, b->g_c4));
     TRY(batch_l2(b, b->g_l2));
@@ -1533,7 +1605,7 @@ cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, in
         } else {
             // inputs of the persistent phases
             for (cch_ctx *c : b->cs)
-                if ((rc = ctx_status(b, c, enqueue_pre(c, b->st, false))) != CCH_OK) return cleanup_fail(rc);
+                if ((rc = ctx_status(b, c, enqueue_pre(c, b->st, false, false))) != CCH_OK) return cleanup_fail(rc);
             float best = 1e30f, ms = 0.0f;
             for (int bm : {64, 32})
                 for (int mult : {1, 2, 4, 8}) {
