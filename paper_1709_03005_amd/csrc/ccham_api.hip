@@ -194,7 +194,8 @@ struct LtPlan {
 
 }  // namespace
 
-constexpr int CCH_NAUX = 4;   // auxiliary streams of a build
+constexpr int CCH_NAUX = 6;   // auxiliary streams of a build: 4 for the symmetry pairs, class 4, L2 block
+constexpr int CCH_NPAIRS_ST = 4;
 
 struct cch_ctx {
     int device = 0;
@@ -230,7 +231,9 @@ struct cch_ctx {
     // independent per-pair work; joined back into `stream` before the phase ends
     hipStream_t aux[CCH_NAUX] = {};
     hipEvent_t fork_ev = nullptr, join_ev[CCH_NAUX] = {};
+    hipEvent_t c4_ev[2] = {}, l2_ev[2] = {};   // timing of the class-4 and L2 streams
     bool have_aux = false;
+    bool overlapped = false;   // the last build ran class 4 and the L2 block beside the pair phases
     int64_t relayout_elems = 0;
     int expansion_passes = 1;   // > 1: the budget split the expansion into column passes
     bool b_shared = false;      // all pairs use one integral-row buffer, laid out just before each product
@@ -341,6 +344,8 @@ cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream)
     for (int i = 0; i < CCH_NAUX && aux_ok; ++i)
         aux_ok = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 2 && aux_ok; ++i)
+        aux_ok = hipEventCreate(&c->c4_ev[i]) == hipSuccess && hipEventCreate(&c->l2_ev[i]) == hipSuccess;
     c->have_aux = aux_ok;   // without them every phase runs on the context stream
     c->opts.precision = CCH_PREC_FP64;
     *out = c;
@@ -367,6 +372,10 @@ cch_status cch_destroy(cch_ctx *c)
         if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
     }
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    for (int i = 0; i < 2; ++i) {
+        if (c->c4_ev[i]) (void)hipEventDestroy(c->c4_ev[i]);
+        if (c->l2_ev[i]) (void)hipEventDestroy(c->l2_ev[i]);
+    }
     delete c;
     return CCH_OK;
 }
@@ -766,15 +775,15 @@ struct Fan {
     {
         if (!on) return hipSuccess;
         hipError_t e = hipEventRecord(c->fork_ev, st);
-        for (int i = 0; i < CCH_NAUX && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->aux[i], c->fork_ev, 0);
+        for (int i = 0; i < CCH_NPAIRS_ST && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->aux[i], c->fork_ev, 0);
         return e;
     }
-    hipStream_t operator()(int i) const { return on ? c->aux[i % CCH_NAUX] : st; }
+    hipStream_t operator()(int i) const { return on ? c->aux[i % CCH_NPAIRS_ST] : st; }
     hipError_t end() const
     {
         if (!on) return hipSuccess;
         hipError_t e = hipSuccess;
-        for (int i = 0; i < CCH_NAUX && e == hipSuccess; ++i) {
+        for (int i = 0; i < CCH_NPAIRS_ST && e == hipSuccess; ++i) {
             e = hipEventRecord(c->join_ev[i], c->aux[i]);
             if (e == hipSuccess) e = hipStreamWaitEvent(st, c->join_ev[i], 0);
         }
@@ -785,7 +794,7 @@ struct Fan {
 // phases 0-2: scans, target elements and densities, relayout; every symmetry
 // pair (and L2-target group) writes only its own buffers, so with `fan` they
 // run on the auxiliary streams side by side
-static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan)
+static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan, bool lt_scans = true)
 {
     const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
     const Fan f{c, st, fan && c->have_aux};
@@ -798,6 +807,7 @@ static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan)
                              p.pr.row_cnt, p.pr.pl, f(w++)));
     }
     for (auto &L : c->lt) {
+        if (!lt_scans) break;
         SymInfo &s = c->syms[L.sym];
         HIPCK(c, launch_scan(SCAN_LT, c->W, c->d_l2, c->n_l2, s.d_dets, s.M, 2 * c->n_o, L.pr.row_off,
                              L.pr.row_cnt, L.pr.pl, f(w++)));
@@ -917,13 +927,45 @@ cch_status cch_build(cch_ctx *c)
     HIPCK(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
     const bool ev = true;
-    TRY(enqueue_pre(c, st, ev, true));
-    TRY(enqueue_gemm(c, st, true));
-    EVREC(4);
-    TRY(enqueue_class4(c, st, true));
-    EVREC(5);
-    TRY(enqueue_l2(c, st));
-    EVREC(6);
+    c->overlapped = c->have_aux;
+    if (c->overlapped) {
+        // class 4 (with its L2 x target scans) and the L2 block depend on no pair
+        // phase and write their own blocks of H: each on a stream of its own
+        // from the start, joined before the mirror
+        EVREC(0);
+        HIPCK(c, hipEventRecord(c->fork_ev, st));
+        hipStream_t s4 = c->aux[CCH_NPAIRS_ST], sl = c->aux[CCH_NPAIRS_ST + 1];
+        HIPCK(c, hipStreamWaitEvent(s4, c->fork_ev, 0));
+        HIPCK(c, hipStreamWaitEvent(sl, c->fork_ev, 0));
+        HIPCK(c, hipEventRecord(c->l2_ev[0], sl));
+        TRY(enqueue_l2(c, sl));
+        HIPCK(c, hipEventRecord(c->l2_ev[1], sl));
+        HIPCK(c, hipEventRecord(c->c4_ev[0], s4));
+        for (auto &L : c->lt) {
+            SymInfo &s = c->syms[L.sym];
+            HIPCK(c, launch_scan(SCAN_LT, c->W, c->d_l2, c->n_l2, s.d_dets, s.M, 2 * c->n_o, L.pr.row_off,
+                                 L.pr.row_cnt, L.pr.pl, s4));
+        }
+        TRY(enqueue_class4(c, s4, false));
+        HIPCK(c, hipEventRecord(c->c4_ev[1], s4));
+        TRY(enqueue_pre(c, st, ev, true, false));
+        TRY(enqueue_gemm(c, st, true));
+        EVREC(4);
+        HIPCK(c, hipEventRecord(c->join_ev[CCH_NPAIRS_ST], s4));
+        HIPCK(c, hipStreamWaitEvent(st, c->join_ev[CCH_NPAIRS_ST], 0));
+        EVREC(5);
+        HIPCK(c, hipEventRecord(c->join_ev[CCH_NPAIRS_ST + 1], sl));
+        HIPCK(c, hipStreamWaitEvent(st, c->join_ev[CCH_NPAIRS_ST + 1], 0));
+        EVREC(6);
+    } else {
+        TRY(enqueue_pre(c, st, ev, false));
+        TRY(enqueue_gemm(c, st, false));
+        EVREC(4);
+        TRY(enqueue_class4(c, st, false));
+        EVREC(5);
+        TRY(enqueue_l2(c, st));
+        EVREC(6);
+    }
     TRY(enqueue_post(c, st));
     EVREC(7);
     c->built = true;
@@ -939,6 +981,10 @@ cch_status cch_build_time(cch_ctx *c, float *total_ms, float *phases)
     if (total_ms) HIPCK(c, hipEventElapsedTime(total_ms, c->ev[0], c->ev[7]));
     if (phases) {
         for (int i = 0; i < 7; ++i) HIPCK(c, hipEventElapsedTime(&phases[i], c->ev[i], c->ev[i + 1]));
+        if (c->overlapped) {   // class 4 and the L2 block on their own streams, beside phases 0-3
+            HIPCK(c, hipEventElapsedTime(&phases[4], c->c4_ev[0], c->c4_ev[1]));
+            HIPCK(c, hipEventElapsedTime(&phases[5], c->l2_ev[0], c->l2_ev[1]));
+        }
         phases[7] = 0.0f;
     }
     return CCH_OK;
