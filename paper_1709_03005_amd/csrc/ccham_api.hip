@@ -113,10 +113,11 @@ int matvec_splits(int D);
 int64_t tn_part_doubles();
 hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, int64_t ldx2, int na,
                      const double *Y, int64_t ldy, int nc, int D, double *part, double *out, int64_t ldo,
-                     int transpose, hipStream_t st);
+                     int transpose, hipStream_t st, double *outT = nullptr, int cT = 0);
 hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, int64_t ldv2, int m, int D,
                      const double *C, int ldc, int ne, const double *base, int64_t ldb, double beta, double alpha,
-                     double *out, int64_t ldo, hipStream_t st);
+                     double *out, int64_t ldo, hipStream_t st, const double *V1z = nullptr,
+                     double *outz = nullptr);
 hipError_t launch_residual(const double *AX, const double *X, int64_t ld, int D, const double *theta, int k,
                            double *R, double *part, double *norms, hipStream_t st);
 hipError_t launch_jacobi_correct(const double *R, int64_t ld, int D, const double *diag, const double *theta,
@@ -126,7 +127,6 @@ hipError_t launch_pchol(const double *G, int ldg, int b, const double *S, int ld
 hipError_t launch_jacobi_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, hipStream_t st);
 hipError_t launch_rr_eig(const double *G, int ldg, int m, double *theta, double *Y, int ldy, int32_t *nfallback,
                          hipStream_t st);
-hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st);
 hipError_t launch_g_ritz(double *G, int ldg, int m, const double *theta, hipStream_t st);
 hipError_t launch_unit_vectors(double *V, int64_t ldv, int D, const int32_t *idx, int b, hipStream_t st);
 hipError_t launch_gather_principal(const double *H, int64_t ld, const int32_t *idx, int ns, double *G, int ldg,
@@ -1896,11 +1896,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         if ((e = hipEventRecord(c->rr1, st)) != hipSuccess) return e;
         ++rr_calls;
         rr_flops += (10.0 / 3.0) * (double)mm * mm * mm;   // tridiagonalisation + back-transformation
-        if ((e = launch_nn(b.V, ldv, mm, nullptr, 0, mm, D, b.Y, mmax, mm, nullptr, 0, 0.0, 1.0, b.V2, ldv, st)) !=
-            hipSuccess)
-            return e;
-        if ((e = launch_nn(b.Wv, ldv, mm, nullptr, 0, mm, D, b.Y, mmax, mm, nullptr, 0, 0.0, 1.0, b.W2, ldv, st)) !=
-            hipSuccess)
+        // V2 = V Y and W2 = W Y in one launch
+        if ((e = launch_nn(b.V, ldv, mm, nullptr, 0, mm, D, b.Y, mmax, mm, nullptr, 0, 0.0, 1.0, b.V2, ldv, st, b.Wv,
+                           b.W2)) != hipSuccess)
             return e;
         std::swap(b.V, b.V2);
         std::swap(b.Wv, b.W2);
@@ -1941,9 +1939,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         DCK(hipEventRecord(c->mv1, st));
         matvecs += nb;
         mv_launches += (nb + 15) / 16;
+        // rows m.. of G and their mirror in the columns m.. of the rows before m
         DCK(launch_tn(b.Wv + (int64_t)m * ldv, ldv, nb, nullptr, 0, nb, b.V, ldv, m + nb, D, b.part,
-                      b.G + (int64_t)m * mmax, mmax, 0, st));
-        DCK(launch_sym_fill(b.G, mmax, m, m + nb, st));
+                      b.G + (int64_t)m * mmax, mmax, 0, st, b.G + m, m));
         m = m0 + nb;
         DCK(rayleigh_ritz(m));
         DCK(hipStreamSynchronize(st));

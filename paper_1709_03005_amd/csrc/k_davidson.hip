@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_tn_mfma(const double *__restrict__ X1, 
 }
 
 __global__ void k_tn_sum(const double *__restrict__ part, int nsplit, int na, int nc, double *__restrict__ out,
-                         int64_t ldo, int transpose)
+                         int64_t ldo, int transpose, double *__restrict__ outT, int cT)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= na * nc) return;
@@ -286,14 +286,17 @@ __global__ void k_tn_sum(const double *__restrict__ part, int nsplit, int na, in
     const double s = (s0 + s1) + (s2 + s3);
     if (transpose) out[(int64_t)c * ldo + a] = s;
     else out[(int64_t)a * ldo + c] = s;
+    if (outT && c < cT) outT[(int64_t)c * ldo + a] = s;   // mirror of the columns before cT
 }
 
 // out[a*ldo + c] (or out[c*ldo + a] when transpose) = X[a] . Y[c], where
 // X[a] = X1[a] for a < na1 and X2[a - na1] for na1 <= a < na; na, nc <= 96,
-// every row 32-byte aligned (leading dimensions multiples of 4)
+// every row 32-byte aligned (leading dimensions multiples of 4). With outT,
+// also outT[c*ldo + a] = X[a] . Y[c] for c < cT (the mirror image of a block of
+// new rows of a symmetric matrix, for the columns that precede them).
 hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, int64_t ldx2, int na,
                      const double *Y, int64_t ldy, int nc, int D, double *part, double *out, int64_t ldo,
-                     int transpose, hipStream_t st)
+                     int transpose, hipStream_t st, double *outT, int cT)
 {
     if (na <= 0 || nc <= 0) return hipSuccess;
     if (na1 < 0 || na1 > na || na > TN_LD || nc > TN_LD || (ldx1 & 3) || (ldy & 3) || ((uintptr_t)X1 & 31) ||
@@ -306,7 +309,7 @@ hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, 
     hipLaunchKernelGGL(k_tn_mfma, dim3(tiles, ns), dim3(256), 0, st, X1, ldx1, na1, X2, ldx2, na, Y, ldy, nc, D, rps,
                        part);
     hipLaunchKernelGGL(k_tn_sum, dim3((na * nc + 255) / 256), dim3(256), 0, st, part, ns, na, nc, out, ldo,
-                       transpose);
+                       transpose, outT, cT);
     return hipGetLastError();
 }
 
@@ -321,9 +324,14 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1,
                                                   const double *__restrict__ V2, int64_t ldv2, int m, int D,
                                                   const double *__restrict__ Cm, int ldc, int ne,
                                                   const double *__restrict__ base, int64_t ldb, double beta,
-                                                  double alpha, double *__restrict__ out, int64_t ldo)
+                                                  double alpha, double *__restrict__ out, int64_t ldo,
+                                                  const double *__restrict__ V1z, double *__restrict__ outz)
 {
     extern __shared__ double cs[];   // [m][NN_E]
+    if (blockIdx.z == 1) {   // the second product of a pair launch: same C, other V1 and out
+        V1 = V1z;
+        out = outz;
+    }
     const int e0 = blockIdx.y * NN_E;
     for (int t = threadIdx.x; t < m * NN_E; t += 256) {
         const int q = t / NN_E, e = e0 + t % NN_E;
@@ -357,16 +365,19 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1,
 
 // out and base may be the same rows (in-place update of one element by one
 // thread); out must not overlap the rows read from V1 or V2.
+// With V1z and outz (and no second panel), one launch also forms
+// outz = beta * base + alpha * V1z C with the same C (the pair of rotations).
 hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, int64_t ldv2, int m, int D,
                      const double *C, int ldc, int ne, const double *base, int64_t ldb, double beta, double alpha,
-                     double *out, int64_t ldo, hipStream_t st)
+                     double *out, int64_t ldo, hipStream_t st, const double *V1z, double *outz)
 {
     if (ne <= 0 || D <= 0) return hipSuccess;
     if (m1 < 0 || m1 > m || (m1 < m && V2 == nullptr)) return hipErrorInvalidValue;
-    const dim3 g((D + 255) / 256, (ne + NN_E - 1) / NN_E), bl(256);
+    if ((V1z == nullptr) != (outz == nullptr) || (V1z && (m1 != m || base))) return hipErrorInvalidValue;
+    const dim3 g((D + 255) / 256, (ne + NN_E - 1) / NN_E, V1z ? 2 : 1), bl(256);
     const size_t shm = sizeof(double) * NN_E * (size_t)(m > 0 ? m : 1);
     hipLaunchKernelGGL(k_nn_small, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta, alpha,
-                       out, ldo);
+                       out, ldo, V1z, outz);
     return hipGetLastError();
 }
 
@@ -615,24 +626,6 @@ hipError_t launch_g_ritz(double *G, int ldg, int m, const double *theta, hipStre
 }
 
 // G[a][b] symmetric fill of a new column block from computed rows
-__global__ void k_sym_fill(double *G, int ldg, int m0, int m1)
-{
-    // rows [m0, m1) were computed for columns [0, m1): mirror into columns
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nr = m1 - m0;
-    if (t >= nr * m1) return;
-    const int r = m0 + t / m1, c = t % m1;
-    if (c < m0) G[(int64_t)c * ldg + r] = G[(int64_t)r * ldg + c];
-}
-
-hipError_t launch_sym_fill(double *G, int ldg, int m0, int m1, hipStream_t st)
-{
-    const int n = (m1 - m0) * m1;
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sym_fill, dim3((n + 255) / 256), dim3(256), 0, st, G, ldg, m0, m1);
-    return hipGetLastError();
-}
-
 // G0[r][c] = H[idx[r]][idx[c]], r, c < ns: a principal submatrix of H
 __global__ void k_gather_principal(const double *__restrict__ H, int64_t ld, const int32_t *__restrict__ idx, int ns,
                                    double *__restrict__ G, int ldg)
