@@ -144,6 +144,17 @@ __device__ __forceinline__ double rr_recip(double q)
     return fma(r, e, r);
 }
 
+// 1/sqrt(x), x > 0, from the hardware estimate and two Newton-Raphson
+// corrections r <- r + r (1 - x r^2) / 2
+__device__ __forceinline__ double rr_rsqrt(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    e = fma(-x * r, r, 1.0);
+    return fma(0.5 * r, e, r);
+}
+
 // a value every lane holds alike (read from LDS), as a wave-uniform scalar
 __device__ __forceinline__ double rr_uni(double v)
 {
@@ -384,10 +395,13 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                             sh.e[k] = alpha;
                             sh.hinv[k] = 0.0;
                         } else {
-                            const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-                            sh.tau[k] = (beta - alpha) / beta;
+                            // short dependent chain: sqrt and the two quotients from the
+                            // refined hardware estimates (about one ulp each)
+                            const double s2 = fma(alpha, alpha, sig);
+                            const double beta = -copysign(s2 * rr_rsqrt(s2), alpha);
+                            sh.tau[k] = fma(-alpha, rr_recip(beta), 1.0);   // (beta - alpha) / beta
                             sh.e[k] = beta;
-                            sh.hinv[k] = 1.0 / (alpha - beta);
+                            sh.hinv[k] = rr_recip(alpha - beta);
                         }
                     }
                 }
@@ -415,11 +429,24 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                     vw[lane + 64] = v1;
                     vw[RR_LD + lane + 64] = w1;
                 }
-                // A' -= v w^T + w v^T on this thread's column and slice
+                // A' -= v w^T + w v^T on this thread's column and slice; loads and
+                // stores through one column index (idle lanes: the padding column),
+                // four rows loaded before any is stored
                 {
                     const double vc = half ? v1 : v0, wc = half ? w1 : w0;
-                    for (int r = k + 1 + slice; r < n; r += nsl)
-                        A[r][cst] = A[r][cc] - (vw[r] * wc + vw[RR_LD + r] * vc);
+                    int r = k + 1 + slice;
+                    for (; r + 3 * nsl < n; r += 4 * nsl) {
+                        double a[4], vr[4], wr[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            a[u] = A[r + u * nsl][cst];
+                            vr[u] = vw[r + u * nsl];
+                            wr[u] = vw[RR_LD + r + u * nsl];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) A[r + u * nsl][cst] = a[u] - (vr[u] * wc + wr[u] * vc);
+                    }
+                    for (; r < n; r += nsl) A[r][cst] = A[r][cst] - (vw[r] * wc + vw[RR_LD + r] * vc);
                 }
                 __syncthreads();
             }
@@ -712,7 +739,18 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
                 double wc = 0.0;
                 for (int q = 0; q < nbs; ++q) wc += q < RR_BSL ? sh.u.part[q][cc] : sh.sc[q - RR_BSL][cc];
                 wc *= t;
-                for (int r = k + 1 + bs; r < n; r += nbs) Z[r][cst] = Z[r][cc] - A[k][r] * wc;
+                int r = k + 1 + bs;
+                for (; r + 3 * nbs < n; r += 4 * nbs) {
+                    double zv[4], vr[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        zv[u] = Z[r + u * nbs][cst];
+                        vr[u] = A[k][r + u * nbs];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) Z[r + u * nbs][cst] = zv[u] - vr[u] * wc;
+                }
+                for (; r < n; r += nbs) Z[r][cst] = Z[r][cst] - A[k][r] * wc;
                 __syncthreads();
             }
         }
