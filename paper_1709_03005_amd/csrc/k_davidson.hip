@@ -497,96 +497,122 @@ __device__ __forceinline__ double pch_wmax(double v)
     return pch_rl(s, 63);
 }
 
-__global__ __launch_bounds__(64) void k_pchol(const double *__restrict__ G, int ldg, int b,
-                                              const double *__restrict__ S, int lds, int m,
-                                              const double *__restrict__ ref, int ref_stride, double rel,
-                                              double *__restrict__ Cout, int ldc, int32_t *__restrict__ rank_out)
+__global__ __launch_bounds__(256) void k_pchol(const double *__restrict__ G, int ldg, int b,
+                                               const double *__restrict__ S, int lds, int m,
+                                               const double *__restrict__ ref, int ref_stride, double rel,
+                                               double *__restrict__ Cout, int ldc, int32_t *__restrict__ rank_out)
 {
-    __shared__ double A[PCH_MAX][PCH_MAX + 1];    // lane l owns column l
+    __shared__ double A[PCH_MAX][PCH_MAX + 1];    // lane l of wave 0 owns column l; column PCH_MAX is padding
     __shared__ double Ss[PCH_M][PCH_MAX + 1];
     __shared__ double Rq[PCH_MAX][PCH_MAX + 1];   // row i of R by original column
     __shared__ double R[PCH_MAX][PCH_MAX + 1];    // R in pivot order
     __shared__ double Ri[PCH_MAX][PCH_MAX + 1];   // its inverse
     __shared__ double Bq[PCH_MAX][PCH_MAX + 1];   // B by original column
+    __shared__ double rdg[PCH_MAX];               // 1 / R[i][i]
     __shared__ int piv[PCH_MAX];
+    __shared__ int rank_sh;
     const int t = threadIdx.x;
-    const int tc = t < PCH_MAX ? t : PCH_MAX - 1;   // in-bounds column for idle lanes
-    for (int e = t; e < m * b; e += 64) Ss[e / b][e % b] = S[(int64_t)(e / b) * lds + e % b];
-    for (int e = t; e < b * b; e += 64) {
+    for (int e = t; e < m * b; e += 256) Ss[e / b][e % b] = S[(int64_t)(e / b) * lds + e % b];
+    for (int e = t; e < b * b; e += 256) {
         const int i = e / b, j = e % b;
         A[i][j] = 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
     }
-    for (int e = t; e < PCH_MAX * PCH_MAX; e += 64) {
+    for (int e = t; e < PCH_MAX * PCH_MAX; e += 256) {
         Rq[e / PCH_MAX][e % PCH_MAX] = 0.0;
         Bq[e / PCH_MAX][e % PCH_MAX] = 0.0;
     }
     __syncthreads();
-    // A -= S^T S (the same products in the same order for (i, j) and (j, i))
-    for (int e = t; e < b * b; e += 64) {
+    // A -= S^T S in four interleaved partial sums, combined in a fixed order:
+    // the same operations for (i, j) and (j, i), so A stays exactly symmetric
+    for (int e = t; e < b * b; e += 256) {
         const int i = e / b, j = e % b;
-        double g = A[i][j];
-        for (int q = 0; q < m; ++q) g = fma(-Ss[q][i], Ss[q][j], g);
-        A[i][j] = g;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 3 < m; q += 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] = fma(Ss[q + u][i], Ss[q + u][j], s4[u]);
+        for (; q < m; ++q) s4[0] = fma(Ss[q][i], Ss[q][j], s4[0]);
+        A[i][j] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     __syncthreads();
-    const bool mine = t < b;
-    const double refd = mine ? rel * rel * (ref ? ref[(int64_t)t * ref_stride] : A[t][t]) : 0.0;
-    // Every value that another lane reads (key through DPP, the R row through
-    // LDS) is formed by selects with the whole wave active, so no lane holds a
-    // stale register; only the stores are masked.
-    bool used = !mine;
-    int r = b;
-    for (int i = 0; i < b; ++i) {
-        // pivot: the largest admissible remaining diagonal (ties: lowest column)
-        const double d = A[tc][tc];
-        const bool cand = !used && d > refd && d > 0.0;
-        const double key = cand ? d : 0.0;
-        const double mx = pch_wmax(key);
-        if (!(mx > 0.0)) {
-            r = i;
-            break;
+    if (t < 64) {
+        // pivoted Cholesky in wave 0 alone (no barrier inside). Every value that
+        // another lane reads (key through DPP, the R row through lane reads) is
+        // formed by selects with the whole wave active; only stores are masked.
+        const bool mine = t < b;
+        const int tc = mine ? t : PCH_MAX;   // own column, or the padding column
+        const double refd = mine ? rel * rel * (ref ? ref[(int64_t)t * ref_stride] : A[t][t]) : 0.0;
+        bool used = !mine;
+        int r = b;
+        for (int i = 0; i < b; ++i) {
+            // pivot: the largest admissible remaining diagonal (ties: lowest column)
+            const double d = A[mine ? t : 0][mine ? t : 0];
+            const bool cand = !used && d > refd && d > 0.0;
+            const double key = cand ? d : 0.0;
+            const double mx = pch_wmax(key);
+            if (!(mx > 0.0)) {
+                r = i;
+                break;
+            }
+            const int p = __ffsll((unsigned long long)__ballot(key == mx)) - 1;
+            const double rp = sqrt(mx);
+            const double quo = A[p][tc] / rp;
+            const double rl = used ? 0.0 : (t == p ? rp : quo);
+            used = used || t == p;
+            if (mine) Rq[i][t] = rl;
+            if (t == 0) piv[i] = p;
+            // Schur complement on the columns still free: lane l updates its
+            // column, four rows loaded before any is stored
+            const unsigned long long freem = __ballot(!used);
+            int q = 0;
+            for (; q + 3 < b; q += 4) {
+                double a4[4], r4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a4[u] = A[q + u][tc];
+                    r4[u] = pch_rl(rl, q + u);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool upd = !used && ((freem >> (q + u)) & 1ull);
+                    A[q + u][tc] = upd ? fma(-r4[u], rl, a4[u]) : a4[u];
+                }
+            }
+            for (; q < b; ++q) {
+                const double a1 = A[q][tc], r1 = pch_rl(rl, q);
+                const bool upd = !used && ((freem >> q) & 1ull);
+                A[q][tc] = upd ? fma(-r1, rl, a1) : a1;
+            }
         }
-        const int p = __ffsll((unsigned long long)__ballot(key == mx)) - 1;
-        const double rpp = sqrt(mx);
-        const double quo = A[p][tc] / rpp;
-        const double rl = used ? 0.0 : (t == p ? rpp : quo);
-        used = used || t == p;
-        if (mine) Rq[i][t] = rl;
-        if (t == 0) piv[i] = p;
-        __syncthreads();
-        // Schur complement on the columns still free: lane l updates its column
-        // with the R row read back from LDS
-        const unsigned long long freem = __ballot(!used);
-        for (int q = 0; q < b; ++q) {
-            const double rq = Rq[i][q];
-            const double a = A[q][tc];
-            if (!used && ((freem >> q) & 1ull)) A[q][tc] = fma(-rq, rl, a);
-        }
+        if (t == 0) rank_sh = r;
     }
     __syncthreads();
-    for (int e = t; e < r * r; e += 64) {
+    const int r = rank_sh;
+    for (int e = t; e < r * r; e += 256) {
         const int i = e / r, j = e % r;
         R[i][j] = (j >= i) ? Rq[i][piv[j]] : 0.0;
     }
+    if (t < r) rdg[t] = 1.0 / Rq[t][piv[t]];
     __syncthreads();
-    // inverse of R, column c per lane
+    // inverse of R, column c per thread (back substitution with the reciprocal
+    // diagonal)
     if (t < r) {
         const int c = t;
         for (int i = c; i >= 0; --i) {
             double s = (i == c) ? 1.0 : 0.0;
             for (int j = i + 1; j <= c; ++j) s -= R[i][j] * Ri[j][c];
-            Ri[i][c] = s / R[i][i];
+            Ri[i][c] = s * rdg[i];
         }
     }
     __syncthreads();
     // B[perm[j]][c] = (R^-1)[j][c]: upper triangular, only j <= c was formed
-    for (int e = t; e < r * r; e += 64) {
+    for (int e = t; e < r * r; e += 256) {
         const int j = e / r, c = e % r;
         Bq[piv[j]][c] = j <= c ? Ri[j][c] : 0.0;
     }
     __syncthreads();
     // M = [-S B; B]
-    for (int e = t; e < (m + b) * b; e += 64) {
+    for (int e = t; e < (m + b) * b; e += 256) {
         const int q = e / b, c = e % b;
         double v;
         if (q < m) {
@@ -604,7 +630,7 @@ hipError_t launch_pchol(const double *G, int ldg, int b, const double *S, int ld
                         int ref_stride, double rel, double *C, int ldc, int32_t *rank, hipStream_t st)
 {
     if (b <= 0 || b > PCH_MAX || m < 0 || m > PCH_M || (m > 0 && S == nullptr)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(64), 0, st, G, ldg, b, S, lds, m, ref, ref_stride, rel, C, ldc, rank);
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(256), 0, st, G, ldg, b, S, lds, m, ref, ref_stride, rel, C, ldc, rank);
     return hipGetLastError();
 }
 
