@@ -43,10 +43,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
     # name: (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    "rayleigh_ritz": ("k_rr.hip", "bff8cf1656ba0378", 40.101, 25.493),
-    "matvec": ("k_davidson.hip", "d4f8c0f582721585", 252277.479, 32000.0),
-    "expansion_gemm": ("k_gemm.hip", "f888765de180c807", 40278.137, 3533.656),
-    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22082.875, 98763.906),
+    "rayleigh_ritz": ("k_rr.hip", "be3527f7d257ea59", 40.911, 25.493),
+    "matvec": ("k_davidson.hip", "c2ad709cede732f3", 252272.634, 17904.762),
+    "expansion_gemm": ("k_gemm.hip", "f888765de180c807", 40278.219, 3533.656),
+    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22123.938, 98768.531),
 }
 
 
