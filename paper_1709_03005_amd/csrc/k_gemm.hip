@@ -20,17 +20,32 @@ namespace cch {
 //   k <  n_slot: (P Q | J J')    = ttcc[P][Q][J][J']       (row copy)
 //   k >= n_slot: -(P J' | J Q)   = -tctc[P][J'][Q][J]     (tile transpose)
 // ---------------------------------------------------------------------------
+// B[k][jj][jj'] = (P Q | ja0+jj, jb0+jj'): the slab of slot k is one contiguous
+// nca x ncb block of B, gathered from nca rows of ttcc; a workgroup copies
+// RJ_PER consecutive elements of a slab (all its loads issued before its stores)
+constexpr int RJ_U = 4, RJ_PER = 256 * RJ_U;
+
 __global__ __launch_bounds__(256) void k_relayout_J(const double *__restrict__ ttcc, int n_o, int n_cont,
                                                     const int32_t *__restrict__ slotP,
                                                     const int32_t *__restrict__ slotQ, int ja0, int nca,
                                                     int jb0, int ncb, double *__restrict__ B)
 {
     const int k = blockIdx.y;
-    const int jj = blockIdx.x;
     const int P = slotP[k], Q = slotQ[k];
-    const double *src = ttcc + (((size_t)P * n_o + Q) * n_cont + (ja0 + jj)) * n_cont + jb0;
-    double *dst = B + ((size_t)k * nca + jj) * ncb;
-    for (int t = threadIdx.x; t < ncb; t += 256) dst[t] = src[t];
+    const double *src = ttcc + ((size_t)P * n_o + Q) * n_cont * n_cont + (size_t)ja0 * n_cont + jb0;
+    double *dst = B + (size_t)k * nca * ncb;
+    const int64_t slab = (int64_t)nca * ncb, e0 = (int64_t)blockIdx.x * RJ_PER + threadIdx.x;
+    double v[RJ_U];
+#pragma unroll
+    for (int u = 0; u < RJ_U; ++u) {
+        const int64_t e = e0 + 256 * u;
+        v[u] = e < slab ? src[(e / ncb) * n_cont + e % ncb] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RJ_U; ++u) {
+        const int64_t e = e0 + 256 * u;
+        if (e < slab) dst[e] = v[u];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_relayout_K(const double *__restrict__ tctc, int n_o, int n_cont,
@@ -65,8 +80,8 @@ hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int 
                            int jb0, int ncb, double *B, hipStream_t st)
 {
     if (n_slot <= 0 || nca <= 0 || ncb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_relayout_J, dim3(nca, n_slot), dim3(256), 0, st, ttcc, n_o, n_cont, slotP, slotQ,
-                       ja0, nca, jb0, ncb, B);
+    hipLaunchKernelGGL(k_relayout_J, dim3((int)(((int64_t)nca * ncb + RJ_PER - 1) / RJ_PER), n_slot), dim3(256), 0, st,
+                       ttcc, n_o, n_cont, slotP, slotQ, ja0, nca, jb0, ncb, B);
     hipLaunchKernelGGL(k_relayout_K, dim3((nca + 31) / 32, (ncb + 31) / 32, n_slot), dim3(256), 0, st, tctc,
                        n_o, n_cont, slotP, slotQ, n_slot, ja0, nca, jb0, ncb, B);
     return hipGetLastError();
