@@ -30,7 +30,6 @@ constexpr int RR_MAX = 96, RR_LD = RR_MAX + 1, RR_NT = 512, RR_NW = RR_NT / 64;
 typedef double rr_dx4 __attribute__((ext_vector_type(4)));
 
 constexpr int RR_SL = 4;     // row slices of the Householder products (x 2 column halves = 8 waves)
-constexpr int RR_BSL = 4;    // row slices of the back-transformation (x 2 column halves)
 constexpr int RR_G = 512;    // shifts of the first multisection pass
 
 struct RRShared {
@@ -41,7 +40,7 @@ struct RRShared {
     double red[2][32];           // alternating reduction buffers
     union {
         int cnt[RR_NT];                  // Sturm counts; Jacobi pairing tables
-        double part[RR_BSL][RR_MAX];     // back-transformation partial products
+        double dbl[RR_NT / 2];           // 16 x 16 Gram matrix of a reflector block
     } u;
     unsigned long long open_mask[2];   // eigenvalues still bracketed (multisection)
     int flag, nrot;
@@ -707,50 +706,113 @@ __global__ __launch_bounds__(RR_NT) void k_rr_eig(const double *__restrict__ G, 
 
         // ---- back-transformation Z <- H_0 H_1 ... H_{n-3} Z --------------------
         // the reflector rows first become the vectors themselves (v_{k+1} = 1,
-        // v_r = x_r hinv below), read as broadcasts; thread (wave w, lane l):
-        // column l + 64 (w & 1), row slice w >> 1 (up to 64 columns: column l,
-        // row slice w; the partials of slices 4..7 go to sc[0..3], free here)
+        // v_r = x_r hinv below)
         for (int t = tid; t < n * n; t += RR_NT) {
             const int k = t / n, r = t % n;
             if (k + 2 < n && r >= k + 1 && sh.tau[k] != 0.0) A[k][r] = r == k + 1 ? 1.0 : A[k][r] * sh.hinv[k];
         }
         __syncthreads();
         {
-            const int nbs = n <= 64 ? 2 * RR_BSL : RR_BSL;
-            const int col = n <= 64 ? lane : lane + 64 * (wv & 1), bs = n <= 64 ? wv : wv >> 1;
-            double *mypart = bs < RR_BSL ? &sh.u.part[bs][0] : &sh.sc[bs - RR_BSL][0];
-            const bool act = col < n;
-            const int cc = col < RR_MAX ? col : RR_MAX - 1;   // in-bounds column for loads
-            const int cst = act ? col : RR_MAX;               // store column (padding when idle)
-            for (int k = n - 3; k >= 0; --k) {
-                const double t = rr_uni(sh.tau[k]);
-                if (t == 0.0) continue;
-                {
-                    double s0 = 0.0, s1 = 0.0;
-                    int r = k + 1 + bs;
-                    for (; r + nbs < n; r += 2 * nbs) {
-                        s0 = fma(A[k][r], Z[r][cc], s0);
-                        s1 = fma(A[k][r + nbs], Z[r + nbs][cc], s1);
-                    }
-                    if (r < n) s0 = fma(A[k][r], Z[r][cc], s0);
-                    if (col < RR_MAX) mypart[col] = act ? s0 + s1 : 0.0;
+            // blocks of 16 reflectors k0..k0+15 as I - V T V^T (T upper triangular,
+            // T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V[:, 0:i]^T v_i), applied
+            // last block first: Z <- Z - V (T (V^T Z)) on FP64 MFMA 16x16x4. Wave w
+            // < nt takes the 16 columns 16w.. of Z: W = V^T Z_w, W' = T W (the MFMA
+            // result items are exactly the next B operand: item v of lane l is row
+            // l/16 + 4v), Z_w -= V W'; a wave touches only its own columns of Z.
+            // Meanwhile the last wave (never one of the nt <= 6 column waves) forms
+            // S = V^T V and T of the next block into the other of two buffers (lane
+            // j owns row j of T, so the recurrence needs no barrier): one barrier
+            // per block.
+            const int nref = n - 2, nt = (n + 15) / 16, ks = (n + 3) / 4;
+            const int nblk = nref > 0 ? (nref + 15) / 16 : 0, tw = RR_NW - 1;
+            double *Tb0 = &sh.sc[0][0], *Tb1 = Tb0 + 256;   // 16 x 16 each (sc is free here)
+            double *Sm = sh.u.dbl;                           // 16 x 16
+            const int li = lane & 15, lk = lane >> 4;
+            // entry r of reflector k with tau_k = tk (zero outside the vector, or if
+            // no reflection)
+            auto vv = [&](int k, double tk, int r) -> double {
+                return (tk != 0.0 && r > k && r < n) ? A[k][r] : 0.0;
+            };
+            auto tau_of = [&](int k) -> double { return k < nref ? sh.tau[k] : 0.0; };
+            auto make_t = [&](int k0, double *Tm) {
+                const int s_lo = (k0 + 1) / 4;   // rows r <= k0 hold no entry of the block
+                const double tl = tau_of(k0 + li);
+                rr_dx4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+                int s4 = s_lo;
+                for (; s4 + 1 < ks; s4 += 2) {
+                    const double x0 = vv(k0 + li, tl, 4 * s4 + lk), x1 = vv(k0 + li, tl, 4 * s4 + 4 + lk);
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, a1, 0, 0, 0);
                 }
-                __syncthreads();
-                double wc = 0.0;
-                for (int q = 0; q < nbs; ++q) wc += q < RR_BSL ? sh.u.part[q][cc] : sh.sc[q - RR_BSL][cc];
-                wc *= t;
-                int r = k + 1 + bs;
-                for (; r + 3 * nbs < n; r += 4 * nbs) {
-                    double zv[4], vr[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        zv[u] = Z[r + u * nbs][cst];
-                        vr[u] = A[k][r + u * nbs];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) Z[r + u * nbs][cst] = zv[u] - vr[u] * wc;
+                if (s4 < ks) {
+                    const double x0 = vv(k0 + li, tl, 4 * s4 + lk);
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, a0, 0, 0, 0);
                 }
-                for (; r < n; r += nbs) Z[r][cst] = Z[r][cst] - A[k][r] * wc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Sm[(lk + 4 * v) * 16 + li] = a0[v] + a1[v];
+                // T by columns; lane j < 16 owns row j; T[j][l] = 0 for l < j, so the
+                // inner sum runs over l < i for every lane
+                const int j = lane & 15;
+                for (int i = 0; i < 16; ++i) {
+                    double y0 = 0.0, y1 = 0.0;
+                    int l = 0;
+                    for (; l + 1 < i; l += 2) {
+                        y0 = fma(Tm[j * 16 + l], Sm[l * 16 + i], y0);
+                        y1 = fma(Tm[j * 16 + l + 1], Sm[(l + 1) * 16 + i], y1);
+                    }
+                    if (l < i) y0 = fma(Tm[j * 16 + l], Sm[l * 16 + i], y0);
+                    const double ti = tau_of(k0 + i);
+                    if (lane < 16) Tm[j * 16 + i] = j < i ? -ti * (y0 + y1) : (j == i ? ti : 0.0);
+                }
+            };
+            if (nblk > 0 && wv == tw) make_t(16 * (nblk - 1), Tb0);
+            __syncthreads();
+            for (int blk = nblk - 1, buf = 0; blk >= 0; --blk, buf ^= 1) {
+                const int k0 = 16 * blk;
+                double *Tcur = buf ? Tb1 : Tb0;
+                if (wv == tw && blk > 0) make_t(16 * (blk - 1), buf ? Tb0 : Tb1);
+                if (wv < nt) {
+                    const int c0 = 16 * wv, s_lo = (k0 + 1) / 4;
+                    const double tl = tau_of(k0 + li);
+                    rr_dx4 w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+                    const bool cok = c0 + li < n;
+                    int s4 = s_lo;
+                    for (; s4 + 1 < ks; s4 += 2) {
+                        const int r = 4 * s4 + lk;
+                        const double z0 = (r < n && cok) ? Z[r][c0 + li] : 0.0;
+                        const double z1 = (r + 4 < n && cok) ? Z[r + 4][c0 + li] : 0.0;
+                        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(k0 + li, tl, r), z0, w0, 0, 0, 0);
+                        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(k0 + li, tl, r + 4), z1, w1, 0, 0, 0);
+                    }
+                    if (s4 < ks) {
+                        const int r = 4 * s4 + lk;
+                        const double z0 = (r < n && cok) ? Z[r][c0 + li] : 0.0;
+                        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(k0 + li, tl, r), z0, w0, 0, 0, 0);
+                    }
+                    rr_dx4 accW;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) accW[v] = w0[v] + w1[v];
+                    rr_dx4 accP = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        accP = __builtin_amdgcn_mfma_f64_16x16x4f64(Tcur[li * 16 + 4 * q + lk], accW[q], accP, 0, 0, 0);
+                    double td[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) td[q] = tau_of(k0 + 4 * q + lk);
+                    for (int rt = (k0 + 1) / 16; rt < nt; ++rt) {
+                        const int r0 = 16 * rt;
+                        rr_dx4 accD = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            accD = __builtin_amdgcn_mfma_f64_16x16x4f64(vv(k0 + 4 * q + lk, td[q], r0 + li), accP[q],
+                                                                        accD, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = r0 + lk + 4 * v;
+                            if (row < n && cok) Z[row][c0 + li] -= accD[v];
+                        }
+                    }
+                }
                 __syncthreads();
             }
         }
