@@ -927,7 +927,9 @@ cch_status cch_build(cch_ctx *c)
     HIPCK(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
     const bool ev = true;
-    c->overlapped = c->have_aux;
+    // the streams pay from a few thousand rows on; below that the event
+    // traffic of the fork and join costs more than the overlap saves
+    c->overlapped = c->have_aux && c->D >= 4096;
     if (c->overlapped) {
         // class 4 (with its L2 x target scans) and the L2 block depend on no pair
         // phase and write their own blocks of H: each on a stream of its own
