@@ -198,6 +198,30 @@ cch_status cch_matrix_device(cch_ctx *ctx, const double **dptr, int64_t *ld);
 /* Diagonal of the matrix (D values). */
 cch_status cch_get_diagonal(cch_ctx *ctx, double *out, int32_t flags);
 
+/* One block of the matrix by the contraction classes of Sec. 2.2, row-major
+ * into out (leading dimension ld >= the block width), host memory, or device
+ * memory with CCH_MEM_DEVICE; elements of the block outside the class are 0.
+ *   cls 1, 3, 5, 6, 7: rows of target symmetry sym_a by columns of sym_b, each
+ *     indexed (n, j) -> n * n_c + j (n the state, j the coupled continuum
+ *     orbital), S_a n_c(a) x S_b n_c(b). sym_a == sym_b: class 1 where the
+ *     states agree (n = n'), class 3 where they differ; sym_a != sym_b coupled
+ *     to the same continuum irrep: class 5 where the continuum orbitals agree
+ *     (j = j', the diagonal of the local block), class 6 where they differ;
+ *     different continuum irreps: class 7 (the whole block).
+ *   cls 4: the L2 rows by the continuum columns of sym_a (n_L2 x S_a n_c(a));
+ *     sym_b is not used.
+ *   cls 2, 8: the L2 block (n_L2 x n_L2), its diagonal (2) or the rest (8);
+ *     neither symmetry is used.
+ * CCH_E_INVALID_ARG for a class that does not occur between the two
+ * symmetries or a symmetry out of range; CCH_E_STATE before cch_build.
+ * Synchronous. */
+cch_status cch_get_block(cch_ctx *ctx, int32_t cls, int32_t sym_a, int32_t sym_b, double *out, int64_t ld,
+                         int32_t flags);
+
+/* Rows and columns of the block cch_get_block returns for (cls, sym_a, sym_b),
+ * with the same argument checks; available after cch_plan. */
+cch_status cch_block_shape(cch_ctx *ctx, int32_t cls, int32_t sym_a, int32_t sym_b, int64_t *rows, int64_t *cols);
+
 /* Determinant-pair artefacts of the excitation scan (Sec. 2.1: XOR and
  * popcount for the degree, masks for the sign, four 16-bit orbital indices
  * per 64-bit label). For every connected pair (degree <= 2), in row-major

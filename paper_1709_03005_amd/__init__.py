@@ -43,7 +43,7 @@ CCH_PAIRS_L2_TARGET = 2
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
     "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_plan", "cch_build",
-    "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_labels",
+    "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
@@ -98,6 +98,8 @@ _SIG = {
     "cch_get_matrix": (i32, [P, P, i64, i32]),
     "cch_matrix_device": (i32, [P, C.POINTER(P), C.POINTER(i64)]),
     "cch_get_diagonal": (i32, [P, P, i32]),
+    "cch_get_block": (i32, [P, i32, i32, i32, P, i64, i32]),
+    "cch_block_shape": (i32, [P, i32, i32, i32, C.POINTER(i64), C.POINTER(i64)]),
     "cch_get_labels": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, C.POINTER(i64)]),
     "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
     "cch_build_time": (i32, [P, C.POINTER(C.c_float), P]),
@@ -245,6 +247,16 @@ class Context:
         D, _ = self.dim()
         out = np.empty(D)
         self._ck(lib.cch_get_diagonal(self.h, out.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
+        return out
+
+    def get_block(self, cls, sym_a=0, sym_b=0):
+        """cch_get_block: one class block (elements outside the class are 0)."""
+        r, c = i64(), i64()
+        self._ck(lib.cch_block_shape(self.h, cls, sym_a, sym_b, C.byref(r), C.byref(c)))
+        out = np.zeros((r.value, c.value))
+        if out.size:
+            self._ck(lib.cch_get_block(self.h, cls, sym_a, sym_b, out.ctypes.data_as(C.c_void_p), max(c.value, 1),
+                                       CCH_MEM_HOST))
         return out
 
     def get_labels(self, which, sym_a=0, sym_b=0):

@@ -106,6 +106,8 @@ hipError_t launch_l2_batched(int W, const L2Task *tasks, int ntask, int64_t tota
 hipError_t launch_class4_batched(int W, const C4Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
 hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
 hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
+hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrows, int64_t col0, int ncols, int mode,
+                            int nca, int ncb, double *out, int64_t ldo, hipStream_t st);
 // Davidson
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
                          int64_t ldw, double *Wp, hipStream_t st);
@@ -1060,6 +1062,84 @@ cch_status cch_get_diagonal(cch_ctx *c, double *out, int32_t flags)
     HIPCK(c, hipMemcpyAsync(out, c->d_diag, c->D * 8,
                             (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
+    return CCH_OK;
+}
+
+// the rectangle of a class block and its element filter (see cch_get_block)
+static cch_status block_geometry(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t sym_b, int64_t *row0, int64_t *nrows,
+                                 int64_t *col0, int64_t *ncols, int *mode, int *nca, int *ncb)
+{
+    const int ns = (int)c->syms.size();
+    *nca = *ncb = 0;
+    if (cls == 2 || cls == 8) {
+        *row0 = *col0 = c->Dc;
+        *nrows = *ncols = c->n_l2;
+        *mode = cls;
+        return CCH_OK;
+    }
+    if (sym_a < 0 || sym_a >= ns) return fail(c, CCH_E_INVALID_ARG, "symmetry %d out of range", sym_a);
+    const SymInfo &sa = c->syms[sym_a];
+    if (cls == 4) {
+        *row0 = c->Dc;
+        *nrows = c->n_l2;
+        *col0 = sa.row0;
+        *ncols = (int64_t)sa.S * sa.nc;
+        *mode = 0;
+        return CCH_OK;
+    }
+    if (sym_b < 0 || sym_b >= ns) return fail(c, CCH_E_INVALID_ARG, "symmetry %d out of range", sym_b);
+    const SymInfo &sb = c->syms[sym_b];
+    const bool same_sym = sym_a == sym_b, same_cont = sa.ja0 == sb.ja0 && sa.nc == sb.nc;
+    bool ok;
+    switch (cls) {
+    case 1: case 3: ok = same_sym; break;
+    case 5: case 6: ok = !same_sym && same_cont; break;
+    case 7: ok = !same_cont; break;
+    default: return fail(c, CCH_E_INVALID_ARG, "no class %d", cls);
+    }
+    if (!ok) return fail(c, CCH_E_INVALID_ARG, "class %d does not occur between symmetries %d and %d", cls, sym_a, sym_b);
+    *row0 = sa.row0;
+    *nrows = (int64_t)sa.S * sa.nc;
+    *col0 = sb.row0;
+    *ncols = (int64_t)sb.S * sb.nc;
+    *mode = cls == 7 ? 0 : cls;
+    *nca = sa.nc;
+    *ncb = sb.nc;
+    return CCH_OK;
+}
+
+cch_status cch_block_shape(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t sym_b, int64_t *rows, int64_t *cols)
+{
+    if (!c || !rows || !cols) return CCH_E_INVALID_ARG;
+    if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    int64_t r0, c0;
+    int mode, nca, ncb;
+    TRY(block_geometry(c, cls, sym_a, sym_b, &r0, rows, &c0, cols, &mode, &nca, &ncb));
+    return CCH_OK;
+}
+
+cch_status cch_get_block(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t sym_b, double *out, int64_t ld, int32_t flags)
+{
+    if (!c || !out) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    int64_t r0, nr, c0, nc;
+    int mode, nca, ncb;
+    TRY(block_geometry(c, cls, sym_a, sym_b, &r0, &nr, &c0, &nc, &mode, &nca, &ncb));
+    if (ld < nc) return fail(c, CCH_E_INVALID_ARG, "ld %lld below the block width %lld", (long long)ld, (long long)nc);
+    if (nr == 0 || nc == 0) return CCH_OK;
+    HIPCK(c, hipSetDevice(c->device));
+    if (flags & CCH_MEM_DEVICE) {
+        HIPCK(c, launch_get_block(c->d_H, c->ld, r0, (int)nr, c0, (int)nc, mode, nca, ncb, out, ld, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        return CCH_OK;
+    }
+    double *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, 8 * (size_t)nr * nc) != hipSuccess) return fail(c, CCH_E_OOM, "block staging");
+    hipError_t e = launch_get_block(c->d_H, c->ld, r0, (int)nr, c0, (int)nc, mode, nca, ncb, tmp, nc, c->stream);
+    if (e == hipSuccess) e = hipMemcpy2DAsync(out, ld * 8, tmp, nc * 8, nc * 8, nr, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_get_block: %s", hipGetErrorString(e));
     return CCH_OK;
 }
 

@@ -50,6 +50,35 @@ hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStrea
     return hipGetLastError();
 }
 
+// out[r * ldo + c] = H[(row0 + r) * ldh + col0 + c] where the element belongs to
+// the selected class, else 0. mode: 0 every element; 1 / 3 same / different
+// target state (r / nca vs c / ncb); 5 / 6 same / different continuum orbital
+// (r % nca vs c % ncb); 2 / 8 diagonal / off-diagonal (r vs c)
+__global__ void k_get_block(const double *__restrict__ H, int64_t ldh, int64_t row0, int nrows, int64_t col0,
+                            int ncols, int mode, int nca, int ncb, double *__restrict__ out, int64_t ldo)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= ncols || r >= nrows) return;
+    bool keep = true;
+    if (mode == 1) keep = r / nca == c / ncb;
+    else if (mode == 3) keep = r / nca != c / ncb;
+    else if (mode == 5) keep = r % nca == c % ncb;
+    else if (mode == 6) keep = r % nca != c % ncb;
+    else if (mode == 2) keep = r == c;
+    else if (mode == 8) keep = r != c;
+    out[(int64_t)r * ldo + c] = keep ? H[(row0 + r) * ldh + col0 + c] : 0.0;
+}
+
+hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrows, int64_t col0, int ncols, int mode,
+                            int nca, int ncb, double *out, int64_t ldo, hipStream_t st)
+{
+    if (nrows <= 0 || ncols <= 0) return hipSuccess;
+    if ((mode == 1 || mode == 3 || mode == 5 || mode == 6) && (nca <= 0 || ncb <= 0)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_get_block, dim3((ncols + 255) / 256, nrows), dim3(256), 0, st, H, ldh, row0, nrows, col0,
+                       ncols, mode, nca, ncb, out, ldo);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t v, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
