@@ -43,10 +43,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
     # name: (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    "rayleigh_ritz": ("k_rr.hip", "be3527f7d257ea59", 40.911, 25.493),
-    "matvec": ("k_davidson.hip", "c2ad709cede732f3", 252272.634, 17904.762),
-    "expansion_gemm": ("k_gemm.hip", "f888765de180c807", 40278.219, 3533.656),
-    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22123.938, 98768.531),
+    "rayleigh_ritz": ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
+    "matvec": ("k_davidson.hip", "c2ad709cede732f3", 252272.643, 17904.762),
+    "expansion_gemm": ("k_gemm.hip", "8cbf1a6f5665b209", 40280.400, 3533.656),
+    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
 }
 
 
