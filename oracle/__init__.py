@@ -13,6 +13,10 @@ Contents
     same Hamiltonian for micro instances, used to pin the Slater-Condon code.
   * `lowest_eigenpairs`: the lowest eigenpairs by LAPACK (numpy.linalg.eigh),
     the plain definition of what the Davidson solve returns.
+  * `target_hamiltonian` and `energy_mode_matrix`: the N-electron target
+    Hamiltonian over the determinants of two target symmetries, and the
+    contracted matrix with the target-only integrals of classes 1, 3, 5, 6
+    and 7 replaced by target energies on the diagonal (Sec. 3.1).
 """
 from __future__ import annotations
 
@@ -213,6 +217,68 @@ def lowest_eigenpairs(H, k):
     """The k lowest eigenpairs of a dense symmetric matrix (LAPACK syevd)."""
     w, v = np.linalg.eigh(H)
     return w[:k], v[:, :k]
+
+
+def _occ_lists(dets):
+    """Occupation lists of bitstring determinants (bit k of word k // 64 set
+    means spin-orbital k is occupied), tested one bit at a time."""
+    dets = np.asarray(dets, dtype=np.uint64)
+    out = []
+    for d in dets:
+        out.append([64 * w + b for w in range(d.shape[0]) for b in range(64)
+                    if (int(d[w]) >> b) & 1])
+    return np.array(out, dtype=np.int32)
+
+
+def target_hamiltonian(inst, a, b):
+    """<eta_am|H|eta_bm'> over the N-electron target determinants of target
+    symmetries a (rows) and b (columns): the Hamiltonian of the target problem
+    of Eq. 2 (target orbitals only, E_core on the diagonal), element by
+    element by the Slater-Condon rules."""
+    A = _occ_lists(inst.syms[a].dets)
+    B = _occ_lists(inst.syms[b].dets)
+    ma, mb = A.shape[0], B.shape[0]
+    v = Oracle(inst).sc_lists(np.repeat(A, mb, axis=0), np.tile(B, (ma, 1)))
+    return v.reshape(ma, mb)
+
+
+def energy_mode_matrix(inst, energies, with_abs=False):
+    """The contracted matrix with target energies on the diagonal (Sec. 3.1,
+    the option of classes 1, 3, 5, 6 and 7). In a continuum element
+    <(a,n,j)|H|(b,n',j')> the terms made of target orbitals only add up to
+    delta_jj' (C_a^T H_T C_b)_nn', E_core included (the continuum electron is
+    a spectator of them); they are removed and delta_ab delta_nn' delta_jj'
+    E_an is added. energies[a] holds the S_a energies of symmetry a. With
+    with_abs, the sum of |terms| and the term count of each element, for
+    the tolerance rule, cover the removed and added terms too."""
+    O = Oracle(inst)
+    if with_abs:
+        H, Ha, K = O.build(with_abs=True)
+    else:
+        H = O.build()
+    row0, r = [], 0
+    for s in inst.syms:
+        row0.append(r)
+        r += s.ci.shape[1] * int(inst.n_c[s.irrep ^ inst.total_irrep])
+    for a, sa in enumerate(inst.syms):
+        nc = int(inst.n_c[sa.irrep ^ inst.total_irrep])
+        for b, sb in enumerate(inst.syms):
+            if sb.irrep != sa.irrep or nc == 0:
+                continue          # different continuum orbitals: no j = j'
+            HT = target_hamiltonian(inst, a, b)
+            P = sa.ci.T @ HT @ sb.ci
+            Pa = np.abs(sa.ci).T @ np.abs(HT) @ np.abs(sb.ci)
+            Sa_, Sb_ = sa.ci.shape[1], sb.ci.shape[1]
+            for n in range(Sa_):
+                for n2 in range(Sb_):
+                    add = (energies[a][n] if (a == b and n == n2) else 0.0) - P[n, n2]
+                    for j in range(nc):
+                        i, k = row0[a] + n * nc + j, row0[b] + n2 * nc + j
+                        H[i, k] += add
+                        if with_abs:
+                            Ha[i, k] += Pa[n, n2] + abs(energies[a][n]) * (a == b and n == n2)
+                            K[i, k] += HT.size + 1
+    return (H, Ha, K) if with_abs else H
 
 
 def tolerance_ok(g, o, abss, cnt, rel=1e-10):

@@ -272,3 +272,78 @@ def test_sampled_elements_equal_full_build():
     cols = rng.integers(0, D, 200)
     v, a, k = O.elements(rows, cols)
     np.testing.assert_allclose(v, H[rows, cols], rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# target energies on the diagonal (Sec. 3.1, classes 1, 3, 5, 6, 7)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kw", MICROS)
+def test_target_hamiltonian_equals_fock_space(kw):
+    """The N-electron target Hamiltonian == the Jordan-Wigner Fock-space
+    operator between the same determinants (no Slater-Condon rule there)."""
+    inst = synth.micro(**kw)
+    HF = fock.fock_hamiltonian(inst)
+    n = 2 * inst.n_orb
+    for a, s in enumerate(inst.syms):
+        idx = [fock.basis_index(synth.det_to_occ(d), n) for d in s.dets]
+        ref = HF[idx][:, idx].toarray()
+        got = oracle.target_hamiltonian(inst, a, a)
+        assert np.abs(ref).max() > 0.1
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def _shared_irrep_instance():
+    # symmetries 0 and 1 share irrep 0 (classes 5 and 6 between them), symmetry
+    # 2 couples to the other continuum irrep (class 7); a non-zero core energy
+    return synth.make_instance(6, 4, 2, [3, 2], [0, 0, 1], [9, 7, 8], [2, 3, 2], 6, 777,
+                               e_core=-3.7, name="energies")
+
+
+def test_energy_mode_equals_removing_target_only_integrals():
+    """The energy-mode matrix on the continuum block == the plain build with
+    every integral over target orbitals only (h_pq, (pq|rs)) and E_core set to
+    zero, plus the energies on the diagonal; class 4 and the L2 block keep the
+    plain build's values."""
+    import dataclasses
+    inst = _shared_irrep_instance()
+    no = inst.n_o
+    h2 = inst.h.copy()
+    h2[:no, :no] = 0.0
+    bare = dataclasses.replace(inst, h=h2, tttt=np.zeros_like(inst.tttt), e_core=0.0)
+    rng = np.random.default_rng(5)
+    E = [rng.uniform(-20.0, -15.0, s.ci.shape[1]) for s in inst.syms]
+    got = oracle.energy_mode_matrix(inst, E)
+    full = oracle.Oracle(inst).build()
+    ref = oracle.Oracle(bare).build()
+    Dc = inst.n_cont_rows()
+    r = 0
+    for a, s in enumerate(inst.syms):
+        nc = int(inst.n_c[s.irrep ^ inst.total_irrep])
+        for n in range(s.ci.shape[1]):
+            for j in range(nc):
+                ref[r, r] += E[a][n]
+                r += 1
+    assert r == Dc
+    scale = np.abs(full).max()
+    np.testing.assert_allclose(got[:Dc, :Dc], ref[:Dc, :Dc], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_array_equal(got[Dc:], full[Dc:])
+    np.testing.assert_array_equal(got[:, Dc:], full[:, Dc:])
+    # the option changes something: the removed part is not zero
+    assert np.abs(got[:Dc, :Dc] - full[:Dc, :Dc]).max() > 0.1
+
+
+def test_energy_mode_with_target_eigenvectors_reproduces_full_build():
+    """With CI vectors that diagonalise the target Hamiltonian and their
+    eigenvalues as energies, the option reproduces the plain matrix."""
+    inst = synth.make_instance(6, 4, 2, [3, 2], [0, 1], [10, 9], [3, 2], 5, 778,
+                               e_core=-2.5, name="eigen")
+    E = []
+    for a, s in enumerate(inst.syms):
+        w, v = np.linalg.eigh(oracle.target_hamiltonian(inst, a, a))
+        S = s.ci.shape[1]
+        s.ci = np.ascontiguousarray(v[:, :S])
+        E.append(w[:S])
+    full = oracle.Oracle(inst).build()
+    got = oracle.energy_mode_matrix(inst, E)
+    np.testing.assert_allclose(got, full, rtol=0, atol=1e-12 * np.abs(full).max())
