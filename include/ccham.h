@@ -175,6 +175,21 @@ cch_status cch_add_target_symmetry(cch_ctx *ctx, int32_t irrep, int32_t n_det,
 cch_status cch_set_l2(cch_ctx *ctx, int32_t n_l2, int32_t n_words, const uint64_t *dets,
                       int32_t flags);
 
+/* Target energies on the diagonal (Sec. 3.1, the option kept for classes 1,
+ * 3, 5, 6 and 7): E[n] holds the n = sum of n_states energies of all target
+ * states, symmetry by symmetry in the order they were added, state by state
+ * within a symmetry (total energies, E_core included). With them, the terms of
+ * a continuum element made of target orbitals only -- which add up to
+ * delta_jj' (C_a^T H_T C_b)_nn', E_core included -- are left out, and
+ * delta_ab delta_nn' delta_jj' E_an is added instead; classes 2, 4 and 8 are
+ * unchanged. When the CI vectors diagonalise the target Hamiltonian and E are
+ * their eigenvalues, the matrix is the one built without the option. n = 0
+ * (E ignored) switches the option off. Before cch_plan, after the last target
+ * symmetry (cch_plan fails with CCH_E_STATE if a symmetry was added since).
+ * Host pointer unless flags holds CCH_MEM_DEVICE. CCH_E_INPUT for a count that
+ * does not match the states or a non-finite energy. */
+cch_status cch_set_target_energies(cch_ctx *ctx, const double *E, int64_t n, int32_t flags);
+
 /* Plan the build (precision, tiles, memory budget). opts may be NULL for the
  * FP64 defaults. Allocates the device matrix. */
 cch_status cch_plan(cch_ctx *ctx, const cch_plan_opts *opts);

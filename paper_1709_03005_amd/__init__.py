@@ -42,7 +42,7 @@ CCH_PAIRS_L2_TARGET = 2
 
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
-    "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_plan", "cch_build",
+    "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_set_target_energies", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
@@ -92,6 +92,7 @@ _SIG = {
     "cch_set_integrals": (i32, [P, P, P, P, P, P, C.c_double, i32]),
     "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
     "cch_set_l2": (i32, [P, i32, i32, P, i32]),
+    "cch_set_target_energies": (i32, [P, P, i64, i32]),
     "cch_plan": (i32, [P, C.POINTER(PlanOpts)]),
     "cch_build": (i32, [P]),
     "cch_get_dim": (i32, [P, C.POINTER(i64), C.POINTER(i64)]),
@@ -217,6 +218,21 @@ class Context:
         n = kd.shape[0]
         w = kd.shape[1] if kd.ndim == 2 else 0
         self._ck(lib.cch_set_l2(self.h, int(n), int(w), pd, fd))
+
+    def set_target_energies(self, energies):
+        """Target energies on the diagonal (one array per target symmetry, or
+        one flat array over all states); None switches the option off."""
+        if energies is None:
+            self._ck(lib.cch_set_target_energies(self.h, None, 0, 0))
+            return
+        if isinstance(energies, (list, tuple)):
+            energies = np.concatenate([np.ravel(np.asarray(e, dtype=np.float64)) for e in energies]) \
+                if len(energies) else np.zeros(0)
+        pe, fe, ke = _arr(energies, np.float64)
+        n = int(ke.numel()) if hasattr(ke, "numel") else int(ke.size)
+        if n == 0:
+            raise CchError(CCH_E_INVALID_ARG, "empty energy list (pass None to switch the option off)")
+        self._ck(lib.cch_set_target_energies(self.h, pe, n, fe))
 
     def plan(self, precision=CCH_PREC_FP64, split_slices=0, autotune=0, max_device_bytes=0):
         o = PlanOpts(precision, split_slices, autotune, 0, max_device_bytes)
@@ -443,10 +459,12 @@ class Batch:
             pass
 
 
-def from_instance(inst, device=0, stream=None, plan=True, **plan_kw) -> Context:
+def from_instance(inst, device=0, stream=None, plan=True, target_energies=None, **plan_kw) -> Context:
     """Context loaded with an instance object carrying the fields the
     interface takes (n_o, tgt_irrep, n_irrep, n_c, total_irrep, h, tttt,
-    tttc, ttcc, tctc, e_core, syms[i].irrep/.dets/.ci, l2_dets)."""
+    tttc, ttcc, tctc, e_core, syms[i].irrep/.dets/.ci, l2_dets); with
+    target_energies (one array per symmetry) the option of target energies on
+    the diagonal is set before the plan."""
     ctx = Context(device, stream)
     ctx.set_orbitals(inst.n_o, inst.tgt_irrep, inst.n_irrep, inst.n_c, inst.total_irrep)
     ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
@@ -454,6 +472,8 @@ def from_instance(inst, device=0, stream=None, plan=True, **plan_kw) -> Context:
         ctx.add_target_symmetry(s.irrep, s.dets, s.ci)
     if inst.l2_dets is not None and len(inst.l2_dets):
         ctx.set_l2(inst.l2_dets)
+    if target_energies is not None:
+        ctx.set_target_energies(target_energies)
     if plan:
         ctx.plan(**plan_kw)
     return ctx

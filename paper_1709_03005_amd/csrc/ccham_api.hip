@@ -20,6 +20,8 @@ namespace cch {
 // launchers defined in the kernel files
 hipError_t launch_pair_values(int W, TgtInts I, const uint64_t *da, const uint64_t *db, PairList pl,
                               int64_t n, double *hv, hipStream_t st);
+hipError_t launch_energy_rows(int nrows, const int32_t *rn, const int32_t *rn2, const double *E, double *HT,
+                              hipStream_t st);
 hipError_t launch_projection(int M, const int64_t *row_off, const int64_t *row_cnt, PairList pl,
                              const double *hv, const double *ca, int Sa, const double *cb, int Sb,
                              int nrows, const int32_t *rn, const int32_t *rn2, double *Y, double *Yo,
@@ -165,7 +167,7 @@ struct DevPairs {
 
 struct SymInfo {
     int irrep = 0, M = 0, S = 0, nc = 0, ja0 = 0;
-    int64_t row0 = 0;
+    int64_t row0 = 0, e_off = 0;   // first row; first of its states' target energies
     uint64_t *d_dets = nullptr;
     double *d_ci = nullptr;
     std::vector<uint64_t> h_dets;
@@ -214,6 +216,10 @@ struct cch_ctx {
     bool have_ints = false;
     double *d_h = nullptr, *d_tttt = nullptr, *d_tttc = nullptr, *d_ttcc = nullptr, *d_tctc = nullptr;
     double e_core = 0.0;
+    // target energies on the diagonal (all states, symmetry by symmetry)
+    bool energy_mode = false;
+    std::vector<double> h_tgtE;
+    double *d_tgtE = nullptr;
     // determinant spaces
     int n_elec = -1;
     std::vector<SymInfo> syms;
@@ -556,6 +562,29 @@ cch_status cch_set_l2(cch_ctx *c, int32_t n_l2, int32_t n_words, const uint64_t 
     return CCH_OK;
 }
 
+cch_status cch_set_target_energies(cch_ctx *c, const double *E, int64_t n, int32_t flags)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (n == 0) {
+        c->energy_mode = false;
+        c->h_tgtE.clear();
+        return CCH_OK;
+    }
+    if (n < 0 || !E) return fail(c, CCH_E_INVALID_ARG, "bad target energies");
+    int64_t states = 0;
+    for (const auto &s : c->syms) states += s.S;
+    if (n != states)
+        return fail(c, CCH_E_INPUT, "%lld target energies for %lld target states", (long long)n, (long long)states);
+    std::vector<double> h((size_t)n);
+    TRY(host_copy(c, h.data(), E, h.size() * 8, flags));
+    for (double v : h)
+        if (!std::isfinite(v)) return fail(c, CCH_E_INPUT, "target energy is not finite");
+    c->h_tgtE = std::move(h);
+    c->energy_mode = true;
+    return CCH_OK;
+}
+
 static cch_status alloc_pairs(cch_ctx *c, DevPairs &p, int mode, const uint64_t *A, int nA, const uint64_t *B, int nB)
 {
     TRY(dalloc(c, &p.row_off, nA));
@@ -611,6 +640,17 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     }
     c->Dc = row;
     c->D = row + c->n_l2;
+    if (c->energy_mode) {
+        int64_t off = 0;
+        for (auto &s : c->syms) {
+            s.e_off = off;
+            off += s.S;
+        }
+        if (off != (int64_t)c->h_tgtE.size())
+            return fail(c, CCH_E_STATE, "target energies cover %zu states, the symmetries hold %lld",
+                        c->h_tgtE.size(), (long long)off);
+        TRY(upload(c, &c->d_tgtE, c->h_tgtE));
+    }
     if (c->D <= 0) return fail(c, CCH_E_STATE, "empty matrix");
     if (c->D > 2000000000LL) return fail(c, CCH_E_LIMIT, "dimension too large");
     c->ld = (c->D + 31) / 32 * 32;
@@ -824,6 +864,9 @@ static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan, boo
         HIPCK(c, launch_pair_values(c->W, I, sa.d_dets, sb.d_dets, p.pr.pl, p.pr.n, p.d_hv, s));
         HIPCK(c, launch_projection(sa.M, p.pr.row_off, p.pr.row_cnt, p.pr.pl, p.d_hv, sa.d_ci, sa.S, sb.d_ci, sb.S,
                                    p.nrows, p.d_rn, p.d_rn2, p.d_Y, p.d_Yo, p.d_HT, p.d_O, s));
+        if (c->energy_mode)
+            HIPCK(c, launch_energy_rows(p.nrows, p.d_rn, p.d_rn2, p.a == p.b ? c->d_tgtE + sa.e_off : nullptr,
+                                        p.d_HT, s));
         HIPCK(c, launch_bucket(p.pr.pl, p.pr.n, p.d_pqidx, c->n_o, p.n_slot, sa.M, p.d_key, p.d_count, p.d_start,
                                p.d_cursor, p.d_sorted, p.d_tmp, p.d_d0, s));
         const int M0 = (sa.irrep == sb.irrep) ? sa.M : 0;

@@ -124,6 +124,25 @@ __global__ __launch_bounds__(256) void k_project(int M, const double *__restrict
     }
 }
 
+// Target energies on the diagonal (Sec. 3.1, classes 1, 3, 5, 6 and 7): the
+// target-only part of every state row (n, n') is replaced by delta_nn' E[n]
+// for a symmetry with itself (E given) and by zero between two symmetries.
+__global__ __launch_bounds__(256) void k_energy_rows(int nrows, const int32_t *__restrict__ rn,
+                                                     const int32_t *__restrict__ rn2,
+                                                     const double *__restrict__ E, double *__restrict__ HT)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < nrows) HT[r] = (E != nullptr && rn[r] == rn2[r]) ? E[rn[r]] : 0.0;
+}
+
+hipError_t launch_energy_rows(int nrows, const int32_t *rn, const int32_t *rn2, const double *E, double *HT,
+                              hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_energy_rows, dim3((nrows + 255) / 256), dim3(256), 0, st, nrows, rn, rn2, E, HT);
+    return hipGetLastError();
+}
+
 hipError_t launch_projection(int M, const int64_t *row_off, const int64_t *row_cnt, PairList pl,
                              const double *hv, const double *ca, int Sa, const double *cb, int Sb,
                              int nrows, const int32_t *rn, const int32_t *rn2, double *Y, double *Yo,
