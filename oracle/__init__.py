@@ -13,6 +13,8 @@ Contents
     same Hamiltonian for micro instances, used to pin the Slater-Condon code.
   * `lowest_eigenpairs`: the lowest eigenpairs by LAPACK (numpy.linalg.eigh),
     the plain definition of what the Davidson solve returns.
+  * `csf_expand`: target CI vectors over multi-determinant CSFs (Eq. 2)
+    rewritten over determinants.
   * `target_hamiltonian` and `energy_mode_matrix`: the N-electron target
     Hamiltonian over the determinants of two target symmetries, and the
     contracted matrix with the target-only integrals of classes 1, 3, 5, 6
@@ -228,6 +230,28 @@ def _occ_lists(dets):
         out.append([64 * w + b for w in range(d.shape[0]) for b in range(64)
                     if (int(d[w]) >> b) & 1])
     return np.array(out, dtype=np.int32)
+
+
+def csf_expand(dets, coef, starts, ci):
+    """Target CI vectors over CSFs (Eq. 2) rewritten over determinants: CSF m
+    is sum_t coef[t] |dets[t]> for t in [starts[m], starts[m+1]); phi_n =
+    sum_m ci[m, n] eta_m = sum_d (sum over the terms of d of coef * ci[m, n]) |d>.
+    Returns the distinct determinants in order of first appearance and their
+    coefficients [n_det, n_states]; terms are added in input order."""
+    dets = np.asarray(dets, dtype=np.uint64)
+    index, order = {}, []
+    for t in range(dets.shape[0]):
+        key = tuple(int(w) for w in dets[t])
+        if key not in index:
+            index[key] = len(order)
+            order.append(t)
+    C = np.zeros((len(order), ci.shape[1]))
+    for m in range(len(starts) - 1):
+        for t in range(starts[m], starts[m + 1]):
+            d = index[tuple(int(w) for w in dets[t])]
+            for n in range(ci.shape[1]):
+                C[d, n] += coef[t] * ci[m, n]
+    return np.ascontiguousarray(dets[order]), C
 
 
 def target_hamiltonian(inst, a, b):

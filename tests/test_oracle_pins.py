@@ -347,3 +347,70 @@ def test_energy_mode_with_target_eigenvectors_reproduces_full_build():
     full = oracle.Oracle(inst).build()
     got = oracle.energy_mode_matrix(inst, E)
     np.testing.assert_allclose(got, full, rtol=0, atol=1e-12 * np.abs(full).max())
+
+
+# ---------------------------------------------------------------------------
+# target states over multi-determinant CSFs (Eq. 2)
+# ---------------------------------------------------------------------------
+
+def _csf_lists(inst, seed):
+    """CSFs of one or two determinants each over the first symmetry's
+    determinants (fixed random coefficients), every determinant used."""
+    rng = np.random.default_rng(seed)
+    dets = inst.syms[0].dets
+    M = dets.shape[0]
+    perm = rng.permutation(M)
+    terms, coef, starts = [], [], [0]
+    i = 0
+    while i < M:
+        k = 1 if (i + 1 == M or rng.random() < 0.4) else 2
+        for t in range(k):
+            terms.append(dets[perm[i + t]])
+            coef.append(1.0 if k == 1 else rng.choice([-1.0, 1.0]) / np.sqrt(2.0))
+        starts.append(len(terms))
+        i += k
+    return np.array(terms, dtype=np.uint64), np.array(coef), starts
+
+
+def test_csf_expand_single_determinants_is_identity():
+    inst = synth.tiny()
+    s = inst.syms[0]
+    d, C = oracle.csf_expand(s.dets, np.ones(s.dets.shape[0]), list(range(s.dets.shape[0] + 1)), s.ci)
+    np.testing.assert_array_equal(d, s.dets)
+    np.testing.assert_array_equal(C, s.ci)
+
+
+@pytest.mark.parametrize("kw", MICROS[:2])
+def test_csf_targets_equal_fock_space(kw):
+    """Contracted continuum block of CSF-expanded targets == the same elements
+    formed in the Fock space from the CSF combinations themselves (the CSF
+    vector sum_t coef_t |det_t u_j>, then v^T H v'): neither Slater-Condon nor
+    csf_expand on that side."""
+    import dataclasses
+    inst = synth.micro(**kw)
+    terms, coef, starts = _csf_lists(inst, 7)
+    ncsf = len(starts) - 1
+    rng = np.random.default_rng(8)
+    S = min(2, ncsf)
+    ci = np.linalg.qr(rng.standard_normal((ncsf, S)))[0]
+    d, C = oracle.csf_expand(terms, coef, starts, ci)
+    s0 = inst.syms[0]
+    exp = dataclasses.replace(inst, syms=[synth.TargetSym(s0.irrep, d, C)], l2_dets=inst.l2_dets[:0])
+    got = oracle.Oracle(exp).build()
+    HF = fock.fock_hamiltonian(inst)
+    n = 2 * inst.n_orb
+    nc = int(inst.n_c[s0.irrep ^ inst.total_irrep])
+    j0 = inst.cont_range(s0.irrep ^ inst.total_irrep)[0]
+    vecs = []
+    for st in range(S):
+        for j in range(nc):
+            v = np.zeros(1 << n)
+            for m in range(ncsf):
+                for t in range(starts[m], starts[m + 1]):
+                    occ = synth.det_to_occ(terms[t]) + [2 * (inst.n_o + j0 + j)]
+                    v[fock.basis_index(occ, n)] += coef[t] * ci[m, st]
+            vecs.append(v)
+    Vm = np.array(vecs).T
+    ref = Vm.T @ (HF @ Vm)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
