@@ -170,6 +170,21 @@ cch_status cch_add_target_symmetry(cch_ctx *ctx, int32_t irrep, int32_t n_det,
                                    int32_t n_states, const double *ci, int32_t flags,
                                    int32_t *sym_id);
 
+/* One target symmetry whose CSFs (Eq. 2) are fixed combinations of
+ * determinants: CSF m is sum_t coef[t] |dets[t]> over the terms
+ * t in [csf_start[m], csf_start[m+1]) (csf_start[0] = 0, every CSF at least
+ * one term; a determinant may appear in several CSFs), each determinant an
+ * ascending product of spin-orbitals as in cch_add_target_symmetry; CI vectors
+ * ci[n_csf][n_states] over the CSFs. The states are rewritten over the
+ * distinct determinants (in order of first appearance, coefficients summed in
+ * term order) and added as by cch_add_target_symmetry, whose checks and limits
+ * then apply (n_states <= distinct determinants). The continuum electron stays
+ * alpha, so the (N+1)-electron functions are spin-adapted for singlet targets.
+ * CCH_E_INPUT for a malformed list or a non-finite coefficient. */
+cch_status cch_add_target_symmetry_csf(cch_ctx *ctx, int32_t irrep, int32_t n_csf, const int32_t *csf_start,
+                                       int32_t n_words, const uint64_t *dets, const double *coef,
+                                       int32_t n_states, const double *ci, int32_t flags, int32_t *sym_id);
+
 /* The L2 functions (Eq. 1, second sum): n_l2 determinants with N+1 electrons
  * in target orbitals, N/2+1 alpha and N/2 beta, irrep total_irrep. */
 cch_status cch_set_l2(cch_ctx *ctx, int32_t n_l2, int32_t n_words, const uint64_t *dets,

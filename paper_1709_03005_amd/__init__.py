@@ -42,7 +42,7 @@ CCH_PAIRS_L2_TARGET = 2
 
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
-    "cch_set_integrals", "cch_add_target_symmetry", "cch_set_l2", "cch_set_target_energies", "cch_plan", "cch_build",
+    "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_target_energies", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
@@ -91,6 +91,7 @@ _SIG = {
     "cch_set_orbitals": (i32, [P, i32, P, i32, P, i32]),
     "cch_set_integrals": (i32, [P, P, P, P, P, P, C.c_double, i32]),
     "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
+    "cch_add_target_symmetry_csf": (i32, [P, i32, i32, P, i32, P, P, i32, P, i32, P]),
     "cch_set_l2": (i32, [P, i32, i32, P, i32]),
     "cch_set_target_energies": (i32, [P, P, i64, i32]),
     "cch_plan": (i32, [P, C.POINTER(PlanOpts)]),
@@ -211,6 +212,28 @@ class Context:
         sid = i32()
         self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
                                              int(kc.shape[1]), pc, fd, C.byref(sid)))
+        return sid.value
+
+    def add_target_symmetry_csf(self, irrep, csf_start, dets, coef, ci) -> int:
+        """cch_add_target_symmetry_csf: CSF m = sum of coef[t] |dets[t]> over
+        t in [csf_start[m], csf_start[m + 1]); ci[n_csf][n_states]."""
+        def host(a, dt):   # a set-up call: every list is read from host memory
+            if hasattr(a, "detach"):
+                a = a.detach().cpu().numpy()
+            return np.ascontiguousarray(a, dtype=dt)
+        st = host(csf_start, np.int32)
+        kd, kk, kc = host(dets, np.uint64), host(coef, np.float64), host(ci, np.float64)
+        if kd.ndim != 2:
+            raise CchError(CCH_E_INVALID_ARG, "dets must be [n_terms][n_words]")
+        pd, pk, pc = (x.ctypes.data_as(C.c_void_p) for x in (kd, kk, kc))
+        fd = CCH_MEM_HOST
+        n_csf = st.size - 1
+        n_terms, n_words = kd.shape
+        if n_csf <= 0 or st[-1] != n_terms or kk.shape[0] != n_terms or kc.ndim != 2 or kc.shape[0] != n_csf:
+            raise CchError(CCH_E_INVALID_ARG, "inconsistent CSF arrays")
+        sid = i32()
+        self._ck(lib.cch_add_target_symmetry_csf(self.h, int(irrep), int(n_csf), st.ctypes.data_as(C.c_void_p),
+                                                 int(n_words), pd, pk, int(kc.shape[1]), pc, fd, C.byref(sid)))
         return sid.value
 
     def set_l2(self, dets):

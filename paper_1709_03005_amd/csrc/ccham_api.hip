@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -542,6 +543,54 @@ cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int
     c->syms.push_back(std::move(s));
     if (sym_id) *sym_id = (int32_t)c->syms.size() - 1;
     return CCH_OK;
+}
+
+cch_status cch_add_target_symmetry_csf(cch_ctx *c, int32_t irrep, int32_t n_csf, const int32_t *csf_start,
+                                       int32_t n_words, const uint64_t *dets, const double *coef, int32_t n_states,
+                                       const double *ci, int32_t flags, int32_t *sym_id)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (n_csf <= 0 || !csf_start || !dets || !coef || !ci) return fail(c, CCH_E_INVALID_ARG, "empty CSF list");
+    if (n_words != c->W) return fail(c, CCH_E_INPUT, "n_words %d != %d", n_words, c->W);
+    if (n_states <= 0 || n_states > n_csf) return fail(c, CCH_E_INVALID_ARG, "bad n_states");
+    std::vector<int32_t> st((size_t)n_csf + 1);
+    TRY(host_copy(c, st.data(), csf_start, st.size() * 4, flags));
+    if (st[0] != 0) return fail(c, CCH_E_INPUT, "csf_start[0] must be 0");
+    for (int m = 0; m < n_csf; ++m)
+        if (st[m + 1] <= st[m]) return fail(c, CCH_E_INPUT, "CSF %d has no determinant", m);
+    const int64_t nt = st[n_csf];
+    std::vector<uint64_t> hd((size_t)nt * n_words);
+    std::vector<double> hc((size_t)nt), hci((size_t)n_csf * n_states);
+    TRY(host_copy(c, hd.data(), dets, hd.size() * 8, flags));
+    TRY(host_copy(c, hc.data(), coef, hc.size() * 8, flags));
+    TRY(host_copy(c, hci.data(), ci, hci.size() * 8, flags));
+    for (double v : hc)
+        if (!std::isfinite(v)) return fail(c, CCH_E_INPUT, "CSF coefficient is not finite");
+    for (double v : hci)
+        if (!std::isfinite(v)) return fail(c, CCH_E_INPUT, "CI coefficient is not finite");
+    // distinct determinants in order of first appearance; each state's
+    // coefficient of a determinant sums coef * ci over its terms in input order
+    std::map<std::vector<uint64_t>, int> index;
+    std::vector<uint64_t> ud;
+    std::vector<int> term_det((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        std::vector<uint64_t> key(hd.begin() + t * n_words, hd.begin() + (t + 1) * n_words);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, (int)index.size()).first;
+            ud.insert(ud.end(), key.begin(), key.end());
+        }
+        term_det[t] = it->second;
+    }
+    const int nd = (int)index.size();
+    std::vector<double> C((size_t)nd * n_states, 0.0);
+    for (int m = 0; m < n_csf; ++m)
+        for (int64_t t = st[m]; t < st[m + 1]; ++t)
+            for (int n = 0; n < n_states; ++n)
+                C[(size_t)term_det[t] * n_states + n] += hc[t] * hci[(size_t)m * n_states + n];
+    return cch_add_target_symmetry(c, irrep, nd, n_words, ud.data(), n_states, C.data(), CCH_MEM_HOST, sym_id);
 }
 
 cch_status cch_set_l2(cch_ctx *c, int32_t n_l2, int32_t n_words, const uint64_t *dets, int32_t flags)
@@ -1568,7 +1617,6 @@ cch_status cch_davidson_set_mlp(cch_ctx *c, cch_mlp *m)
 // ---------------------------------------------------------------------------
 // batched build
 // ---------------------------------------------------------------------------
-#include <map>
 
 struct cch_batch {
     std::vector<cch_ctx *> cs;
