@@ -69,6 +69,7 @@ WORKLOADS = {
     "small": ("small", 10, 1e-8, "rows"),
     "precision": ("precision", 10, 1e-8, "elements"),
     "learned": ("learned_test", 10, 1e-8, "elements"),
+    "l2heavy": ("l2heavy", 10, 1e-8, "elements"),   # D = 122815, dense matrix of 121 GB
 }
 
 

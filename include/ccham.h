@@ -228,6 +228,14 @@ cch_status cch_matrix_device(cch_ctx *ctx, const double **dptr, int64_t *ld);
 /* Diagonal of the matrix (D values). */
 cch_status cch_get_diagonal(cch_ctx *ctx, double *out, int32_t flags);
 
+/* Sampled elements out[i] = H[rows[i]][cols[i]], i < n, of the built matrix
+ * (Sec. 2.2), for matrices too large to copy whole. rows, cols and out are
+ * host arrays unless flags holds CCH_MEM_DEVICE (then all three are device
+ * arrays). Synchronous. CCH_E_INVALID_ARG for an index outside [0, D),
+ * CCH_E_STATE before cch_build. */
+cch_status cch_get_elements(cch_ctx *ctx, int64_t n, const int64_t *rows, const int64_t *cols, double *out,
+                            int32_t flags);
+
 /* One block of the matrix by the contraction classes of Sec. 2.2, row-major
  * into out (leading dimension ld >= the block width), host memory, or device
  * memory with CCH_MEM_DEVICE; elements of the block outside the class are 0.

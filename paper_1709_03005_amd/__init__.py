@@ -43,7 +43,7 @@ CCH_PAIRS_L2_TARGET = 2
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
     "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_target_energies", "cch_plan", "cch_build",
-    "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_block", "cch_block_shape", "cch_get_labels",
+    "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_elements", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
@@ -101,6 +101,7 @@ _SIG = {
     "cch_matrix_device": (i32, [P, C.POINTER(P), C.POINTER(i64)]),
     "cch_get_diagonal": (i32, [P, P, i32]),
     "cch_get_block": (i32, [P, i32, i32, i32, P, i64, i32]),
+    "cch_get_elements": (i32, [P, i64, P, P, P, i32]),
     "cch_block_shape": (i32, [P, i32, i32, i32, C.POINTER(i64), C.POINTER(i64)]),
     "cch_get_labels": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, C.POINTER(i64)]),
     "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
@@ -287,6 +288,17 @@ class Context:
         out = np.empty(D)
         self._ck(lib.cch_get_diagonal(self.h, out.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
         return out
+
+    def get_elements(self, rows, cols):
+        """cch_get_elements: H[rows[i]][cols[i]] without copying the matrix."""
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        c = np.ascontiguousarray(cols, dtype=np.int64)
+        if r.shape != c.shape:
+            raise CchError(CCH_E_INVALID_ARG, "rows and cols differ in shape")
+        out = np.zeros(r.size)
+        self._ck(lib.cch_get_elements(self.h, int(r.size), r.ctypes.data_as(C.c_void_p),
+                                      c.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
+        return out.reshape(r.shape)
 
     def get_block(self, cls, sym_a=0, sym_b=0):
         """cch_get_block: one class block (elements outside the class are 0)."""

@@ -109,6 +109,8 @@ hipError_t launch_l2_batched(int W, const L2Task *tasks, int ntask, int64_t tota
 hipError_t launch_class4_batched(int W, const C4Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
 hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
 hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
+hipError_t launch_gather_elements(const double *H, int64_t ldh, const int64_t *rows, const int64_t *cols, int64_t n,
+                                  double *out, hipStream_t st);
 hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrows, int64_t col0, int ncols, int mode,
                             int nca, int ncb, double *out, int64_t ldo, hipStream_t st);
 // Davidson
@@ -1154,6 +1156,36 @@ cch_status cch_get_diagonal(cch_ctx *c, double *out, int32_t flags)
     HIPCK(c, hipMemcpyAsync(out, c->d_diag, c->D * 8,
                             (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
+    return CCH_OK;
+}
+
+cch_status cch_get_elements(cch_ctx *c, int64_t n, const int64_t *rows, const int64_t *cols, double *out,
+                            int32_t flags)
+{
+    if (!c || n < 0 || (n > 0 && (!rows || !cols || !out))) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    if (n == 0) return CCH_OK;
+    std::vector<int64_t> hr((size_t)n), hc((size_t)n);
+    TRY(host_copy(c, hr.data(), rows, hr.size() * 8, flags));
+    TRY(host_copy(c, hc.data(), cols, hc.size() * 8, flags));
+    for (int64_t i = 0; i < n; ++i)
+        if (hr[i] < 0 || hr[i] >= c->D || hc[i] < 0 || hc[i] >= c->D)
+            return fail(c, CCH_E_INVALID_ARG, "element %lld: index (%lld, %lld) outside [0, %lld)", (long long)i,
+                        (long long)hr[i], (long long)hc[i], (long long)c->D);
+    int64_t *d_idx = nullptr;
+    double *d_out = nullptr;
+    hipError_t e = hipMalloc((void **)&d_idx, 16 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_out, 8 * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_idx, hr.data(), 8 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_idx + n, hc.data(), 8 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_gather_elements(c->d_H, c->ld, d_idx, d_idx + n, n, d_out, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d_out, 8 * (size_t)n,
+                           (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_idx);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_get_elements: %s", hipGetErrorString(e));
     return CCH_OK;
 }
 

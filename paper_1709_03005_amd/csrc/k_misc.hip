@@ -79,6 +79,23 @@ hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrow
     return hipGetLastError();
 }
 
+// out[i] = H[rows[i]][cols[i]], indices checked by the caller
+__global__ void k_gather_elements(const double *__restrict__ H, int64_t ldh, const int64_t *__restrict__ rows,
+                                  const int64_t *__restrict__ cols, int64_t n, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = H[rows[i] * ldh + cols[i]];
+}
+
+hipError_t launch_gather_elements(const double *H, int64_t ldh, const int64_t *rows, const int64_t *cols, int64_t n,
+                                  double *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_elements, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, H, ldh, rows, cols, n,
+                       out);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t v, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

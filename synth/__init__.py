@@ -338,6 +338,14 @@ def learned_test(seed=999):
                          name="learned_test")
 
 
+def l2heavy(seed=808):
+    """Shaped like the paper's phosphoric-acid case (a small contracted part,
+    a large L2 part, N = 122815 in total): 40 target orbitals, N=12, 2000
+    target determinants in 1 symmetry, 4 states x 178 continuum orbitals = 712
+    contracted rows, 122103 L2 functions; about 0.9 GB of integrals."""
+    return make_instance(40, 12, 1, 178, [0], 2000, 4, 122103, seed, name="l2heavy")
+
+
 def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
     """Draw (D, n_o, symmetries, states, continuum, N) from the batch ranges;
     draws whose dense (tt|cc) + (tc|tc) storage would exceed max_int_bytes,
@@ -412,5 +420,5 @@ def micro(seed, n_o=3, n_elec=2, n_c=2, n_irrep=1, n_det=None, n_states=None,
 
 CONFIGS = {
     "tiny": tiny, "small": small, "wide": wide, "medium": medium,
-    "precision": precision, "learned_test": learned_test,
+    "precision": precision, "learned_test": learned_test, "l2heavy": l2heavy,
 }
