@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mlp"],
                     help="Davidson correction: diagonal (Jacobi) or the trained network "
                          "(paper_1709_03005_amd/mlp_weights.npy)")
+    ap.add_argument("--sparse-l2", action="store_true",
+                    help="Davidson mat-vec with the L2 block as CSR of its non-zeros (formed in each solve)")
     ap.add_argument("--target-energies", action="store_true",
                     help="build classes 1, 3, 5, 6, 7 with target energies on the diagonal in place of "
                          "the target-only integrals (synthetic energies; the timing does not depend on them)")
@@ -295,7 +297,7 @@ def main():
 
     def step():
         ctx.build()
-        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, precond=pc)
+        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, precond=pc, sparse_l2=args.sparse_l2)
         return ev, info, rc
 
     for _ in range(args.warmup):
@@ -415,6 +417,7 @@ def main():
         del G, H64
     out["precision"] = args.precision
     out["target_energies"] = bool(args.target_energies)
+    out["sparse_l2"] = bool(args.sparse_l2)
     out["precond"] = args.precond
     if net is not None:
         # the plain (Jacobi) solve of the same matrix, outside the timed region

@@ -54,6 +54,7 @@ typedef int32_t cch_status;
 #define CCH_MEM_HOST 0
 #define CCH_MEM_DEVICE 1
 #define CCH_DAV_RESIDUALS 2   /* cch_davidson: evecs holds 2k rows, residuals after the vectors */
+#define CCH_DAV_SPARSE_L2 4   /* cch_davidson: the L2 block (classes 2 and 8) as CSR in the mat-vec */
 
 /* precision of the CI-contraction / expansion GEMMs (cch_plan_opts) */
 #define CCH_PREC_FP64 0
@@ -279,7 +280,13 @@ cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sy
 /* Lowest opts->k eigenpairs of the built matrix by block Davidson in FP64 on
  * the device. evals[k]; evecs[k][D] (row-major: eigenvector e at evecs + e*D);
  * either may be NULL. With flags & CCH_DAV_RESIDUALS, evecs has 2k rows and
- * rows k..2k-1 receive the residuals H x - theta x. Returns
+ * rows k..2k-1 receive the residuals H x - theta x. With flags &
+ * CCH_DAV_SPARSE_L2 the mat-vec reads the continuum rows and columns from the
+ * dense matrix and the L2 block (classes 2 and 8, sparse when the L2
+ * determinants are far apart) as CSR of its non-zeros, formed from the built
+ * matrix on the first such solve after each build (device memory: 12 bytes
+ * per non-zero, kept until cch_destroy); the eigenpairs agree with the dense
+ * mat-vec's to rounding. Returns
  * CCH_E_NOT_CONVERGED (with the best pairs) when max_iter is reached.
  * Synchronous. */
 cch_status cch_davidson(cch_ctx *ctx, const cch_dav_opts *opts, double *evals,

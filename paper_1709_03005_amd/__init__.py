@@ -29,6 +29,7 @@ CCH_E_NOT_CONVERGED = -7
 CCH_MEM_HOST = 0
 CCH_MEM_DEVICE = 1
 CCH_DAV_RESIDUALS = 2
+CCH_DAV_SPARSE_L2 = 4
 CCH_PREC_FP64 = 0
 CCH_PREC_FP32 = 1
 CCH_PREC_SPLIT_BF16 = 2
@@ -323,7 +324,7 @@ class Context:
         return dict(x=x, y=y, deg=d, label=lab, phase=ph)
 
     def davidson(self, k, tol=1e-8, max_iter=200, max_subspace=0, precond=CCH_PRECOND_JACOBI,
-                 want_vectors=True, residuals=False, block=0):
+                 want_vectors=True, residuals=False, block=0, sparse_l2=False):
         """(eigenvalues, vectors or None, info, status); with residuals=True the
         vectors array has 2k rows, residuals H x - theta x after the vectors."""
         D, _ = self.dim()
@@ -333,7 +334,8 @@ class Context:
         o = DavOpts(k, max_iter, max_subspace, precond, tol, block, 0)
         rc = lib.cch_davidson(self.h, C.byref(o), ev.ctypes.data_as(C.c_void_p),
                               vec.ctypes.data_as(C.c_void_p) if vec is not None else None,
-                              C.byref(info), CCH_MEM_HOST | (CCH_DAV_RESIDUALS if residuals else 0))
+                              C.byref(info), CCH_MEM_HOST | (CCH_DAV_RESIDUALS if residuals else 0)
+                              | (CCH_DAV_SPARSE_L2 if sparse_l2 else 0))
         self._ck(rc, ok=(CCH_OK, CCH_E_NOT_CONVERGED))
         return ev, vec, info, rc
 

@@ -114,6 +114,13 @@ hipError_t launch_gather_elements(const double *H, int64_t ldh, const int64_t *r
 hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrows, int64_t col0, int ncols, int mode,
                             int nca, int ncb, double *out, int64_t ldo, hipStream_t st);
 // Davidson
+hipError_t launch_l2_csr_count(const double *H, int64_t ld, int Dc, int nl2, int64_t *cnt, hipStream_t st);
+hipError_t launch_l2_csr_fill(const double *H, int64_t ld, int Dc, int nl2, const int64_t *off, int32_t *col,
+                              double *val, hipStream_t st);
+hipError_t launch_matvec_l2csr(const double *H, int64_t ld, int D, int Dc, const int64_t *off, const int32_t *col,
+                               const double *val, const double *V, int64_t ldv, int b, double *W, int64_t ldw,
+                               double *Wp, hipStream_t st);
+int64_t l2csr_scratch(int D, int Dc);
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
                          int64_t ldw, double *Wp, hipStream_t st);
 int matvec_splits(int D);
@@ -233,6 +240,13 @@ struct cch_ctx {
     bool planned = false, built = false;
     cch_plan_opts opts{};
     int64_t D = 0, Dc = 0, ld = 0;
+    int64_t build_gen = 0;   // builds started; a cached CSR of the L2 block belongs to one
+    struct {
+        int64_t gen = -1, nnz = 0, cap = 0;
+        int64_t *off = nullptr;
+        int32_t *col = nullptr;
+        double *val = nullptr;
+    } csr;
     double *d_H = nullptr, *d_diag = nullptr, *d_B = nullptr;
     std::vector<PairPlan> pp;
     std::vector<LtPlan> lt;
@@ -369,6 +383,9 @@ cch_status cch_destroy(cch_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (void *p : c->allocs) (void)hipFree(p);
+    (void)hipFree(c->csr.off);
+    (void)hipFree(c->csr.col);
+    (void)hipFree(c->csr.val);
     if (c->have_events)
         for (auto &ev : c->ev) (void)hipEventDestroy(ev);
     if (c->mv0) (void)hipEventDestroy(c->mv0);
@@ -1067,6 +1084,7 @@ cch_status cch_build(cch_ctx *c)
     TRY(enqueue_post(c, st));
     EVREC(7);
     c->built = true;
+    ++c->build_gen;
     c->timed = true;
     return CCH_OK;
 }
@@ -1919,6 +1937,7 @@ cch_status cch_batch_build(cch_batch *b)
     BCK(b, hipEventElapsedTime(&b->last_ms, b->e0, b->e1));
     for (cch_ctx *c : b->cs) {
         c->built = true;
+        ++c->build_gen;
         c->timed = false;
     }
     return CCH_OK;
@@ -1981,6 +2000,39 @@ struct DavBufs {
 };
 }  // namespace
 
+// CSR of the L2 block of the current build (kept until the next build)
+static cch_status ensure_l2csr(cch_ctx *c, hipStream_t st)
+{
+    if (c->csr.gen == c->build_gen) return CCH_OK;
+    const int nl2 = c->n_l2, Dc = (int)c->Dc;
+    if (!c->csr.off && hipMalloc((void **)&c->csr.off, 8 * ((size_t)nl2 + 1)) != hipSuccess)
+        return fail(c, CCH_E_OOM, "L2 row offsets");
+    int64_t *cnt = nullptr;
+    if (hipMalloc((void **)&cnt, 8 * (size_t)nl2) != hipSuccess) return fail(c, CCH_E_OOM, "L2 row counts");
+    int64_t nnz = 0;
+    hipError_t e = launch_l2_csr_count(c->d_H, c->ld, Dc, nl2, cnt, st);
+    if (e == hipSuccess) e = launch_exclusive_scan(cnt, c->csr.off, nl2, c->csr.off + nl2, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nnz, c->csr.off + nl2, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "L2 non-zero count: %s", hipGetErrorString(e));
+    if (nnz > c->csr.cap) {
+        (void)hipFree(c->csr.col);
+        (void)hipFree(c->csr.val);
+        c->csr.col = nullptr;
+        c->csr.val = nullptr;
+        c->csr.cap = 0;
+        if (hipMalloc((void **)&c->csr.col, 4 * (size_t)std::max<int64_t>(nnz, 1)) != hipSuccess ||
+            hipMalloc((void **)&c->csr.val, 8 * (size_t)std::max<int64_t>(nnz, 1)) != hipSuccess)
+            return fail(c, CCH_E_OOM, "L2 CSR of %lld non-zeros", (long long)nnz);
+        c->csr.cap = nnz;
+    }
+    HIPCK(c, launch_l2_csr_fill(c->d_H, c->ld, Dc, nl2, c->csr.off, c->csr.col, c->csr.val, st));
+    c->csr.gen = c->build_gen;
+    c->csr.nnz = nnz;
+    return CCH_OK;
+}
+
 cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double *evecs, cch_dav_info *info,
                         int32_t flags)
 {
@@ -2006,6 +2058,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     HIPCK(c, hipSetDevice(c->device));
     hipStream_t st = c->stream;
     auto t0 = std::chrono::steady_clock::now();
+    // the L2 block as CSR in the mat-vec (formed here, inside the solve's time)
+    const bool sparse = (flags & CCH_DAV_SPARSE_L2) && c->n_l2 > 0;
+    if (sparse) TRY(ensure_l2csr(c, st));
 
     const int64_t ldv = ((int64_t)D + 31) / 32 * 32;
     const int BMAX = 32;                       // block columns (<= 2k <= 32)
@@ -2032,7 +2087,9 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.P1, 8 * (size_t)mmax * BMAX) &&
               A((void **)&b.part, 8 * (size_t)std::max<int64_t>((int64_t)nch * mmax * 16, tn_part_doubles())) && A((void **)&b.norms, 8 * (size_t)blk) &&
               A((void **)&b.idx, 4 * (size_t)mmax) &&
-              A((void **)&b.Wp, 8 * (size_t)16 * D * (matvec_splits(D) + 1)) && A((void **)&b.nfb, 4) &&
+              A((void **)&b.Wp, 8 * (size_t)std::max<int64_t>((int64_t)16 * D * (matvec_splits(D) + 1),
+                                                                sparse ? l2csr_scratch(D, (int)c->Dc) : 0)) &&
+              A((void **)&b.nfb, 4) &&
               A((void **)&b.rrfb, 4);
     const bool want_mlp = o->precond == CCH_PRECOND_MLP;
     if (ok && want_mlp)
@@ -2139,8 +2196,12 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         // kept; the rank is read with the residual norms below
         const int m0 = m;
         DCK(hipEventRecord(c->mv0, st));
-        DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp,
-                          st));
+        if (sparse)
+            DCK(launch_matvec_l2csr(c->d_H, c->ld, D, (int)c->Dc, c->csr.off, c->csr.col, c->csr.val,
+                                    b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp, st));
+        else
+            DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp,
+                              st));
         DCK(hipEventRecord(c->mv1, st));
         matvecs += nb;
         mv_launches += (nb + 15) / 16;

@@ -3,7 +3,8 @@ contracted rows + 122103 L2 functions, D = 122815, a dense matrix of 121 GB
 on the device): sampled elements of every block class read back with
 cch_get_elements and compared with the oracle one by one, exact symmetry of
 the sampled pairs, and the Davidson residual certificate ||H x - theta x||
-computed by the library on the device matrix. Also cch_get_elements itself
+computed by the library on the device matrix, with the dense mat-vec and
+with the L2 block as CSR (the same eigenvalues). Also cch_get_elements itself
 against the full read-out on a small instance, and its index check."""
 import numpy as np
 import pytest
@@ -47,7 +48,12 @@ def test_l2heavy_size_parity():
         g = ctx.get_elements(rows, cols)
         gt = ctx.get_elements(cols, rows)
         ev, vr, info, rc = ctx.davidson(5, tol=1e-8, residuals=True)
-    print(f"[l2heavy] davidson rc={rc} iterations={info.iterations}", flush=True)
+        print(f"[l2heavy] davidson rc={rc} iterations={info.iterations}", flush=True)
+        ev_s, vs, info_s, rc_s = ctx.davidson(5, tol=1e-8, residuals=True, sparse_l2=True)
+    print(f"[l2heavy] sparse-L2 davidson rc={rc_s} iterations={info_s.iterations}", flush=True)
+    assert rc_s == cc.CCH_OK
+    assert np.all(np.abs(ev_s - ev) <= 1e-10 * np.abs(ev).max())
+    assert np.linalg.norm(vs[5:], axis=1).max() < 2e-8
     v, a, k = oracle.Oracle(inst).elements(rows, cols)
     ok, _ = oracle.tolerance_ok(g, v, a, k)
     assert ok.all(), [(int(r), int(c), g[i], v[i]) for i, (r, c) in enumerate(zip(rows, cols)) if not ok[i]][:5]
