@@ -2137,15 +2137,17 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     // the new block, the residual norms): one synchronisation per iteration
     struct HostIO {
         int32_t rank;
-        int32_t pad;
+        int32_t seq;   // written by the stream after each iteration's last kernel
         double res[16];
     };
     HostIO *hio = nullptr;
+    int32_t seqno = 0;
     if (hipHostMalloc((void **)&hio, sizeof(HostIO), hipHostMallocCoherent) != hipSuccess) {
         cleanup();
         return fail(c, CCH_E_OOM, "pinned host buffer");
     }
     tmp_host = hio;
+    __atomic_store_n(&hio->seq, 0, __ATOMIC_RELEASE);   // before any posted number
     double *hres = hio->res;
     DavSel sel{};
     cch_status rc = CCH_E_NOT_CONVERGED;
@@ -2210,9 +2212,25 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
                       b.G + (int64_t)m * mmax, mmax, 0, st, b.G + m, m));
         m = m0 + nb;
         DCK(rayleigh_ritz(m));
-        DCK(hipStreamSynchronize(st));
+        // the stream posts the iteration's number into the pinned block after its
+        // last kernel; the host spins on it (bounded), then falls back to a
+        // stream synchronisation, which also covers a missed post
+        ++seqno;
+        DCK(hipStreamWriteValue32(st, &hio->seq, (uint32_t)seqno, 0));
+        {
+            bool seen = false;
+            const auto ts = std::chrono::steady_clock::now();
+            for (int spin = 0; !seen; ++spin) {
+                seen = __atomic_load_n(&hio->seq, __ATOMIC_ACQUIRE) == seqno;
+                if (!seen && (spin & 1023) == 1023 &&
+                    std::chrono::steady_clock::now() - ts > std::chrono::milliseconds(20))
+                    break;
+            }
+            if (!seen) DCK(hipStreamSynchronize(st));
+        }
         {
             float ms = 0.0f;
+            DCK(hipEventSynchronize(c->rr1));
             DCK(hipEventElapsedTime(&ms, c->mv0, c->mv1));
             mv_ms += ms;
             DCK(hipEventElapsedTime(&ms, c->rr0, c->rr1));
