@@ -238,7 +238,7 @@ def main():
                          "the target-only integrals (synthetic energies; the timing does not depend on them)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "ccham runs on one GPU per process (no multi-GPU path); --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
 
