@@ -55,6 +55,7 @@ typedef int32_t cch_status;
 #define CCH_MEM_DEVICE 1
 #define CCH_DAV_RESIDUALS 2   /* cch_davidson: evecs holds 2k rows, residuals after the vectors */
 #define CCH_DAV_SPARSE_L2 4   /* cch_davidson: the L2 block (classes 2 and 8) as CSR in the mat-vec */
+#define CCH_LOWER 8           /* cch_get_matrix: only the lower triangle (Sec. 2.2) is required */
 
 /* precision of the CI-contraction / expansion GEMMs (cch_plan_opts) */
 #define CCH_PREC_FP64 0
@@ -219,7 +220,13 @@ cch_status cch_build(cch_ctx *ctx);
 /* D = dimension, n_cont_rows = rows of continuum functions (before the L2). */
 cch_status cch_get_dim(const cch_ctx *ctx, int64_t *D, int64_t *n_cont_rows);
 
-/* Copy the full symmetric matrix to out (row-major, leading dimension ld >= D). */
+/* Copy the symmetric matrix to out (row-major, leading dimension ld >= D),
+ * host memory, or device memory with CCH_MEM_DEVICE. With CCH_LOWER only the
+ * lower triangle (j <= i) is guaranteed to be written (the copy stops at the
+ * diagonal of each row block, about half the bytes); without it every element.
+ * The copy runs in row blocks of at most 1 GiB. A host copy is checked after
+ * the transfer: its diagonal must equal the device's diagonal bit for bit,
+ * else CCH_E_HIP (the contents of out are then undefined). Synchronous. */
 cch_status cch_get_matrix(cch_ctx *ctx, double *out, int64_t ld, int32_t flags);
 
 /* Device pointer and leading dimension of the resident matrix (owned by ctx,

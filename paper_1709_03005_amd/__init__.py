@@ -30,6 +30,7 @@ CCH_MEM_HOST = 0
 CCH_MEM_DEVICE = 1
 CCH_DAV_RESIDUALS = 2
 CCH_DAV_SPARSE_L2 = 4
+CCH_LOWER = 8
 CCH_PREC_FP64 = 0
 CCH_PREC_FP32 = 1
 CCH_PREC_SPLIT_BF16 = 2
@@ -271,12 +272,14 @@ class Context:
         self._ck(lib.cch_get_dim(self.h, C.byref(D), C.byref(Dc)))
         return D.value, Dc.value
 
-    def get_matrix(self, out=None):
+    def get_matrix(self, out=None, lower=False):
+        """The matrix (D x D); with lower=True only the lower triangle is
+        guaranteed (the rest of a new array is zero)."""
         D, _ = self.dim()
         if out is None:
-            out = np.empty((D, D))
+            out = np.zeros((D, D)) if lower else np.empty((D, D))
         p, f, k = _arr(out, np.float64)
-        self._ck(lib.cch_get_matrix(self.h, p, D, f))
+        self._ck(lib.cch_get_matrix(self.h, p, D, f | (CCH_LOWER if lower else 0)))
         return out
 
     def matrix_device(self):

@@ -335,6 +335,14 @@ static cch_status host_copy(cch_ctx *c, void *dst, const void *src, size_t bytes
     return CCH_OK;
 }
 
+// context fields for the allocation-free entry point (ccham_noalloc.hip); not exported
+__attribute__((visibility("hidden"))) int32_t cch_ctx_device(const cch_ctx *c) { return c->device; }
+__attribute__((visibility("hidden"))) hipStream_t cch_ctx_stream(const cch_ctx *c) { return c->stream; }
+__attribute__((visibility("hidden"))) cch_status cch_ctx_fail(cch_ctx *c, cch_status code, const char *msg)
+{
+    return fail(c, code, "%s", msg);
+}
+
 // exported functions keep the C linkage of their declarations in ccham.h
 
 const char *cch_version(void) { return "ccham 0.1.0 (gfx950)"; }
@@ -1152,9 +1160,29 @@ cch_status cch_get_matrix(cch_ctx *c, double *out, int64_t ld, int32_t flags)
     if (!c || !out) return CCH_E_INVALID_ARG;
     if (!c->built) return fail(c, CCH_E_STATE, "build first");
     if (ld < c->D) return fail(c, CCH_E_INVALID_ARG, "ld < D");
-    HIPCK(c, hipMemcpy2DAsync(out, ld * 8, c->d_H, c->ld * 8, c->D * 8, c->D,
-                              (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    const bool to_dev = flags & CCH_MEM_DEVICE, lower = flags & CCH_LOWER;
+    const hipMemcpyKind kind = to_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    // row blocks of at most 1 GiB; with CCH_LOWER each block stops at its last
+    // row's diagonal (the rectangle holding the block's lower-triangle part)
+    const int64_t D = c->D, rows_per = std::max<int64_t>(1, (int64_t(1) << 30) / (8 * D));
+    for (int64_t r0 = 0; r0 < D; r0 += rows_per) {
+        const int64_t nr = std::min(rows_per, D - r0), width = lower ? r0 + nr : D;
+        HIPCK(c, hipMemcpy2DAsync(out + r0 * ld, ld * 8, c->d_H + r0 * c->ld, c->ld * 8, width * 8, nr, kind,
+                                  c->stream));
+    }
     HIPCK(c, hipStreamSynchronize(c->stream));
+    if (!to_dev) {
+        // read-back check: the copied diagonal must equal the device diagonal
+        // (a copy that silently delivered other bytes is reported, not returned)
+        std::vector<double> dg((size_t)D);
+        HIPCK(c, hipMemcpy(dg.data(), c->d_diag, 8 * (size_t)D, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < D; ++i) {
+            const double v = out[i * ld + i];
+            if (std::memcmp(&v, &dg[(size_t)i], 8) != 0)
+                return fail(c, CCH_E_HIP, "read-back check failed: copied H[%lld][%lld] = %.17g, device diagonal %.17g",
+                            (long long)i, (long long)i, v, dg[(size_t)i]);
+        }
+    }
     return CCH_OK;
 }
 

@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "Instance", "TargetSym", "make_instance", "det_to_occ", "occ_to_det",
     "tiny", "small", "wide", "medium", "precision", "learned_test",
-    "learned_train", "batch_instance", "micro", "CONFIGS",
+    "learned_train", "batch_instance", "micro", "boundary", "mid", "CONFIGS",
 ]
 
 
@@ -346,6 +346,62 @@ def l2heavy(seed=808):
     return make_instance(40, 12, 1, 178, [0], 2000, 4, 122103, seed, name="l2heavy")
 
 
+def _active_dets(rng, n_o, n_a, n_b, tgt_irrep, irrep, active, count):
+    """Determinants with n_a alpha and n_b beta electrons, all in the listed
+    active orbitals, of one irrep, in seeded order; the first `count`."""
+    n_words = (2 * n_o + 63) // 64
+    tir = np.asarray(tgt_irrep, dtype=np.int64)
+    cand = []
+    for oa in itertools.combinations(active, n_a):
+        for ob in itertools.combinations(active, n_b):
+            r = 0
+            for o in oa + ob:
+                r ^= int(tir[o])
+            if r == irrep:
+                cand.append(sorted([2 * o for o in oa] + [2 * o + 1 for o in ob]))
+    if len(cand) < count:
+        raise ValueError("active space too small for the requested count")
+    order = np.argsort(rng.random(len(cand)), kind="stable")[:count]
+    return np.stack([occ_to_det(cand[i], n_words) for i in order])
+
+
+def boundary(words, seed=131):
+    """Determinants straddling every 64-bit word boundary of a 3- or 4-word
+    bitstring (Sec. 2.1 reports wrong masks at multiples of 64): N = 4
+    electrons in eight active orbitals placed on both sides of spin-orbitals
+    64 and 128 (3 words: 66 target orbitals) or 64, 128 and 192 (4 words:
+    100 target orbitals), two irreps, two target symmetries of 300 and 280
+    determinants with 4 and 3 states, 12 continuum orbitals per irrep and
+    400 L2 functions: D = 484."""
+    if words == 3:
+        n_o, active = 66, [0, 1, 31, 32, 62, 63, 64, 65]
+    elif words == 4:
+        n_o, active = 100, [0, 31, 32, 63, 64, 95, 96, 99]
+    else:
+        raise ValueError("words must be 3 or 4")
+    rng = np.random.default_rng(seed + words)
+    n_irrep, n_elec, n_c = 2, 4, 12
+    tgt_irrep, cont_irrep = _irreps(n_o, n_irrep, [n_c] * n_irrep)
+    h, tttt, tttc, ttcc, tctc = _gen_integrals(rng, n_o, tgt_irrep, cont_irrep)
+    syms = []
+    for irr, m, st in ((0, 300, 4), (1, 280, 3)):
+        dets = _active_dets(rng, n_o, 2, 2, tgt_irrep, irr, active, m)
+        syms.append(TargetSym(irr, dets, _ci(rng, m, st)))
+    l2 = _active_dets(rng, n_o, 3, 2, tgt_irrep, 0, active, 400)
+    return Instance(n_o=n_o, n_elec=n_elec, n_irrep=n_irrep, tgt_irrep=tgt_irrep,
+                    n_c=np.full(n_irrep, n_c, np.int32), total_irrep=0, h=h, tttt=tttt,
+                    tttc=tttc, ttcc=ttcc, tctc=tctc, e_core=0.0, syms=syms, l2_dets=l2,
+                    name=f"boundary{words}", seed=seed + words)
+
+
+def mid(seed=313):
+    """The precision shape at half size, for checks that need the whole
+    matrix on the host: 40 target orbitals, N = 12, 4000 determinants in one
+    symmetry, 20 states, 300 continuum orbitals, 14000 L2 functions:
+    D = 20000 (two-word determinants)."""
+    return make_instance(40, 12, 1, 300, [0], 4000, 20, 14000, seed, name="mid")
+
+
 def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
     """Draw (D, n_o, symmetries, states, continuum, N) from the batch ranges;
     draws whose dense (tt|cc) + (tc|tc) storage would exceed max_int_bytes,
@@ -421,4 +477,5 @@ def micro(seed, n_o=3, n_elec=2, n_c=2, n_irrep=1, n_det=None, n_states=None,
 CONFIGS = {
     "tiny": tiny, "small": small, "wide": wide, "medium": medium,
     "precision": precision, "learned_test": learned_test, "l2heavy": l2heavy,
+    "boundary3": lambda: boundary(3), "boundary4": lambda: boundary(4), "mid": mid,
 }
