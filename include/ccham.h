@@ -315,6 +315,19 @@ cch_status cch_subspace_eig(cch_ctx *ctx, const double *G, int32_t ldg, int32_t 
                             double *theta, double *Y, int32_t ldy, int32_t method,
                             int32_t *fallback, int32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as cch_subspace_eig, with no device
+ * allocation or free. Its staging buffers (used for host arrays) and its
+ * fallback counter live in one fixed array per GPU of 148 480 bytes, held by
+ * each GPU the library runs on until the process ends; m <= 96
+ * (CCH_E_INVALID_ARG beyond). Every call on a GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (several threads, or concurrent
+ * streams) race, and the caller must serialise them. Synchronous. */
+cch_status cch_subspace_eig_noalloc(cch_ctx *ctx, const double *G, int32_t ldg, int32_t m,
+                                    double *theta, double *Y, int32_t ldy, int32_t method,
+                                    int32_t *fallback, int32_t flags);
+
 /* Device time of the last cch_build in milliseconds (HIP events around the
  * queued work on the context's stream), and per-phase times (phases[8],
  * NULL allowed): 0 excitation scans, 1 target elements + densities,

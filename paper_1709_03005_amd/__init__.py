@@ -50,7 +50,7 @@ EXPORTS = [
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
     "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
-    "cch_davidson_set_mlp", "cch_subspace_eig", "cch_plan_info",
+    "cch_davidson_set_mlp", "cch_subspace_eig", "cch_plan_info", "cch_subspace_eig_noalloc",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -127,6 +127,7 @@ _SIG = {
     "cch_mlp_features": (i32, [P, C.c_double, P, i32]),
     "cch_davidson_set_mlp": (i32, [P, P]),
     "cch_subspace_eig": (i32, [P, P, i32, i32, P, P, i32, i32, C.POINTER(i32), i32]),
+    "cch_subspace_eig_noalloc": (i32, [P, P, i32, i32, P, P, i32, i32, C.POINTER(i32), i32]),
     "cch_plan_info": (i32, [P, C.POINTER(i64), C.POINTER(i32)]),
 }
 for _n, (_r, _a) in _SIG.items():
@@ -367,6 +368,18 @@ class Context:
         self._ck(lib.cch_subspace_eig(self.h, G.ctypes.data_as(C.c_void_p), G.shape[1], m,
                                       theta.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p), m, method,
                                       C.byref(fb), CCH_MEM_HOST))
+        return theta, Y, bool(fb.value)
+
+    def subspace_eig_noalloc(self, G, method=CCH_EIG_AUTO):
+        """cch_subspace_eig_noalloc: as subspace_eig, with no device allocation."""
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        m = G.shape[0]
+        theta = np.zeros(m)
+        Y = np.zeros((m, m))
+        fb = C.c_int32()
+        self._ck(lib.cch_subspace_eig_noalloc(self.h, G.ctypes.data_as(C.c_void_p), G.shape[1], m,
+                                              theta.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p), m,
+                                              method, C.byref(fb), CCH_MEM_HOST))
         return theta, Y, bool(fb.value)
 
     def mlp_features(self, theta):
