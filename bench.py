@@ -3,17 +3,23 @@
 One step = the whole hot path on one batch of synthetic input, inputs already
 resident in HBM: cch_build (excitation scans, target densities, relayout,
 FP64 MFMA expansion, class 4, classes 2/8, mirror) followed by cch_davidson
-(lowest k eigenpairs to residual tol, FP64). Default workload: the medium
-configuration (30 target orbitals, N = 10, 4 symmetries x 500 dets x 5 states,
-150 continuum orbitals per irrep, 5000 L2; D = 8000; lowest 10 to 1e-8).
+(lowest k eigenpairs to residual tol, FP64, diagonal correction). This is the
+plain form. Default workload: the learned-preconditioner test instance, the
+largest single-GPU configuration (40 target orbitals, N = 12, 8000 dets x 50
+states, 400 continuum orbitals, 40000 L2; D = 60000; lowest 10 to 1e-8).
 
-Workloads: medium (default), tiny, small, precision (D = 40000), learned
-(D = 60000; --precond mlp solves with the trained network and reports the
-Jacobi solve of the same matrix beside it), batch (64 instances, batched vs
-one after another).
+Beside the timed plain steps, the chosen forms are timed on the same matrix
+(outside the timed region): the Davidson solve with the trained network's
+correction (learned workload), with the L2 block as CSR in the mat-vec, and,
+on the precision workload, the reduced-precision expansion products.
+
+Workloads: learned (default), medium (D = 8000), medium_te (D = 8000, true
+target states with their energies on the diagonal; classes 5 and 6 between
+symmetries sharing a determinant space), tiny, small, precision (D = 40000),
+l2heavy (D = 122815), batch (64 instances, batched vs one after another).
 
 Prints ONE JSON line. `value` = lower-triangle Hamiltonian elements per second
-of the whole step (build + solve); the build-only rate and the
+of the whole plain step (build + solve); the build-only rate and the
 time-to-eigenpairs are separate fields.
 """
 from __future__ import annotations
@@ -34,27 +40,27 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # (one FMA per lane per cycle) x 2.4 GHz = 78.6 TFLOP/s
 FP64_VALU_PEAK_TFLOPS = 78.6
 
-# HBM bytes per launch of the medium workload's kernels: rocprofv3 FETCH_SIZE
-# and WRITE_SIZE passes (KiB per dispatch, averaged over one step), scaled by
-# what the same counters read for a plain 512 MiB device copy (bench.py
-# --workload copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them).
-# Keyed by the source file of the kernel and its hash when counted: a kernel
-# changed since reports null.
+# HBM bytes per launch of a workload's kernels: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (KiB per dispatch, averaged over one step), scaled by what
+# the same counters read for a plain 512 MiB device copy (bench.py --workload
+# copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them). Keyed by
+# workload and kernel, with the source file of the kernel and its hash when
+# counted: a kernel changed since reports null.
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
-    # name: (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    "rayleigh_ritz": ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
-    "matvec": ("k_davidson.hip", "c2ad709cede732f3", 252272.643, 17904.762),
-    "expansion_gemm": ("k_gemm.hip", "8cbf1a6f5665b209", 40280.400, 3533.656),
-    "l2_block": ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
+    # (workload, name): (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("medium", "rayleigh_ritz"): ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
+    ("medium", "matvec"): ("k_davidson.hip", "c2ad709cede732f3", 252272.643, 17904.762),
+    ("medium", "expansion_gemm"): ("k_gemm.hip", "8cbf1a6f5665b209", 40280.400, 3533.656),
+    ("medium", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
 }
 
 
 def traffic_bytes(kernel, workload):
     """Counter-measured HBM bytes per launch, or None."""
     import hashlib
-    t = TRAFFIC.get(kernel)
-    if t is None or workload != "medium":
+    t = TRAFFIC.get((workload, kernel))
+    if t is None:
         return None
     src = os.path.join(ROOT, "paper_1709_03005_amd", "csrc", t[0])
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != t[1]:
@@ -64,12 +70,16 @@ def traffic_bytes(kernel, workload):
 
 WORKLOADS = {
     # name: (generator, k, tol, CPU-baseline mode)
+    "learned": ("learned_test", 10, 1e-8, "elements"),
     "medium": ("medium", 10, 1e-8, "rows"),
+    # true target states on the diagonal (target-energy option), two pairs of
+    # symmetries sharing a determinant space: classes 5 and 6 in the build
+    "medium_te": ("medium_pairs", 10, 1e-8, "rows"),
     "tiny": ("tiny", 5, 1e-8, "rows"),
     "small": ("small", 10, 1e-8, "rows"),
     "precision": ("precision", 10, 1e-8, "elements"),
-    "learned": ("learned_test", 10, 1e-8, "elements"),
     "l2heavy": ("l2heavy", 10, 1e-8, "elements"),   # D = 122815, dense matrix of 121 GB
+    "l2huge": ("l2huge", 10, 1e-8, "elements"),     # D = 250712, only with the sparse L2 build
 }
 
 
@@ -77,8 +87,79 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _oracle_rate(O, inst, mode, budget_s, rng):
+    """(elements/s, sample description, oracle seconds, (rows, cols, values))
+    of the oracle on a bounded sample of the matrix (see cpu_baseline)."""
+    import numpy as np
+    D = inst.dim()
+    Dc = inst.n_cont_rows()
+    if mode == "elements":
+        counts = {"cont_cont": Dc * (Dc + 1) / 2, "l2_cont": float(inst.n_l2) * Dc,
+                  "l2_l2": inst.n_l2 * (inst.n_l2 + 1) / 2}
+        per_el, n_tot, t_tot = {}, 0, 0.0
+        got_r, got_c, got_v = [], [], []
+        for cls, cnt in counts.items():
+            if cnt == 0:
+                continue
+            n_s, t_c, n_c = 16, 0.0, 0
+            while t_c < budget_s / 3 and n_c < (1 << 17):
+                if cls == "cont_cont":
+                    r = rng.integers(0, Dc, n_s); c = rng.integers(0, Dc, n_s)
+                elif cls == "l2_cont":
+                    r = rng.integers(Dc, D, n_s); c = rng.integers(0, Dc, n_s)
+                else:
+                    r = rng.integers(Dc, D, n_s); c = rng.integers(Dc, D, n_s)
+                r, c = np.maximum(r, c), np.minimum(r, c)
+                t = time.perf_counter()
+                v, _, _ = O.elements(r, c)
+                t_c += time.perf_counter() - t
+                got_r.append(r); got_c.append(c); got_v.append(v)
+                n_c += n_s
+                n_s *= 2
+            per_el[cls] = t_c / n_c
+            n_tot += n_c
+            t_tot += t_c
+            log(f"cpu baseline {cls}: {n_c} elements in {t_c:.1f} s")
+        total = sum(counts.values())
+        est = sum(counts[c] * per_el[c] for c in per_el)
+        desc = (f"{n_tot} seeded lower-triangle elements of the same matrix, drawn per block class "
+                f"({', '.join(f'{c}: {per_el[c] * 1e6:.1f} us/element' for c in per_el)}), "
+                f"weighted by the class sizes; {t_tot:.1f} s of oracle time")
+        return total / est, desc, t_tot, tuple(np.concatenate(x) for x in (got_r, got_c, got_v))
+    groups = 0
+    t_total = 0.0
+    n_el = 0
+    got_r, got_c, got_v = [], [], []
+    while t_total < budget_s * 0.5 and groups < 8:
+        rows_c = []
+        r0 = 0
+        for sy in inst.syms:
+            nc = int(inst.n_c[sy.irrep ^ inst.total_irrep])
+            S = sy.ci.shape[1]
+            if nc:
+                jj = int(rng.integers(nc))
+                rows_c += [r0 + n * nc + jj for n in range(S)]
+            r0 += S * nc
+        n_l2_rows = max(1, int(round(len(rows_c) * inst.n_l2 / max(Dc, 1))))
+        rows_l = list(Dc + rng.choice(inst.n_l2, size=min(n_l2_rows, inst.n_l2), replace=False))
+        rows = np.array(rows_c + rows_l, dtype=np.int64)
+        t = time.perf_counter()
+        Hr = O.build_rows(rows)
+        t_total += time.perf_counter() - t
+        n_el += rows.size * D
+        groups += 1
+        pick = rng.integers(0, D, 64)
+        got_r.append(np.repeat(rows, pick.size)); got_c.append(np.tile(pick, rows.size))
+        got_v.append(np.asarray(Hr)[:, pick].ravel())
+        log(f"cpu baseline group {groups}: {rows.size} rows, {t_total:.1f} s")
+    desc = (f"{groups} stratified row groups of the same matrix ({n_el // D} full rows: one continuum "
+            f"orbital x all states per symmetry + L2 rows in proportion), {t_total:.1f} s")
+    return n_el / t_total, desc, t_total, tuple(np.concatenate(x) for x in (got_r, got_c, got_v))
+
+
 def cpu_baseline(inst, mode="rows", budget_s=20.0):
-    """The CPU oracle, timed on a bounded sample of the same matrix.
+    """The CPU oracle, timed on a bounded sample of the same matrix, with all
+    the host's threads and with one thread.
 
     mode "rows": stratified groups of full rows, each group the rows of one
     continuum orbital (all states) per target symmetry plus L2 rows in the
@@ -90,72 +171,26 @@ def cpu_baseline(inst, mode="rows", budget_s=20.0):
     per-element path on a seeded sample of each block class of the lower
     triangle (continuum-continuum, L2-continuum, L2-L2); the per-class
     times per element are weighted by the class sizes into one rate for the
-    whole lower triangle."""
+    whole lower triangle.
+
+    Returns the baseline record and the sampled oracle elements (rows, cols,
+    values), against which the benchmark states the error of every form."""
     import numpy as np
 
     import oracle
     O = oracle.Oracle(inst)
-    D = inst.dim()
-    Dc = inst.n_cont_rows()
-    rng = np.random.default_rng(7)
-    if mode == "elements":
-        counts = {"cont_cont": Dc * (Dc + 1) / 2, "l2_cont": float(inst.n_l2) * Dc,
-                  "l2_l2": inst.n_l2 * (inst.n_l2 + 1) / 2}
-        per_el, n_tot, t_tot = {}, 0, 0.0
-        for cls, cnt in counts.items():
-            if cnt == 0:
-                continue
-            n_s, t_c, n_c = 16, 0.0, 0
-            while t_c < budget_s / 6 and n_c < (1 << 17):
-                if cls == "cont_cont":
-                    r = rng.integers(0, Dc, n_s); c = rng.integers(0, Dc, n_s)
-                elif cls == "l2_cont":
-                    r = rng.integers(Dc, D, n_s); c = rng.integers(0, Dc, n_s)
-                else:
-                    r = rng.integers(Dc, D, n_s); c = rng.integers(Dc, D, n_s)
-                r, c = np.maximum(r, c), np.minimum(r, c)
-                t = time.perf_counter()
-                O.elements(r, c)
-                t_c += time.perf_counter() - t
-                n_c += n_s
-                n_s *= 2
-            per_el[cls] = t_c / n_c
-            n_tot += n_c
-            t_tot += t_c
-            log(f"cpu baseline {cls}: {n_c} elements in {t_c:.1f} s")
-        total = sum(counts.values())
-        est = sum(counts[c] * per_el[c] for c in per_el)
-        return {"value": total / est, "unit": "elements/s", "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": f"{n_tot} seeded lower-triangle elements of the same matrix, drawn per block class "
-                          f"({', '.join(f'{c}: {per_el[c] * 1e6:.1f} us/element' for c in per_el)}), "
-                          f"weighted by the class sizes; {t_tot:.1f} s of oracle time",
-                "seconds": t_tot}
-    groups = 0
-    t_total = 0.0
-    n_el = 0
-    while t_total < budget_s * 0.5 and groups < 8:
-        rows_c = []
-        r0 = 0
-        for s in inst.syms:
-            nc = int(inst.n_c[s.irrep ^ inst.total_irrep])
-            S = s.ci.shape[1]
-            if nc:
-                jj = int(rng.integers(nc))
-                rows_c += [r0 + n * nc + jj for n in range(S)]
-            r0 += S * nc
-        n_l2_rows = max(1, int(round(len(rows_c) * inst.n_l2 / max(Dc, 1))))
-        rows_l = list(Dc + rng.choice(inst.n_l2, size=min(n_l2_rows, inst.n_l2), replace=False))
-        rows = np.array(rows_c + rows_l, dtype=np.int64)
-        t = time.perf_counter()
-        O.build_rows(rows)
-        t_total += time.perf_counter() - t
-        n_el += rows.size * D
-        groups += 1
-        log(f"cpu baseline group {groups}: {rows.size} rows, {t_total:.1f} s")
-    return {"value": n_el / t_total, "unit": "elements/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{groups} stratified row groups of the same matrix ({n_el // D} full rows: one continuum "
-                      f"orbital x all states per symmetry + L2 rows in proportion), {t_total:.1f} s",
-            "seconds": t_total}
+    nthr = oracle.num_threads()
+    v_all, d_all, t_all, sample = _oracle_rate(O, inst, mode, budget_s, np.random.default_rng(7))
+    oracle.set_threads(1)
+    try:
+        v_one, d_one, t_one, _ = _oracle_rate(O, inst, mode, budget_s / 2, np.random.default_rng(8))
+    finally:
+        oracle.set_threads(nthr)
+    rec = {"value": v_all, "unit": "elements/s", "cores": nthr, "kind": "oracle", "sample": d_all,
+           "seconds": t_all,
+           "single_thread": {"value": v_one, "unit": "elements/s", "cores": 1, "sample": d_one,
+                             "seconds": t_one}}
+    return rec, sample
 
 
 def bench_batch(args):
@@ -204,7 +239,8 @@ def bench_batch(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (64 seeded instances)",
         "config": {"workload": "batch", "instances": len(insts), "dims": [I.dim() for I in insts],
-                   "total_lower_elements": lower},
+                   "target_symmetries": [len(I.syms) for I in insts],
+                   "integrals": "symmetry-packed (tt|cc), (tc|tc)", "total_lower_elements": lower},
         "batched_device_ms": float(np.median(dev)),
         "plain_ms": float(np.median(plain)) * 1e3,
         "plain_elements_per_s": lower / float(np.median(plain)),
@@ -217,22 +253,46 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def _prec(name, cc):
+    if name == "fp64":
+        return cc.CCH_PREC_FP64, 0
+    if name == "fp32":
+        return cc.CCH_PREC_FP32, 0
+    if name.startswith("bf16x"):
+        return cc.CCH_PREC_SPLIT_BF16, int(name[5:])
+    raise SystemExit(f"unknown precision form {name}")
+
+
+def _solve_stats(ctx, cc, k, tol, reps, **kw):
+    """Median wall time (ms), iterations and eigenvalues of `reps` solves."""
+    import numpy as np
+    ms, it, ev, rc = [], [], None, None
+    for _ in range(reps):
+        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, **kw)
+        ms.append(info.seconds * 1e3)
+        it.append(info.iterations)
+    return float(np.median(ms)), int(np.median(it)), np.array(ev), int(rc), info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["batch", "copy"],
+    ap.add_argument("--workload", default="learned", choices=sorted(WORKLOADS) + ["batch", "copy"],
                     help="copy: three plain 512 MiB device copies, the calibration run for HBM counters")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="time the plain step only (no chosen forms)")
     ap.add_argument("--precision", default="fp64",
-                    help="expansion GEMM form: fp64, fp32, or bf16xS (split-BF16 with S slices)")
+                    help="expansion GEMM form of the timed step: fp64, fp32, or bf16xS (split-BF16, S slices)")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mlp"],
-                    help="Davidson correction: diagonal (Jacobi) or the trained network "
+                    help="Davidson correction of the timed step: diagonal (Jacobi) or the trained network "
                          "(paper_1709_03005_amd/mlp_weights.npy)")
     ap.add_argument("--sparse-l2", action="store_true",
-                    help="Davidson mat-vec with the L2 block as CSR of its non-zeros (formed in each solve)")
+                    help="timed step with the L2 block as CSR of its non-zeros in the mat-vec")
+    ap.add_argument("--sparse-build", action="store_true",
+                    help="classes 2 and 8 built and stored as CSR (cch_plan CCH_PLAN_SPARSE_L2); implied by l2huge")
     ap.add_argument("--target-energies", action="store_true",
                     help="build classes 1, 3, 5, 6, 7 with target energies on the diagonal in place of "
                          "the target-only integrals (synthetic energies; the timing does not depend on them)")
@@ -267,33 +327,46 @@ def main():
 
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
-    if args.precision == "fp64":
-        prec, slices = cc.CCH_PREC_FP64, 0
-    elif args.precision == "fp32":
-        prec, slices = cc.CCH_PREC_FP32, 0
-    elif args.precision.startswith("bf16x"):
-        prec, slices = cc.CCH_PREC_SPLIT_BF16, int(args.precision[5:])
-    else:
-        raise SystemExit(f"unknown --precision {args.precision}")
+    prec, slices = _prec(args.precision, cc)
+    energies = None
+    if args.target_energies:
+        energies = [-1.0 - 0.01 * np.arange(sym.ci.shape[1]) for sym in inst.syms]
+    if args.workload == "medium_te":
+        # the target states: eigenvectors of each determinant space's target
+        # Hamiltonian (read from a build of the library, diagonalised on the
+        # host as a target CI program would); the first member of a pair takes
+        # the lowest S, the second the next S, with their energies
+        t = time.perf_counter()
+        c0 = cc.from_instance(inst, device=0, stream=stream)
+        c0.build()
+        energies = []
+        for a in range(0, len(inst.syms), 2):
+            w, v = np.linalg.eigh(c0.target_hamiltonian(a, a))
+            S = inst.syms[a].ci.shape[1]
+            inst.syms[a].ci = np.ascontiguousarray(v[:, :S])
+            inst.syms[a + 1].ci = np.ascontiguousarray(v[:, S:2 * S])
+            energies += [w[:S], w[S:2 * S]]
+        c0.close()
+        log(f"target states from the target Hamiltonian in {time.perf_counter() - t:.1f} s")
     t_up = time.perf_counter()
     ctx = cc.from_instance(inst, device=0, stream=stream, plan=False)   # inputs host -> HBM
-    if args.target_energies:
-        ctx.set_target_energies([-1.0 - 0.01 * np.arange(sym.ci.shape[1]) for sym in inst.syms])
+    if energies is not None:
+        ctx.set_target_energies(energies)
     ctx.sync()
     upload_s = time.perf_counter() - t_up
+    sparse_build = args.sparse_build or args.workload == "l2huge"
     t = time.perf_counter()
-    ctx.plan(precision=prec, split_slices=slices)
+    ctx.plan(precision=prec, split_slices=slices, sparse_l2=sparse_build)
     ctx.sync()
     plan_s = time.perf_counter() - t
     log(f"planned in {plan_s:.1f} s")
-    work = ctx.work_counts()
-    lower = work["lower_elements"]
+    lower = ctx.work_counts()["lower_elements"]
     net = None
-    if args.precond == "mlp":
+    if args.precond == "mlp" or (args.workload == "learned" and not args.no_forms):
         net = cc.Mlp(device=0, stream=stream)
         net.set_weights(np.load(os.path.join(ROOT, "paper_1709_03005_amd", "mlp_weights.npy")))
         ctx.set_mlp(net)
-    pc = cc.CCH_PRECOND_MLP if net is not None else cc.CCH_PRECOND_JACOBI
+    pc = cc.CCH_PRECOND_MLP if args.precond == "mlp" else cc.CCH_PRECOND_JACOBI
 
     def step():
         ctx.build()
@@ -330,24 +403,40 @@ def main():
     ph = np.median(np.array(phases), axis=0)
     names = ["scan", "target_densities", "relayout", "expansion_gemm", "class4", "l2_block", "mirror_diag"]
     phase_ms = {n: float(v) for n, v in zip(names, ph[:7])}
+    work = ctx.work_detail()
+    ev_plain = np.array(ev)
 
     # roofline figures per kernel family (algorithmic work / measured device time)
     D = inst.dim()
     mv_bytes = 8.0 * D * D                               # H streamed once per launch
     mv_avg_ms = float(np.sum(mv_ms) / max(np.sum(mv_n), 1))
+
+    def entry(bound, work_units, ms, peak, unit, scale, total_ms=None, **extra):
+        """work_units of algorithmic work done in ms of device time; total_ms:
+        the kernel's device time per step when ms covers one launch"""
+        achieved = work_units / max(ms * 1e-3, 1e-12) / scale
+        return dict(bound=bound, achieved=achieved, peak=peak, unit=unit,
+                    total_ms_per_step=ms if total_ms is None else total_ms, **extra)
+
     kernels = {
-        "matvec": {"bound": "hbm", "achieved": mv_bytes / (mv_avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "avg_ms": mv_avg_ms, "launches_per_step": float(np.mean(mv_n)),
-                   "total_ms_per_step": float(np.mean(mv_ms))},
-        "expansion_gemm": {"bound": "mfma",
-                           "achieved": work["gemm_flops"] / (phase_ms["expansion_gemm"] * 1e-3) / 1e12,
-                           "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "total_ms_per_step": phase_ms["expansion_gemm"]},
-        "l2_block": {"bound": "hbm",
-                     "achieved": 8.0 * work["l2_lower_elements"] / (phase_ms["l2_block"] * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "total_ms_per_step": phase_ms["l2_block"]},
-        "relayout": {"bound": "hbm", "achieved": work["relayout_bytes"] / max(phase_ms["relayout"], 1e-9) / 1e6,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "total_ms_per_step": phase_ms["relayout"]},
+        "matvec": entry("hbm", mv_bytes, mv_avg_ms, HBM_PEAK_GBS, "GB/s", 1e9, total_ms=float(np.mean(mv_ms)),
+                        avg_ms=mv_avg_ms, launches_per_step=float(np.mean(mv_n)),
+                        note="8 D^2 bytes per launch (H read once)"),
+        "expansion_gemm": entry("mfma", work["gemm_flops"], phase_ms["expansion_gemm"], FP64_MFMA_PEAK_TFLOPS,
+                                "TFLOP/s", 1e12, note="2 x rows x cols x K per symmetry pair, FP64 MFMA"),
+        "class4": entry("alu", work["class4_flops"], phase_ms["class4"], FP64_VALU_PEAK_TFLOPS, "TFLOP/s", 1e12,
+                        note="2 S n_c flops per connected L2 x target pair (Eq. 5), FP64 FMA on the vector "
+                             "units; phase time includes its L2 x target scan"),
+        "densities": entry("alu", work["density_flops"], phase_ms["target_densities"], FP64_VALU_PEAK_TFLOPS,
+                           "TFLOP/s", 1e12,
+                           note="transition densities of Eq. 8 (one multiply-add per (n, n') row per density "
+                                "update); the phase also holds the target pair values, the projection and "
+                                "the bucket sort, so this is a lower bound of the density kernel's rate"),
+        "l2_block": entry("hbm", 8.0 * work["l2_lower_elements"], phase_ms["l2_block"], HBM_PEAK_GBS, "GB/s",
+                          1e9, note="8 B written per lower-triangle L2 element"),
+        "relayout": entry("hbm", work["relayout_bytes"], phase_ms["relayout"], HBM_PEAK_GBS, "GB/s", 1e9),
+        "mirror": entry("hbm", work["mirror_bytes"], phase_ms["mirror_diag"], HBM_PEAK_GBS, "GB/s", 1e9,
+                        note="16 B per element above the diagonal; phase includes the diagonal copy"),
     }
     rr_avg_ms = float(np.sum(rr_ms) / max(np.sum(rr_n), 1))
     kernels["rayleigh_ritz"] = {
@@ -356,14 +445,13 @@ def main():
         "launches_per_step": float(np.mean(rr_n)), "total_ms_per_step": float(np.mean(rr_ms)),
         "fallbacks_per_step": float(np.mean(rr_fb)),
         "note": "one workgroup per solve (m <= 96): latency-bound; flops = (10/3) m^3 per solve"}
-    for v in kernels.values():
-        v["frac"] = v["achieved"] / v["peak"]
-    dom = max(kernels, key=lambda n: kernels[n]["total_ms_per_step"])
-    roof = dict(kernels[dom])
     for name, v in kernels.items():
+        v["frac"] = v["achieved"] / v["peak"]
         v["traffic"] = traffic_bytes(name, args.workload)
-    roof = {"kernel": dom, "bound": roof["bound"], "achieved": roof["achieved"], "peak": roof["peak"],
-            "unit": roof["unit"], "frac": roof["frac"], "traffic": kernels[dom]["traffic"]}
+    dom = max(kernels, key=lambda n: kernels[n]["total_ms_per_step"])
+    r = kernels[dom]
+    roof = {"kernel": dom, "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+            "unit": r["unit"], "frac": r["frac"], "traffic": r["traffic"]}
 
     out = {
         "metric": METRIC,
@@ -382,13 +470,20 @@ def main():
         "config": {"workload": args.workload, "dim": D, "n_cont_rows": inst.n_cont_rows(), "n_l2": inst.n_l2,
                    "n_target_orbitals": inst.n_o, "n_electrons": inst.n_elec,
                    "symmetries": len(inst.syms), "k": k, "tol": tol},
+        "form": {"precision": args.precision, "precond": args.precond, "sparse_l2": bool(args.sparse_l2),
+                 "sparse_build": bool(sparse_build), "device_bytes": ctx.plan_info()[0],
+                 "target_energies": energies is not None,
+                 "target_states": "target-Hamiltonian eigenvectors" if args.workload == "medium_te"
+                 else ("random orthonormal, synthetic energies" if energies is not None else "random orthonormal")},
         "build_ms": build_ms,
         "build_elements_per_s": lower / (build_ms * 1e-3),
         "davidson_ms": float(np.median(dav_s)) * 1e3,
+        # the solve's wall time above starts while the asynchronous build still runs
+        "solve_ms_excluding_build": ms_step - build_ms,
         "davidson_iterations": int(np.median(dav_it)),
         "davidson_max_residual": float(np.max(resid)),
-        "davidson_status": [int(r) for r in rcs],
-        "lowest_eigenvalue": float(ev[0]),
+        "davidson_status": [int(x) for x in rcs],
+        "lowest_eigenvalue": float(ev_plain[0]),
         "phase_ms": phase_ms,
         "kernels": kernels,
         "work": work,
@@ -398,42 +493,88 @@ def main():
         "pcie_inclusive_elements_per_s": lower / (upload_s + plan_s + ms_step * 1e-3),
         "roofline": roof,
     }
-    if prec != cc.CCH_PREC_FP64:
-        # error of this form against the FP64 build (itself checked against the oracle)
-        G = ctx.get_matrix()
-        ev_lo = np.array(ev)
-        ref = cc.from_instance(inst, device=0, stream=stream)
-        ref.build()
-        H64 = ref.get_matrix()
-        ev64, _, _, _ = ref.davidson(k, tol=tol, want_vectors=False)
-        ref.close()
-        out["precision_error"] = {
-            "mode": args.precision,
-            "max_abs_element_error": float(np.abs(G - H64).max()),
-            "max_abs_element": float(np.abs(H64).max()),
-            "max_abs_eigenvalue_error": float(np.abs(ev_lo - ev64).max()),
-            "reference": "FP64 build of the same inputs (parity-checked against the oracle)",
-        }
-        del G, H64
-    out["precision"] = args.precision
-    out["target_energies"] = bool(args.target_energies)
-    out["sparse_l2"] = bool(args.sparse_l2)
-    out["precond"] = args.precond
+    sample = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], sample = cpu_baseline(inst, cpu_mode)
+
+    def errors(c2):
+        """Max-abs error of sampled elements against the oracle's values (read
+        back with cch_get_elements, so large matrices need no host copy)."""
+        if sample is None:
+            return None
+        rs, cs, vs = sample
+        g = c2.get_elements(rs, cs)
+        return {"max_abs_error_vs_oracle": float(np.abs(g - vs).max()), "elements": int(vs.size),
+                "max_abs_oracle_element": float(np.abs(vs).max())}
+
+    out["parity_sample"] = errors(ctx)
+    forms = {}
+    if not args.no_forms:
+        reps = 3
+        if args.workload in ("learned", "l2heavy", "precision", "medium") and not sparse_build:
+            # the whole step with classes 2 and 8 built and stored sparse
+            c2 = cc.from_instance(inst, device=0, stream=stream, sparse_l2=True)
+            bt2, st2, it2 = [], [], []
+            for rep in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c2.build()
+                ev2, _, inf2, rc2 = c2.davidson(k, tol=tol, want_vectors=False)
+                torch.cuda.synchronize()
+                if rep:
+                    st2.append((time.perf_counter() - t0) * 1e3)
+                    bt2.append(c2.build_time()[0])
+                    it2.append(inf2.iterations)
+            lw2 = c2.work_counts()["lower_elements"]
+            forms["sparse_l2_build"] = {
+                "ms_per_step": float(np.median(st2)), "build_ms": float(np.median(bt2)),
+                "iterations": int(np.median(it2)), "status": int(rc2),
+                "lower_elements": lw2, "elements_per_s": lw2 / (float(np.median(st2)) * 1e-3),
+                "device_bytes": c2.plan_info()[0], "dense_device_bytes": ctx.plan_info()[0],
+                "max_abs_eigenvalue_difference": float(np.abs(np.array(ev2) - ev_plain).max()),
+                "element_error": errors(c2),
+                "note": "classes 2 and 8 built and stored as CSR of the structural non-zeros (lower_elements "
+                        "counts the dense parts and those non-zeros); the solve reads the panels and the CSR"}
+            c2.close()
+        if args.workload in ("learned", "l2heavy", "precision", "medium") and not sparse_build:
+            ms_s, it_s, ev_s, rc_s, _ = _solve_stats(ctx, cc, k, tol, reps, sparse_l2=True)
+            forms["sparse_l2_matvec"] = {"davidson_ms": ms_s, "iterations": it_s, "status": rc_s,
+                                         "max_abs_eigenvalue_difference": float(np.abs(ev_s - ev_plain).max()),
+                                         "note": "L2 block as CSR in the mat-vec (CSR formed in each solve "
+                                                 "after a build: inside the first solve's time)"}
+        if net is not None and args.precond != "mlp":
+            ms_m, it_m, ev_m, rc_m, inf_m = _solve_stats(ctx, cc, k, tol, reps, precond=cc.CCH_PRECOND_MLP)
+            ms_j, it_j, _, _, _ = _solve_stats(ctx, cc, k, tol, reps)
+            forms["mlp_preconditioner"] = {
+                "davidson_ms": ms_m, "iterations": it_m, "status": rc_m, "fallbacks": int(inf_m.fallbacks),
+                "jacobi_ms": ms_j, "jacobi_iterations": it_j, "time_gain": ms_j / ms_m,
+                "iteration_gain": it_j / max(it_m, 1),
+                "max_abs_eigenvalue_difference": float(np.abs(ev_m - ev_plain).max())}
+        if args.workload == "precision" and prec == cc.CCH_PREC_FP64:
+            for name in ("fp32", "bf16x3", "bf16x7"):
+                p2, s2 = _prec(name, cc)
+                c2 = cc.from_instance(inst, device=0, stream=stream, precision=p2, split_slices=s2,
+                                      target_energies=energies)
+                bt2, gm2 = [], []
+                for _ in range(reps + 1):
+                    c2.build()
+                    b2, ph2 = c2.build_time()
+                    bt2.append(b2)
+                    gm2.append(ph2[3])
+                ms2, it2, ev2, rc2, _ = _solve_stats(c2, cc, k, tol, 1)
+                diag = c2.get_diagonal()
+                forms[name] = {"build_ms": float(np.median(bt2[1:])),
+                               "expansion_ms": float(np.median(gm2[1:])),
+                               "fp64_expansion_ms": phase_ms["expansion_gemm"],
+                               "davidson_ms": ms2, "status": rc2,
+                               "max_abs_eigenvalue_error_vs_fp64": float(np.abs(ev2 - ev_plain).max()),
+                               "diagonal_nonzero": bool(np.abs(diag).max() > 0),
+                               "element_error": errors(c2)}
+                c2.close()
+    out["chosen_forms"] = forms
     if net is not None:
-        # the plain (Jacobi) solve of the same matrix, outside the timed region
-        ev_j, _, inf_j, rc_j = ctx.davidson(k, tol=tol, want_vectors=False)
-        out["precond_ab"] = {
-            "mlp_ms": out["davidson_ms"], "mlp_iterations": out["davidson_iterations"],
-            "mlp_fallbacks": int(info.fallbacks),
-            "jacobi_ms": inf_j.seconds * 1e3, "jacobi_iterations": int(inf_j.iterations),
-            "jacobi_status": int(rc_j),
-            "time_gain": inf_j.seconds * 1e3 / out["davidson_ms"],
-            "max_abs_eigenvalue_difference": float(np.abs(np.array(ev) - ev_j).max()),
-        }
         ctx.set_mlp(None)
         net.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, cpu_mode)
     ctx.close()
     print(json.dumps(out))
 

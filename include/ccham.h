@@ -57,6 +57,9 @@ typedef int32_t cch_status;
 #define CCH_DAV_SPARSE_L2 4   /* cch_davidson: the L2 block (classes 2 and 8) as CSR in the mat-vec */
 #define CCH_LOWER 8           /* cch_get_matrix: only the lower triangle (Sec. 2.2) is required */
 
+/* cch_plan_opts.flags */
+#define CCH_PLAN_SPARSE_L2 1  /* classes 2 and 8 built and stored as CSR, never dense (see cch_plan) */
+
 /* precision of the CI-contraction / expansion GEMMs (cch_plan_opts) */
 #define CCH_PREC_FP64 0
 #define CCH_PREC_FP32 1
@@ -81,7 +84,7 @@ typedef struct {
     int32_t precision;      /* CCH_PREC_* for the expansion GEMMs */
     int32_t split_slices;   /* slices per operand for CCH_PREC_SPLIT_BF16 (2..8) */
     int32_t autotune;       /* 1: time candidate tile shapes on the device */
-    int32_t reserved;
+    int32_t flags;          /* CCH_PLAN_* (0: the whole matrix stored dense) */
     int64_t max_device_bytes; /* 0: no limit. Else the plan's device memory stays
                                  within it: in FP64 mode the integral rows of the
                                  expansion product are laid out and multiplied in
@@ -162,6 +165,21 @@ cch_status cch_set_integrals(cch_ctx *ctx, const double *h, const double *tttt,
                              const double *tttc, const double *ttcc, const double *tctc,
                              double e_core, int32_t flags);
 
+/* The same integrals with (tt|cc) and (tc|tc) in a symmetry-packed layout
+ * (Sec. 3.3: the integrals dominate memory; values that symmetry forbids are
+ * not stored). For the target pair (P, Q), with x = irrep(P) XOR irrep(Q),
+ * one record holds a block for each continuum irrep ca in increasing order:
+ * the n_c[ca] x n_c[ca XOR x] values (P Q | j j') (ttcc) or (P j | Q j')
+ * (tctc), row-major, j of irrep ca and j' of irrep ca XOR x (indices local to
+ * their irreps). Records follow in pair order P * n_o + Q, so each array
+ * holds sum over (P, Q) of sum over ca of n_c[ca] n_c[ca XOR x] values (for
+ * four irreps of equal size a quarter of the dense array). h, tttt and tttc,
+ * the rest of the arguments and the errors are those of cch_set_integrals;
+ * the matrix built is the same as from the dense arrays, bit for bit. */
+cch_status cch_set_integrals_packed(cch_ctx *ctx, const double *h, const double *tttt,
+                                    const double *tttc, const double *ttcc, const double *tctc,
+                                    double e_core, int32_t flags);
+
 /* One target symmetry (Eq. 2): n_det determinants of n_words words each
  * (n_words = ceil(2 n_o / 64)), every one with N electrons, N/2 of each
  * spin, irrep `irrep`, all distinct; CI vectors ci[n_det][n_states]
@@ -208,7 +226,21 @@ cch_status cch_set_l2(cch_ctx *ctx, int32_t n_l2, int32_t n_words, const uint64_
 cch_status cch_set_target_energies(cch_ctx *ctx, const double *E, int64_t n, int32_t flags);
 
 /* Plan the build (precision, tiles, memory budget). opts may be NULL for the
- * FP64 defaults. Allocates the device matrix. */
+ * FP64 defaults. Allocates the device matrix.
+ * With opts->flags & CCH_PLAN_SPARSE_L2 the L2 block (classes 2 and 8; Sec.
+ * 2.2 names the off-diagonal pure-L2 class as the sparse one) is built and
+ * stored as CSR of its structural non-zeros -- the L2 determinant pairs
+ * within a double substitution, found by the excitation scan over all pairs,
+ * both triangles, columns ascending, 12 bytes each -- and never as a dense
+ * block. The rest is stored dense: the continuum columns of every row (the
+ * continuum block and class 4, D x Dc) and the transpose of class 4 (Dc x
+ * n_L2). Device memory is then about 8 (2 D Dc + ...) + 12 nnz bytes instead
+ * of 8 D^2, so L2-heavy matrices far beyond the dense limit fit one GPU.
+ * Every value equals the dense build's bit for bit. Such a context: solves
+ * with the sparse L2 mat-vec (cch_davidson's CCH_DAV_SPARSE_L2 is implied);
+ * serves cch_get_matrix, cch_get_elements, cch_get_block and
+ * cch_get_diagonal from its parts; refuses cch_matrix_device (CCH_E_STATE)
+ * and cannot join a batch. */
 cch_status cch_plan(cch_ctx *ctx, const cch_plan_opts *opts);
 
 /* Build the contracted matrix on the device (asynchronous on the stream):
@@ -284,6 +316,18 @@ cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sy
                           int32_t *x, int32_t *y, int8_t *degree, uint64_t *label,
                           int8_t *phase, int64_t cap, int64_t *n);
 
+/* The N-electron target Hamiltonian between the determinants of target
+ * symmetries sym_a (rows) and sym_b (columns): out[x][y] = <D_ax|H|D_by> over
+ * target orbitals only, E_core on the diagonal (Sec. 3.1: the target-only
+ * integrals, whose contraction the target-energy option replaces; Eq. 2's
+ * CI vectors are eigenvectors of it when the target states are exact). The
+ * values are those the build evaluated for its target pairs (zero where the
+ * determinants are more than two substitutions apart). out is M_a x M_b
+ * row-major with leading dimension ld >= M_b, host memory, or device memory
+ * with CCH_MEM_DEVICE. After cch_build; synchronous. */
+cch_status cch_target_hamiltonian(cch_ctx *ctx, int32_t sym_a, int32_t sym_b, double *out, int64_t ld,
+                                  int32_t flags);
+
 /* Lowest opts->k eigenpairs of the built matrix by block Davidson in FP64 on
  * the device. evals[k]; evecs[k][D] (row-major: eigenvector e at evecs + e*D);
  * either may be NULL. With flags & CCH_DAV_RESIDUALS, evecs has 2k rows and
@@ -328,6 +372,35 @@ cch_status cch_subspace_eig_noalloc(cch_ctx *ctx, const double *G, int32_t ldg, 
                                     double *theta, double *Y, int32_t ldy, int32_t method,
                                     int32_t *fallback, int32_t flags);
 
+/* Timing and work of cch_eig_all (device times from HIP events). */
+typedef struct {
+    double tridiag_ms;          /* Householder tridiagonalisation */
+    double eigenvalues_ms;      /* bisection on Sturm counts */
+    double vectors_ms;          /* twisted factorisations, cluster orthogonalisation, back-transformation */
+    int32_t clusters;           /* runs of eigenvalues closer than 1e-5 ||T|| (re-orthogonalised) */
+    int32_t clustered;          /* eigenvalues in those runs */
+    double tridiag_bytes;       /* algorithmic bytes of the trailing-block passes (one read + one write per
+                                   element per column) */
+    double backtransform_flops; /* 2 n^3 when vectors are formed */
+} cch_eig_info;
+
+/* Every eigenpair of a dense real symmetric matrix in FP64 on the context's
+ * device (Sec. 3.2: often all eigenvectors are required, and a dense
+ * diagonaliser serves then). A = NULL: the built matrix (n = 0 or D; not
+ * for CCH_PLAN_SPARSE_L2 contexts, CCH_E_STATE); else A is n x n row-major
+ * with leading dimension lda >= n, both triangles read. w[n] receives the
+ * eigenvalues ascending; V (may be NULL: eigenvalues only) receives the
+ * orthonormal eigenvectors as rows, eigenvector e at V + e * ldv (ldv >= n).
+ * Householder tridiagonalisation, bisection on Sturm counts, twisted
+ * factorisations with modified Gram-Schmidt inside clusters of eigenvalues
+ * closer than 1e-5 ||T||, and the back-transformation in blocks of 32
+ * reflectors on FP64 MFMA. Work space about 3 n^2 doubles of device memory
+ * (n^2 for eigenvalues only). A, w and V are host memory, or device memory
+ * with CCH_MEM_DEVICE. info may be NULL. CCH_E_INPUT for a non-finite
+ * matrix. Synchronous. */
+cch_status cch_eig_all(cch_ctx *ctx, const double *A, int64_t lda, int32_t n, double *w, double *V, int64_t ldv,
+                       int32_t flags, cch_eig_info *info);
+
 /* Device time of the last cch_build in milliseconds (HIP events around the
  * queued work on the context's stream), and per-phase times (phases[8],
  * NULL allowed): 0 excitation scans, 1 target elements + densities,
@@ -336,12 +409,33 @@ cch_status cch_subspace_eig_noalloc(cch_ctx *ctx, const double *G, int32_t ldg, 
 cch_status cch_build_time(cch_ctx *ctx, float *total_ms, float *phases);
 
 /* Work counts of the planned build, for throughput and roofline figures:
- * out[0] lower-triangle elements (D(D+1)/2), out[1] expansion GEMM flops
- * (2 * rows * cols * K summed over symmetry pairs), out[2] connected target
- * pairs, out[3] connected L2 x target pairs, out[4] relayout bytes moved
- * (read + write), out[5] class-4 outputs, out[6] L2 lower-triangle
- * elements, out[7] number of symmetry pairs. */
+ * out[0] lower-triangle elements computed (D(D+1)/2 when stored dense; with
+ * CCH_PLAN_SPARSE_L2 the dense parts plus the L2 block's structural non-zeros
+ * of the lower triangle), out[1] expansion GEMM flops (2 * rows * cols * K
+ * summed over symmetry pairs), out[2] connected target pairs, out[3]
+ * connected L2 x target pairs, out[4] relayout bytes moved (read + write),
+ * out[5] class-4 outputs, out[6] L2 lower-triangle elements computed (all of
+ * them dense, the structural non-zeros sparse), out[7] number of symmetry
+ * pairs. */
 cch_status cch_work_counts(const cch_ctx *ctx, double *out8);
+
+/* Algorithmic work of the last build, for throughput and roofline figures;
+ * out[i] for i < n (entries 13 and up are 0). Synchronous (it counts the
+ * excitation lists the build produced, and the connected L2 pairs by a
+ * counting pass of the excitation scan). CCH_E_STATE before cch_build.
+ *   0-7  as cch_work_counts;
+ *   8    connected target pairs of degree 0 or 1 (those the transition
+ *        densities of Eq. 8 use);
+ *   9    transition-density flops: one multiply-add (2 flops) per (n, n') row
+ *        per density update; a degree-0 pair makes 1.5 N updates (every
+ *        occupied spin-orbital in the spin-summed diagonal, the alpha ones in
+ *        the alpha-resolved one), an alpha excitation 2, a beta one 1;
+ *   10   class-4 flops (Eq. 5): 2 S n_c per connected L2 x target pair (one
+ *        outer product of a CI row with an integral row over j);
+ *   11   connected L2 x L2 pairs (degree <= 2), lower triangle with the
+ *        diagonal: the structural non-zeros of classes 2 and 8;
+ *   12   bytes of the mirror: 16 per element above the diagonal. */
+cch_status cch_work_detail(cch_ctx *ctx, double *out, int32_t n);
 
 /* Device memory held by the planned context (bytes) and the number of passes
  * the expansion product takes under cch_plan_opts.max_device_bytes (1 when

@@ -71,6 +71,8 @@ def _load():
     lib.orc_excitation.restype = C.c_int
     lib.orc_excitation.argtypes = [P, P, C.c_int, P, P, P]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [C.c_int]
     _lib = lib
     return lib
 
@@ -78,7 +80,10 @@ def _load():
 class _Ints(C.Structure):
     _fields_ = [("n_o", C.c_int32), ("n_cont", C.c_int32),
                 ("h", C.c_void_p), ("tttt", C.c_void_p), ("tttc", C.c_void_p),
-                ("ttcc", C.c_void_p), ("tctc", C.c_void_p), ("e_core", C.c_double)]
+                ("ttcc", C.c_void_p), ("tctc", C.c_void_p), ("e_core", C.c_double),
+                ("pk_rec", C.c_void_p), ("pk_blk", C.c_void_p), ("n_irrep", C.c_int32),
+                ("t_irrep", C.c_void_p), ("c_irrep", C.c_void_p), ("c_local", C.c_void_p),
+                ("c_count", C.c_void_p)]
 
 
 class _Inst(C.Structure):
@@ -105,10 +110,19 @@ class Oracle:
             a = np.ascontiguousarray(a, dtype=dt)
             keep.append(a)
             return a
+        pk = [None] * 6
+        if getattr(inst, "packed", False):
+            # the symmetry-packed (tt|cc) / (tc|tc) layout: record and block offsets
+            import synth
+            rec, blk = synth.packed_layout(inst.tgt_irrep, inst.n_c)
+            ci = np.repeat(np.arange(inst.n_irrep), inst.n_c)
+            loc = np.concatenate([np.arange(n) for n in inst.n_c]) if inst.n_cont else np.zeros(0)
+            pk = [_ptr(c(rec, np.int64)), _ptr(c(blk.ravel(), np.int64)), _ptr(c(inst.tgt_irrep, np.int32)),
+                  _ptr(c(ci, np.int32)), _ptr(c(loc, np.int32)), _ptr(c(inst.n_c, np.int32))]
         ints = _Ints(inst.n_o, inst.n_cont, _ptr(c(inst.h, np.float64)),
                      _ptr(c(inst.tttt, np.float64)), _ptr(c(inst.tttc, np.float64)),
                      _ptr(c(inst.ttcc, np.float64)), _ptr(c(inst.tctc, np.float64)),
-                     float(inst.e_core))
+                     float(inst.e_core), pk[0], pk[1], int(inst.n_irrep), pk[2], pk[3], pk[4], pk[5])
         cs = c(np.concatenate([[0], np.cumsum(inst.n_c)]), np.int32)
         irr = c([s.irrep for s in inst.syms], np.int32)
         nd = c([s.dets.shape[0] for s in inst.syms], np.int32)
@@ -213,6 +227,11 @@ def excitation(A, B):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    _load().orc_set_threads(int(n))
 
 
 def lowest_eigenpairs(H, k):

@@ -49,7 +49,27 @@ typedef struct {
     const double *ttcc;  /* [n_o][n_o][nc][nc]  (pq|jj') */
     const double *tctc;  /* [n_o][nc][n_o][nc]  (pj|qj') */
     double e_core;
+    /* symmetry-packed ttcc / tctc (pk_rec != NULL): record pk_rec[P * n_o + Q]
+     * holds, for each continuum irrep ca, the block of n_c[ca] x n_c[ca ^ x]
+     * values (x = irrep(P) ^ irrep(Q)) at offset pk_blk[x * n_irrep + ca];
+     * values outside the blocks are zero by symmetry */
+    const int64_t *pk_rec;
+    const int64_t *pk_blk;
+    int32_t n_irrep;
+    const int32_t *t_irrep;   /* [n_o] */
+    const int32_t *c_irrep;   /* [nc] */
+    const int32_t *c_local;   /* [nc] index inside its irrep */
+    const int32_t *c_count;   /* [n_irrep] */
 } orc_ints;
+
+/* (P Q | a b) of the packed layout, P, Q target, a, b continuum (local j) */
+static double packed_cc(const orc_ints *I, const double *arr, int P, int Q, int a, int b)
+{
+    const int x = I->t_irrep[P] ^ I->t_irrep[Q], ca = I->c_irrep[a];
+    if ((ca ^ I->c_irrep[b]) != x) return 0.0;
+    return arr[I->pk_rec[(size_t)P * I->n_o + Q] + I->pk_blk[x * I->n_irrep + ca] +
+               (int64_t)I->c_local[a] * I->c_count[ca ^ x] + I->c_local[b]];
+}
 
 typedef struct {
     orc_ints ints;
@@ -89,11 +109,13 @@ static double X(const orc_ints *I, int p, int q, int r, int s)
     if (ncnt == 2) {
         if ((cp && cq) || (cr && cs)) {       /* (tt|cc) */
             if (cp) { int t0 = p, t1 = q; p = r; q = s; r = t0; s = t1; }
+            if (I->pk_rec) return packed_cc(I, I->ttcc, p, q, r - no, s - no);
             return I->ttcc[(((size_t)p * no + q) * nc + (r - no)) * nc + (s - no)];
         }
         /* one continuum index in each pair: (tc|tc) */
         if (cp) { int t = p; p = q; q = t; }
         if (cr) { int t = r; r = s; s = t; }
+        if (I->pk_rec) return packed_cc(I, I->tctc, p, r, q - no, s - no);
         return I->tctc[(((size_t)p * nc + (q - no)) * no + r) * nc + (s - no)];
     }
     return NAN;   /* never needed: at most one continuum electron */
@@ -743,5 +765,16 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads the oracle's parallel loops use from now on (n >= 1); harness
+ * control for timing, no effect on any value. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

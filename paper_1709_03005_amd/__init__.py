@@ -31,6 +31,7 @@ CCH_MEM_DEVICE = 1
 CCH_DAV_RESIDUALS = 2
 CCH_DAV_SPARSE_L2 = 4
 CCH_LOWER = 8
+CCH_PLAN_SPARSE_L2 = 1
 CCH_PREC_FP64 = 0
 CCH_PREC_FP32 = 1
 CCH_PREC_SPLIT_BF16 = 2
@@ -51,6 +52,7 @@ EXPORTS = [
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
     "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
     "cch_davidson_set_mlp", "cch_subspace_eig", "cch_plan_info", "cch_subspace_eig_noalloc",
+    "cch_work_detail", "cch_target_hamiltonian", "cch_eig_all", "cch_set_integrals_packed",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -67,12 +69,18 @@ lib = C.CDLL(LIB_PATH)
 
 class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("split_slices", C.c_int32), ("autotune", C.c_int32),
-                ("reserved", C.c_int32), ("max_device_bytes", C.c_int64)]
+                ("flags", C.c_int32), ("max_device_bytes", C.c_int64)]
 
 
 class DavOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_subspace", C.c_int32),
                 ("precond", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("reserved", C.c_int32)]
+
+
+class EigInfo(C.Structure):
+    _fields_ = [("tridiag_ms", C.c_double), ("eigenvalues_ms", C.c_double), ("vectors_ms", C.c_double),
+                ("clusters", C.c_int32), ("clustered", C.c_int32), ("tridiag_bytes", C.c_double),
+                ("backtransform_flops", C.c_double)]
 
 
 class DavInfo(C.Structure):
@@ -92,6 +100,7 @@ _SIG = {
     "cch_sync": (i32, [P]),
     "cch_set_orbitals": (i32, [P, i32, P, i32, P, i32]),
     "cch_set_integrals": (i32, [P, P, P, P, P, P, C.c_double, i32]),
+    "cch_set_integrals_packed": (i32, [P, P, P, P, P, P, C.c_double, i32]),
     "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
     "cch_add_target_symmetry_csf": (i32, [P, i32, i32, P, i32, P, P, i32, P, i32, P]),
     "cch_set_l2": (i32, [P, i32, i32, P, i32]),
@@ -109,6 +118,9 @@ _SIG = {
     "cch_davidson": (i32, [P, C.POINTER(DavOpts), P, P, C.POINTER(DavInfo), i32]),
     "cch_build_time": (i32, [P, C.POINTER(C.c_float), P]),
     "cch_work_counts": (i32, [P, P]),
+    "cch_work_detail": (i32, [P, P, i32]),
+    "cch_target_hamiltonian": (i32, [P, i32, i32, P, i64, i32]),
+    "cch_eig_all": (i32, [P, P, i64, i32, P, P, i64, i32, C.POINTER(EigInfo)]),
     "cch_batch_create": (i32, [C.POINTER(P), P, i32, i32]),
     "cch_batch_build": (i32, [P]),
     "cch_batch_time": (i32, [P, C.POINTER(C.c_float)]),
@@ -206,6 +218,12 @@ class Context:
         flags = ps[0][1]
         self._ck(lib.cch_set_integrals(self.h, *[p[0] for p in ps], float(e_core), flags))
 
+    def set_integrals_packed(self, h, tttt, tttc, ttcc, tctc, e_core=0.0):
+        """cch_set_integrals_packed: (tt|cc) and (tc|tc) in the symmetry-packed layout."""
+        ps = [_arr(x, np.float64) for x in (h, tttt, tttc, ttcc, tctc)]
+        flags = ps[0][1]
+        self._ck(lib.cch_set_integrals_packed(self.h, *[p[0] for p in ps], float(e_core), flags))
+
     def add_target_symmetry(self, irrep, dets, ci) -> int:
         pd, fd, kd = _arr(dets, np.uint64)
         pc, fc, kc = _arr(ci, np.float64)
@@ -216,6 +234,7 @@ class Context:
         sid = i32()
         self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
                                              int(kc.shape[1]), pc, fd, C.byref(sid)))
+        self._ndet = getattr(self, "_ndet", []) + [int(n_det)]
         return sid.value
 
     def add_target_symmetry_csf(self, irrep, csf_start, dets, coef, ci) -> int:
@@ -238,6 +257,8 @@ class Context:
         sid = i32()
         self._ck(lib.cch_add_target_symmetry_csf(self.h, int(irrep), int(n_csf), st.ctypes.data_as(C.c_void_p),
                                                  int(n_words), pd, pk, int(kc.shape[1]), pc, fd, C.byref(sid)))
+        # the library keeps the distinct determinants of the terms
+        self._ndet = getattr(self, "_ndet", []) + [int(np.unique(kd, axis=0).shape[0])]
         return sid.value
 
     def set_l2(self, dets):
@@ -261,8 +282,9 @@ class Context:
             raise CchError(CCH_E_INVALID_ARG, "empty energy list (pass None to switch the option off)")
         self._ck(lib.cch_set_target_energies(self.h, pe, n, fe))
 
-    def plan(self, precision=CCH_PREC_FP64, split_slices=0, autotune=0, max_device_bytes=0):
-        o = PlanOpts(precision, split_slices, autotune, 0, max_device_bytes)
+    def plan(self, precision=CCH_PREC_FP64, split_slices=0, autotune=0, max_device_bytes=0, sparse_l2=False):
+        """cch_plan; sparse_l2=True: classes 2 and 8 built and stored as CSR."""
+        o = PlanOpts(precision, split_slices, autotune, CCH_PLAN_SPARSE_L2 if sparse_l2 else 0, max_device_bytes)
         self._ck(lib.cch_plan(self.h, C.byref(o)))
 
     def build(self):
@@ -348,6 +370,43 @@ class Context:
         self._ck(lib.cch_work_counts(self.h, out.ctypes.data_as(C.c_void_p)))
         keys = ["lower_elements", "gemm_flops", "target_pairs", "l2_target_pairs", "relayout_bytes",
                 "class4_outputs", "l2_lower_elements", "sym_pairs"]
+        return dict(zip(keys, out.tolist()))
+
+    def eig_all(self, A=None, vectors=True):
+        """cch_eig_all: (eigenvalues ascending, eigenvectors as rows or None,
+        EigInfo) of a host matrix A, or of the built matrix when A is None."""
+        if A is None:
+            n, _ = self.dim()
+            pa, lda = None, 0
+        else:
+            A = np.ascontiguousarray(A, dtype=np.float64)
+            n = A.shape[0]
+            pa, lda = A.ctypes.data_as(C.c_void_p), A.shape[1]
+        w = np.zeros(n)
+        V = np.zeros((n, n)) if vectors else None
+        info = EigInfo()
+        self._ck(lib.cch_eig_all(self.h, pa, lda, n if A is not None else 0, w.ctypes.data_as(C.c_void_p),
+                                 V.ctypes.data_as(C.c_void_p) if vectors else None, n, CCH_MEM_HOST,
+                                 C.byref(info)))
+        return w, V, info
+
+    def target_hamiltonian(self, sym_a, sym_b):
+        """cch_target_hamiltonian: <D_ax|H|D_by> over target determinants."""
+        ma = self._ndet[sym_a]
+        mb = self._ndet[sym_b]
+        out = np.zeros((ma, mb))
+        self._ck(lib.cch_target_hamiltonian(self.h, sym_a, sym_b, out.ctypes.data_as(C.c_void_p), max(mb, 1),
+                                            CCH_MEM_HOST))
+        return out
+
+    def work_detail(self):
+        """cch_work_detail: the work counts plus the per-kernel algorithmic work
+        of the last build."""
+        out = np.zeros(16)
+        self._ck(lib.cch_work_detail(self.h, out.ctypes.data_as(C.c_void_p), 16))
+        keys = ["lower_elements", "gemm_flops", "target_pairs", "l2_target_pairs", "relayout_bytes",
+                "class4_outputs", "l2_lower_elements", "sym_pairs", "density_pairs", "density_flops",
+                "class4_flops", "l2_pairs", "mirror_bytes"]
         return dict(zip(keys, out.tolist()))
 
     def plan_info(self):
@@ -520,7 +579,10 @@ def from_instance(inst, device=0, stream=None, plan=True, target_energies=None, 
     the diagonal is set before the plan."""
     ctx = Context(device, stream)
     ctx.set_orbitals(inst.n_o, inst.tgt_irrep, inst.n_irrep, inst.n_c, inst.total_irrep)
-    ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
+    if getattr(inst, "packed", False):
+        ctx.set_integrals_packed(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
+    else:
+        ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
     for s in inst.syms:
         ctx.add_target_symmetry(s.irrep, s.dets, s.ci)
     if inst.l2_dets is not None and len(inst.l2_dets):

@@ -37,7 +37,7 @@ hipError_t launch_gamma(int W, PairList pl, const int64_t *start, const int64_t 
                         double *At, hipStream_t st);
 hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int n_cont,
                            const int32_t *slotP, const int32_t *slotQ, int n_slot, int ja0, int nca,
-                           int jb0, int ncb, double *B, hipStream_t st);
+                           int jb0, int ncb, double *B, hipStream_t st, const PackedCC *pk);
 struct ExpandEpi {
     double *H;
     int64_t ld;
@@ -108,6 +108,10 @@ hipError_t launch_expand_f64_batched(const GemmTask *tasks, int ntask, int64_t t
 hipError_t launch_l2_batched(int W, const L2Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
 hipError_t launch_class4_batched(int W, const C4Task *tasks, int ntask, int64_t total, int grid, hipStream_t st);
 hipError_t launch_mirror(double *H, int64_t ld, int D, hipStream_t st);
+hipError_t launch_scatter_pairs(const int32_t *px, const int32_t *py, const double *v, int64_t n, int transpose,
+                                double *out, int64_t ldo, hipStream_t st);
+hipError_t launch_pair_census(const int8_t *deg, const uint64_t *label, int64_t n, unsigned long long *out,
+                              hipStream_t st);
 hipError_t launch_diag(const double *H, int64_t ld, int D, double *out, hipStream_t st);
 hipError_t launch_gather_elements(const double *H, int64_t ldh, const int64_t *rows, const int64_t *cols, int64_t n,
                                   double *out, hipStream_t st);
@@ -117,9 +121,36 @@ hipError_t launch_get_block(const double *H, int64_t ldh, int64_t row0, int nrow
 hipError_t launch_l2_csr_count(const double *H, int64_t ld, int Dc, int nl2, int64_t *cnt, hipStream_t st);
 hipError_t launch_l2_csr_fill(const double *H, int64_t ld, int Dc, int nl2, const int64_t *off, int32_t *col,
                               double *val, hipStream_t st);
-hipError_t launch_matvec_l2csr(const double *H, int64_t ld, int D, int Dc, const int64_t *off, const int32_t *col,
-                               const double *val, const double *V, int64_t ldv, int b, double *W, int64_t ldw,
-                               double *Wp, hipStream_t st);
+hipError_t launch_matvec_l2csr(const double *P, int64_t ldp, const double *R, int64_t ldr, int rc0, int D, int Dc,
+                               const int64_t *off, const int32_t *col, const double *val, const double *V,
+                               int64_t ldv, int b, double *W, int64_t ldw, double *Wp, hipStream_t st);
+// sparse L2 block (classes 2 and 8 as CSR)
+hipError_t launch_l2s_struct(int W, const uint64_t *dets, int n, const int64_t *off, int64_t *cnt, int32_t *col,
+                             hipStream_t st);
+hipError_t launch_l2s_values(int W, const uint64_t *dets, int n, const TgtInts &I, const int64_t *off,
+                             const int32_t *col, double *val, double *diag, hipStream_t st);
+hipError_t launch_transpose_c4(const double *P, int64_t ldp, int Dc, int nl2, double *R, int64_t ldr, hipStream_t st);
+hipError_t launch_sparse_gather(const SparseMat &S, const int64_t *rows, const int64_t *cols, int64_t n, double *out,
+                                hipStream_t st);
+hipError_t launch_sparse_principal(const SparseMat &S, const int32_t *idx, int ns, double *G, int ldg, hipStream_t st);
+hipError_t launch_sparse_rows(const SparseMat &S, int64_t r0, int nr, int64_t c0, int ncols, int mode, double *out,
+                              int64_t ldo, hipStream_t st);
+hipError_t launch_sparse_row_norms(const SparseMat &S, int D, double *rho, hipStream_t st);
+// full-spectrum eigensolver
+hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
+                           const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
+                           hipStream_t st);
+hipError_t launch_trd_step(double *A, int64_t lda, int n, int j, const TrdVec &V, hipStream_t st);
+hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, int n, const int32_t *bs,
+                                  const int32_t *bm, const int32_t *bk, double lo, double hi, double pivmin,
+                                  double *w, hipStream_t st);
+hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int32_t *bs, const int32_t *bm,
+                              const double *w, double pivmin, double *Z, int64_t ldz, double *S, int64_t lds,
+                              hipStream_t st);
+hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, hipStream_t st);
+hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, int nb, double *Vb, hipStream_t st);
+hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st);
+hipError_t launch_transpose_sq(const double *Z, int64_t ldz, int n, double *out, int64_t ldo, hipStream_t st);
 int64_t l2csr_scratch(int D, int Dc);
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
                          int64_t ldw, double *Wp, hipStream_t st);
@@ -225,6 +256,11 @@ struct cch_ctx {
     // integrals
     bool have_ints = false;
     double *d_h = nullptr, *d_tttt = nullptr, *d_tttc = nullptr, *d_ttcc = nullptr, *d_tctc = nullptr;
+    // symmetry-packed (tt|cc) / (tc|tc): record offsets per target pair (device)
+    // and block offsets blk[x * n_irrep + ca] inside a record (host)
+    bool packed = false;
+    int64_t *d_pk_rec = nullptr;
+    std::vector<int64_t> pk_blk;
     double e_core = 0.0;
     // target energies on the diagonal (all states, symmetry by symmetry)
     bool energy_mode = false;
@@ -246,8 +282,14 @@ struct cch_ctx {
         int64_t *off = nullptr;
         int32_t *col = nullptr;
         double *val = nullptr;
+        bool planned = false;   // sparse plan: allocated with the plan (freed with it)
     } csr;
     double *d_H = nullptr, *d_diag = nullptr, *d_B = nullptr;
+    // CCH_PLAN_SPARSE_L2: d_H holds the continuum columns of every row (leading
+    // dimension ld >= Dc), d_R the transpose of class 4, csr the L2 block
+    bool sparse = false;
+    double *d_R = nullptr;
+    int64_t ldr = 0;
     std::vector<PairPlan> pp;
     std::vector<LtPlan> lt;
     hipEvent_t ev[8] = {};
@@ -391,9 +433,11 @@ cch_status cch_destroy(cch_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (void *p : c->allocs) (void)hipFree(p);
-    (void)hipFree(c->csr.off);
-    (void)hipFree(c->csr.col);
-    (void)hipFree(c->csr.val);
+    if (!c->csr.planned) {
+        (void)hipFree(c->csr.off);
+        (void)hipFree(c->csr.col);
+        (void)hipFree(c->csr.val);
+    }
     if (c->have_events)
         for (auto &ev : c->ev) (void)hipEventDestroy(ev);
     if (c->mv0) (void)hipEventDestroy(c->mv0);
@@ -483,6 +527,54 @@ cch_status cch_set_integrals(cch_ctx *c, const double *h, const double *tttt, co
         TRY(copy_in(c, c->d_tctc, tctc, n2c * 8, flags));
     }
     HIPCK(c, hipStreamSynchronize(c->stream));
+    c->e_core = e_core;
+    c->have_ints = true;
+    return CCH_OK;
+}
+
+cch_status cch_set_integrals_packed(cch_ctx *c, const double *h, const double *tttt, const double *tttc,
+                                    const double *ttcc, const double *tctc, double e_core, int32_t flags)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->have_ints) return fail(c, CCH_E_STATE, "integrals already set");
+    if (!h || !tttt || (c->n_cont && (!tttc || !ttcc || !tctc)))
+        return fail(c, CCH_E_INVALID_ARG, "integral pointer is NULL");
+    if (!std::isfinite(e_core)) return fail(c, CCH_E_INPUT, "e_core is not finite");
+    const int ni = c->n_irrep, no = c->n_o;
+    // block offsets inside a record, record sizes per x, record offsets per pair
+    std::vector<int64_t> blk((size_t)ni * ni), size((size_t)ni), rec((size_t)no * no + 1, 0);
+    for (int x = 0; x < ni; ++x) {
+        int64_t off = 0;
+        for (int ca = 0; ca < ni; ++ca) {
+            blk[(size_t)x * ni + ca] = off;
+            off += (int64_t)c->n_c[ca] * c->n_c[ca ^ x];
+        }
+        size[x] = off;
+    }
+    for (int P = 0; P < no; ++P)
+        for (int Q = 0; Q < no; ++Q)
+            rec[(size_t)P * no + Q + 1] = rec[(size_t)P * no + Q] + size[c->tgt_irrep[P] ^ c->tgt_irrep[Q]];
+    const size_t npk = (size_t)rec[(size_t)no * no];
+    const size_t nc = c->n_cont, norb = c->n_orb;
+    const size_t nh = norb * norb, n4 = (size_t)no * no * no * no, n3c = (size_t)no * no * no * nc;
+    TRY(dalloc(c, &c->d_h, nh));
+    TRY(dalloc(c, &c->d_tttt, n4));
+    TRY(dalloc(c, &c->d_tttc, n3c));
+    TRY(dalloc(c, &c->d_ttcc, npk));
+    TRY(dalloc(c, &c->d_tctc, npk));
+    TRY(dalloc(c, &c->d_pk_rec, rec.size()));
+    TRY(copy_in(c, c->d_h, h, nh * 8, flags));
+    TRY(copy_in(c, c->d_tttt, tttt, n4 * 8, flags));
+    if (nc) {
+        TRY(copy_in(c, c->d_tttc, tttc, n3c * 8, flags));
+        TRY(copy_in(c, c->d_ttcc, ttcc, npk * 8, flags));
+        TRY(copy_in(c, c->d_tctc, tctc, npk * 8, flags));
+    }
+    TRY(copy_in(c, c->d_pk_rec, rec.data(), rec.size() * 8, CCH_MEM_HOST));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->pk_blk = std::move(blk);
+    c->packed = true;
     c->e_core = e_core;
     c->have_ints = true;
     return CCH_OK;
@@ -702,6 +794,7 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
         if (opts->precision == CCH_PREC_SPLIT_BF16 && (opts->split_slices < 1 || opts->split_slices > 8))
             return fail(c, CCH_E_INVALID_ARG, "split_slices must be 1..8");
         if (opts->max_device_bytes < 0) return fail(c, CCH_E_INVALID_ARG, "negative memory budget");
+        if (opts->flags & ~CCH_PLAN_SPARSE_L2) return fail(c, CCH_E_INVALID_ARG, "unknown plan flags %d", opts->flags);
         c->opts = *opts;
     }
     HIPCK(c, hipSetDevice(c->device));
@@ -729,7 +822,9 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     }
     if (c->D <= 0) return fail(c, CCH_E_STATE, "empty matrix");
     if (c->D > 2000000000LL) return fail(c, CCH_E_LIMIT, "dimension too large");
-    c->ld = (c->D + 31) / 32 * 32;
+    c->sparse = (c->opts.flags & CCH_PLAN_SPARSE_L2) != 0;
+    // dense: D x D; sparse L2 block: d_H keeps only the continuum columns
+    c->ld = c->sparse ? std::max<int64_t>(32, (c->Dc + 31) / 32 * 32) : (c->D + 31) / 32 * 32;
     // symmetry pairs a >= b
     int64_t maxB = 0;
     for (int a = 0; a < (int)c->syms.size(); ++a) {
@@ -809,6 +904,27 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     c->relayout_elems = maxB;
     TRY(dalloc(c, &c->d_H, (size_t)c->D * c->ld));
     TRY(dalloc(c, &c->d_diag, c->D));
+    if (c->sparse) {
+        // transpose of class 4, and the L2 block's CSR sized by a counting pass
+        // of the excitation scan over all L2 pairs (the columns are listed by
+        // the build)
+        c->ldr = std::max<int64_t>(32, ((int64_t)c->n_l2 + 31) / 32 * 32);
+        TRY(dalloc(c, &c->d_R, (size_t)std::max<int64_t>(c->Dc, 1) * c->ldr));
+        TRY(dalloc(c, &c->csr.off, (size_t)c->n_l2 + 1));
+        int64_t *cnt = nullptr;
+        TRY(dalloc(c, &cnt, std::max(c->n_l2, 1)));
+        int64_t nnz = 0;
+        if (c->n_l2 > 0) {
+            HIPCK(c, launch_l2s_struct(c->W, c->d_l2, c->n_l2, nullptr, cnt, nullptr, c->stream));
+            HIPCK(c, launch_exclusive_scan(cnt, c->csr.off, c->n_l2, c->csr.off + c->n_l2, c->stream));
+            HIPCK(c, hipMemcpyAsync(&nnz, c->csr.off + c->n_l2, 8, hipMemcpyDeviceToHost, c->stream));
+            HIPCK(c, hipStreamSynchronize(c->stream));
+        }
+        TRY(dalloc(c, &c->csr.col, std::max<int64_t>(nnz, 1)));
+        TRY(dalloc(c, &c->csr.val, std::max<int64_t>(nnz, 1)));
+        c->csr.nnz = c->csr.cap = nnz;
+        c->csr.planned = true;
+    }
     if (c->opts.precision == CCH_PREC_FP64) {
         const int64_t budget = c->opts.max_device_bytes;
         if (budget == 0 || c->bytes + 8 * maxB <= budget) {
@@ -909,6 +1025,22 @@ struct Fan {
     }
 };
 
+// where the integral rows of a symmetry pair's relayout start in the packed
+// layout (continuum rows from j0 of the first symmetry's range)
+static PackedCC packed_cc(const cch_ctx *c, const PairPlan &p, int j0)
+{
+    PackedCC pk{};
+    if (!c->packed) return pk;
+    const SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
+    const int ca = sa.irrep ^ c->total_irrep, cb = sb.irrep ^ c->total_irrep, x = ca ^ cb;
+    pk.rec = c->d_pk_rec;
+    pk.boffJ = c->pk_blk[(size_t)x * c->n_irrep + ca] + (int64_t)j0 * sb.nc;
+    pk.boffK = c->pk_blk[(size_t)x * c->n_irrep + cb];
+    pk.jr0 = j0;
+    pk.nca_full = sa.nc;
+    return pk;
+}
+
 // phases 0-2: scans, target elements and densities, relayout; every symmetry
 // pair (and L2-target group) writes only its own buffers, so with `fan` they
 // run on the auxiliary streams side by side
@@ -959,8 +1091,9 @@ static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan, boo
         if (sa.nc == 0 || sb.nc == 0) continue;
         if (c->b_shared) continue;   // one shared buffer: rows are laid out pass by pass in phase 3
         const hipStream_t s = f(w++);
+        const PackedCC pk = packed_cc(c, p, 0);
         HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot, sa.ja0,
-                                 sa.nc, sb.ja0, sb.nc, p.d_B, s));
+                                 sa.nc, sb.ja0, sb.nc, p.d_B, s, c->packed ? &pk : nullptr));
         const int K = 2 * p.n_slot, N = sa.nc * sb.nc;
         if (c->opts.precision == CCH_PREC_FP32) {
             HIPCK(c, launch_to_f32(p.d_At, p.d_At32, (int64_t)K * p.nrows, s));
@@ -1001,8 +1134,9 @@ static cch_status enqueue_gemm(cch_ctx *c, hipStream_t st, bool fan)
             // the product's columns (j, j') of those rows; each output keeps its sum over K
             for (int j0 = 0; j0 < sa.nc; j0 += p.jj_chunk) {
                 const int nj = std::min(p.jj_chunk, sa.nc - j0);
+                const PackedCC pk = packed_cc(c, p, j0);
                 HIPCK(c, launch_relayout(c->d_ttcc, c->d_tctc, c->n_o, c->n_cont, p.d_slotP, p.d_slotQ, p.n_slot,
-                                         sa.ja0 + j0, nj, sb.ja0, sb.nc, p.d_B, st));
+                                         sa.ja0 + j0, nj, sb.ja0, sb.nc, p.d_B, st, c->packed ? &pk : nullptr));
                 ExpandEpi e2 = ep;
                 e2.row0a += j0;
                 e2.ja0 += j0;
@@ -1028,17 +1162,36 @@ static cch_status enqueue_l2(cch_ctx *c, hipStream_t st)
 {
     if (c->n_l2 > 0) {
         const TgtInts I{c->d_h, c->d_tttt, c->n_o, c->n_orb, c->e_core};
-        L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
-        HIPCK(c, launch_l2_block(c->W, a, st));
+        if (c->sparse) {
+            // column lists of the L2 rows, then the values (and the L2 part of the diagonal)
+            HIPCK(c, launch_l2s_struct(c->W, c->d_l2, c->n_l2, c->csr.off, nullptr, c->csr.col, st));
+            HIPCK(c, launch_l2s_values(c->W, c->d_l2, c->n_l2, I, c->csr.off, c->csr.col, c->csr.val,
+                                       c->d_diag + c->Dc, st));
+        } else {
+            L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
+            HIPCK(c, launch_l2_block(c->W, a, st));
+        }
     }
     return CCH_OK;
 }
 
 static cch_status enqueue_post(cch_ctx *c, hipStream_t st)
 {
+    if (c->sparse) {
+        // upper triangle of the continuum block, its diagonal, and the transpose of class 4
+        HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->Dc, st));
+        HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->Dc, c->d_diag, st));
+        HIPCK(c, launch_transpose_c4(c->d_H, c->ld, (int)c->Dc, c->n_l2, c->d_R, c->ldr, st));
+        return CCH_OK;
+    }
     HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->D, st));
     HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->D, c->d_diag, st));
     return CCH_OK;
+}
+
+static SparseMat sparse_mat(const cch_ctx *c)
+{
+    return SparseMat{c->d_H, c->ld, c->d_R, c->ldr, c->csr.off, c->csr.col, c->csr.val, c->Dc};
 }
 
 cch_status cch_build(cch_ctx *c)
@@ -1093,6 +1246,7 @@ cch_status cch_build(cch_ctx *c)
     EVREC(7);
     c->built = true;
     ++c->build_gen;
+    if (c->sparse) c->csr.gen = c->build_gen;   // the build wrote the CSR itself
     c->timed = true;
     return CCH_OK;
 }
@@ -1135,14 +1289,123 @@ cch_status cch_work_counts(const cch_ctx *c, double *out)
     }
     for (auto &L : c->lt) ltp += (double)L.pr.n;
     for (auto &s : c->syms) c4 += (double)c->n_l2 * s.S * s.nc;
-    out[0] = (double)c->D * (c->D + 1) / 2.0;
+    // lower-triangle elements: every element of the dense parts; of a sparse
+    // L2 block its structural non-zeros (the CSR holds both triangles)
+    const double l2_lower = c->sparse ? ((double)c->csr.nnz + c->n_l2) / 2.0
+                                      : (double)c->n_l2 * (c->n_l2 + 1) / 2.0;
+    out[0] = c->sparse ? (double)c->Dc * (c->Dc + 1) / 2.0 + (double)c->n_l2 * c->Dc + l2_lower
+                       : (double)c->D * (c->D + 1) / 2.0;
     out[1] = gemm;
     out[2] = tp;
     out[3] = ltp;
     out[4] = 16.0 * (double)c->relayout_elems;
     out[5] = c4;
-    out[6] = (double)c->n_l2 * (c->n_l2 + 1) / 2.0;
+    out[6] = l2_lower;
     out[7] = (double)c->pp.size();
+    return CCH_OK;
+}
+
+cch_status cch_target_hamiltonian(cch_ctx *c, int32_t sym_a, int32_t sym_b, double *out, int64_t ld, int32_t flags)
+{
+    if (!c || !out) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    const int ns = (int)c->syms.size();
+    if (sym_a < 0 || sym_a >= ns || sym_b < 0 || sym_b >= ns) return fail(c, CCH_E_INVALID_ARG, "bad symmetry");
+    const int ma = c->syms[sym_a].M, mb = c->syms[sym_b].M;
+    if (ld < mb) return fail(c, CCH_E_INVALID_ARG, "ld %lld below %d columns", (long long)ld, mb);
+    // the pair list of (max, min): its values are <det of the larger index|H|det of the smaller>
+    const int hi = std::max(sym_a, sym_b), lo = std::min(sym_a, sym_b);
+    const PairPlan *pp = nullptr;
+    for (auto &p : c->pp)
+        if (p.a == hi && p.b == lo) pp = &p;
+    if (!pp) return fail(c, CCH_E_STATE, "no pair list for symmetries %d, %d", hi, lo);
+    HIPCK(c, hipSetDevice(c->device));
+    const bool dev = flags & CCH_MEM_DEVICE;
+    double *d = out;
+    int64_t ldo = ld;
+    if (!dev) {
+        ldo = mb;
+        if (hipMalloc((void **)&d, 8 * (size_t)std::max(1, ma) * std::max(1, mb)) != hipSuccess)
+            return fail(c, CCH_E_OOM, "target Hamiltonian staging");
+    }
+    hipError_t e = hipSuccess;
+    if (ldo == mb) e = launch_fill_f64(d, 0.0, (int64_t)ma * mb, c->stream);
+    else
+        for (int r = 0; r < ma && e == hipSuccess; ++r) e = launch_fill_f64(d + (int64_t)r * ldo, 0.0, mb, c->stream);
+    if (e == hipSuccess)
+        e = launch_scatter_pairs(pp->pr.pl.x, pp->pr.pl.y, pp->d_hv, pp->pr.n, sym_a < sym_b ? 1 : 0, d, ldo,
+                                 c->stream);
+    if (e == hipSuccess && !dev)
+        e = hipMemcpy2DAsync(out, 8 * ld, d, 8 * ldo, 8 * (size_t)mb, ma, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!dev) (void)hipFree(d);
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_target_hamiltonian: %s", hipGetErrorString(e));
+    return CCH_OK;
+}
+
+cch_status cch_work_detail(cch_ctx *c, double *out, int32_t n)
+{
+    if (!c || (n > 0 && !out) || n < 0) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    double v[16] = {};
+    TRY(cch_work_counts(c, v));
+    HIPCK(c, hipSetDevice(c->device));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    std::vector<void *> tmp;
+    auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
+    auto galloc = [&](void **p, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+        if (e == hipSuccess) tmp.push_back(*p);
+        return e;
+    };
+    unsigned long long *cnt = nullptr;
+    hipError_t e = galloc((void **)&cnt, 4 * sizeof(unsigned long long));
+    double pairs01 = 0.0, gamma = 0.0;
+    const double ne = c->n_elec;
+    for (auto &p : c->pp) {
+        if (e != hipSuccess) break;
+        unsigned long long h[4] = {};
+        e = launch_pair_census(p.pr.pl.deg, p.pr.pl.label, p.pr.n, cnt, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        pairs01 += (double)(h[0] + h[1] + h[2]);
+        // density updates per pair: degree 0 adds every occupied spin-orbital to
+        // the spin-summed diagonal and the alpha ones to the alpha-resolved one
+        // (1.5 N); an alpha excitation feeds both densities (2), a beta one the
+        // spin-summed density only (1); each update is one multiply-add per row
+        gamma += 2.0 * p.nrows * (1.5 * ne * (double)h[0] + 2.0 * (double)h[1] + (double)h[2]);
+    }
+    double c4 = 0.0;
+    for (auto &L : c->lt) {
+        const SymInfo &s = c->syms[L.sym];
+        c4 += 2.0 * s.S * (double)s.nc * (double)L.pr.n;
+    }
+    double l2pairs = 0.0;
+    if (e == hipSuccess && c->n_l2 > 0) {
+        int64_t *rc = nullptr, *ro = nullptr, *tot = nullptr, h = 0;
+        e = galloc((void **)&rc, 8 * (size_t)c->n_l2);
+        if (e == hipSuccess) e = galloc((void **)&ro, 8 * (size_t)c->n_l2);
+        if (e == hipSuccess) e = galloc((void **)&tot, 8);
+        if (e == hipSuccess)
+            e = launch_scan(SCAN_LL, c->W, c->d_l2, c->n_l2, c->d_l2, c->n_l2, 2 * c->n_o, nullptr, rc, PairList{},
+                            c->stream);
+        if (e == hipSuccess) e = launch_exclusive_scan(rc, ro, c->n_l2, tot, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, tot, 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        l2pairs = (double)h;
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_work_detail: %s", hipGetErrorString(e));
+    v[8] = pairs01;
+    v[9] = gamma;
+    v[10] = c4;
+    v[11] = l2pairs;
+    // mirror: 16 bytes per element above the diagonal of the dense parts (a
+    // sparse L2 block also writes the transpose of class 4)
+    v[12] = c->sparse ? 16.0 * (double)c->Dc * (double)(c->Dc - 1) / 2.0 + 16.0 * (double)c->Dc * c->n_l2
+                      : 16.0 * (double)c->D * (double)(c->D - 1) / 2.0;
+    for (int i = 0; i < n && i < 16; ++i) out[i] = v[i];
+    for (int i = 16; i < n; ++i) out[i] = 0.0;
     return CCH_OK;
 }
 
@@ -1165,12 +1428,37 @@ cch_status cch_get_matrix(cch_ctx *c, double *out, int64_t ld, int32_t flags)
     // row blocks of at most 1 GiB; with CCH_LOWER each block stops at its last
     // row's diagonal (the rectangle holding the block's lower-triangle part)
     const int64_t D = c->D, rows_per = std::max<int64_t>(1, (int64_t(1) << 30) / (8 * D));
-    for (int64_t r0 = 0; r0 < D; r0 += rows_per) {
-        const int64_t nr = std::min(rows_per, D - r0), width = lower ? r0 + nr : D;
-        HIPCK(c, hipMemcpy2DAsync(out + r0 * ld, ld * 8, c->d_H + r0 * c->ld, c->ld * 8, width * 8, nr, kind,
-                                  c->stream));
+    HIPCK(c, hipSetDevice(c->device));
+    if (c->sparse) {
+        // rows expanded from the panels and the CSR, block by block (into the
+        // caller's device array, or through a staging block for host output)
+        const SparseMat S = sparse_mat(c);
+        double *stage = nullptr;
+        if (!to_dev && hipMalloc((void **)&stage, 8 * (size_t)rows_per * D) != hipSuccess)
+            return fail(c, CCH_E_OOM, "read-out staging block");
+        hipError_t e = hipSuccess;
+        for (int64_t r0 = 0; r0 < D && e == hipSuccess; r0 += rows_per) {
+            const int64_t nr = std::min(rows_per, D - r0), width = lower ? r0 + nr : D;
+            if (to_dev) {
+                e = launch_sparse_rows(S, r0, (int)nr, 0, (int)width, 0, out + r0 * ld, ld, c->stream);
+            } else {
+                e = launch_sparse_rows(S, r0, (int)nr, 0, (int)width, 0, stage, width, c->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpy2DAsync(out + r0 * ld, ld * 8, stage, width * 8, width * 8, nr, kind, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);   // the staging block is reused
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(stage);
+        if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_get_matrix: %s", hipGetErrorString(e));
+    } else {
+        for (int64_t r0 = 0; r0 < D; r0 += rows_per) {
+            const int64_t nr = std::min(rows_per, D - r0), width = lower ? r0 + nr : D;
+            HIPCK(c, hipMemcpy2DAsync(out + r0 * ld, ld * 8, c->d_H + r0 * c->ld, c->ld * 8, width * 8, nr, kind,
+                                      c->stream));
+        }
+        HIPCK(c, hipStreamSynchronize(c->stream));
     }
-    HIPCK(c, hipStreamSynchronize(c->stream));
     if (!to_dev) {
         // read-back check: the copied diagonal must equal the device diagonal
         // (a copy that silently delivered other bytes is reported, not returned)
@@ -1190,6 +1478,7 @@ cch_status cch_matrix_device(cch_ctx *c, const double **dptr, int64_t *ld)
 {
     if (!c || !dptr || !ld) return CCH_E_INVALID_ARG;
     if (!c->planned) return fail(c, CCH_E_STATE, "plan first");
+    if (c->sparse) return fail(c, CCH_E_STATE, "the L2 block is stored as CSR (CCH_PLAN_SPARSE_L2): no dense matrix");
     *dptr = c->d_H;
     *ld = c->ld;
     return CCH_OK;
@@ -1224,7 +1513,9 @@ cch_status cch_get_elements(cch_ctx *c, int64_t n, const int64_t *rows, const in
     if (e == hipSuccess) e = hipMalloc((void **)&d_out, 8 * (size_t)n);
     if (e == hipSuccess) e = hipMemcpyAsync(d_idx, hr.data(), 8 * (size_t)n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_idx + n, hc.data(), 8 * (size_t)n, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_gather_elements(c->d_H, c->ld, d_idx, d_idx + n, n, d_out, c->stream);
+    if (e == hipSuccess)
+        e = c->sparse ? launch_sparse_gather(sparse_mat(c), d_idx, d_idx + n, n, d_out, c->stream)
+                      : launch_gather_elements(c->d_H, c->ld, d_idx, d_idx + n, n, d_out, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, d_out, 8 * (size_t)n,
                            (flags & CCH_MEM_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
@@ -1298,6 +1589,31 @@ cch_status cch_get_block(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t sym_b, 
     if (ld < nc) return fail(c, CCH_E_INVALID_ARG, "ld %lld below the block width %lld", (long long)ld, (long long)nc);
     if (nr == 0 || nc == 0) return CCH_OK;
     HIPCK(c, hipSetDevice(c->device));
+    if (c->sparse && (mode == 2 || mode == 8)) {
+        // the L2 block from its CSR, in row blocks of at most 1 GiB
+        const SparseMat S = sparse_mat(c);
+        const int64_t rows_per = std::max<int64_t>(1, (int64_t(1) << 30) / (8 * nc));
+        double *stage = nullptr;
+        if (!(flags & CCH_MEM_DEVICE) && hipMalloc((void **)&stage, 8 * (size_t)rows_per * nc) != hipSuccess)
+            return fail(c, CCH_E_OOM, "block staging");
+        hipError_t e = hipSuccess;
+        for (int64_t i0 = 0; i0 < nr && e == hipSuccess; i0 += rows_per) {
+            const int64_t m = std::min(rows_per, nr - i0);
+            if (flags & CCH_MEM_DEVICE) {
+                e = launch_sparse_rows(S, r0 + i0, (int)m, c0, (int)nc, mode, out + i0 * ld, ld, c->stream);
+            } else {
+                e = launch_sparse_rows(S, r0 + i0, (int)m, c0, (int)nc, mode, stage, nc, c->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpy2DAsync(out + i0 * ld, ld * 8, stage, nc * 8, nc * 8, m, hipMemcpyDeviceToHost,
+                                         c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(stage);
+        if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_get_block: %s", hipGetErrorString(e));
+        return CCH_OK;
+    }
     if (flags & CCH_MEM_DEVICE) {
         HIPCK(c, launch_get_block(c->d_H, c->ld, r0, (int)nr, c0, (int)nc, mode, nca, ncb, out, ld, c->stream));
         HIPCK(c, hipStreamSynchronize(c->stream));
@@ -1365,6 +1681,225 @@ cch_status cch_subspace_eig(cch_ctx *c, const double *G, int32_t ldg, int32_t m,
 #undef ECK
     cleanup();
     if (fallback) *fallback = hf;
+    return CCH_OK;
+}
+
+cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, double *w, double *V, int64_t ldv,
+                       int32_t flags, cch_eig_info *info)
+{
+    if (!c || !w) return CCH_E_INVALID_ARG;
+    const bool own = A == nullptr;   // the built matrix
+    if (own) {
+        if (!c->built) return fail(c, CCH_E_STATE, "build first (or pass a matrix)");
+        if (c->sparse) return fail(c, CCH_E_STATE, "the L2 block is stored as CSR (CCH_PLAN_SPARSE_L2)");
+        if (n != 0 && n != c->D) return fail(c, CCH_E_INVALID_ARG, "n must be 0 or D for the built matrix");
+        n = (int32_t)c->D;
+    } else if (n < 1 || lda < n) {
+        return fail(c, CCH_E_INVALID_ARG, "need n >= 1 and lda >= n");
+    }
+    if (V && ldv < n) return fail(c, CCH_E_INVALID_ARG, "ldv < n");
+    HIPCK(c, hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const bool dev = flags & CCH_MEM_DEVICE;
+    const int64_t ld = ((int64_t)n + 31) / 32 * 32;
+    const int NB = 32;
+    std::vector<void *> tmp;
+    auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
+    auto al = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) return false;
+        tmp.push_back(*p);
+        return true;
+    };
+    double *W = nullptr, *Z = nullptr, *S = nullptr, *vec = nullptr, *Vb = nullptr, *G = nullptr, *T = nullptr,
+           *w_d = nullptr;
+    const bool want_v = V != nullptr;
+    bool ok = al((void **)&W, 8 * (size_t)n * ld) && al((void **)&vec, 8 * (size_t)10 * n + 64) &&
+              al((void **)&w_d, 8 * (size_t)n);
+    if (ok && want_v)
+        // S: the twisted-factorisation scratch, then two 32 x n products of the back-transformation
+        ok = al((void **)&Z, 8 * (size_t)n * ld) &&
+             al((void **)&S, 8 * (size_t)std::max<int64_t>((int64_t)n * ld, (int64_t)2 * NB * n)) &&
+             al((void **)&Vb, 8 * (size_t)n * NB) && al((void **)&G, 8 * NB * NB) && al((void **)&T, 8 * NB * NB);
+    if (!ok) {
+        cleanup();
+        return fail(c, CCH_E_OOM, "eigensolver work space for n = %d", n);
+    }
+#define EGK(x)                                                                                  \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) {                                                                 \
+            cleanup();                                                                          \
+            return fail(c, CCH_E_HIP, "%s: %s", #x, hipGetErrorString(e_));                    \
+        }                                                                                       \
+    } while (0)
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    EGK(hipEventCreate(&e0));
+    EGK(hipEventCreate(&e1));
+    EGK(hipEventCreate(&e2));
+    EGK(hipEventCreate(&e3));
+    auto evclean = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        (void)hipEventDestroy(e3);
+    };
+    // the matrix into the work array (both triangles are read)
+    if (own)
+        EGK(hipMemcpy2DAsync(W, 8 * ld, c->d_H, 8 * c->ld, 8 * (size_t)n, n, hipMemcpyDeviceToDevice, st));
+    else
+        EGK(hipMemcpy2DAsync(W, 8 * ld, A, 8 * lda, 8 * (size_t)n, n,
+                             dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    EGK(hipEventRecord(e0, st));
+    TrdVec tv{vec, vec + n, vec + 2 * (int64_t)n, vec + 3 * (int64_t)n, vec + 4 * (int64_t)n,
+              vec + 5 * (int64_t)n, vec + 6 * (int64_t)n, vec + 7 * (int64_t)n};
+    double *e2v = vec + 8 * (int64_t)n;
+    for (int j = 0; j < n; ++j) EGK(launch_trd_step(W, ld, n, j, tv, st));
+    EGK(hipEventRecord(e1, st));
+    // Gershgorin interval, pivot floor and the split of T into unreduced
+    // blocks (off-diagonals below the rounding of their neighbours set to 0)
+    std::vector<double> hd((size_t)n), he((size_t)std::max(n - 1, 1));
+    EGK(hipMemcpyAsync(hd.data(), tv.d, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    if (n > 1) EGK(hipMemcpyAsync(he.data(), tv.e, 8 * (size_t)(n - 1), hipMemcpyDeviceToHost, st));
+    EGK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(hd[i]) || (i < n - 1 && !std::isfinite(he[i]))) {
+            evclean();
+            cleanup();
+            return fail(c, CCH_E_INPUT, "non-finite tridiagonal entry (the matrix holds a non-finite value)");
+        }
+    for (int i = 0; i + 1 < n; ++i)
+        if (std::fabs(he[i]) <= 2.220446049250313e-16 * 0.5 * (std::fabs(hd[i]) + std::fabs(hd[i + 1])))
+            he[i] = 0.0;
+    double lo = 1e300, hi = -1e300, emax = 0.0, tnorm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(he[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(he[i]) : 0.0);
+        lo = std::min(lo, hd[i] - r);
+        hi = std::max(hi, hd[i] + r);
+        if (i < n - 1) emax = std::max(emax, he[i] * he[i]);
+        tnorm = std::max(tnorm, std::fabs(hd[i]) + r);
+    }
+    const double pad = 2.0 * std::max(tnorm, 1e-300) * 1e-15 + 1e-300;
+    lo -= pad;
+    hi += pad;
+    const double pivmin = 2.2250738585072014e-308 * std::max(1.0, emax);
+    // eigenvalue slots block by block: (block start, block rows, index in the block)
+    std::vector<int32_t> bs((size_t)n), bm((size_t)n), bk((size_t)n);
+    int nblocks = 0;
+    for (int b0 = 0; b0 < n;) {
+        int b1 = b0 + 1;
+        while (b1 < n && he[b1 - 1] != 0.0) ++b1;
+        for (int i = b0; i < b1; ++i) {
+            bs[i] = b0;
+            bm[i] = b1 - b0;
+            bk[i] = i - b0;
+        }
+        ++nblocks;
+        b0 = b1;
+    }
+    int32_t *d_bs = nullptr, *d_bm = nullptr, *d_bk = nullptr;
+    if (!al((void **)&d_bs, 4 * (size_t)n) || !al((void **)&d_bm, 4 * (size_t)n) || !al((void **)&d_bk, 4 * (size_t)n)) {
+        evclean();
+        cleanup();
+        return fail(c, CCH_E_OOM, "eigensolver block tables");
+    }
+    if (n > 1) EGK(hipMemcpyAsync(tv.e, he.data(), 8 * (size_t)(n - 1), hipMemcpyHostToDevice, st));
+    EGK(hipMemcpyAsync(d_bs, bs.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+    EGK(hipMemcpyAsync(d_bm, bm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+    EGK(hipMemcpyAsync(d_bk, bk.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+    EGK(launch_tri_eigenvalues(tv.d, tv.e, e2v, n, d_bs, d_bm, d_bk, lo, hi, pivmin, vec + 9 * (int64_t)n, st));
+    // ascending order over all blocks (stable: ties keep the block order)
+    std::vector<double> wb((size_t)n);
+    EGK(hipMemcpyAsync(wb.data(), vec + 9 * (int64_t)n, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    EGK(hipStreamSynchronize(st));
+    std::vector<int> ord((size_t)n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wb[a] < wb[b]; });
+    std::vector<double> hw((size_t)n);
+    std::vector<int32_t> sbs((size_t)n), sbm((size_t)n);
+    for (int p = 0; p < n; ++p) {
+        hw[p] = wb[ord[p]];
+        sbs[p] = bs[ord[p]];
+        sbm[p] = bm[ord[p]];
+    }
+    EGK(hipMemcpyAsync(w_d, hw.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    EGK(hipEventRecord(e2, st));
+    int clusters = 0, clustered = 0;
+    if (want_v) {
+        EGK(hipMemcpyAsync(d_bs, sbs.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        EGK(hipMemcpyAsync(d_bm, sbm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        EGK(launch_tri_vectors(tv.d, tv.e, n, d_bs, d_bm, w_d, pivmin, Z, ld, S, ld, st));
+        // clusters: eigenvalues of one block closer than 1e-5 ||T|| to the
+        // previous one of the same block, re-orthogonalised in order
+        const double gap = 1e-5 * std::max(tnorm, 1e-300);
+        std::map<int, std::vector<int32_t>> per_block;   // block start -> its columns, ascending
+        for (int p = 0; p < n; ++p) per_block[sbs[p]].push_back(p);
+        std::vector<int32_t> cl_cols;
+        std::vector<std::array<int, 4>> cl;   // (offset in cl_cols, count, block start, block rows)
+        for (auto &kv : per_block) {
+            const std::vector<int32_t> &cols = kv.second;
+            for (size_t a = 0; a < cols.size();) {
+                size_t b = a + 1;
+                while (b < cols.size() && hw[cols[b]] - hw[cols[b - 1]] < gap) ++b;
+                if (b - a > 1) {
+                    cl.push_back({(int)cl_cols.size(), (int)(b - a), kv.first, sbm[cols[a]]});
+                    cl_cols.insert(cl_cols.end(), cols.begin() + a, cols.begin() + b);
+                    ++clusters;
+                    clustered += (int)(b - a);
+                }
+                a = b;
+            }
+        }
+        if (!cl.empty()) {
+            int32_t *d_cl = nullptr;
+            if (!al((void **)&d_cl, 4 * cl_cols.size())) {
+                evclean();
+                cleanup();
+                return fail(c, CCH_E_OOM, "eigensolver cluster lists");
+            }
+            EGK(hipMemcpyAsync(d_cl, cl_cols.data(), 4 * cl_cols.size(), hipMemcpyHostToDevice, st));
+            for (auto &q : cl) EGK(launch_cluster_mgs(Z, ld, q[2], q[3], d_cl + q[0], q[1], st));
+        }
+        // Z = Q Z_T: the blocks of reflectors from the last to the first
+        const int nref = n - 1;
+        const int nblk = (nref + NB - 1) / NB;
+        for (int bi = nblk - 1; bi >= 0; --bi) {
+            const int j0 = bi * NB, nb = std::min(NB, nref - j0), m = n - j0 - 1;
+            double *Zs = Z + (int64_t)(j0 + 1) * ld;
+            double *Wt = S, *W2 = S + (int64_t)NB * n;   // the twisted-factorisation scratch is free now
+            EGK(launch_copy_reflectors(W, ld, n, j0, nb, Vb, st));
+            EGK(launch_eig_gemm(nb, nb, m, 1.0, Vb, 1, nb, Vb, nb, 1, 0.0, G, nb, st));
+            EGK(launch_larft(G, tv.tau + j0, nb, T, st));
+            EGK(launch_eig_gemm(nb, n, m, 1.0, Vb, 1, nb, Zs, ld, 1, 0.0, Wt, n, st));
+            EGK(launch_eig_gemm(nb, n, nb, 1.0, T, nb, 1, Wt, n, 1, 0.0, W2, n, st));
+            EGK(launch_eig_gemm(m, n, nb, -1.0, Vb, nb, 1, W2, n, 1, 1.0, Zs, ld, st));
+        }
+        // rows of the output are the eigenvectors
+        if (dev) {
+            EGK(launch_transpose_sq(Z, ld, n, V, ldv, st));
+        } else {
+            EGK(launch_transpose_sq(Z, ld, n, S, ld, st));
+            EGK(hipMemcpy2DAsync(V, 8 * ldv, S, 8 * ld, 8 * (size_t)n, n, hipMemcpyDeviceToHost, st));
+        }
+    }
+    EGK(hipEventRecord(e3, st));
+    EGK(hipMemcpyAsync(w, w_d, 8 * (size_t)n, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    EGK(hipStreamSynchronize(st));
+    if (info) {
+        float t01 = 0.0f, t12 = 0.0f, t23 = 0.0f;
+        EGK(hipEventElapsedTime(&t01, e0, e1));
+        EGK(hipEventElapsedTime(&t12, e1, e2));
+        EGK(hipEventElapsedTime(&t23, e2, e3));
+        info->tridiag_ms = t01;
+        info->eigenvalues_ms = t12;
+        info->vectors_ms = t23;
+        info->clusters = clusters;
+        info->clustered = clustered;
+        info->tridiag_bytes = 16.0 * ((double)n * (n - 1) * (2.0 * n - 1) / 6.0);   // sum over columns of (n-j-1)^2 reads + writes
+        info->backtransform_flops = want_v ? 2.0 * (double)n * n * n : 0.0;
+    }
+#undef EGK
+    evclean();
+    cleanup();
     return CCH_OK;
 }
 
@@ -1671,7 +2206,9 @@ cch_status cch_mlp_features(cch_ctx *c, double theta, float *X, int32_t flags)
     hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipMemcpy(th, &theta, 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(sel, &zero, 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_row_norms(c->d_H, c->ld, D, rho, c->stream);
+    if (e == hipSuccess)
+        e = c->sparse ? launch_sparse_row_norms(sparse_mat(c), D, rho, c->stream)
+                      : launch_row_norms(c->d_H, c->ld, D, rho, c->stream);
     if (e == hipSuccess) e = launch_mlp_features_theta(c->d_diag, rho, D, (int)c->Dc, theta, dX, c->stream);
     if (e == hipSuccess && !(flags & CCH_MEM_DEVICE))
         e = hipMemcpyAsync(X, dX, 16 * (size_t)D, hipMemcpyDeviceToHost, c->stream);
@@ -1805,6 +2342,8 @@ cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, in
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, CCH_E_INVALID_ARG, "context %d is NULL", i);
         if (!ctxs[i]->planned) return bfail(nullptr, CCH_E_STATE, "context %d is not planned", i);
+        if (ctxs[i]->sparse)
+            return bfail(nullptr, CCH_E_STATE, "context %d stores its L2 block as CSR (CCH_PLAN_SPARSE_L2)", i);
         if (ctxs[i]->b_shared)
             return bfail(nullptr, CCH_E_STATE, "context %d was planned in several expansion passes", i);
         if (ctxs[i]->opts.precision != CCH_PREC_FP64)
@@ -2087,8 +2626,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     hipStream_t st = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     // the L2 block as CSR in the mat-vec (formed here, inside the solve's time)
-    const bool sparse = (flags & CCH_DAV_SPARSE_L2) && c->n_l2 > 0;
-    if (sparse) TRY(ensure_l2csr(c, st));
+    const bool sparse = ((flags & CCH_DAV_SPARSE_L2) || c->sparse) && c->n_l2 > 0;
+    if (sparse && !c->sparse) TRY(ensure_l2csr(c, st));
 
     const int64_t ldv = ((int64_t)D + 31) / 32 * 32;
     const int BMAX = 32;                       // block columns (<= 2k <= 32)
@@ -2147,7 +2686,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     int nb = kr;
     const int ns = std::min(mmax, D);
     DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
-    DCK(launch_gather_principal(c->d_H, c->ld, b.idx, ns, b.G, mmax, st));
+    if (c->sparse) DCK(launch_sparse_principal(sparse_mat(c), b.idx, ns, b.G, mmax, st));
+    else DCK(launch_gather_principal(c->d_H, c->ld, b.idx, ns, b.G, mmax, st));
     DCK(launch_rr_eig(b.G, mmax, ns, b.theta, b.Y, mmax, b.rrfb, st));
     DCK(launch_fill_f64(b.T, 0.0, (int64_t)nb * ldv, st));
     DCK(launch_seed_scatter(b.T, ldv, b.idx, b.Y, mmax, ns, nb, st));
@@ -2157,7 +2697,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     int rr_calls = 0, dropped = 0;
     bool use_mlp = want_mlp;
     if (want_mlp) {
-        DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
+        if (c->sparse) DCK(launch_sparse_row_norms(sparse_mat(c), D, b.rho, st));
+        else DCK(launch_row_norms(c->d_H, c->ld, D, b.rho, st));
         DCK(hipMemsetAsync(b.nfb, 0, 4, st));
     }
     DCK(hipMemsetAsync(b.rrfb, 0, 4, st));
@@ -2227,7 +2768,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         const int m0 = m;
         DCK(hipEventRecord(c->mv0, st));
         if (sparse)
-            DCK(launch_matvec_l2csr(c->d_H, c->ld, D, (int)c->Dc, c->csr.off, c->csr.col, c->csr.val,
+            DCK(launch_matvec_l2csr(c->d_H, c->ld, c->sparse ? c->d_R : c->d_H, c->sparse ? c->ldr : c->ld,
+                                    c->sparse ? (int)c->Dc : 0, D, (int)c->Dc, c->csr.off, c->csr.col, c->csr.val,
                                     b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp, st));
         else
             DCK(launch_matvec(c->d_H, c->ld, D, b.V + (int64_t)m * ldv, ldv, nb, b.Wv + (int64_t)m * ldv, ldv, b.Wp,

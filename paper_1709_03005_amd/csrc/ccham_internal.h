@@ -51,6 +51,26 @@ __device__ __forceinline__ int first_bits(const uint64_t *x, int *out, int maxn)
     return n;
 }
 
+// the two lowest set bits of x, ascending (-1 where absent), without loops
+// or branches: each word offers its lowest bit and the bit after it, and the
+// first two offers found in word order are kept (the excitation scan runs
+// this for every determinant pair, with lanes of one wave on different pairs)
+template <int W>
+__device__ __forceinline__ void low_two(const uint64_t *x, int *b0, int *b1)
+{
+    int f0 = -1, f1 = -1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint64_t v = x[w], rest = v & (v - 1ull);
+        const int t0 = v ? 64 * w + (int)__builtin_ctzll(v) : -1;
+        const int t1 = rest ? 64 * w + (int)__builtin_ctzll(rest) : -1;
+        f1 = f0 < 0 ? t1 : (f1 < 0 ? t0 : f1);
+        f0 = f0 < 0 ? t0 : f0;
+    }
+    *b0 = f0;
+    *b1 = f1;
+}
+
 __device__ __forceinline__ uint64_t pack_label(int f0, int f1, int f2, int f3)
 {
     return (uint64_t)(uint16_t)f0 | ((uint64_t)(uint16_t)f1 << 16) |
@@ -75,8 +95,8 @@ __device__ __forceinline__ int excite(const uint64_t *A, const uint64_t *B, int 
     uint64_t hb[W], pb[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { hb[w] = B[w] & ~A[w]; pb[w] = A[w] & ~B[w]; }
-    first_bits<W>(hb, h, 2);
-    first_bits<W>(pb, p, 2);
+    low_two<W>(hb, &h[0], &h[1]);
+    low_two<W>(pb, &p[0], &p[1]);
     int c = count_between<W>(B, min(h[0], p[0]), max(h[0], p[0]));
     if (deg == 2) {
         uint64_t B2[W];
@@ -107,13 +127,14 @@ __device__ __forceinline__ int excite_cont_l2(const uint64_t *D, const uint64_t 
     uint64_t hb[W], pb[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) { hb[w] = L[w] & ~D[w]; pb[w] = D[w] & ~L[w]; }
-    first_bits<W>(hb, h, 2);
+    low_two<W>(hb, &h[0], &h[1]);
     int c;
     if (deg == 1) {
         *pt = -1;
         c = count_between<W>(L, h[0], top);
     } else {
-        first_bits<W>(pb, pt, 1);
+        int unused;
+        low_two<W>(pb, pt, &unused);
         c = count_between<W>(L, min(h[0], *pt), max(h[0], *pt));
         uint64_t L2[W];
 #pragma unroll
@@ -204,6 +225,39 @@ struct PairList {
 };
 
 enum ScanMode { SCAN_TT = 0, SCAN_LL = 1, SCAN_LT = 2 };
+
+// the symmetry-packed two-continuum integrals, for one relayout launch: record
+// of the target pair (P, Q) at rec[P * n_o + Q]; inside it, the (tt|cc) rows
+// of this launch start at boffJ (row length ncb), the (tc|tc) block of the
+// second symmetry's irrep at boffK (row length nca_full, rows from column jr0)
+struct PackedCC {
+    const int64_t *rec;
+    int64_t boffJ, boffK;
+    int jr0, nca_full;
+};
+
+// work vectors of the Householder tridiagonalisation (length n each except
+// scal): vp = v_{j-1}, wp = w_{j-1}, vn = v_j, p = tau_j A v_j; the diagonal
+// d, the off-diagonal e and the reflector scalars tau of T
+struct TrdVec {
+    double *vp, *wp, *vn, *p;
+    double *d, *e, *tau;
+    double *scal;
+};
+
+// a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for
+// c < Dc (every row), R[r][c - Dc] for r < Dc <= c, and the L2 block's rows
+// as CSR (columns relative to Dc, ascending)
+struct SparseMat {
+    const double *P;
+    int64_t ldp;
+    const double *R;
+    int64_t ldr;
+    const int64_t *off;
+    const int32_t *col;
+    const double *val;
+    int64_t Dc;
+};
 
 }  // namespace cch
 

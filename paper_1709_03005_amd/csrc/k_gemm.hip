@@ -75,11 +75,66 @@ __global__ __launch_bounds__(256) void k_relayout_K(const double *__restrict__ t
     }
 }
 
+// the same rows from the symmetry-packed layout: one record per target pair,
+// the (tt|cc) rows of this launch contiguous (row length ncb), the (tc|tc)
+// block read row by row over j and turned through LDS
+__global__ __launch_bounds__(256) void k_relayout_Jp(const double *__restrict__ ttcc, PackedCC pk, int n_o,
+                                                     const int32_t *__restrict__ slotP,
+                                                     const int32_t *__restrict__ slotQ, int nca, int ncb,
+                                                     double *__restrict__ B)
+{
+    const int k = blockIdx.y;
+    const double *src = ttcc + pk.rec[(size_t)slotP[k] * n_o + slotQ[k]] + pk.boffJ;
+    double *dst = B + (size_t)k * nca * ncb;
+    const int64_t slab = (int64_t)nca * ncb, e0 = (int64_t)blockIdx.x * RJ_PER + threadIdx.x;
+    double v[RJ_U];
+#pragma unroll
+    for (int u = 0; u < RJ_U; ++u) {
+        const int64_t e = e0 + 256 * u;
+        v[u] = e < slab ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RJ_U; ++u) {
+        const int64_t e = e0 + 256 * u;
+        if (e < slab) dst[e] = v[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_relayout_Kp(const double *__restrict__ tctc, PackedCC pk, int n_o,
+                                                     const int32_t *__restrict__ slotP,
+                                                     const int32_t *__restrict__ slotQ, int n_slot, int nca,
+                                                     int ncb, double *__restrict__ B)
+{
+    __shared__ double tile[32][33];
+    const int k = blockIdx.z;
+    const double *src = tctc + pk.rec[(size_t)slotP[k] * n_o + slotQ[k]] + pk.boffK;
+    const int jj0 = blockIdx.x * 32, jp0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // (P j' | Q j): row j' of the block, contiguous in j
+    for (int r = ty; r < 32; r += 8) {
+        const int jp = jp0 + r, jj = jj0 + tx;
+        tile[r][tx] = (jp < ncb && jj < nca) ? src[(int64_t)jp * pk.nca_full + pk.jr0 + jj] : 0.0;
+    }
+    __syncthreads();
+    double *dst = B + (size_t)(n_slot + k) * nca * ncb;
+    for (int r = ty; r < 32; r += 8) {
+        const int jj = jj0 + r, jp = jp0 + tx;
+        if (jj < nca && jp < ncb) dst[(size_t)jj * ncb + jp] = -tile[tx][r];
+    }
+}
+
 hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int n_cont,
                            const int32_t *slotP, const int32_t *slotQ, int n_slot, int ja0, int nca,
-                           int jb0, int ncb, double *B, hipStream_t st)
+                           int jb0, int ncb, double *B, hipStream_t st, const PackedCC *pk)
 {
     if (n_slot <= 0 || nca <= 0 || ncb <= 0) return hipSuccess;
+    if (pk) {
+        hipLaunchKernelGGL(k_relayout_Jp, dim3((int)(((int64_t)nca * ncb + RJ_PER - 1) / RJ_PER), n_slot), dim3(256),
+                           0, st, ttcc, *pk, n_o, slotP, slotQ, nca, ncb, B);
+        hipLaunchKernelGGL(k_relayout_Kp, dim3((nca + 31) / 32, (ncb + 31) / 32, n_slot), dim3(256), 0, st, tctc, *pk,
+                           n_o, slotP, slotQ, n_slot, nca, ncb, B);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_relayout_J, dim3((int)(((int64_t)nca * ncb + RJ_PER - 1) / RJ_PER), n_slot), dim3(256), 0, st,
                        ttcc, n_o, n_cont, slotP, slotQ, ja0, nca, jb0, ncb, B);
     hipLaunchKernelGGL(k_relayout_K, dim3((nca + 31) / 32, (ncb + 31) / 32, n_slot), dim3(256), 0, st, tctc,

@@ -1,6 +1,8 @@
 // Matrix bookkeeping kernels: mirror of the lower triangle (the matrix is
 // real symmetric and only the lower triangle is evaluated, Sec. 2.2),
 // diagonal extraction, and fills that replace memsets on the stream.
+#include <algorithm>
+
 #include "ccham_internal.h"
 
 namespace cch {
@@ -113,6 +115,61 @@ __global__ void k_fill_f64(double *__restrict__ p, double v, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// census of a pair list for the work counts: out[0] degree-0 pairs, out[1]
+// degree-1 pairs whose excitation is alpha, out[2] degree-1 beta, out[3]
+// degree-2 pairs (integer atomics: the counts do not depend on the order)
+__global__ __launch_bounds__(256) void k_pair_census(const int8_t *__restrict__ deg,
+                                                     const uint64_t *__restrict__ label, int64_t n,
+                                                     unsigned long long *__restrict__ out)
+{
+    unsigned long long c[4] = {0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int d = deg[i];
+        if (d == 0) ++c[0];
+        else if (d == 1) ++c[(label[i] & 1u) ? 2 : 1];   // field 0 = particle spin-orbital, bit 0 = spin
+        else ++c[3];
+    }
+    __shared__ unsigned long long red[4][256];
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = c[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) atomicAdd(&out[threadIdx.x], red[threadIdx.x][0]);
+}
+
+hipError_t launch_pair_census(const int8_t *deg, const uint64_t *label, int64_t n, unsigned long long *out,
+                              hipStream_t st)
+{
+    hipError_t e = launch_fill_i64(reinterpret_cast<int64_t *>(out), 0, 4, st);
+    if (e != hipSuccess || n <= 0) return e;
+    const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_pair_census, dim3(grid), dim3(256), 0, st, deg, label, n, out);
+    return hipGetLastError();
+}
+
+// out[x][y] (or out[y][x] when transposed) = value of pair i of a pair list
+__global__ void k_scatter_pairs(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+                                const double *__restrict__ v, int64_t n, int transpose, double *__restrict__ out,
+                                int64_t ldo)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t x = px[i], y = py[i];
+    out[transpose ? y * ldo + x : x * ldo + y] = v[i];
+}
+
+hipError_t launch_scatter_pairs(const int32_t *px, const int32_t *py, const double *v, int64_t n, int transpose,
+                                double *out, int64_t ldo, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, px, py, v, n, transpose,
+                       out, ldo);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t st)

@@ -89,8 +89,8 @@ hipError_t launch_l2_csr_fill(const double *H, int64_t ld, int Dc, int nl2, cons
 typedef double px4 __attribute__((ext_vector_type(4)));
 constexpr int PN_U = 8;   // 4-row MFMA steps per register block
 
-__global__ __launch_bounds__(256) void k_panel_mfma(const double *__restrict__ H, int64_t ld, int r0, int r1, int c0,
-                                                    int c1, const double *__restrict__ V, int64_t ldv, int b,
+__global__ __launch_bounds__(256) void k_panel_mfma(const double *__restrict__ H, int64_t ld, int hc0, int r0, int r1,
+                                                    int c0, int c1, const double *__restrict__ V, int64_t ldv, int b,
                                                     int rps, double *__restrict__ Wp)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_panel_mfma(const double *__restrict__ H
     for (int t = 0; t < 4; ++t) {
         const int c = cb0 + 16 * t + q;
         colok[t] = c < c1;
-        hcol[t] = H + (colok[t] ? c : 0);
+        hcol[t] = H + (colok[t] ? c - hc0 : 0);   // column c of the matrix is column c - hc0 of H
     }
     px4 acc[4];
 #pragma unroll
@@ -218,23 +218,27 @@ int64_t l2csr_scratch(int D, int Dc)
     return a + b + (int64_t)16 * D;   // panel partials, then the transposed block
 }
 
-static hipError_t panel(const double *H, int64_t ld, int r0, int r1, int c0, int c1, const double *V, int64_t ldv,
-                        int b, double *W, int64_t ldw, double *Wp, hipStream_t st)
+static hipError_t panel(const double *H, int64_t ld, int hc0, int r0, int r1, int c0, int c1, const double *V,
+                        int64_t ldv, int b, double *W, int64_t ldw, double *Wp, hipStream_t st)
 {
     if (r1 <= r0 || c1 <= c0) return hipSuccess;
     const int ns = panel_splits(r1 - r0, c1 - c0);
     int rps = (r1 - r0 + ns - 1) / ns;
     rps = (rps + 4 * PN_U - 1) / (4 * PN_U) * (4 * PN_U);
     const int nsu = (r1 - r0 + rps - 1) / rps;
-    hipLaunchKernelGGL(k_panel_mfma, dim3((c1 - c0 + 255) / 256, nsu), dim3(256), 0, st, H, ld, r0, r1, c0, c1, V, ldv,
-                       b, rps, Wp);
+    hipLaunchKernelGGL(k_panel_mfma, dim3((c1 - c0 + 255) / 256, nsu), dim3(256), 0, st, H, ld, hc0, r0, r1, c0, c1, V,
+                       ldv, b, rps, Wp);
     hipLaunchKernelGGL(k_panel_reduce, dim3((c1 - c0 + 255) / 256, b), dim3(256), 0, st, Wp, nsu, c0, c1, b, W, ldw);
     return hipGetLastError();
 }
 
-hipError_t launch_matvec_l2csr(const double *H, int64_t ld, int D, int Dc, const int64_t *off, const int32_t *col,
-                               const double *val, const double *V, int64_t ldv, int b, double *W, int64_t ldw,
-                               double *Wp, hipStream_t st)
+// P: rows 0..D-1, columns < Dc (leading dimension ldp); R: rows < Dc, the
+// matrix's column c >= Dc at R column c - rc0 (leading dimension ldr). The
+// dense matrix passes itself for both (rc0 = 0); a sparse-L2 matrix its two
+// panels (rc0 = Dc).
+hipError_t launch_matvec_l2csr(const double *P, int64_t ldp, const double *R, int64_t ldr, int rc0, int D, int Dc,
+                               const int64_t *off, const int32_t *col, const double *val, const double *V,
+                               int64_t ldv, int b, double *W, int64_t ldw, double *Wp, hipStream_t st)
 {
     if (D <= 0 || b <= 0) return hipSuccess;
     if (Dc < 0 || Dc > D) return hipErrorInvalidValue;
@@ -245,8 +249,8 @@ hipError_t launch_matvec_l2csr(const double *H, int64_t ld, int D, int Dc, const
         const int bb = std::min(16, b - q0);
         const double *Vq = V + (int64_t)q0 * ldv;
         double *Wq = W + (int64_t)q0 * ldw;
-        hipError_t e = panel(H, ld, 0, D, 0, Dc, Vq, ldv, bb, Wq, ldw, WpA, st);    // columns < Dc, all rows
-        if (e == hipSuccess) e = panel(H, ld, 0, Dc, Dc, D, Vq, ldv, bb, Wq, ldw, WpB, st);   // rows < Dc
+        hipError_t e = panel(P, ldp, 0, 0, D, 0, Dc, Vq, ldv, bb, Wq, ldw, WpA, st);   // columns < Dc, all rows
+        if (e == hipSuccess) e = panel(R, ldr, rc0, 0, Dc, Dc, D, Vq, ldv, bb, Wq, ldw, WpB, st);   // rows < Dc
         if (e != hipSuccess) return e;
         if (nl2 > 0) {
             hipLaunchKernelGGL(k_vt16, dim3((D + 255) / 256), dim3(256), 0, st, Vq, ldv, D, bb, VT);

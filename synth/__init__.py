@@ -61,6 +61,7 @@ class Instance:
     l2_dets: np.ndarray = None   # uint64 [n_l2, W]
     name: str = ""
     seed: int = 0
+    packed: bool = False         # ttcc / tctc hold the symmetry-packed layout (packed_layout)
 
     @property
     def n_cont(self) -> int:
@@ -136,7 +137,7 @@ def _irreps(n_o, n_irrep, n_c):
     return tgt, cont
 
 
-def _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, sd2=0.1):
+def _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, sd2=0.1, skip_cc=False):
     n_cont = len(cont_irrep)
     n_orb = n_o + n_cont
     oi = np.concatenate([tgt_irrep, cont_irrep]).astype(np.int64)
@@ -172,6 +173,8 @@ def _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, sd2=0.1):
             blk[(ti[p] ^ ti[q] ^ ti[:, None] ^ ci[None, :]) != 0] = 0.0
             tttc[p, q] = blk
             tttc[q, p] = blk
+    if skip_cc:
+        return h, tttt, tttc, None, None
     # ttcc (pq|jj'): symmetric in p, q and in j, j'
     ttcc = np.empty((n_o, n_o, n_cont, n_cont))
     dcc = np.exp(-np.abs(gc[:, None] - gc[None, :]) / 4.0)
@@ -198,6 +201,130 @@ def _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, sd2=0.1):
             tctc[p, :, q, :] = x
             tctc[q, :, p, :] = x.T
     return h, tttt, tttc, ttcc, tctc
+
+
+def packed_layout(tgt_irrep, n_c):
+    """Offsets of the symmetry-packed two-continuum integrals. For the target
+    pair (P, Q), with x = irrep(P) ^ irrep(Q), one record holds a block per
+    continuum irrep ca: the n_c[ca] x n_c[ca ^ x] values of (P Q | j j') (for
+    ttcc) or (P j | Q j') (for tctc), j of irrep ca and j' of irrep ca ^ x,
+    row-major; every other value is zero by symmetry. Returns rec (n_o^2 + 1
+    record offsets, pair P * n_o + Q) and blk (blk[x][ca], offsets inside a
+    record)."""
+    n_c = np.asarray(n_c, dtype=np.int64)
+    ni = len(n_c)
+    blk = np.zeros((ni, ni), np.int64)
+    size = np.zeros(ni, np.int64)
+    for x in range(ni):
+        off = 0
+        for ca in range(ni):
+            blk[x, ca] = off
+            off += n_c[ca] * n_c[ca ^ x]
+        size[x] = off
+    ti = np.asarray(tgt_irrep, dtype=np.int64)
+    rec = np.concatenate([[0], np.cumsum(size[(ti[:, None] ^ ti[None, :]).ravel()])]).astype(np.int64)
+    return rec, blk
+
+
+def pack_integrals(inst):
+    """The instance with ttcc and tctc in the symmetry-packed layout (pure
+    data movement from the dense arrays)."""
+    if inst.packed:
+        return inst
+    rec, blk = packed_layout(inst.tgt_irrep, inst.n_c)
+    n_o, ni = inst.n_o, inst.n_irrep
+    cs = np.concatenate([[0], np.cumsum(inst.n_c)])
+    ttcc = np.zeros(rec[-1])
+    tctc = np.zeros(rec[-1])
+    for P in range(n_o):
+        for Q in range(n_o):
+            x = int(inst.tgt_irrep[P]) ^ int(inst.tgt_irrep[Q])
+            r0 = rec[P * n_o + Q]
+            for ca in range(ni):
+                cb = ca ^ x
+                o = r0 + blk[x, ca]
+                nab = inst.n_c[ca] * inst.n_c[cb]
+                ttcc[o:o + nab] = inst.ttcc[P, Q, cs[ca]:cs[ca + 1], cs[cb]:cs[cb + 1]].ravel()
+                tctc[o:o + nab] = inst.tctc[P, cs[ca]:cs[ca + 1], Q, cs[cb]:cs[cb + 1]].ravel()
+    out = Instance(**{f: getattr(inst, f) for f in inst.__dataclass_fields__})
+    out.ttcc, out.tctc, out.packed = ttcc, tctc, True
+    return out
+
+
+def unpack_integrals(inst):
+    """The instance with dense ttcc and tctc rebuilt from the packed layout
+    (pure data movement; zeros where symmetry forbids a value)."""
+    if not inst.packed:
+        return inst
+    rec, blk = packed_layout(inst.tgt_irrep, inst.n_c)
+    n_o, ni, nc = inst.n_o, inst.n_irrep, inst.n_cont
+    cs = np.concatenate([[0], np.cumsum(inst.n_c)])
+    ttcc = np.zeros((n_o, n_o, nc, nc))
+    tctc = np.zeros((n_o, nc, n_o, nc))
+    for P in range(n_o):
+        for Q in range(n_o):
+            x = int(inst.tgt_irrep[P]) ^ int(inst.tgt_irrep[Q])
+            r0 = rec[P * n_o + Q]
+            for ca in range(ni):
+                cb = ca ^ x
+                o = r0 + blk[x, ca]
+                sh = (inst.n_c[ca], inst.n_c[cb])
+                n = sh[0] * sh[1]
+                ttcc[P, Q, cs[ca]:cs[ca + 1], cs[cb]:cs[cb + 1]] = inst.ttcc[o:o + n].reshape(sh)
+                tctc[P, cs[ca]:cs[ca + 1], Q, cs[cb]:cs[cb + 1]] = inst.tctc[o:o + n].reshape(sh)
+    out = Instance(**{f: getattr(inst, f) for f in inst.__dataclass_fields__})
+    out.ttcc, out.tctc, out.packed = ttcc, tctc, False
+    return out
+
+
+def _gen_packed_cc(rng, n_o, tgt_irrep, n_c, sd2=0.1):
+    """ttcc and tctc drawn directly in the packed layout, with the law of the
+    dense generator (N(0, sd2) times the decay in global orbital indices,
+    (pq|jj') symmetric in p, q and in j, j', (pj|qj') symmetric under
+    (p, j) <-> (q, j'), symmetry zeros not stored)."""
+    n_c = np.asarray(n_c, dtype=np.int64)
+    ni = len(n_c)
+    rec, blk = packed_layout(tgt_irrep, n_c)
+    ti = np.asarray(tgt_irrep, dtype=np.int64)
+    cs = np.concatenate([[0], np.cumsum(n_c)])
+    gc = n_o + np.arange(int(cs[-1]), dtype=np.float64)
+    ttcc = np.zeros(rec[-1])
+    tctc = np.zeros(rec[-1])
+
+    def view(arr, P, Q, ca):
+        x = int(ti[P] ^ ti[Q])
+        o = rec[P * n_o + Q] + blk[x, ca]
+        return arr[o:o + n_c[ca] * n_c[ca ^ x]].reshape(n_c[ca], n_c[ca ^ x])
+
+    for p in range(n_o):
+        dp = np.exp(-np.abs(p - gc) / 4.0)
+        for q in range(p + 1):
+            x = int(ti[p] ^ ti[q])
+            dq = np.exp(-np.abs(q - gc) / 4.0)
+            for ca in range(ni):
+                cb = ca ^ x
+                ja, jb = slice(cs[ca], cs[ca + 1]), slice(cs[cb], cs[cb + 1])
+                # (pq|jj'): blocks (ca, cb) and (cb, ca) are transposes; (ca, ca) symmetric
+                if ca <= cb:
+                    X = rng.standard_normal((n_c[ca], n_c[cb])) * sd2
+                    if ca == cb:
+                        X = np.tril(X) + np.tril(X, -1).T
+                    X *= np.exp(-np.abs(gc[ja][:, None] - gc[jb][None, :]) / 4.0) * math.exp(-abs(p - q) / 4.0)
+                    view(ttcc, p, q, ca)[:] = X
+                    view(ttcc, p, q, cb)[:] = X.T
+                    view(ttcc, q, p, ca)[:] = X
+                    view(ttcc, q, p, cb)[:] = X.T
+                # (pj|qj'): record (q, p) holds the transposes; p == q symmetric blocks
+                Y = rng.standard_normal((n_c[ca], n_c[cb])) * sd2
+                if p == q:
+                    if ca > cb:
+                        continue          # filled as the transpose of block cb
+                    if ca == cb:
+                        Y = np.tril(Y) + np.tril(Y, -1).T
+                Y *= dp[ja][:, None] * dq[jb][None, :]
+                view(tctc, p, q, ca)[:] = Y
+                view(tctc, q, p, cb)[:] = Y.T
+    return ttcc, tctc
 
 
 # ----------------------------------------------------------------------------
@@ -271,9 +398,11 @@ def _ci(rng, m, s):
 # ----------------------------------------------------------------------------
 
 def make_instance(n_o, n_elec, n_irrep, n_c, sym_irreps, n_det, n_states,
-                  n_l2, seed, e_core=0.0, name="", total_irrep=0):
+                  n_l2, seed, e_core=0.0, name="", total_irrep=0, packed=False):
     """n_c: continuum orbitals per irrep (int or list); sym_irreps: irreps of
-    the target symmetries; n_det/n_states: per symmetry (int or list)."""
+    the target symmetries; n_det/n_states: per symmetry (int or list).
+    packed: (tt|cc) and (tc|tc) drawn directly in the symmetry-packed layout
+    (never dense; a different draw order from the dense generator)."""
     if n_elec % 2:
         raise ValueError("n_elec must be even (n_alpha = n_beta = N/2)")
     rng = np.random.default_rng(seed)
@@ -284,7 +413,11 @@ def make_instance(n_o, n_elec, n_irrep, n_c, sym_irreps, n_det, n_states,
     n_det = [n_det] * nsym if np.isscalar(n_det) else list(n_det)
     n_states = [n_states] * nsym if np.isscalar(n_states) else list(n_states)
     tgt_irrep, cont_irrep = _irreps(n_o, n_irrep, n_c)
-    h, tttt, tttc, ttcc, tctc = _gen_integrals(rng, n_o, tgt_irrep, cont_irrep)
+    if packed:
+        h, tttt, tttc, _, _ = _gen_integrals(rng, n_o, tgt_irrep, cont_irrep, skip_cc=True)
+        ttcc, tctc = _gen_packed_cc(rng, n_o, tgt_irrep, n_c)
+    else:
+        h, tttt, tttc, ttcc, tctc = _gen_integrals(rng, n_o, tgt_irrep, cont_irrep)
     na = nb = n_elec // 2
     syms = []
     for irr, m, s in zip(sym_irreps, n_det, n_states):
@@ -295,7 +428,7 @@ def make_instance(n_o, n_elec, n_irrep, n_c, sym_irreps, n_det, n_states,
     return Instance(n_o=n_o, n_elec=n_elec, n_irrep=n_irrep, tgt_irrep=tgt_irrep,
                     n_c=n_c, total_irrep=total_irrep, h=h, tttt=tttt, tttc=tttc,
                     ttcc=ttcc, tctc=tctc, e_core=float(e_core), syms=syms,
-                    l2_dets=l2, name=name, seed=seed)
+                    l2_dets=l2, name=name, seed=seed, packed=packed)
 
 
 def tiny(seed=101):
@@ -344,6 +477,31 @@ def l2heavy(seed=808):
     target determinants in 1 symmetry, 4 states x 178 continuum orbitals = 712
     contracted rows, 122103 L2 functions; about 0.9 GB of integrals."""
     return make_instance(40, 12, 1, 178, [0], 2000, 4, 122103, seed, name="l2heavy")
+
+
+def paired(n_o=30, n_elec=10, n_det=500, n_states=5, n_c=150, n_l2=5000, seed=222, name="medium_pairs"):
+    """Target states in pairs of symmetries that share one determinant space
+    and so one continuum irrep (the emulation of singlet and triplet target
+    states of one spatial symmetry, Fig. 2; classes 5 and 6 appear between the
+    two members of a pair): two irreps, four target symmetries with irreps
+    0, 0, 1, 1 where the second member of each pair holds the same
+    determinants as the first. The CI vectors are random orthonormal
+    placeholders: the caller replaces them by eigenvectors of the target
+    Hamiltonian (the lowest n_states for the first member, the next n_states
+    for the second). Defaults: the medium shape, D = 4 x 5 x 150 + 5000 =
+    8000."""
+    inst = make_instance(n_o, n_elec, 2, n_c, [0, 0, 1, 1], n_det, n_states, n_l2, seed, name=name)
+    inst.syms[1].dets = inst.syms[0].dets.copy()
+    inst.syms[3].dets = inst.syms[2].dets.copy()
+    return inst
+
+
+def l2huge(seed=818):
+    """The phosphoric-acid shape with twice its L2 functions: 40 target
+    orbitals, N=12, 2000 target determinants in 1 symmetry, 4 states x 178
+    continuum orbitals = 712 contracted rows, 250000 L2 functions
+    (D = 250712: a dense matrix would need 503 GB)."""
+    return make_instance(40, 12, 1, 178, [0], 2000, 4, 250000, seed, name="l2huge")
 
 
 def _active_dets(rng, n_o, n_a, n_b, tgt_irrep, irrep, active, count):
@@ -402,11 +560,11 @@ def mid(seed=313):
     return make_instance(40, 12, 1, 300, [0], 4000, 20, 14000, seed, name="mid")
 
 
-def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
+def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20, packed=False):
     """Draw (D, n_o, symmetries, states, continuum, N) from the batch ranges;
-    draws whose dense (tt|cc) + (tc|tc) storage would exceed max_int_bytes,
-    whose L2 count would be negative, or whose L2 space is too small are
-    redrawn."""
+    draws whose (tt|cc) + (tc|tc) storage would exceed max_int_bytes (dense,
+    or in the symmetry-packed layout with packed=True), whose L2 count would
+    be negative, or whose L2 space is too small are redrawn."""
     while True:
         d = int(rng.integers(d_lo, d_hi + 1))
         n_o = int(rng.integers(12, 41))
@@ -417,7 +575,9 @@ def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
         n_elec = int(rng.choice([4, 6, 8, 10, 12]))
         n_l2 = d - n_sym * s * nc
         n_cont = n_sym * nc
-        if n_l2 < 0 or 16 * n_o * n_o * n_cont * n_cont > max_int_bytes:
+        # packed: each target pair keeps n_irrep blocks of nc x nc values
+        cc_bytes = 16 * n_o * n_o * (n_irrep * nc * nc if packed else n_cont * n_cont)
+        if n_l2 < 0 or cc_bytes > max_int_bytes:
             continue
         na = n_elec // 2
         if n_l2 > math.comb(n_o, na + 1) * math.comb(n_o, na) // (4 * n_irrep):
@@ -425,14 +585,16 @@ def _batch_like(rng, seed, d_lo, d_hi, name, max_int_bytes=256 << 20):
         break
     m = max(s, int(rng.integers(2 * s, 8 * s + 1)))
     return make_instance(n_o, n_elec, n_irrep, nc, list(range(n_sym)), m, s, n_l2,
-                         seed, name=name)
+                         seed, name=name, packed=packed)
 
 
 def batch_instance(i):
     """One of the 64 batched instances: D ~ U[500, 6000], 12-40 target
-    orbitals, 5-30 states, 50-200 continuum orbitals per irrep."""
+    orbitals, 1, 2 or 4 target symmetries (as many irreps), 5-30 states,
+    50-200 continuum orbitals per irrep; (tt|cc) and (tc|tc) in the
+    symmetry-packed layout, at most 1 GiB of them."""
     rng = np.random.default_rng(400 + i)
-    return _batch_like(rng, 400 + i, 500, 6000, f"batch{i}")
+    return _batch_like(rng, 400 + i, 500, 6000, f"batch{i}", max_int_bytes=1 << 30, packed=True)
 
 
 def learned_train(i):
@@ -477,5 +639,6 @@ def micro(seed, n_o=3, n_elec=2, n_c=2, n_irrep=1, n_det=None, n_states=None,
 CONFIGS = {
     "tiny": tiny, "small": small, "wide": wide, "medium": medium,
     "precision": precision, "learned_test": learned_test, "l2heavy": l2heavy,
-    "boundary3": lambda: boundary(3), "boundary4": lambda: boundary(4), "mid": mid,
+    "boundary3": lambda: boundary(3), "boundary4": lambda: boundary(4), "mid": mid, "l2huge": l2huge,
+    "medium_pairs": paired,
 }

@@ -6,6 +6,7 @@ from __future__ import annotations
 import itertools
 
 import numpy as np
+import scipy.linalg.lapack as lapack
 
 import synth
 
@@ -65,3 +66,25 @@ def substitution_sign(A, B):
     for h, p in zip(holes, parts):
         sub[sub.index(h)] = p
     return perm_parity(sub), holes, parts
+
+
+def negative_inertia(A):
+    """Number of negative eigenvalues of the symmetric matrix A (destroyed),
+    from the 1x1 and 2x2 blocks of its Bunch-Kaufman factorisation."""
+    n = A.shape[0]
+    Af = A.T                      # C-ordered symmetric == Fortran-ordered, no copy
+    lw = lapack.dsytrf_lwork(n, lower=1)
+    ldu, ipiv, info = lapack.dsytrf(Af, lower=1, overwrite_a=1, lwork=int(lw[0]))
+    assert info >= 0, info
+    neg = 0
+    i = 0
+    while i < n:
+        if ipiv[i] > 0:           # 1x1 block
+            neg += ldu[i, i] < 0
+            i += 1
+        else:                     # 2x2 block [[a, b], [b, c]] in rows i, i+1
+            a, b, c = ldu[i, i], ldu[i + 1, i], ldu[i + 1, i + 1]
+            ev = np.linalg.eigvalsh(np.array([[a, b], [b, c]]))
+            neg += int((ev < 0).sum())
+            i += 2
+    return neg

@@ -3,7 +3,9 @@
 L2 functions: D = 40000, two-word determinants): sampled elements of every
 block class against the oracle computed one by one, exact symmetry of sampled
 pairs, and the Davidson residual certificate ||H x - theta x|| on the
-verified matrix. Then the reduced-precision expansion products (FP32, split
+verified matrix, and Sylvester's inertia (LDL^T of H - sigma I, sigma halfway
+between theta_10 and theta_11) proving that the ten pairs are the lowest ten.
+Then the reduced-precision expansion products (FP32, split
 BF16 with 3 and 7 slices) are built at the same size and the same sampled
 elements are compared with the same oracle values: the max-abs element error
 against the FP64 oracle is printed and bounded per mode (FP32 and 3 slices:
@@ -32,7 +34,7 @@ def _fp64():
             ctx.build()
             print("[precision] built", flush=True)
             G = ctx.get_matrix()
-            ev, vec, info, rc = ctx.davidson(10, tol=1e-8)
+            ev, vec, info, rc = ctx.davidson(11, tol=1e-8)   # one pair more for the inertia check
         print(f"[precision] davidson rc={rc} iters={info.iterations}", flush=True)
         rng = np.random.default_rng(5)
         rows = np.concatenate([rng.integers(0, Dc, 24), rng.integers(Dc, D, 24), rng.integers(Dc, D, 24),
@@ -40,8 +42,8 @@ def _fp64():
         cols = np.concatenate([rng.integers(0, Dc, 24), rng.integers(0, Dc, 24), rng.integers(Dc, D, 24),
                                rows[-8:]])
         v, a, k = oracle.Oracle(inst).elements(rows, cols)
-        _state.update(inst=inst, G=G, ev=ev, vec=vec, rc=rc, rows=rows, cols=cols, v=v, a=a, k=k,
-                      scale=float(np.abs(G).max()))
+        _state.update(inst=inst, G=G, ev=ev[:10], vec=vec[:10], ev11=ev, vec11=vec, rc=rc, rows=rows, cols=cols,
+                      v=v, a=a, k=k, scale=float(np.abs(G).max()))
     return _state
 
 
@@ -88,3 +90,23 @@ def test_precision_modes_at_size(mode, slices, bound):
     assert err <= bound * scale
     assert rc == cc.CCH_OK
     assert eerr <= max(10 * bound * scale, 1e-10 * np.abs(s["ev"]).max())
+
+
+def test_precision_lowest_k_by_inertia():
+    """Runs last: it factorises the host copy of the matrix in place."""
+    import time
+    from tests.helpers import negative_inertia
+    s = _fp64()
+    G, ev, vec = s["G"], s["ev11"], s["vec11"]
+    k = 10
+    r = np.linalg.norm(G @ vec.T - vec.T * ev[None, :], axis=0)
+    assert r.max() < 2e-8, r
+    assert ev[k] - ev[k - 1] > 1e-6
+    sigma = 0.5 * (ev[k - 1] + ev[k])
+    G[np.diag_indices(G.shape[0])] -= sigma
+    t0 = time.time()
+    neg = negative_inertia(G)
+    print(f"[precision] eigenvalues below sigma = {sigma:.12f}: {neg} (LDL^T of D = {G.shape[0]} in "
+          f"{time.time() - t0:.1f} s)", flush=True)
+    _state.clear()
+    assert neg == k

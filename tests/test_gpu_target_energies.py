@@ -117,3 +117,65 @@ def test_option_misuse_is_refused_and_can_be_switched_off():
         with pytest.raises(cc.CchError) as e:
             ctx.plan()
         assert e.value.code == cc.CCH_E_STATE
+
+
+def _true_target_states(Hs, inst):
+    """CI vectors and energies of the paired instance from the target
+    Hamiltonian of each determinant space: the first member of a pair takes
+    the lowest S eigenvectors, the second the next S."""
+    E = []
+    for a in range(0, len(inst.syms), 2):
+        w, v = np.linalg.eigh(Hs[a])
+        S = inst.syms[a].ci.shape[1]
+        inst.syms[a].ci = np.ascontiguousarray(v[:, :S])
+        inst.syms[a + 1].ci = np.ascontiguousarray(v[:, S:2 * S])
+        E += [w[:S], w[S:2 * S]]
+    return E
+
+
+def test_target_hamiltonian_readout():
+    """cch_target_hamiltonian against the oracle's Slater-Condon target
+    Hamiltonian, for every pair of symmetries (same and different irreps,
+    both orders)."""
+    import paper_1709_03005_amd as cc
+    inst = _shared()
+    with cc.from_instance(inst) as ctx:
+        ctx.build()
+        for a in range(len(inst.syms)):
+            for b in range(len(inst.syms)):
+                g = ctx.target_hamiltonian(a, b)
+                o = oracle.target_hamiltonian(inst, a, b)
+                assert g.shape == o.shape
+                np.testing.assert_allclose(g, o, rtol=0, atol=1e-12 * max(1.0, np.abs(o).max()))
+
+
+def test_true_target_states_paired_symmetries():
+    """The target-energy option with true target states: CI vectors and
+    energies from the library's own target Hamiltonian (eigh on the host), on
+    pairs of symmetries sharing one determinant space (classes 5 and 6 between
+    the members of a pair, class 7 across pairs). Every element against the
+    oracle's energy form; the plain build with the same CI vectors has the
+    same matrix to rounding (the states diagonalise the target Hamiltonian),
+    and both share their lowest eigenvalues."""
+    import paper_1709_03005_amd as cc
+    inst = synth.paired(12, 6, 100, 3, 20, 300, seed=5, name="pairs_small")
+    with cc.from_instance(inst) as c0:
+        c0.build()
+        Hs = {a: c0.target_hamiltonian(a, a) for a in range(0, 4, 2)}
+    E = _true_target_states(Hs, inst)
+    H, A, K = oracle.energy_mode_matrix(inst, E, with_abs=True)
+    with cc.from_instance(inst, target_energies=E) as ce, cc.from_instance(inst) as cp:
+        ce.build()
+        cp.build()
+        G, Gp = ce.get_matrix(), cp.get_matrix()
+        b5 = ce.get_block(5, 1, 0)
+        b6 = ce.get_block(6, 1, 0)
+        ev, _, _, rc = ce.davidson(5, tol=1e-10, want_vectors=False)
+        evp, _, _, rcp = cp.davidson(5, tol=1e-10, want_vectors=False)
+    ok, _ = oracle.tolerance_ok(G, H, A, K)
+    assert ok.all(), np.argwhere(~ok)[:5]
+    assert np.abs(b5).max() > 0 and np.abs(b6).max() > 0
+    scale = np.abs(H).max()
+    assert np.abs(G - Gp).max() < 1e-9 * scale
+    assert rc == rcp == cc.CCH_OK
+    assert np.abs(ev - evp).max() < 1e-9 * scale
