@@ -341,13 +341,143 @@ __global__ __launch_bounds__(256) void k_expand_bf16split(const __bf16 *__restri
         }
 }
 
+// The same product with every slice of a K step in LDS at once (S <= 4):
+// each A and B tile is read from memory once per K step instead of once per
+// slice pair, and the pairs of one level t + u share an FP32 accumulator.
+// Exactness: a level holds at most s pairs, each product of two slices is at
+// most 2^16 in magnitude, and the accumulators are folded into FP64 every
+// 64 k, so a sum never exceeds s * 64 * 2^16 <= 2^24.
+constexpr int FBK = 32, FKW = 64;
+
+template <int S>
+__global__ __launch_bounds__(256) void k_expand_bf16fused(const __bf16 *__restrict__ SA,
+                                                          const __bf16 *__restrict__ SB,
+                                                          const double *__restrict__ sigA,
+                                                          const double *__restrict__ sigB, int nrows, int N,
+                                                          int ldk, ExpandEpi ep)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[S][LBM][FBK + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[S][LBN][FBK + 8];
+    const int tiles_m = (nrows + LBM - 1) / LBM, tiles_n = (N + LBN - 1) / LBN;
+    const int lb = xcd_remap_l(blockIdx.x, tiles_m * tiles_n);
+    const int r0 = (lb % tiles_m) * LBM, c0 = (lb / tiles_m) * LBN;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    double acc64[2][4][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
+    fx4 acc[S][2][4];   // level t + u - 2
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[l][a][b] = (fx4){0.f, 0.f, 0.f, 0.f};
+    // the next K step's tiles are loaded into registers while the current
+    // one is multiplied from LDS
+    bf16x8 pa[S], pb[S][2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const __bf16 *At_ = SA + (size_t)t * nrows * ldk;
+            const __bf16 *Bt_ = SB + (size_t)t * N * ldk;
+            const int rr = threadIdx.x >> 2, kc = (threadIdx.x & 3) * 8;
+            const int r = r0 + rr;
+            pa[t] = r < nrows ? *(const bf16x8 *)(At_ + (size_t)r * ldk + k0 + kc) : (bf16x8){};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = threadIdx.x + 256 * q;
+                const int c = c0 + (e >> 2);
+                pb[t][q] = c < N ? *(const bf16x8 *)(Bt_ + (size_t)c * ldk + k0 + (e & 3) * 8) : (bf16x8){};
+            }
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < ldk; k0 += FBK) {
+        __syncthreads();   // the previous step is done with the LDS tiles
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            *(bf16x8 *)&As[t][threadIdx.x >> 2][(threadIdx.x & 3) * 8] = pa[t];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = threadIdx.x + 256 * q;
+                *(bf16x8 *)&Bs[t][e >> 2][(e & 3) * 8] = pb[t][q];
+            }
+        }
+        __syncthreads();
+        if (k0 + FBK < ldk) gload(k0 + FBK);
+        const int kk = 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            bf16x8 af[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) af[a] = *(const bf16x8 *)&As[t][wm * 32 + a * 16 + (lane & 15)][kk];
+#pragma unroll
+            for (int u = 0; u < S - t; ++u) {
+                bf16x8 bfr[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bfr[b] = *(const bf16x8 *)&Bs[u][wn * 64 + b * 16 + (lane & 15)][kk];
+                const int l = t + u;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[l][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[l][a][b], 0, 0, 0);
+            }
+        }
+        if (((k0 + FBK) % FKW) == 0 || k0 + FBK >= ldk) {
+#pragma unroll
+            for (int l = 0; l < S; ++l) {
+                const double scale = ldexp(1.0, -8 * (l + 2));
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc64[a][b][v] += scale * (double)acc[l][a][b][v];
+                        acc[l][a][b] = (fx4){0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+            const double sa = r < nrows ? sigA[r] : 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = c0 + wn * 64 + b * 16 + (lane & 15);
+                const double sb = c < N ? sigB[c] : 0.0;
+                epilogue_store(ep, r, c, nrows, N, acc64[a][b][v] * sa * sb);
+            }
+        }
+}
+
 hipError_t launch_expand_bf16split(const __bf16 *SA, const __bf16 *SB, const double *sigA, const double *sigB,
                                    int s, int nrows, int N, int ldk, const ExpandEpi &ep, hipStream_t st)
 {
     if (nrows <= 0 || N <= 0) return hipSuccess;
     if (ldk % 64) return hipErrorInvalidValue;
     const int tiles = ((nrows + LBM - 1) / LBM) * ((N + LBN - 1) / LBN);
-    hipLaunchKernelGGL(k_expand_bf16split, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, s, nrows, N, ldk, ep);
+    switch (s) {
+    case 1: hipLaunchKernelGGL(k_expand_bf16fused<1>, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, nrows, N,
+                               ldk, ep); break;
+    case 2: hipLaunchKernelGGL(k_expand_bf16fused<2>, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, nrows, N,
+                               ldk, ep); break;
+    case 3: hipLaunchKernelGGL(k_expand_bf16fused<3>, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, nrows, N,
+                               ldk, ep); break;
+    case 4: hipLaunchKernelGGL(k_expand_bf16fused<4>, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, nrows, N,
+                               ldk, ep); break;
+    default:
+        hipLaunchKernelGGL(k_expand_bf16split, dim3(tiles), dim3(256), 0, st, SA, SB, sigA, sigB, s, nrows, N, ldk,
+                           ep);
+    }
     return hipGetLastError();
 }
 
