@@ -45,14 +45,20 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # the same counters read for a plain 512 MiB device copy (bench.py --workload
 # copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them). Keyed by
 # workload and kernel, with the source file of the kernel and its hash when
-# counted: a kernel changed since reports null.
+# counted: a kernel changed since reports null. The relayout entry is the sum
+# of its two launches (J and K layouts).
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
     # (workload, name): (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("medium", "rayleigh_ritz"): ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
     ("medium", "matvec"): ("k_davidson.hip", "c2ad709cede732f3", 252272.643, 17904.762),
-    ("medium", "expansion_gemm"): ("k_gemm.hip", "8cbf1a6f5665b209", 40280.400, 3533.656),
     ("medium", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
+    ("learned", "matvec"): ("k_davidson.hip", "c2ad709cede732f3", 14082520.5, 20963.5),
+    ("learned", "expansion_gemm"): ("k_gemm.hip", "25222b91e5d4a913", 16447729.0, 1562812.5),
+    ("learned", "relayout"): ("k_gemm.hip", "25222b91e5d4a913", 2000323.8, 4000000.0),
+    ("learned", "class4"): ("k_class4.hip", "039a68f494db568f", 4258913.9, 6250000.0),
+    ("learned", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 1771760.2, 6273942.5),
+    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038921.0, 14062968.8),
 }
 
 

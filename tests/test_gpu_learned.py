@@ -3,9 +3,13 @@ weights: on held-out instances drawn like the training set and on the
 60000-dimensional test instance (40 target orbitals, N = 12, 8000
 determinants, 50 states, 400 continuum orbitals, 40000 L2 functions), both
 forms reach the same lowest 10 eigenpairs to residual 1e-8 on a matrix whose
-sampled elements match the oracle. The gain in iterations and solve time is
-printed whatever its sign. Non-finite weights fall back to the Jacobi step
-on every row and the solve still converges."""
+sampled elements match the oracle. The measured outcome is asserted against
+the committed expectation: the trained network gains nothing over the
+Jacobi step on these inputs (iteration ratios between 0.8 and 1.25 were
+measured), so the test requires the learned solve to stay within 25% of the
+Jacobi iterations -- a regression guard, not a claim of gain. Non-finite
+weights fall back to the Jacobi step on every row and the solve still
+converges."""
 import os
 
 import numpy as np
@@ -46,6 +50,8 @@ def _ab(cc, ctx, net, name, k=10, tol=1e-8):
     print(f"[{name}] Jacobi {inf_j.iterations} it {1e3 * inf_j.seconds:.1f} ms | MLP {inf_m.iterations} it "
           f"{1e3 * inf_m.seconds:.1f} ms (fallbacks {inf_m.fallbacks}) | iteration gain "
           f"{inf_j.iterations / inf_m.iterations:.3f}x, time gain {inf_j.seconds / inf_m.seconds:.3f}x", flush=True)
+    # the committed expectation: no gain, and no loss beyond 25% in iterations
+    assert inf_m.iterations <= 1.25 * inf_j.iterations, (inf_m.iterations, inf_j.iterations)
     return (ev_j, x_j), (ev_m, x_m)
 
 
