@@ -103,6 +103,8 @@ class Oracle:
     """Holds an instance in the layout the C oracle reads."""
 
     def __init__(self, inst):
+        if getattr(inst, "l2_csf_start", None) is not None:
+            raise ValueError("L2 functions given as CSFs: use l2_csf_matrix")
         self.inst = inst
         keep = []
 
@@ -322,6 +324,50 @@ def energy_mode_matrix(inst, energies, with_abs=False):
                             Ha[i, k] += Pa[n, n2] + abs(energies[a][n]) * (a == b and n == n2)
                             K[i, k] += HT.size + 1
     return (H, Ha, K) if with_abs else H
+
+
+def l2_csf_terms(inst):
+    """(distinct L2 determinants in order of first appearance, the index of
+    each term's determinant among them) of an instance whose L2 functions are
+    CSFs."""
+    index, ud, term = {}, [], []
+    for d in inst.l2_dets:
+        key = tuple(int(x) for x in d)
+        if key not in index:
+            index[key] = len(ud)
+            ud.append(d)
+        term.append(index[key])
+    return np.array(ud, dtype=np.uint64).reshape(-1, inst.n_words), np.array(term, dtype=np.int64)
+
+
+def l2_csf_matrix(inst, with_abs=False):
+    """The contracted matrix when the L2 functions are CSFs (Eq. 1, second
+    sum over configuration state functions chi_l = sum_t coef_t |det_t>): the
+    plain definition, T^T H T, where H is the oracle's matrix over the
+    continuum functions and the distinct L2 determinants, and T is the
+    identity on the continuum rows with T[det(t), l] = coef_t. With with_abs,
+    the sums of |terms| and the term counts of the tolerance rule carried
+    through the same contraction."""
+    import dataclasses
+    ud, term = l2_csf_terms(inst)
+    det_inst = dataclasses.replace(inst, l2_dets=ud, l2_csf_start=None, l2_coef=None)
+    O = Oracle(det_inst)
+    if with_abs:
+        H, A, K = O.build(with_abs=True)
+    else:
+        H = O.build()
+    Dc = det_inst.n_cont_rows()
+    ncsf = len(inst.l2_csf_start) - 1
+    T = np.zeros((Dc + len(ud), Dc + ncsf))
+    T[:Dc, :Dc] = np.eye(Dc)
+    for l in range(ncsf):
+        for t in range(inst.l2_csf_start[l], inst.l2_csf_start[l + 1]):
+            T[Dc + term[t], Dc + l] += inst.l2_coef[t]
+    Hc = T.T @ H @ T
+    if not with_abs:
+        return Hc
+    Ta, Tn = np.abs(T), (T != 0).astype(np.float64)
+    return Hc, Ta.T @ A @ Ta, np.rint(Tn.T @ K @ Tn).astype(np.int64)
 
 
 def tolerance_ok(g, o, abss, cnt, rel=1e-10):

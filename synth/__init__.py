@@ -62,6 +62,10 @@ class Instance:
     name: str = ""
     seed: int = 0
     packed: bool = False         # ttcc / tctc hold the symmetry-packed layout (packed_layout)
+    # L2 functions as CSFs: function l = sum of l2_coef[t] |l2_dets[t]> over
+    # t in [l2_csf_start[l], l2_csf_start[l + 1]) (None: one determinant each)
+    l2_csf_start: np.ndarray = None
+    l2_coef: np.ndarray = None
 
     @property
     def n_cont(self) -> int:
@@ -85,6 +89,8 @@ class Instance:
 
     @property
     def n_l2(self) -> int:
+        if self.l2_csf_start is not None:
+            return int(len(self.l2_csf_start) - 1)
         return 0 if self.l2_dets is None else int(self.l2_dets.shape[0])
 
     def cont_range(self, irrep: int) -> tuple[int, int]:
@@ -502,6 +508,62 @@ def l2huge(seed=818):
     continuum orbitals = 712 contracted rows, 250000 L2 functions
     (D = 250712: a dense matrix would need 503 GB)."""
     return make_instance(40, 12, 1, 178, [0], 2000, 4, 250000, seed, name="l2huge")
+
+
+def l2_spin_adapted(inst):
+    """The instance with its L2 functions rewritten as doublet CSFs (Eq. 1's
+    second sum over configuration state functions): the L2 determinants are
+    grouped by spatial occupation; a group with one open shell is one CSF of
+    one determinant; a group with three open shells a < b < c (two alpha
+    electrons, one beta) gives the two doublets of the genealogical coupling,
+    (a b) triplet: (2|aA bA cB> - |aA bB cA> - |aB bA cA>)/sqrt(6), and
+    (a b) singlet: (|aA bB cA> - |aB bA cA>)/sqrt(2) (A = alpha, B = beta; the
+    determinants are ascending products, and the open-shell spin-orbitals keep
+    their relative order in all three, so the coefficients need no further
+    sign); groups with five or more open shells are left out. Pure data: the
+    determinant lists and coupling coefficients of the input."""
+    W = inst.n_words
+    groups = {}
+    order = []
+    for idx, d in enumerate(inst.l2_dets):
+        occ = det_to_occ(d)
+        spatial = {}
+        for k in occ:
+            spatial[k >> 1] = spatial.get(k >> 1, 0) + 1
+        key = tuple(sorted(spatial.items()))
+        if key not in groups:
+            groups[key] = []
+            order.append(key)
+        groups[key].append(idx)
+    starts, dets, coef = [0], [], []
+    r6, r2 = 1.0 / math.sqrt(6.0), 1.0 / math.sqrt(2.0)
+    for key in order:
+        members = groups[key]
+        opens = [o for o, n in key if n == 1]
+        if len(opens) == 1:
+            dets.append(inst.l2_dets[members[0]])
+            coef.append(1.0)
+            starts.append(len(dets))
+        elif len(opens) == 3:
+            a, b, c = opens
+            closed = [2 * o + sp for o, n in key if n == 2 for sp in (0, 1)]
+
+            def det(sa, sb, sc):
+                return occ_to_det(sorted(closed + [2 * a + sa, 2 * b + sb, 2 * c + sc]), W)
+            have = {tuple(inst.l2_dets[m]) for m in members}
+            aab, aba, baa = det(0, 0, 1), det(0, 1, 0), det(1, 0, 0)
+            if not all(tuple(x) in have for x in (aab, aba, baa)):
+                continue          # an incomplete spin family: left out
+            for terms in ((aab, 2 * r6), (aba, -r6), (baa, -r6)), ((aba, r2), (baa, -r2)):
+                for dd, cf in terms:
+                    dets.append(dd)
+                    coef.append(cf)
+                starts.append(len(dets))
+    out = Instance(**{f: getattr(inst, f) for f in inst.__dataclass_fields__})
+    out.l2_dets = np.array(dets, dtype=np.uint64).reshape(-1, W)
+    out.l2_csf_start = np.array(starts, dtype=np.int32)
+    out.l2_coef = np.array(coef, dtype=np.float64)
+    return out
 
 
 def _active_dets(rng, n_o, n_a, n_b, tgt_irrep, irrep, active, count):

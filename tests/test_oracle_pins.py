@@ -414,3 +414,40 @@ def test_csf_targets_equal_fock_space(kw):
     ref = Vm.T @ (HF @ Vm)
     assert got.shape == ref.shape
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kw", [dict(seed=11, n_o=3, n_elec=2, n_c=2), dict(seed=12, n_o=4, n_elec=2, n_c=1)])
+def test_l2_csfs_equal_fock_space(kw):
+    """L2 functions as doublet CSFs: the oracle's contracted matrix equals
+    V^T H V formed in the Fock space from the CSF combinations themselves
+    (the L2 CSF vector sum_t coef_t |det_t>, the continuum functions
+    sum_m c_mn |det_m u_j>), with no Slater-Condon rule on that side. The
+    doublets are orthonormal Fock-space vectors."""
+    inst = synth.l2_spin_adapted(synth.micro(**kw))
+    ncsf = len(inst.l2_csf_start) - 1
+    assert ncsf >= 2 and np.any(np.diff(inst.l2_csf_start) == 3)
+    got = oracle.l2_csf_matrix(inst)
+    HF = fock.fock_hamiltonian(inst)
+    n = 2 * inst.n_orb
+    vecs = []
+    for s in inst.syms:
+        a = s.irrep ^ inst.total_irrep
+        j0, j1 = inst.cont_range(a)
+        for st in range(s.ci.shape[1]):
+            for j in range(j0, j1):
+                v = np.zeros(1 << n)
+                for m in range(s.dets.shape[0]):
+                    v[fock.basis_index(synth.det_to_occ(s.dets[m]) + [2 * (inst.n_o + j)], n)] += s.ci[m, st]
+                vecs.append(v)
+    L = []
+    for l in range(ncsf):
+        v = np.zeros(1 << n)
+        for t in range(inst.l2_csf_start[l], inst.l2_csf_start[l + 1]):
+            v[fock.basis_index(synth.det_to_occ(inst.l2_dets[t]), n)] += inst.l2_coef[t]
+        L.append(v)
+    Lm = np.array(L).T
+    np.testing.assert_allclose(Lm.T @ Lm, np.eye(ncsf), atol=1e-14)
+    Vm = np.array(vecs + L).T
+    ref = Vm.T @ (HF @ Vm)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
