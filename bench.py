@@ -46,19 +46,19 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them). Keyed by
 # workload and kernel, with the source file of the kernel and its hash when
 # counted: a kernel changed since reports null. The relayout entry is the sum
-# of its two launches (J and K layouts).
+# of its two launches (J and K layouts), the mat-vec entry the sum of the
+# product and its reduction of partial sums.
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
     # (workload, name): (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("medium", "rayleigh_ritz"): ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
-    ("medium", "matvec"): ("k_davidson.hip", "c2ad709cede732f3", 252272.643, 17904.762),
     ("medium", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
-    ("learned", "matvec"): ("k_davidson.hip", "c2ad709cede732f3", 14082520.5, 20963.5),
-    ("learned", "expansion_gemm"): ("k_gemm.hip", "25222b91e5d4a913", 16447729.0, 1562812.5),
-    ("learned", "relayout"): ("k_gemm.hip", "25222b91e5d4a913", 2000323.8, 4000000.0),
-    ("learned", "class4"): ("k_class4.hip", "039a68f494db568f", 4258913.9, 6250000.0),
-    ("learned", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 1771760.2, 6273942.5),
-    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038921.0, 14062968.8),
+    ("learned", "matvec"): ("k_davidson.hip", "fbb8ec7203eb9e17", 7423127.2, 656699.2),
+    ("learned", "expansion_gemm"): ("k_gemm.hip", "25222b91e5d4a913", 16846593.3, 1562812.5),
+    ("learned", "relayout"): ("k_gemm.hip", "25222b91e5d4a913", 2000325.9, 4000000.1),
+    ("learned", "class4"): ("k_class4.hip", "039a68f494db568f", 4258166.5, 6250000.0),
+    ("learned", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 1773224.4, 6273909.5),
+    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038920.8, 14062968.8),
 }
 
 
@@ -414,7 +414,10 @@ def main():
 
     # roofline figures per kernel family (algorithmic work / measured device time)
     D = inst.dim()
-    mv_bytes = 8.0 * D * D                               # H streamed once per launch
+    # dense H from D = 16384 on: the lower triangle read once per 16 vectors
+    # (each element used for both of its products); below, the whole of H
+    symmetric_mv = D >= 16384 and not args.sparse_l2
+    mv_bytes = 4.0 * D * (D + 1.0) if symmetric_mv else 8.0 * D * D
     mv_avg_ms = float(np.sum(mv_ms) / max(np.sum(mv_n), 1))
 
     def entry(bound, work_units, ms, peak, unit, scale, total_ms=None, **extra):
@@ -427,7 +430,9 @@ def main():
     kernels = {
         "matvec": entry("hbm", mv_bytes, mv_avg_ms, HBM_PEAK_GBS, "GB/s", 1e9, total_ms=float(np.mean(mv_ms)),
                         avg_ms=mv_avg_ms, launches_per_step=float(np.mean(mv_n)),
-                        note="8 D^2 bytes per launch (H read once)"),
+                        note=("4 D (D + 1) bytes per launch (the lower triangle of H read once; the "
+                              "product and its reduction of partial sums)") if symmetric_mv else
+                        "8 D^2 bytes per launch (H read once)"),
         "expansion_gemm": entry("mfma", work["gemm_flops"], phase_ms["expansion_gemm"], FP64_MFMA_PEAK_TFLOPS,
                                 "TFLOP/s", 1e12, note="2 x rows x cols x K per symmetry pair, FP64 MFMA"),
         "class4": entry("alu", work["class4_flops"], phase_ms["class4"], FP64_VALU_PEAK_TFLOPS, "TFLOP/s", 1e12,

@@ -328,6 +328,20 @@ cch_status cch_get_labels(cch_ctx *ctx, int32_t which, int32_t sym_a, int32_t sy
 cch_status cch_target_hamiltonian(cch_ctx *ctx, int32_t sym_a, int32_t sym_b, double *out, int64_t ld,
                                   int32_t flags);
 
+/* W = H V for b vectors of the built matrix (the product every iterative
+ * diagonaliser of Sec. 3.2 is made of), in FP64 on the device. V and W hold
+ * one vector per row: V[q * ldv + i], W[q * ldw + i], q < b, i < D,
+ * ldv, ldw >= D; host arrays unless flags holds CCH_MEM_DEVICE (then both are
+ * device arrays of the context's device and W may not overlap V). A dense
+ * context reads the lower triangle of H once per 16 vectors; a context
+ * planned with CCH_PLAN_SPARSE_L2 reads its continuum panels and the CSR of
+ * the L2 block. The sums run in a fixed order: equal inputs give equal bits.
+ * Scratch (and, for host arrays, staging) is allocated per call.
+ * CCH_E_STATE before cch_build, CCH_E_INVALID_ARG for b < 0, a NULL array
+ * with b > 0 or a leading dimension below D. Synchronous. */
+cch_status cch_apply(cch_ctx *ctx, const double *V, int64_t ldv, int32_t b, double *W, int64_t ldw,
+                     int32_t flags);
+
 /* Lowest opts->k eigenpairs of the built matrix by block Davidson in FP64 on
  * the device. evals[k]; evecs[k][D] (row-major: eigenvector e at evecs + e*D);
  * either may be NULL. With flags & CCH_DAV_RESIDUALS, evecs has 2k rows and

@@ -52,7 +52,7 @@ EXPORTS = [
     "cch_mlp_num_params", "cch_mlp_create", "cch_mlp_destroy", "cch_mlp_last_error", "cch_mlp_set_weights",
     "cch_mlp_get_weights", "cch_mlp_forward", "cch_mlp_grad", "cch_mlp_train_step", "cch_mlp_features",
     "cch_davidson_set_mlp", "cch_subspace_eig", "cch_plan_info", "cch_subspace_eig_noalloc",
-    "cch_work_detail", "cch_target_hamiltonian", "cch_eig_all", "cch_set_integrals_packed",
+    "cch_work_detail", "cch_target_hamiltonian", "cch_eig_all", "cch_set_integrals_packed", "cch_apply",
 ]
 CCH_BATCH_AUTOTUNE = 1
 
@@ -111,6 +111,7 @@ _SIG = {
     "cch_get_matrix": (i32, [P, P, i64, i32]),
     "cch_matrix_device": (i32, [P, C.POINTER(P), C.POINTER(i64)]),
     "cch_get_diagonal": (i32, [P, P, i32]),
+    "cch_apply": (i32, [P, P, i64, i32, P, i64, i32]),
     "cch_get_block": (i32, [P, i32, i32, i32, P, i64, i32]),
     "cch_get_elements": (i32, [P, i64, P, P, P, i32]),
     "cch_block_shape": (i32, [P, i32, i32, i32, C.POINTER(i64), C.POINTER(i64)]),
@@ -315,6 +316,17 @@ class Context:
         out = np.empty(D)
         self._ck(lib.cch_get_diagonal(self.h, out.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
         return out
+
+    def apply(self, V):
+        """cch_apply: H V for the rows of V (b x D, host), as a b x D array."""
+        D, _ = self.dim()
+        V = np.ascontiguousarray(np.atleast_2d(V), dtype=np.float64)
+        if V.shape[1] != D:
+            raise CchError(CCH_E_INVALID_ARG, f"vectors of length {V.shape[1]}, D = {D}")
+        W = np.zeros_like(V)
+        self._ck(lib.cch_apply(self.h, V.ctypes.data_as(C.c_void_p), D, V.shape[0], W.ctypes.data_as(C.c_void_p),
+                               D, CCH_MEM_HOST))
+        return W
 
     def get_elements(self, rows, cols):
         """cch_get_elements: H[rows[i]][cols[i]] without copying the matrix."""

@@ -155,6 +155,7 @@ int64_t l2csr_scratch(int D, int Dc);
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
                          int64_t ldw, double *Wp, hipStream_t st);
 int matvec_splits(int D);
+int64_t matvec_scratch_doubles(int D);
 int64_t tn_part_doubles();
 hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, int64_t ldx2, int na,
                      const double *Y, int64_t ldy, int nc, int D, double *part, double *out, int64_t ldo,
@@ -1494,6 +1495,39 @@ cch_status cch_get_diagonal(cch_ctx *c, double *out, int32_t flags)
     return CCH_OK;
 }
 
+cch_status cch_apply(cch_ctx *c, const double *V, int64_t ldv, int32_t b, double *W, int64_t ldw, int32_t flags)
+{
+    if (!c || b < 0 || (b > 0 && (!V || !W))) return CCH_E_INVALID_ARG;
+    if (!c->built) return fail(c, CCH_E_STATE, "build first");
+    const int64_t D = c->D;
+    if (b == 0 || D == 0) return CCH_OK;
+    if (ldv < D || ldw < D) return fail(c, CCH_E_INVALID_ARG, "leading dimensions %lld, %lld below D = %lld",
+                                        (long long)ldv, (long long)ldw, (long long)D);
+    const bool dev = flags & CCH_MEM_DEVICE;
+    const int64_t lv = dev ? ldv : D, lw = dev ? ldw : D;
+    const int64_t nscr = c->sparse ? l2csr_scratch((int)D, (int)c->Dc) : matvec_scratch_doubles((int)D);
+    double *dV = dev ? const_cast<double *>(V) : nullptr, *dW = dev ? W : nullptr, *Wp = nullptr;
+    hipError_t e = hipMalloc((void **)&Wp, 8 * (size_t)std::max<int64_t>(nscr, 1));
+    if (e == hipSuccess && !dev) e = hipMalloc((void **)&dV, 8 * (size_t)(D * b));
+    if (e == hipSuccess && !dev) e = hipMalloc((void **)&dW, 8 * (size_t)(D * b));
+    if (e == hipSuccess && !dev)
+        e = hipMemcpy2DAsync(dV, 8 * D, V, 8 * ldv, 8 * D, b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = c->sparse ? launch_matvec_l2csr(c->d_H, c->ld, c->d_R, c->ldr, (int)c->Dc, (int)D, (int)c->Dc, c->csr.off,
+                                            c->csr.col, c->csr.val, dV, lv, b, dW, lw, Wp, c->stream)
+                      : launch_matvec(c->d_H, c->ld, (int)D, dV, lv, b, dW, lw, Wp, c->stream);
+    if (e == hipSuccess && !dev)
+        e = hipMemcpy2DAsync(W, 8 * ldw, dW, 8 * D, 8 * D, b, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(Wp);
+    if (!dev) {
+        (void)hipFree(dV);
+        (void)hipFree(dW);
+    }
+    if (e != hipSuccess) return fail(c, CCH_E_HIP, "cch_apply: %s", hipGetErrorString(e));
+    return CCH_OK;
+}
+
 cch_status cch_get_elements(cch_ctx *c, int64_t n, const int64_t *rows, const int64_t *cols, double *out,
                             int32_t flags)
 {
@@ -2654,7 +2688,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
               A((void **)&b.P1, 8 * (size_t)mmax * BMAX) &&
               A((void **)&b.part, 8 * (size_t)std::max<int64_t>((int64_t)nch * mmax * 16, tn_part_doubles())) && A((void **)&b.norms, 8 * (size_t)blk) &&
               A((void **)&b.idx, 4 * (size_t)mmax) &&
-              A((void **)&b.Wp, 8 * (size_t)std::max<int64_t>((int64_t)16 * D * (matvec_splits(D) + 1),
+              A((void **)&b.Wp, 8 * (size_t)std::max<int64_t>(matvec_scratch_doubles(D),
                                                                 sparse ? l2csr_scratch(D, (int)c->Dc) : 0)) &&
               A((void **)&b.nfb, 4) &&
               A((void **)&b.rrfb, 4);

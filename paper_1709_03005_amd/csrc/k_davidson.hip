@@ -14,73 +14,6 @@
 namespace cch {
 
 // ---------------------------------------------------------------------------
-// K8: W[q][r] = sum_c H[r][c] V[q][c], q < b <= BMAX
-// ---------------------------------------------------------------------------
-constexpr int MV_ROWS_PER_WAVE = 4;
-constexpr int MV_CH = 256;
-
-template <int BMAX>
-__global__ __launch_bounds__(256) void k_matvec(const double *__restrict__ H, int64_t ld, int D,
-                                                const double *__restrict__ V, int64_t ldv, int b,
-                                                double *__restrict__ Wo, int64_t ldw)
-{
-    __shared__ double vs[BMAX][MV_CH];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int rbase = (blockIdx.x * 4 + wv) * MV_ROWS_PER_WAVE;
-    double acc[MV_ROWS_PER_WAVE][BMAX];
-#pragma unroll
-    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r)
-#pragma unroll
-        for (int q = 0; q < BMAX; ++q) acc[r][q] = 0.0;
-    const double *hr[MV_ROWS_PER_WAVE];
-#pragma unroll
-    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
-        const int row = min(rbase + r, D - 1);
-        hr[r] = H + (int64_t)row * ld;
-    }
-    for (int c0 = 0; c0 < D; c0 += MV_CH) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < BMAX * MV_CH; t += 256) {
-            const int q = t / MV_CH, c = c0 + t % MV_CH;
-            vs[q][t % MV_CH] = (q < b && c < D) ? V[(int64_t)q * ldv + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < MV_CH / 64; ++u) {
-            const int cl = lane + 64 * u, c = c0 + cl;
-            double hv[MV_ROWS_PER_WAVE];
-#pragma unroll
-            for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) hv[r] = c < D ? __builtin_nontemporal_load(hr[r] + c) : 0.0;
-#pragma unroll
-            for (int q = 0; q < BMAX; ++q) {
-                const double v = vs[q][cl];
-#pragma unroll
-                for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) acc[r][q] = fma(hv[r], v, acc[r][q]);
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
-#pragma unroll
-        for (int q = 0; q < BMAX; ++q) {
-            double v = acc[r][q];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            acc[r][q] = v;
-        }
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < MV_ROWS_PER_WAVE; ++r) {
-            const int row = rbase + r;
-            if (row < D)
-#pragma unroll
-                for (int q = 0; q < BMAX; ++q)
-                    if (q < b) Wo[(int64_t)q * ldw + row] = acc[r][q];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // K8 on the matrix cores: W^T = V^T H (H symmetric), FP64 MFMA 16x16x4.
 // Each wave owns a 16-column strip of H and a range of rows of H (split-K
 // across blockIdx.y); the B operand is 4 rows x 16 columns of H (four 128-byte
@@ -146,6 +79,222 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const double *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// K8 from the lower triangle only (H symmetric): every element H[r][c] with
+// r > c is read once and used twice, for W[.][c] += H[r][c] V[.][r] (the
+// column product) and W[.][r] += H[r][c] V[.][c] (the row product); the
+// diagonal once. Half the bytes of the full product for the same MFMA work.
+//
+// The lower triangle is cut into strips of SV_CW columns; a strip's rows
+// (from its diagonal down) into items of rb rows, one workgroup (8 waves)
+// per item, two workgroups per compute unit (at most 128 registers a lane).
+// An item is walked in chunks of SV_CH rows and, inside a chunk, in tiles of
+// SV_CH x SV_SB staged through LDS with the chunk's V rows and the tile's V
+// columns (the next tile is loaded into registers while the current one is
+// multiplied). The waves take turns by sub-block parity: in a tile, the four
+// waves of one parity form the column product of one 16-column strip each
+// over the tile's rows (accumulated over the whole item), the other four the
+// row product of 16 rows each over the tile's columns (accumulated over the
+// chunk). A chunk's row sums (the two parities added in LDS) go to
+// P2[strip][q][row]; at the end of the item the column sums go to
+// P1[item][q][col]. k_symv_reduce adds, for row i, P2 of every strip left of
+// and including i's, then P1 of every item of i's strip, in a fixed order
+// (deterministic). Tiles on the diagonal zero the elements above it (and, in
+// the row product, the diagonal itself); tiles wholly above it are skipped.
+// ---------------------------------------------------------------------------
+constexpr int SV_CW = 512, SV_SB = 64, SV_CH = 64, SV_NSB = SV_CW / SV_SB;
+constexpr int SV_LS = SV_SB + 1;     // LDS row strides in doubles (odd: conflict-free column reads)
+constexpr int SV_LR = SV_CH + 1;
+
+__host__ __device__ inline int sv_items(int D, int J, int rb) { return (D - J * SV_CW + rb - 1) / rb; }
+
+__global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, int64_t ld, int D,
+                                                  const double *__restrict__ V, int64_t ldv, int b, int rb,
+                                                  double *__restrict__ P1, double *__restrict__ P2)
+{
+    __shared__ double Hs[SV_CH * SV_LS];
+    __shared__ double Vc[16 * SV_LS];
+    __shared__ double Vr[16 * SV_LR];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    int J = 0, base = 0;
+    for (;;) {
+        const int n = sv_items(D, J, rb);
+        if ((int)blockIdx.x < base + n) break;
+        base += n;
+        ++J;
+    }
+    const int J0 = J * SV_CW;
+    const int R0 = J0 + ((int)blockIdx.x - base) * rb, R1 = min(D, R0 + rb);
+    const int nsb_d = min(SV_NSB, (D - J0 + SV_SB - 1) / SV_SB);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 ph[4];
+    double pv[2], pr[2];
+    auto load_tile = [&](int r0, int c0, bool first) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int g = tid + 512 * i, row = g >> 5, c = c0 + 2 * (g & 31), r = r0 + row;
+            d2 v = (d2){0.0, 0.0};
+            if (r < R1) {
+                const double *src = H + (int64_t)r * ld + c;
+                if (c + 1 < D) v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(src));
+                else if (c < D) v.x = src[0];
+            }
+            ph[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 512 * i, q = e >> 6, c = c0 + (e & 63);
+            pv[i] = (q < b && c < D) ? V[(int64_t)q * ldv + c] : 0.0;
+        }
+        if (first) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int e = tid + 512 * i, q = e >> 6, r = r0 + (e & 63);
+                pr[i] = (q < b && r < R1) ? V[(int64_t)q * ldv + r] : 0.0;
+            }
+        }
+    };
+    auto store_tile = [&](bool first) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int g = tid + 512 * i, row = g >> 5, cl = 2 * (g & 31);
+            Hs[row * SV_LS + cl] = ph[i].x;
+            Hs[row * SV_LS + cl + 1] = ph[i].y;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 512 * i;
+            Vc[(e >> 6) * SV_LS + (e & 63)] = pv[i];
+        }
+        if (first) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int e = tid + 512 * i;
+                Vr[(e >> 6) * SV_LR + (e & 63)] = pr[i];
+            }
+        }
+    };
+    auto nsb_of = [&](int r0) { return r0 < R1 ? min(nsb_d, (r0 + SV_CH - J0 + SV_SB - 1) / SV_SB) : 0; };
+    const int st = w & 3, par = w >> 2;
+    dx4m acc1[SV_NSB / 2];
+#pragma unroll
+    for (int m = 0; m < SV_NSB / 2; ++m) acc1[m] = (dx4m){0.0, 0.0, 0.0, 0.0};
+    load_tile(R0, J0, true);
+    for (int r0 = R0; r0 < R1; r0 += SV_CH) {
+        const int nsb = nsb_of(r0), nsb_next = nsb_of(r0 + SV_CH);
+        dx4m acc2[1];
+        acc2[0] = (dx4m){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < SV_NSB; ++s) {
+            if (s < nsb) {
+                const int c0 = J0 + SV_SB * s;
+                __syncthreads();
+                store_tile(s == 0);
+                __syncthreads();
+                {
+                    const bool more = s + 1 < nsb;
+                    if (more || nsb_next > 0) load_tile(more ? r0 : r0 + SV_CH, more ? c0 + SV_SB : J0, !more);
+                }
+                const bool diag = r0 <= c0 + SV_SB - 1;
+                if ((s & 1) == par) {
+                    // column product: strip st, 64 rows
+#pragma unroll 2
+                    for (int u = 0; u < SV_CH / 4; ++u) {
+                        const int rl = 4 * u + hi, cl = 16 * st + lo;
+                        const double a = Vr[lo * SV_LR + rl];
+                        double h = Hs[rl * SV_LS + cl];
+                        if (diag && r0 + rl < c0 + cl) h = 0.0;
+                        acc1[s >> 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, h, acc1[s >> 1], 0, 0, 0);
+                    }
+                } else {
+                    // row product: rows 16 st.., 64 columns, two chains
+#pragma unroll 2
+                    for (int u = 0; u < SV_SB / 4; ++u) {
+                        const int cl = 4 * u + hi, rl = 16 * st + lo;
+                        const double a = Vc[lo * SV_LS + cl];
+                        double h = Hs[rl * SV_LS + cl];
+                        if (diag && r0 + rl <= c0 + cl) h = 0.0;
+                        acc2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, h, acc2[0], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (par == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Vr[(st * 4 + v) * 64 + lane] = acc2[0][v];
+        }
+        __syncthreads();
+        if (par == 0) {
+            const int r = r0 + 16 * st + lo;
+            if (r < R1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = hi + 4 * v;
+                    if (q < b) P2[((int64_t)J * b + q) * D + r] = (acc2[0][v]) + Vr[(st * 4 + v) * 64 + lane];
+                }
+            }
+        }
+    }
+    const int64_t item = blockIdx.x;
+#pragma unroll
+    for (int m = 0; m < SV_NSB / 2; ++m) {
+        const int c = J0 + SV_SB * (2 * m + par) + 16 * st + lo;
+        if (c < D) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q = hi + 4 * v;
+                if (q < b) P1[(item * b + q) * SV_CW + (c - J0)] = acc1[m][v];
+            }
+        }
+    }
+}
+
+__global__ void k_symv_reduce(const double *__restrict__ P1, const double *__restrict__ P2, int D, int b, int rb,
+                              double *__restrict__ Wo, int64_t ldw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (i >= D || q >= b) return;
+    const int J = i / SV_CW;
+    double s = 0.0;
+    int base = 0;
+    for (int j = 0; j < J; ++j) {
+        s += P2[((int64_t)j * b + q) * D + i];
+        base += sv_items(D, j, rb);
+    }
+    s += P2[((int64_t)J * b + q) * D + i];
+    const int n = sv_items(D, J, rb);
+    for (int t = 0; t < n; ++t) s += P1[((int64_t)(base + t) * b + q) * SV_CW + (i - J * SV_CW)];
+    Wo[(int64_t)q * ldw + i] = s;
+}
+
+// item height of the symmetric product: the largest of 2048 .. 128 rows that
+// still gives at least 4096 items (eight rounds of two workgroups per
+// compute unit: short tails)
+static int symv_rows_per_item(int D)
+{
+    int rb = 2048;
+    for (; rb > 128; rb /= 2) {
+        int64_t items = 0;
+        for (int J = 0; J * SV_CW < D; ++J) items += sv_items(D, J, rb);
+        if (items >= 4096) break;
+    }
+    return rb;
+}
+
+static int64_t symv_items(int D, int rb)
+{
+    int64_t items = 0;
+    for (int J = 0; J * SV_CW < D; ++J) items += sv_items(D, J, rb);
+    return items;
+}
+
+// the symmetric product pays off once the matrix is large enough to fill the
+// chip with its items; below, the full product with split-K
+constexpr int SYMV_MIN_D = 16384;
+
 __global__ void k_matvec_reduce(const double *__restrict__ Wp, int ks, int D, int b, double *__restrict__ Wo,
                                 int64_t ldw)
 {
@@ -170,18 +319,43 @@ hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, in
                          int64_t ldw, double *Wp, hipStream_t st)
 {
     if (D <= 0 || b <= 0) return hipSuccess;
+    if (D >= SYMV_MIN_D) {
+        const int rb = symv_rows_per_item(D);
+        const int64_t items = symv_items(D, rb);
+        const int nstrip = (D + SV_CW - 1) / SV_CW;
+        double *P1 = Wp, *P2 = Wp + items * 16 * SV_CW;
+        (void)nstrip;
+        for (int q0 = 0; q0 < b; q0 += 16) {
+            const int bb = std::min(16, b - q0);
+            hipLaunchKernelGGL(k_symv, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, V + (int64_t)q0 * ldv, ldv,
+                               bb, rb, P1, P2);
+            hipLaunchKernelGGL(k_symv_reduce, dim3((D + 255) / 256, bb), dim3(256), 0, st, P1, P2, D, bb, rb,
+                               W + (int64_t)q0 * ldw, ldw);
+        }
+        return hipGetLastError();
+    }
     const int ks = matvec_splits(D);
     int rps = (D + ks - 1) / ks;
     rps = (rps + 4 * MVM_UNROLL - 1) / (4 * MVM_UNROLL) * (4 * MVM_UNROLL);
     const int ksu = (D + rps - 1) / rps;
     for (int q0 = 0; q0 < b; q0 += 16) {
         const int bb = std::min(16, b - q0);
-        hipLaunchKernelGGL(k_matvec_mfma, dim3((D + 64 * MVM_NS - 1) / (64 * MVM_NS), ksu), dim3(256), 0, st, H, ld, D,
-                           V + (int64_t)q0 * ldv, ldv, bb, rps, Wp);
+        hipLaunchKernelGGL(k_matvec_mfma, dim3((D + 64 * MVM_NS - 1) / (64 * MVM_NS), ksu), dim3(256), 0, st, H, ld,
+                           D, V + (int64_t)q0 * ldv, ldv, bb, rps, Wp);
         hipLaunchKernelGGL(k_matvec_reduce, dim3((D + 255) / 256, bb), dim3(256), 0, st, Wp, ksu, D, bb,
                            W + (int64_t)q0 * ldw, ldw);
     }
     return hipGetLastError();
+}
+
+// doubles of the Wp scratch launch_matvec needs for dimension D
+int64_t matvec_scratch_doubles(int D)
+{
+    const int64_t full = (int64_t)16 * D * (matvec_splits(D) + 1);
+    if (D < SYMV_MIN_D) return full;
+    const int rb = symv_rows_per_item(D);
+    const int64_t nstrip = (D + SV_CW - 1) / SV_CW;
+    return std::max(full, symv_items(D, rb) * 16 * SV_CW + nstrip * 16 * (int64_t)D);
 }
 
 // ---------------------------------------------------------------------------
