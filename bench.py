@@ -435,9 +435,10 @@ def main():
                         "8 D^2 bytes per launch (H read once)"),
         "expansion_gemm": entry("mfma", work["gemm_flops"], phase_ms["expansion_gemm"], FP64_MFMA_PEAK_TFLOPS,
                                 "TFLOP/s", 1e12, note="2 x rows x cols x K per symmetry pair, FP64 MFMA"),
-        "class4": entry("alu", work["class4_flops"], phase_ms["class4"], FP64_VALU_PEAK_TFLOPS, "TFLOP/s", 1e12,
-                        note="2 S n_c flops per connected L2 x target pair (Eq. 5), FP64 FMA on the vector "
-                             "units; phase time includes its L2 x target scan"),
+        "class4": entry("mfma", work["class4_flops"], phase_ms["class4"], FP64_MFMA_PEAK_TFLOPS, "TFLOP/s", 1e12,
+                        note="2 S n_c flops per term of a connected L2 x target pair (Eq. 5), FP64 MFMA "
+                             "(16 states x 16 continuum orbitals per tile); phase time includes its L2 x "
+                             "target scan"),
         "densities": entry("alu", work["density_flops"], phase_ms["target_densities"], FP64_VALU_PEAK_TFLOPS,
                            "TFLOP/s", 1e12,
                            note="transition densities of Eq. 8 (one multiply-add per (n, n') row per density "

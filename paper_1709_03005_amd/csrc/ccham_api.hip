@@ -2422,7 +2422,7 @@ cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, in
         for (auto &L : c->lt) {
             const SymInfo &s = c->syms[L.sym];
             if (s.nc == 0 || c->n_l2 == 0) continue;
-            C4Task k{class4_args(c, L), c->n_l2, (s.nc + 63) / 64, c4t[c->W]};
+            C4Task k{class4_args(c, L), c->n_l2, (s.nc + C4_JB - 1) / C4_JB, c4t[c->W]};
             c4t[c->W] += (int64_t)k.n_l2 * k.jtiles;
             c4[c->W].push_back(k);
         }

@@ -248,6 +248,9 @@ struct TrdVec {
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for
 // c < Dc (every row), R[r][c - Dc] for r < Dc <= c, and the L2 block's rows
 // as CSR (columns relative to Dc, ascending)
+// continuum orbitals per class-4 workgroup (the j block of one L2 row)
+constexpr int C4_JB = 512;
+
 struct SparseMat {
     const double *P;
     int64_t ldp;
