@@ -210,6 +210,24 @@ cch_status cch_add_target_symmetry_csf(cch_ctx *ctx, int32_t irrep, int32_t n_cs
 cch_status cch_set_l2(cch_ctx *ctx, int32_t n_l2, int32_t n_words, const uint64_t *dets,
                       int32_t flags);
 
+/* The L2 functions as configuration state functions (Eq. 1's second sum;
+ * Sec. 2 builds the matrix from CSF lists): CSF l is
+ * sum_{t = csf_start[l]}^{csf_start[l+1]-1} coef[t] |dets[t]>, each determinant
+ * with N+1 electrons in target orbitals (N/2+1 alpha, N/2 beta, irrep
+ * total_irrep), n_words 64-bit words each; a determinant may appear in several
+ * CSFs. Replaces any earlier cch_set_l2 / cch_set_l2_csf. The matrix then has
+ * n_csf L2 rows and columns: the build forms the blocks over the distinct
+ * determinants (in order of first appearance) and contracts them with the
+ * coefficients, which needs device memory for both matrices; classes 2, 4
+ * and 8 then hold <chi_l|H|chi_l'> and the contracted class-4 rows.
+ * cch_get_labels still lists determinant pairs. Not with CCH_PLAN_SPARSE_L2
+ * (cch_plan fails with CCH_E_STATE) nor in a batch. Host pointers unless
+ * flags holds CCH_MEM_DEVICE. CCH_E_INPUT for csf_start[0] != 0, a CSF without
+ * determinants, a non-finite coefficient or a determinant that fails the
+ * checks of cch_set_l2. Before cch_plan. */
+cch_status cch_set_l2_csf(cch_ctx *ctx, int32_t n_csf, const int32_t *csf_start, int32_t n_words,
+                          const uint64_t *dets, const double *coef, int32_t flags);
+
 /* Target energies on the diagonal (Sec. 3.1, the option kept for classes 1,
  * 3, 5, 6 and 7): E[n] holds the n = sum of n_states energies of all target
  * states, symmetry by symmetry in the order they were added, state by state

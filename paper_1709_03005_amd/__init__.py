@@ -45,7 +45,7 @@ CCH_PAIRS_L2_TARGET = 2
 
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
-    "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_target_energies", "cch_plan", "cch_build",
+    "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_l2_csf", "cch_set_target_energies", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_elements", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
@@ -104,6 +104,7 @@ _SIG = {
     "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
     "cch_add_target_symmetry_csf": (i32, [P, i32, i32, P, i32, P, P, i32, P, i32, P]),
     "cch_set_l2": (i32, [P, i32, i32, P, i32]),
+    "cch_set_l2_csf": (i32, [P, i32, P, i32, P, P, i32]),
     "cch_set_target_energies": (i32, [P, P, i64, i32]),
     "cch_plan": (i32, [P, C.POINTER(PlanOpts)]),
     "cch_build": (i32, [P]),
@@ -267,6 +268,17 @@ class Context:
         n = kd.shape[0]
         w = kd.shape[1] if kd.ndim == 2 else 0
         self._ck(lib.cch_set_l2(self.h, int(n), int(w), pd, fd))
+
+    def set_l2_csf(self, csf_start, dets, coef):
+        """cch_set_l2_csf: L2 function l = sum over terms t in
+        [csf_start[l], csf_start[l+1]) of coef[t] |dets[t]>."""
+        st = np.ascontiguousarray(csf_start, dtype=np.int32)
+        d = np.ascontiguousarray(dets, dtype=np.uint64)
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        if d.ndim != 2 or d.shape[0] != cf.size or st.size < 2:
+            raise CchError(CCH_E_INVALID_ARG, "CSF terms and coefficients differ in count")
+        self._ck(lib.cch_set_l2_csf(self.h, int(st.size - 1), st.ctypes.data_as(C.c_void_p), int(d.shape[1]),
+                                    d.ctypes.data_as(C.c_void_p), cf.ctypes.data_as(C.c_void_p), CCH_MEM_HOST))
 
     def set_target_energies(self, energies):
         """Target energies on the diagonal (one array per target symmetry, or
@@ -586,7 +598,8 @@ class Batch:
 def from_instance(inst, device=0, stream=None, plan=True, target_energies=None, **plan_kw) -> Context:
     """Context loaded with an instance object carrying the fields the
     interface takes (n_o, tgt_irrep, n_irrep, n_c, total_irrep, h, tttt,
-    tttc, ttcc, tctc, e_core, syms[i].irrep/.dets/.ci, l2_dets); with
+    tttc, ttcc, tctc, e_core, syms[i].irrep/.dets/.ci, l2_dets, and for L2
+    functions given as CSFs l2_csf_start and l2_coef); with
     target_energies (one array per symmetry) the option of target energies on
     the diagonal is set before the plan."""
     ctx = Context(device, stream)
@@ -597,7 +610,9 @@ def from_instance(inst, device=0, stream=None, plan=True, target_energies=None, 
         ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
     for s in inst.syms:
         ctx.add_target_symmetry(s.irrep, s.dets, s.ci)
-    if inst.l2_dets is not None and len(inst.l2_dets):
+    if getattr(inst, "l2_csf_start", None) is not None:
+        ctx.set_l2_csf(inst.l2_csf_start, inst.l2_dets, inst.l2_coef)
+    elif inst.l2_dets is not None and len(inst.l2_dets):
         ctx.set_l2(inst.l2_dets)
     if target_energies is not None:
         ctx.set_target_energies(target_energies)

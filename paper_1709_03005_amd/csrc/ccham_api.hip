@@ -84,6 +84,8 @@ struct L2Args {
     int64_t row0;
 };
 hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st);
+hipError_t launch_l2csf_gather(const double *Hd, int64_t ldd, int Dc, int ncsf, const int32_t *start,
+                               const int32_t *det, const double *coef, double *H, int64_t ld, hipStream_t st);
 struct GemmTask {
     const double *At;
     const double *B;
@@ -270,9 +272,22 @@ struct cch_ctx {
     // determinant spaces
     int n_elec = -1;
     std::vector<SymInfo> syms;
-    int n_l2 = 0;
+    int n_l2 = 0;               // L2 determinants
     uint64_t *d_l2 = nullptr;
     std::vector<uint64_t> h_l2;
+    // L2 functions as CSFs (cch_set_l2_csf): the build writes the matrix over
+    // the L2 determinants into d_Hd (Dd x ldd); k_l2csf_gather then forms the
+    // matrix over the CSFs in d_H
+    int n_l2r = 0;              // L2 rows of the matrix: the CSFs, else the determinants
+    bool l2csf = false;
+    std::vector<int32_t> h_csf_start, h_csf_det;
+    std::vector<double> h_csf_coef;
+    int32_t *d_csf_start = nullptr, *d_csf_det = nullptr;
+    double *d_csf_coef = nullptr;
+    double *d_Hd = nullptr;
+    int64_t Dd = 0, ldd = 0;
+    double *d_Hb = nullptr;     // the matrix the build kernels write: d_H, or d_Hd with CSFs
+    int64_t ldb = 0;
     // plan
     bool planned = false, built = false;
     cch_plan_opts opts{};
@@ -727,7 +742,52 @@ cch_status cch_set_l2(cch_ctx *c, int32_t n_l2, int32_t n_words, const uint64_t 
     TRY(dalloc(c, &c->d_l2, hd.size()));
     if (n_l2) HIPCK(c, hipMemcpy(c->d_l2, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
     c->n_l2 = n_l2;
+    c->n_l2r = n_l2;
+    c->l2csf = false;
     c->h_l2 = std::move(hd);
+    return CCH_OK;
+}
+
+cch_status cch_set_l2_csf(cch_ctx *c, int32_t n_csf, const int32_t *csf_start, int32_t n_words, const uint64_t *dets,
+                          const double *coef, int32_t flags)
+{
+    if (!c) return CCH_E_INVALID_ARG;
+    if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
+    if (c->n_elec < 0) return fail(c, CCH_E_STATE, "add a target symmetry first (it fixes N)");
+    if (c->planned) return fail(c, CCH_E_STATE, "already planned");
+    if (n_csf <= 0 || !csf_start || !dets || !coef) return fail(c, CCH_E_INVALID_ARG, "empty CSF list");
+    if (n_words != c->W) return fail(c, CCH_E_INPUT, "n_words %d != %d", n_words, c->W);
+    std::vector<int32_t> st((size_t)n_csf + 1);
+    TRY(host_copy(c, st.data(), csf_start, st.size() * 4, flags));
+    if (st[0] != 0) return fail(c, CCH_E_INPUT, "csf_start[0] must be 0");
+    for (int l = 0; l < n_csf; ++l)
+        if (st[l + 1] <= st[l]) return fail(c, CCH_E_INPUT, "CSF %d has no determinant", l);
+    const int64_t nt = st[n_csf];
+    std::vector<uint64_t> hd((size_t)nt * n_words);
+    std::vector<double> hc((size_t)nt);
+    TRY(host_copy(c, hd.data(), dets, hd.size() * 8, flags));
+    TRY(host_copy(c, hc.data(), coef, hc.size() * 8, flags));
+    for (double v : hc)
+        if (!std::isfinite(v)) return fail(c, CCH_E_INPUT, "CSF coefficient is not finite");
+    // distinct determinants in order of first appearance
+    std::map<std::vector<uint64_t>, int> index;
+    std::vector<uint64_t> ud;
+    std::vector<int32_t> term_det((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        std::vector<uint64_t> key(hd.begin() + t * n_words, hd.begin() + (t + 1) * n_words);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, (int)index.size()).first;
+            ud.insert(ud.end(), key.begin(), key.end());
+        }
+        term_det[t] = it->second;
+    }
+    TRY(cch_set_l2(c, (int32_t)index.size(), n_words, ud.data(), CCH_MEM_HOST));
+    c->n_l2r = n_csf;
+    c->l2csf = true;
+    c->h_csf_start = std::move(st);
+    c->h_csf_det = std::move(term_det);
+    c->h_csf_coef = std::move(hc);
     return CCH_OK;
 }
 
@@ -809,7 +869,7 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
         row += (int64_t)s.S * s.nc;
     }
     c->Dc = row;
-    c->D = row + c->n_l2;
+    c->D = row + c->n_l2r;
     if (c->energy_mode) {
         int64_t off = 0;
         for (auto &s : c->syms) {
@@ -824,6 +884,8 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     if (c->D <= 0) return fail(c, CCH_E_STATE, "empty matrix");
     if (c->D > 2000000000LL) return fail(c, CCH_E_LIMIT, "dimension too large");
     c->sparse = (c->opts.flags & CCH_PLAN_SPARSE_L2) != 0;
+    if (c->sparse && c->l2csf)
+        return fail(c, CCH_E_STATE, "L2 functions given as CSFs need the dense L2 block (no CCH_PLAN_SPARSE_L2)");
     // dense: D x D; sparse L2 block: d_H keeps only the continuum columns
     c->ld = c->sparse ? std::max<int64_t>(32, (c->Dc + 31) / 32 * 32) : (c->D + 31) / 32 * 32;
     // symmetry pairs a >= b
@@ -905,6 +967,18 @@ cch_status cch_plan(cch_ctx *c, const cch_plan_opts *opts)
     c->relayout_elems = maxB;
     TRY(dalloc(c, &c->d_H, (size_t)c->D * c->ld));
     TRY(dalloc(c, &c->d_diag, c->D));
+    c->d_Hb = c->d_H;
+    c->ldb = c->ld;
+    if (c->l2csf) {
+        c->Dd = c->Dc + c->n_l2;
+        c->ldd = (c->Dd + 31) / 32 * 32;
+        TRY(dalloc(c, &c->d_Hd, (size_t)c->Dd * c->ldd));
+        TRY(upload(c, &c->d_csf_start, c->h_csf_start));
+        TRY(upload(c, &c->d_csf_det, c->h_csf_det));
+        TRY(upload(c, &c->d_csf_coef, c->h_csf_coef));
+        c->d_Hb = c->d_Hd;
+        c->ldb = c->ldd;
+    }
     if (c->sparse) {
         // transpose of class 4, and the L2 block's CSR sized by a counting pass
         // of the excitation scan over all L2 pairs (the columns are listed by
@@ -984,8 +1058,8 @@ static Class4Args class4_args(cch_ctx *c, const LtPlan &L)
     a.row_off = L.pr.row_off;
     a.row_cnt = L.pr.row_cnt;
     a.pl = L.pr.pl;
-    a.H = c->d_H;
-    a.ld = c->ld;
+    a.H = c->d_Hb;
+    a.ld = c->ldb;
     a.row_l2 = c->Dc;
     a.col0 = s.row0;
     a.pairs_per_chunk = std::max(1, std::min(64, 1024 / (1 + 2 * c->n_elec)));
@@ -995,7 +1069,7 @@ static Class4Args class4_args(cch_ctx *c, const LtPlan &L)
 static ExpandEpi expand_epi(cch_ctx *c, const PairPlan &p)
 {
     const SymInfo &sa = c->syms[p.a], &sb = c->syms[p.b];
-    return ExpandEpi{c->d_H, c->ld, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT,
+    return ExpandEpi{c->d_Hb, c->ldb, sa.row0, sb.row0, sa.nc, sb.nc, sa.ja0, sb.ja0, p.d_rn, p.d_rn2, p.d_HT,
                      p.d_O, c->d_h, c->n_o, c->n_orb};
 }
 
@@ -1169,7 +1243,7 @@ static cch_status enqueue_l2(cch_ctx *c, hipStream_t st)
             HIPCK(c, launch_l2s_values(c->W, c->d_l2, c->n_l2, I, c->csr.off, c->csr.col, c->csr.val,
                                        c->d_diag + c->Dc, st));
         } else {
-            L2Args a{c->d_l2, c->n_l2, I, c->d_H, c->ld, c->Dc};
+            L2Args a{c->d_l2, c->n_l2, I, c->d_Hb, c->ldb, c->Dc};
             HIPCK(c, launch_l2_block(c->W, a, st));
         }
     }
@@ -1185,6 +1259,9 @@ static cch_status enqueue_post(cch_ctx *c, hipStream_t st)
         HIPCK(c, launch_transpose_c4(c->d_H, c->ld, (int)c->Dc, c->n_l2, c->d_R, c->ldr, st));
         return CCH_OK;
     }
+    if (c->l2csf)   // the matrix over the CSFs (lower triangle) from the one over the determinants
+        HIPCK(c, launch_l2csf_gather(c->d_Hd, c->ldd, (int)c->Dc, c->n_l2r, c->d_csf_start, c->d_csf_det,
+                                     c->d_csf_coef, c->d_H, c->ld, st));
     HIPCK(c, launch_mirror(c->d_H, c->ld, (int)c->D, st));
     HIPCK(c, launch_diag(c->d_H, c->ld, (int)c->D, c->d_diag, st));
     return CCH_OK;
@@ -1568,7 +1645,7 @@ static cch_status block_geometry(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t
     *nca = *ncb = 0;
     if (cls == 2 || cls == 8) {
         *row0 = *col0 = c->Dc;
-        *nrows = *ncols = c->n_l2;
+        *nrows = *ncols = c->n_l2r;
         *mode = cls;
         return CCH_OK;
     }
@@ -1576,7 +1653,7 @@ static cch_status block_geometry(cch_ctx *c, int32_t cls, int32_t sym_a, int32_t
     const SymInfo &sa = c->syms[sym_a];
     if (cls == 4) {
         *row0 = c->Dc;
-        *nrows = c->n_l2;
+        *nrows = c->n_l2r;
         *col0 = sa.row0;
         *ncols = (int64_t)sa.S * sa.nc;
         *mode = 0;
@@ -2378,6 +2455,8 @@ cch_status cch_batch_create(cch_batch **out, cch_ctx *const *ctxs, int32_t n, in
         if (!ctxs[i]->planned) return bfail(nullptr, CCH_E_STATE, "context %d is not planned", i);
         if (ctxs[i]->sparse)
             return bfail(nullptr, CCH_E_STATE, "context %d stores its L2 block as CSR (CCH_PLAN_SPARSE_L2)", i);
+        if (ctxs[i]->l2csf)
+            return bfail(nullptr, CCH_E_STATE, "context %d has L2 functions given as CSFs", i);
         if (ctxs[i]->b_shared)
             return bfail(nullptr, CCH_E_STATE, "context %d was planned in several expansion passes", i);
         if (ctxs[i]->opts.precision != CCH_PREC_FP64)
@@ -2605,7 +2684,7 @@ struct DavBufs {
 static cch_status ensure_l2csr(cch_ctx *c, hipStream_t st)
 {
     if (c->csr.gen == c->build_gen) return CCH_OK;
-    const int nl2 = c->n_l2, Dc = (int)c->Dc;
+    const int nl2 = c->n_l2r, Dc = (int)c->Dc;
     if (!c->csr.off && hipMalloc((void **)&c->csr.off, 8 * ((size_t)nl2 + 1)) != hipSuccess)
         return fail(c, CCH_E_OOM, "L2 row offsets");
     int64_t *cnt = nullptr;
@@ -2660,7 +2739,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     hipStream_t st = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     // the L2 block as CSR in the mat-vec (formed here, inside the solve's time)
-    const bool sparse = ((flags & CCH_DAV_SPARSE_L2) || c->sparse) && c->n_l2 > 0;
+    const bool sparse = ((flags & CCH_DAV_SPARSE_L2) || c->sparse) && c->n_l2r > 0;
     if (sparse && !c->sparse) TRY(ensure_l2csr(c, st));
 
     const int64_t ldv = ((int64_t)D + 31) / 32 * 32;

@@ -84,6 +84,57 @@ hipError_t launch_l2_block(int W, const L2Args &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// L2 functions given as CSFs, chi_l = sum_t coef_t |det_t> (Eq. 1's second
+// sum over configuration state functions): the lower triangle of the matrix
+// over the CSFs from the lower triangle of the one built over the distinct L2
+// determinants (Hd, not mirrored): continuum rows are copied, a class-4 row
+// is sum_t coef_t Hd[det_t][c], an L2 x L2 element sum_t sum_u coef_t coef_u
+// Hd[det_t][det_u] (read from the lower triangle), terms in input order. One
+// workgroup per row.
+__global__ __launch_bounds__(256) void k_l2csf_gather(const double *__restrict__ Hd, int64_t ldd, int Dc,
+                                                      const int32_t *__restrict__ start,
+                                                      const int32_t *__restrict__ det,
+                                                      const double *__restrict__ coef, double *__restrict__ H,
+                                                      int64_t ld)
+{
+    const int64_t r = blockIdx.x;
+    double *out = H + r * ld;
+    if (r < Dc) {
+        const double *in = Hd + r * ldd;
+        for (int64_t c = threadIdx.x; c <= r; c += blockDim.x) out[c] = in[c];
+        return;
+    }
+    const int a = (int)(r - Dc);
+    const int t0 = start[a], t1 = start[a + 1];
+    for (int64_t c = threadIdx.x; c <= r; c += blockDim.x) {
+        double v = 0.0;
+        if (c < Dc) {
+            for (int t = t0; t < t1; ++t) v += coef[t] * Hd[(Dc + (int64_t)det[t]) * ldd + c];
+        } else {
+            const int b = (int)(c - Dc), u0 = start[b], u1 = start[b + 1];
+            for (int t = t0; t < t1; ++t) {
+                const int64_t x = Dc + (int64_t)det[t];
+                double s = 0.0;
+                for (int u = u0; u < u1; ++u) {
+                    const int64_t y = Dc + (int64_t)det[u];
+                    s += coef[u] * (x >= y ? Hd[x * ldd + y] : Hd[y * ldd + x]);
+                }
+                v += coef[t] * s;
+            }
+        }
+        out[c] = v;
+    }
+}
+
+hipError_t launch_l2csf_gather(const double *Hd, int64_t ldd, int Dc, int ncsf, const int32_t *start,
+                               const int32_t *det, const double *coef, double *H, int64_t ld, hipStream_t st)
+{
+    const int64_t D = (int64_t)Dc + ncsf;
+    if (D <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_l2csf_gather, dim3((unsigned)D), dim3(256), 0, st, Hd, ldd, Dc, start, det, coef, H, ld);
+    return hipGetLastError();
+}
+
 // persistent form over many instances with the same word count
 struct L2Task {
     L2Args a;
