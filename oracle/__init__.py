@@ -92,7 +92,7 @@ class _Inst(C.Structure):
                 ("cont_start", C.c_void_p), ("sym_irrep", C.c_void_p),
                 ("sym_ndet", C.c_void_p), ("sym_nstate", C.c_void_p),
                 ("sym_dets", C.c_void_p), ("sym_ci", C.c_void_p),
-                ("l2_dets", C.c_void_p)]
+                ("l2_dets", C.c_void_p), ("sym_cspin", C.c_void_p)]
 
 
 def _ptr(a):
@@ -135,9 +135,14 @@ class Oracle:
         cp = c([x.ctypes.data for x in cis] or [0], np.uint64)
         l2 = c(inst.l2_dets if inst.l2_dets is not None else np.zeros((0, inst.n_words)),
                np.uint64)
+        # continuum spin per target determinant (NULL entries: alpha)
+        spins = [c(s.cont_spin, np.int8) if getattr(s, "cont_spin", None) is not None else None
+                 for s in inst.syms]
+        sp = c([x.ctypes.data if x is not None else 0 for x in spins] or [0], np.uint64)
+        any_spin = any(x is not None for x in spins)
         self._st = _Inst(ints, inst.n_elec, inst.n_words, len(inst.syms), l2.shape[0],
                          inst.total_irrep, _ptr(cs), _ptr(irr), _ptr(nd), _ptr(ns),
-                         _ptr(dp), _ptr(cp), _ptr(l2))
+                         _ptr(dp), _ptr(cp), _ptr(l2), _ptr(sp) if any_spin else None)
         self._keep = keep
         self._ints = ints
         self.lib = _load()

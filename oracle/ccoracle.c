@@ -21,8 +21,9 @@
  * Conventions (fixed by the library's interface; the paper leaves them open):
  *   - spin-orbital k = 2*orbital + spin, alpha = 0; determinants are ascending
  *     products a+_k1 a+_k2 ... |0>, k1 < k2 < ...;
- *   - the continuum electron has alpha spin and is the highest-indexed
- *     spin-orbital of a continuum function: u_j = 2*(n_o + j);
+ *   - the continuum electron is the highest-indexed spin-orbital of a
+ *     continuum function: u_j = 2*(n_o + j) + sigma, sigma its spin (0 alpha,
+ *     1 beta; given per target determinant, alpha unless stated);
  *   - the only shortcut taken: a pair whose target parts differ in more than
  *     two spin-orbitals is skipped, since its (N+1)-electron determinants then
  *     differ in more than two as well and the Slater-Condon element is zero.
@@ -85,6 +86,9 @@ typedef struct {
     const uint64_t *const *sym_dets; /* [n_sym] -> [ndet][n_words] */
     const double *const *sym_ci;     /* [n_sym] -> [ndet][nstate] */
     const uint64_t *l2_dets;         /* [n_l2][n_words] */
+    /* continuum spin per target determinant (0 alpha, 1 beta) of each
+     * symmetry; NULL (or a NULL entry): alpha throughout */
+    const int8_t *const *sym_cspin;
 } orc_inst;
 
 /* ------------------------------------------------------------------------ */
@@ -333,11 +337,18 @@ static rowid decode_row(const orc_inst *I, int64_t r)
     return id;
 }
 
-/* continuum function |eta_im u_j>: target occupation plus u_j = 2(n_o+j), last */
+/* continuum spin of target determinant m of a symmetry (0 alpha, 1 beta) */
+static int cspin(const orc_inst *I, int sym, int m)
+{
+    return (I->sym_cspin && I->sym_cspin[sym]) ? I->sym_cspin[sym][m] : 0;
+}
+
+/* continuum function |eta_im u_j sigma_m>: target occupation plus the
+ * spin-orbital 2(n_o+j) + sigma_m, last */
 static int cont_occ(const orc_inst *I, int sym, int m, int j, int *occ)
 {
     int n = det_occ(I->sym_dets[sym] + (size_t)m * I->n_words, I->n_words, occ);
-    occ[n++] = 2 * (I->ints.n_o + j);
+    occ[n++] = 2 * (I->ints.n_o + j) + cspin(I, sym, m);
     return n;
 }
 
@@ -458,7 +469,7 @@ void orc_elements(const orc_inst *I, int64_t n, const int64_t *rows, const int64
                 int nb = det_occ(I->l2_dets + (size_t)C.l * W, W, B);
                 for (int m = 0; m < I->sym_ndet[R.sym]; ++m) {
                     memcpy(A, occ[R.sym] + (size_t)m * N, sizeof(int) * (size_t)N);
-                    A[N] = top;
+                    A[N] = top + cspin(I, R.sym, m);
                     if (N + 1 != nb) continue;
                     if (n_missing(A, N, B, nb) > 1) continue;
                     double ab; int nt;
@@ -473,11 +484,11 @@ void orc_elements(const orc_inst *I, int64_t n, const int64_t *rows, const int64
                 const int topc = 2 * (I->ints.n_o + C.j);
                 for (int m = 0; m < I->sym_ndet[R.sym]; ++m) {
                     memcpy(A, occ[R.sym] + (size_t)m * N, sizeof(int) * (size_t)N);
-                    A[N] = top;
+                    A[N] = top + cspin(I, R.sym, m);
                     for (int64_t k = c->off[m]; k < c->off[m + 1]; ++k) {
                         const int m2 = c->m2[k];
                         memcpy(B, occ[C.sym] + (size_t)m2 * N, sizeof(int) * (size_t)N);
-                        B[N] = topc;
+                        B[N] = topc + cspin(I, C.sym, m2);
                         double ab; int nt;
                         double v = slater_condon(&I->ints, A, B, N + 1, &ab, &nt);
                         double w = cr[(size_t)m * Sr + R.n] * cc[(size_t)m2 * Sc + C.n];

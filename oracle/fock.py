@@ -117,3 +117,19 @@ def basis_index(occ, n):
     for k in occ:
         idx |= 1 << (n - 1 - k)
     return idx
+
+
+def spin_squared(n):
+    """S^2 = S- S+ + Sz^2 + Sz on the Fock space of n spin-orbitals (spin of
+    mode k is k % 2, alpha = 0), with S+ = sum_k a+_{2k} a_{2k+1} and
+    Sz = (1/2) sum_k (n_{2k} - n_{2k+1}); returns (S^2, Sz)."""
+    a = _annihilators(n)
+    ad = [x.T.tocsr() for x in a]
+    dim = 1 << n
+    Sp = sp.csr_matrix((dim, dim))
+    Sz = sp.csr_matrix((dim, dim))
+    for k in range(n // 2):
+        Sp = Sp + ad[2 * k] @ a[2 * k + 1]
+        Sz = Sz + 0.5 * (ad[2 * k] @ a[2 * k] - ad[2 * k + 1] @ a[2 * k + 1])
+    Sm = Sp.T.tocsr()
+    return (Sm @ Sp + Sz @ Sz + Sz).tocsr(), Sz.tocsr()

@@ -41,6 +41,7 @@ class TargetSym:
     irrep: int
     dets: np.ndarray      # uint64 [M, W]
     ci: np.ndarray        # float64 [M, S] row-major
+    cont_spin: np.ndarray = None   # int8 [M]: continuum spin per det (0 alpha, 1 beta); None: alpha
 
 
 @dataclass
@@ -563,6 +564,81 @@ def l2_spin_adapted(inst):
     out.l2_dets = np.array(dets, dtype=np.uint64).reshape(-1, W)
     out.l2_csf_start = np.array(starts, dtype=np.int32)
     out.l2_coef = np.array(coef, dtype=np.float64)
+    return out
+
+
+def _spin_flips(occ, to_alpha):
+    """Occupation lists reached by turning one electron of a singly occupied
+    orbital from beta to alpha (to_alpha) or from alpha to beta; the two
+    spin-orbitals 2k, 2k + 1 are adjacent, so every such ladder step has
+    sign +1 on ascending determinants."""
+    s = set(occ)
+    out = []
+    for k in sorted({o >> 1 for o in occ}):
+        src, dst = (2 * k + 1, 2 * k) if to_alpha else (2 * k, 2 * k + 1)
+        if src in s and dst not in s:
+            out.append(sorted((s - {src}) | {dst}))
+    return out
+
+
+def triplet_doublet(inst, n_states=None, seed=0):
+    """The instance with each target symmetry's states replaced by triplet
+    target states coupled with the continuum electron to doublets (total
+    S = M_S = 1/2), the coupling of triplet targets the paper's CSF-driven
+    build allows (Eq. 2): channel function
+        sqrt(2/3) |T, M=1> u_beta - sqrt(1/3) |T, M=0> u_alpha.
+    |T, 1> lies in the M_S = 1 determinants reached by turning one beta
+    electron of a singly occupied orbital of the symmetry's determinants
+    alpha, projected on S = 1 (the null space of S+ there), with seeded
+    orthonormal coefficients; |T, 0> = S- |T, 1> / sqrt(2). The continuum spin
+    is given per determinant: 1 (beta) for the M_S = 1 ones, 0 for the
+    M_S = 0 ones. Pure data: ladder operators on occupation lists."""
+    import scipy.linalg
+    rng = np.random.default_rng(seed)
+    W = inst.n_words
+    syms = []
+    for s in inst.syms:
+        m1, idx1 = [], {}
+        for d in s.dets:
+            for o in _spin_flips(det_to_occ(d), True):
+                if tuple(o) not in idx1:
+                    idx1[tuple(o)] = len(m1)
+                    m1.append(o)
+        if not m1:
+            raise ValueError("no M_S = 1 determinant reachable")
+        m2, idx2, sp_rows = [], {}, []
+        for c, o in enumerate(m1):
+            for o2 in _spin_flips(o, True):
+                if tuple(o2) not in idx2:
+                    idx2[tuple(o2)] = len(m2)
+                    m2.append(o2)
+                sp_rows.append((idx2[tuple(o2)], c))
+        Splus = np.zeros((len(m2), len(m1)))
+        for r, c in sp_rows:
+            Splus[r, c] += 1.0
+        Z = scipy.linalg.null_space(Splus) if len(m2) else np.eye(len(m1))
+        S = min(n_states or s.ci.shape[1], Z.shape[1])
+        if S < 1:
+            raise ValueError("no triplet in the M_S = 1 space")
+        Q, _ = np.linalg.qr(rng.standard_normal((Z.shape[1], S)))
+        c1 = Z @ Q
+        m0, idx0, sm_rows = [], {}, []
+        for c, o in enumerate(m1):
+            for o0 in _spin_flips(o, False):
+                if tuple(o0) not in idx0:
+                    idx0[tuple(o0)] = len(m0)
+                    m0.append(o0)
+                sm_rows.append((idx0[tuple(o0)], c))
+        Sminus = np.zeros((len(m0), len(m1)))
+        for r, c in sm_rows:
+            Sminus[r, c] += 1.0
+        c0 = Sminus @ c1 / math.sqrt(2.0)
+        dets = np.array([occ_to_det(o, W) for o in m1 + m0], dtype=np.uint64).reshape(-1, W)
+        ci = np.vstack([math.sqrt(2.0 / 3.0) * c1, -math.sqrt(1.0 / 3.0) * c0])
+        spin = np.concatenate([np.ones(len(m1), np.int8), np.zeros(len(m0), np.int8)])
+        syms.append(TargetSym(s.irrep, dets, np.ascontiguousarray(ci), spin))
+    out = Instance(**{f: getattr(inst, f) for f in inst.__dataclass_fields__})
+    out.syms = syms
     return out
 
 

@@ -14,15 +14,18 @@ import synth
 def uncontracted_functions(inst):
     """(N+1)-electron determinants of the uncontracted basis, in the order
     (symmetry i, target det m, continuum j) then L2 l; continuum electron
-    u_j = spin-orbital 2*(n_o + j), alpha, last."""
+    u_j = spin-orbital 2*(n_o + j) + sigma_m, last (sigma_m the determinant's
+    continuum spin, alpha unless given)."""
     funcs = []
     for s in inst.syms:
         a = s.irrep ^ inst.total_irrep
         j0, j1 = inst.cont_range(a)
+        spin = getattr(s, "cont_spin", None)
         for m in range(s.dets.shape[0]):
             occ = synth.det_to_occ(s.dets[m])
+            sig = 0 if spin is None else int(spin[m])
             for j in range(j0, j1):
-                funcs.append(occ + [2 * (inst.n_o + j)])
+                funcs.append(occ + [2 * (inst.n_o + j) + sig])
     for l in range(inst.n_l2):
         funcs.append(synth.det_to_occ(inst.l2_dets[l]))
     return funcs

@@ -451,3 +451,49 @@ def test_l2_csfs_equal_fock_space(kw):
     ref = Vm.T @ (HF @ Vm)
     assert got.shape == ref.shape
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+TD_MICROS = [dict(seed=1, n_o=3, n_elec=2, n_c=2), dict(seed=3, n_o=4, n_elec=2, n_c=1, n_irrep=2, n_states=2),
+             dict(seed=4, n_o=4, n_elec=4, n_c=1, n_states=3)]
+
+
+@pytest.mark.parametrize("kw", TD_MICROS)
+def test_triplet_doublet_channels_are_doublets(kw):
+    """The triplet-coupled channel functions of the test inputs are doublets:
+    S^2 v = 3/4 v and S_z v = 1/2 v in the Fock space, with the continuum
+    electron's spin taken from its determinant (the data the beta-continuum
+    parity rests on)."""
+    inst = synth.triplet_doublet(synth.micro(**kw), seed=7)
+    assert any(np.any(s.cont_spin == 1) for s in inst.syms)
+    n = 2 * inst.n_orb
+    S2, Sz = fock.spin_squared(n)
+    funcs = uncontracted_functions(inst)
+    T = contraction_matrix(inst)
+    Dc = inst.n_cont_rows()
+    V = np.zeros((1 << n, Dc))
+    for i, f in enumerate(funcs):
+        if i < T.shape[0] - inst.n_l2:
+            V[fock.basis_index(f, n)] += T[i, :Dc]
+    assert np.abs(V).max() > 0.1
+    np.testing.assert_allclose(S2 @ V, 0.75 * V, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(Sz @ V, 0.5 * V, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kw", TD_MICROS)
+def test_triplet_doublet_contracted_equals_fock_space(kw):
+    """Beta continuum electrons (doublet coupling of triplet targets): the
+    oracle's contracted matrix, from its build and from its sampled-element
+    path, equals T^T H T in the Fock space with each continuum electron at
+    2 (n_o + j) + sigma."""
+    inst = synth.triplet_doublet(synth.micro(**kw), seed=7)
+    Hf, _ = _fock_block(inst)
+    T = contraction_matrix(inst)
+    ref = T.T @ Hf @ T
+    O = oracle.Oracle(inst)
+    got = O.build()
+    assert got.shape == ref.shape == (inst.dim(), inst.dim())
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+    r, c = np.meshgrid(np.arange(inst.dim()), np.arange(inst.dim()), indexing="ij")
+    np.testing.assert_allclose(O.elements(r.ravel(), c.ravel())[0].reshape(got.shape), ref, rtol=0, atol=1e-13)
+    # the spin-flip exchange elements are there: channels of different continuum spin couple
+    assert np.abs(ref[:inst.n_cont_rows(), :inst.n_cont_rows()]).max() > 0.1
