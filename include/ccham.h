@@ -190,6 +190,24 @@ cch_status cch_add_target_symmetry(cch_ctx *ctx, int32_t irrep, int32_t n_det,
                                    int32_t n_states, const double *ci, int32_t flags,
                                    int32_t *sym_id);
 
+/* One target symmetry whose continuum functions carry a continuum electron of
+ * either spin (Eq. 1 with spin-coupled channels; the CSF-driven build of
+ * Sec. 2 couples e.g. triplet target states with the continuum electron to
+ * doublets: sqrt(2/3) |T, 1> u_beta - sqrt(1/3) |T, 0> u_alpha). As
+ * cch_add_target_symmetry, with cont_spin[n_det] the continuum spin of each
+ * determinant's function (0 alpha, 1 beta): a continuum function is
+ * sum_m c_imn |D_m u_j sigma_m>. The total M_S stays +1/2, so a determinant
+ * with a beta continuum electron has N/2 + 1 alpha and N/2 - 1 beta
+ * electrons, one with an alpha continuum electron N/2 of each. Pairs of
+ * determinants with different continuum spins couple through the exchange
+ * integrals (P j'|j Q) of spin-flip single substitutions; the L2 functions
+ * (M_S = +1/2) are unchanged. Host pointers unless flags holds
+ * CCH_MEM_DEVICE. CCH_E_INPUT for a spin other than 0 or 1 or an alpha count
+ * that does not match the spin; CCH_E_INVALID_ARG for cont_spin == NULL. */
+cch_status cch_add_target_symmetry_spin(cch_ctx *ctx, int32_t irrep, int32_t n_det, int32_t n_words,
+                                        const uint64_t *dets, const int8_t *cont_spin, int32_t n_states,
+                                        const double *ci, int32_t flags, int32_t *sym_id);
+
 /* One target symmetry whose CSFs (Eq. 2) are fixed combinations of
  * determinants: CSF m is sum_t coef[t] |dets[t]> over the terms
  * t in [csf_start[m], csf_start[m+1]) (csf_start[0] = 0, every CSF at least

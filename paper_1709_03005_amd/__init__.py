@@ -45,7 +45,7 @@ CCH_PAIRS_L2_TARGET = 2
 
 EXPORTS = [
     "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
-    "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_l2_csf", "cch_set_target_energies", "cch_plan", "cch_build",
+    "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_spin", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_l2_csf", "cch_set_target_energies", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_elements", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
     "cch_batch_time", "cch_batch_info", "cch_batch_destroy", "cch_batch_last_error",
@@ -102,6 +102,7 @@ _SIG = {
     "cch_set_integrals": (i32, [P, P, P, P, P, P, C.c_double, i32]),
     "cch_set_integrals_packed": (i32, [P, P, P, P, P, P, C.c_double, i32]),
     "cch_add_target_symmetry": (i32, [P, i32, i32, i32, P, i32, P, i32, C.POINTER(i32)]),
+    "cch_add_target_symmetry_spin": (i32, [P, i32, i32, i32, P, P, i32, P, i32, C.POINTER(i32)]),
     "cch_add_target_symmetry_csf": (i32, [P, i32, i32, P, i32, P, P, i32, P, i32, P]),
     "cch_set_l2": (i32, [P, i32, i32, P, i32]),
     "cch_set_l2_csf": (i32, [P, i32, P, i32, P, P, i32]),
@@ -226,7 +227,9 @@ class Context:
         flags = ps[0][1]
         self._ck(lib.cch_set_integrals_packed(self.h, *[p[0] for p in ps], float(e_core), flags))
 
-    def add_target_symmetry(self, irrep, dets, ci) -> int:
+    def add_target_symmetry(self, irrep, dets, ci, cont_spin=None) -> int:
+        """cch_add_target_symmetry, or cch_add_target_symmetry_spin when
+        cont_spin (0 alpha / 1 beta per determinant) is given."""
         pd, fd, kd = _arr(dets, np.uint64)
         pc, fc, kc = _arr(ci, np.float64)
         n_det, n_words = kd.shape
@@ -234,8 +237,18 @@ class Context:
             # the library reads n_det rows of ci: refuse a shorter array here
             raise CchError(CCH_E_INVALID_ARG, f"ci has shape {tuple(kc.shape)}, expected ({n_det}, n_states)")
         sid = i32()
-        self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
-                                             int(kc.shape[1]), pc, fd, C.byref(sid)))
+        if cont_spin is None:
+            self._ck(lib.cch_add_target_symmetry(self.h, int(irrep), int(n_det), int(n_words), pd,
+                                                 int(kc.shape[1]), pc, fd, C.byref(sid)))
+        else:
+            sp = np.ascontiguousarray(cont_spin, dtype=np.int8)
+            if sp.shape != (n_det,):
+                raise CchError(CCH_E_INVALID_ARG, f"cont_spin has shape {sp.shape}, expected ({n_det},)")
+            if fd != CCH_MEM_HOST:
+                raise CchError(CCH_E_INVALID_ARG, "continuum spins are passed with host determinants")
+            self._ck(lib.cch_add_target_symmetry_spin(self.h, int(irrep), int(n_det), int(n_words), pd,
+                                                      sp.ctypes.data_as(C.c_void_p), int(kc.shape[1]), pc, fd,
+                                                      C.byref(sid)))
         self._ndet = getattr(self, "_ndet", []) + [int(n_det)]
         return sid.value
 
@@ -609,7 +622,7 @@ def from_instance(inst, device=0, stream=None, plan=True, target_energies=None, 
     else:
         ctx.set_integrals(inst.h, inst.tttt, inst.tttc, inst.ttcc, inst.tctc, inst.e_core)
     for s in inst.syms:
-        ctx.add_target_symmetry(s.irrep, s.dets, s.ci)
+        ctx.add_target_symmetry(s.irrep, s.dets, s.ci, getattr(s, "cont_spin", None))
     if getattr(inst, "l2_csf_start", None) is not None:
         ctx.set_l2_csf(inst.l2_csf_start, inst.l2_dets, inst.l2_coef)
     elif inst.l2_dets is not None and len(inst.l2_dets):

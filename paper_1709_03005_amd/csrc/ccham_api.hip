@@ -32,9 +32,9 @@ hipError_t launch_bucket(PairList pl, int64_t n, const int32_t *pqidx, int n_o, 
                          int64_t *tmp, int64_t *d0, hipStream_t st);
 hipError_t launch_gamma(int W, PairList pl, const int64_t *start, const int64_t *count,
                         const int64_t *sorted, const int64_t *d0, int M0, const int32_t *slotP,
-                        const int32_t *slotQ, int n_slot, const uint64_t *da, const double *ca, int Sa,
-                        const double *cb, int Sb, int nrows, const int32_t *rn, const int32_t *rn2,
-                        double *At, hipStream_t st);
+                        const int32_t *slotQ, int n_slot, const uint64_t *da, const int8_t *spa, const int8_t *spb,
+                        const double *ca, int Sa, const double *cb, int Sb, int nrows, const int32_t *rn,
+                        const int32_t *rn2, double *At, hipStream_t st);
 hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int n_cont,
                            const int32_t *slotP, const int32_t *slotQ, int n_slot, int ja0, int nca,
                            int jb0, int ncb, double *B, hipStream_t st, const PackedCC *pk);
@@ -58,22 +58,6 @@ hipError_t launch_slices(const double *At, int nrows, const double *B, int K, in
                          double *sigA, __bf16 *SA, double *sigB, __bf16 *SB, hipStream_t st);
 hipError_t launch_expand_bf16split(const __bf16 *SA, const __bf16 *SB, const double *sigA, const double *sigB,
                                    int s, int nrows, int N, int ldk, const ExpandEpi &ep, hipStream_t st);
-struct Class4Args {
-    const uint64_t *tdets;
-    const double *ci;
-    int S;
-    const double *h;
-    const double *tttc;
-    int n_o, n_orb, n_cont;
-    int ja0, nc;
-    const int64_t *row_off, *row_cnt;
-    PairList pl;
-    double *H;
-    int64_t ld;
-    int64_t row_l2;
-    int64_t col0;
-    int pairs_per_chunk;
-};
 hipError_t launch_class4(int W, const Class4Args &a, int n_l2, hipStream_t st);
 struct L2Args {
     const uint64_t *dets;
@@ -96,11 +80,6 @@ struct GemmTask {
 };
 struct L2Task {
     L2Args a;
-    int64_t first;
-};
-struct C4Task {
-    Class4Args a;
-    int n_l2, jtiles;
     int64_t first;
 };
 int expand_tiles(int nrows, int N, int bm);
@@ -213,6 +192,7 @@ struct SymInfo {
     int irrep = 0, M = 0, S = 0, nc = 0, ja0 = 0;
     int64_t row0 = 0, e_off = 0;   // first row; first of its states' target energies
     uint64_t *d_dets = nullptr;
+    int8_t *d_cspin = nullptr;   // continuum spin per det (0 alpha, 1 beta); nullptr: alpha throughout
     double *d_ci = nullptr;
     std::vector<uint64_t> h_dets;
 };
@@ -597,7 +577,7 @@ cch_status cch_set_integrals_packed(cch_ctx *c, const double *h, const double *t
 }
 
 static cch_status check_dets(cch_ctx *c, const std::vector<uint64_t> &d, int n, int nelec, int na, int irrep,
-                             const char *what)
+                             const char *what, const int8_t *spin = nullptr)
 {
     const int W = c->W, nso = 2 * c->n_o;
     for (int i = 0; i < n; ++i) {
@@ -620,7 +600,9 @@ static cch_status check_dets(cch_ctx *c, const std::vector<uint64_t> &d, int n, 
             }
         }
         if (ne != nelec) return fail(c, CCH_E_INPUT, "%s det %d has %d electrons, expected %d", what, i, ne, nelec);
-        if (nal != na) return fail(c, CCH_E_INPUT, "%s det %d has %d alpha electrons, expected %d", what, i, nal, na);
+        const int want = na + (spin ? spin[i] : 0);   // a beta continuum electron: one more alpha in the target
+        if (nal != want)
+            return fail(c, CCH_E_INPUT, "%s det %d has %d alpha electrons, expected %d", what, i, nal, want);
         if (ir != irrep) return fail(c, CCH_E_INPUT, "%s det %d has irrep %d, expected %d", what, i, ir, irrep);
     }
     // distinct
@@ -639,8 +621,9 @@ static cch_status check_dets(cch_ctx *c, const std::vector<uint64_t> &d, int n, 
     return CCH_OK;
 }
 
-cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int32_t n_words, const uint64_t *dets,
-                                   int32_t n_states, const double *ci, int32_t flags, int32_t *sym_id)
+static cch_status add_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int32_t n_words, const uint64_t *dets,
+                               const int8_t *cont_spin, int32_t n_states, const double *ci, int32_t flags,
+                               int32_t *sym_id)
 {
     if (!c) return CCH_E_INVALID_ARG;
     if (!c->have_orb) return fail(c, CCH_E_STATE, "set orbitals first");
@@ -652,6 +635,17 @@ cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int
     if (n_states > 256) return fail(c, CCH_E_LIMIT, "n_states > 256");
     std::vector<uint64_t> hd((size_t)n_det * n_words);
     TRY(host_copy(c, hd.data(), dets, hd.size() * 8, flags));
+    std::vector<int8_t> hs;
+    bool beta = false;
+    if (cont_spin) {
+        hs.resize((size_t)n_det);
+        TRY(host_copy(c, hs.data(), cont_spin, hs.size(), flags));
+        for (int m = 0; m < n_det; ++m) {
+            if (hs[m] != 0 && hs[m] != 1)
+                return fail(c, CCH_E_INPUT, "continuum spin of det %d is %d (0 alpha, 1 beta)", m, (int)hs[m]);
+            beta |= hs[m] == 1;
+        }
+    }
     int nelec = 0;
     for (int w = 0; w < n_words; ++w) nelec += popc64(hd[w]);
     if (c->n_elec < 0) {
@@ -660,7 +654,7 @@ cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int
     } else if (nelec != c->n_elec) {
         return fail(c, CCH_E_INPUT, "det 0 has %d electrons, expected %d", nelec, c->n_elec);
     }
-    TRY(check_dets(c, hd, n_det, nelec, nelec / 2, irrep, "target"));
+    TRY(check_dets(c, hd, n_det, nelec, nelec / 2, irrep, "target", beta ? hs.data() : nullptr));
     std::vector<double> hc((size_t)n_det * n_states);
     TRY(host_copy(c, hc.data(), ci, hc.size() * 8, flags));
     for (double v : hc)
@@ -673,11 +667,29 @@ cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int
     TRY(dalloc(c, &s.d_ci, hc.size()));
     HIPCK(c, hipMemcpy(s.d_dets, hd.data(), hd.size() * 8, hipMemcpyHostToDevice));
     HIPCK(c, hipMemcpy(s.d_ci, hc.data(), hc.size() * 8, hipMemcpyHostToDevice));
+    if (beta) {
+        TRY(dalloc(c, &s.d_cspin, hs.size()));
+        HIPCK(c, hipMemcpy(s.d_cspin, hs.data(), hs.size(), hipMemcpyHostToDevice));
+    }
     s.h_dets = std::move(hd);
     c->n_elec = nelec;
     c->syms.push_back(std::move(s));
     if (sym_id) *sym_id = (int32_t)c->syms.size() - 1;
     return CCH_OK;
+}
+
+cch_status cch_add_target_symmetry(cch_ctx *c, int32_t irrep, int32_t n_det, int32_t n_words, const uint64_t *dets,
+                                   int32_t n_states, const double *ci, int32_t flags, int32_t *sym_id)
+{
+    return add_symmetry(c, irrep, n_det, n_words, dets, nullptr, n_states, ci, flags, sym_id);
+}
+
+cch_status cch_add_target_symmetry_spin(cch_ctx *c, int32_t irrep, int32_t n_det, int32_t n_words,
+                                        const uint64_t *dets, const int8_t *cont_spin, int32_t n_states,
+                                        const double *ci, int32_t flags, int32_t *sym_id)
+{
+    if (c && !cont_spin) return fail(c, CCH_E_INVALID_ARG, "no continuum spins");
+    return add_symmetry(c, irrep, n_det, n_words, dets, cont_spin, n_states, ci, flags, sym_id);
 }
 
 cch_status cch_add_target_symmetry_csf(cch_ctx *c, int32_t irrep, int32_t n_csf, const int32_t *csf_start,
@@ -1045,6 +1057,7 @@ static Class4Args class4_args(cch_ctx *c, const LtPlan &L)
 {
     const SymInfo &s = c->syms[L.sym];
     Class4Args a{};
+    a.cspin = s.d_cspin;
     a.tdets = s.d_dets;
     a.ci = s.d_ci;
     a.S = s.S;
@@ -1154,8 +1167,8 @@ static cch_status enqueue_pre(cch_ctx *c, hipStream_t st, bool ev, bool fan, boo
                                p.d_cursor, p.d_sorted, p.d_tmp, p.d_d0, s));
         const int M0 = (sa.irrep == sb.irrep) ? sa.M : 0;
         HIPCK(c, launch_gamma(c->W, p.pr.pl, p.d_start, p.d_count, p.d_sorted, p.d_d0, M0, p.d_slotP, p.d_slotQ,
-                              p.n_slot, sa.d_dets, sa.d_ci, sa.S, sb.d_ci, sb.S, p.nrows, p.d_rn, p.d_rn2, p.d_At,
-                              s));
+                              p.n_slot, sa.d_dets, sa.d_cspin, sb.d_cspin, sa.d_ci, sa.S, sb.d_ci, sb.S, p.nrows,
+                              p.d_rn, p.d_rn2, p.d_At, s));
     }
     HIPCK(c, f.end());
     EVREC(2);

@@ -248,6 +248,32 @@ struct TrdVec {
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for
 // c < Dc (every row), R[r][c - Dc] for r < Dc <= c, and the L2 block's rows
 // as CSR (columns relative to Dc, ascending)
+// class 4 of one target symmetry (k_class4.hip)
+struct Class4Args {
+    const uint64_t *tdets;   // target dets of the symmetry [M][W]
+    const int8_t *cspin;     // continuum spin per target det (0 alpha, 1 beta); nullptr: alpha
+    const double *ci;        // [M][S]
+    int S;
+    const double *h;         // [n_orb][n_orb]
+    const double *tttc;      // [n_o][n_o][n_o][n_cont]
+    int n_o, n_orb, n_cont;
+    int ja0, nc;             // continuum range of the symmetry
+    const int64_t *row_off, *row_cnt;   // L2 x target pairs per L2 row
+    PairList pl;
+    double *H;
+    int64_t ld;
+    int64_t row_l2;          // first L2 row of the matrix
+    int64_t col0;            // first column of the symmetry block
+    int pairs_per_chunk;
+};
+
+// one (instance, symmetry) block of the persistent class-4 launch
+struct C4Task {
+    Class4Args a;
+    int n_l2, jtiles;
+    int64_t first;   // first global work item of this block
+};
+
 // continuum orbitals per class-4 workgroup (the j block of one L2 row)
 constexpr int C4_JB = 512;
 

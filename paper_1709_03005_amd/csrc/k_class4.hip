@@ -9,10 +9,11 @@
 //     out[n][j] = sum_t (coef_t c_{m_t n}) X_t[j]
 // where each term t is a row of the one-electron integrals h[H][j] or of
 // the (tt|tc) integrals (ab|c j), read for a tile of j:
-//   single substitution (chi_l = D_m + h, h alpha), sign s:
-//       s [ h_{hj} + sum_{k in D_m} (KK|Hj) - sum_{k in D_m, alpha} (KH|Kj) ]
+//   single substitution (chi_l = D_m + h, h of the continuum spin sigma_m), sign s:
+//       s [ h_{hj} + sum_{k in D_m} (KK|Hj) - sum_{k in D_m, spin sigma_m} (KH|Kj) ]
 //   double (chi_l = D_m - p + h1 + h2), sign s:
-//       s [ (P H1|H2 j) d(sp,sh1) d(alpha,sh2) - (P H2|H1 j) d(sp,sh2) d(alpha,sh1) ]
+//       s [ (P H1|H2 j) d(sp,sh1) d(sigma_m,sh2) - (P H2|H1 j) d(sp,sh2) d(sigma_m,sh1) ]
+// (sigma_m the continuum spin given with D_m, alpha unless stated).
 // The product runs on the FP64 matrix cores: for a block of 64 terms the
 // A operand is (coef_t c_{m_t n}) (terms x states, staged in LDS from the CI
 // rows) and the B operand the gathered integral rows X_t[j] (terms x j),
@@ -27,22 +28,6 @@
 
 namespace cch {
 
-struct Class4Args {
-    const uint64_t *tdets;   // target dets of the symmetry [M][W]
-    const double *ci;        // [M][S]
-    int S;
-    const double *h;         // [n_orb][n_orb]
-    const double *tttc;      // [n_o][n_o][n_o][n_cont]
-    int n_o, n_orb, n_cont;
-    int ja0, nc;             // continuum range of the symmetry
-    const int64_t *row_off, *row_cnt;   // L2 x target pairs per L2 row
-    PairList pl;
-    double *H;
-    int64_t ld;
-    int64_t row_l2;          // first L2 row of the matrix
-    int64_t col0;            // first column of the symmetry block
-    int pairs_per_chunk;
-};
 
 constexpr int C4_TERMS = 1024;
 constexpr int C4_TB = 64;          // terms per MFMA block (16 k-steps)
@@ -86,21 +71,23 @@ __device__ __forceinline__ void class4_row(const Class4Args &a, int l, int jblk,
                 const int64_t pi = p0 + c0 + threadIdx.x;
                 const int deg = a.pl.deg[pi];
                 const uint64_t lab = a.pl.label[pi];
+                const int sg = a.cspin ? a.cspin[a.pl.y[pi]] : 0;   // continuum spin
                 if (deg == 1) {
                     const int h = lab_field(lab, 1);
-                    if ((h & 1) == 0) {
+                    if ((h & 1) == sg) {
                         const uint64_t *d = a.tdets + (size_t)a.pl.y[pi] * W;
-                        int ne = 0, na = 0;
+                        const uint64_t mask = sg ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+                        int ne = 0, ns = 0;
 #pragma unroll
                         for (int w = 0; w < W; ++w) {
                             ne += __popcll(d[w]);
-                            na += __popcll(d[w] & 0x5555555555555555ull);
+                            ns += __popcll(d[w] & mask);
                         }
-                        cnt = 1 + ne + na;
+                        cnt = 1 + ne + ns;
                     }
                 } else {
                     const int pt = lab_field(lab, 0), h1 = lab_field(lab, 1), h2 = lab_field(lab, 2);
-                    cnt = ((pt & 1) == (h1 & 1) && (h2 & 1) == 0) + ((pt & 1) == (h2 & 1) && (h1 & 1) == 0);
+                    cnt = ((pt & 1) == (h1 & 1) && (h2 & 1) == sg) + ((pt & 1) == (h2 & 1) && (h1 & 1) == sg);
                 }
             }
             int incl = cnt;
@@ -120,11 +107,12 @@ __device__ __forceinline__ void class4_row(const Class4Args &a, int l, int jblk,
             const uint64_t lab = a.pl.label[pi];
             const double s = (double)a.pl.phase[pi];
             const int m = a.pl.y[pi];
+            const int sg = a.cspin ? a.cspin[m] : 0;
             int o = poff[threadIdx.x];
             const size_t n_o = a.n_o;
             if (deg == 1) {
                 const int h = lab_field(lab, 1);
-                if ((h & 1) == 0) {
+                if ((h & 1) == sg) {
                     const int H = h >> 1;
                     trow[o] = a.h + (size_t)H * a.n_orb + a.n_o + a.ja0;
                     tcoef[o] = s;
@@ -140,7 +128,7 @@ __device__ __forceinline__ void class4_row(const Class4Args &a, int l, int jblk,
                             trow[o] = a.tttc + ((K * n_o + K) * n_o + H) * a.n_cont + a.ja0;
                             tcoef[o] = s;
                             tm[o++] = m;
-                            if ((k & 1) == 0) {
+                            if ((k & 1) == sg) {
                                 trow[o] = a.tttc + ((K * n_o + H) * n_o + K) * a.n_cont + a.ja0;
                                 tcoef[o] = -s;
                                 tm[o++] = m;
@@ -151,12 +139,12 @@ __device__ __forceinline__ void class4_row(const Class4Args &a, int l, int jblk,
             } else {
                 const int pt = lab_field(lab, 0), h1 = lab_field(lab, 1), h2 = lab_field(lab, 2);
                 const size_t P = pt >> 1, H1 = h1 >> 1, H2 = h2 >> 1;
-                if ((pt & 1) == (h1 & 1) && (h2 & 1) == 0) {
+                if ((pt & 1) == (h1 & 1) && (h2 & 1) == sg) {
                     trow[o] = a.tttc + ((P * n_o + H1) * n_o + H2) * a.n_cont + a.ja0;
                     tcoef[o] = s;
                     tm[o++] = m;
                 }
-                if ((pt & 1) == (h2 & 1) && (h1 & 1) == 0) {
+                if ((pt & 1) == (h2 & 1) && (h1 & 1) == sg) {
                     trow[o] = a.tttc + ((P * n_o + H2) * n_o + H1) * a.n_cont + a.ja0;
                     tcoef[o] = -s;
                     tm[o++] = m;
@@ -248,12 +236,6 @@ hipError_t launch_class4(int W, const Class4Args &a, int n_l2, hipStream_t st)
 }
 
 // persistent form over many (instance, symmetry) blocks with the same word count
-struct C4Task {
-    Class4Args a;
-    int n_l2, jtiles;
-    int64_t first;
-};
-
 template <int W>
 __global__ __launch_bounds__(256) void k_class4_batched(const C4Task *__restrict__ tasks, int ntask, int64_t total)
 {

@@ -26,12 +26,16 @@ __global__ __launch_bounds__(256) void k_pair_values(TgtInts I, const uint64_t *
     int h[2] = {lab_field(lab, 1), lab_field(lab, 3)};
     int p[2] = {lab_field(lab, 0), lab_field(lab, 2)};
     uint64_t A[W], B[W];
+    int dm = 0;   // alpha electrons of the bra minus those of the ket
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         A[w] = da[(size_t)pl.x[i] * W + w];
         B[w] = db[(size_t)pl.y[i] * W + w];
+        dm += __popcll(A[w] & 0x5555555555555555ull) - __popcll(B[w] & 0x5555555555555555ull);
     }
-    hv[i] = sc_value<W>(I, A, B, deg, h, p, pl.phase[i]);
+    // target determinants of different M_S (given with continuum electrons of
+    // different spin): the spin-free H_T has no element between them
+    hv[i] = dm ? 0.0 : sc_value<W>(I, A, B, deg, h, p, pl.phase[i]);
 }
 
 hipError_t launch_pair_values(int W, TgtInts I, const uint64_t *da, const uint64_t *db, PairList pl,
@@ -238,7 +242,9 @@ hipError_t launch_bucket(PairList pl, int64_t n, const int32_t *pqidx, int n_o, 
 // Gamma: one workgroup per label slot k = (P, Q).
 //   J[r] = sum over degree-1 pairs with label (P,Q) of s c_a[m][n] c_b[m'][n']
 //          (+ for P == Q the degree-0 pairs weighted by the occupation of P)
-//   K[r] = the same restricted to alpha-spin excitations / alpha occupation.
+//   K[r] = the exchange weights: excitations from a hole of the bra's continuum
+//          spin to a particle of the ket's (alpha -> alpha when both continuum
+//          electrons are alpha) / occupation of P with the continuum spin.
 // Output Kt-major: At[k][r] = J, At[n_slot + k][r] = K.
 // ---------------------------------------------------------------------------
 constexpr int GAM_BATCH = 16;
@@ -252,6 +258,8 @@ __global__ __launch_bounds__(256) void k_gamma(PairList pl, const int64_t *__res
                                                const int32_t *__restrict__ slotP,
                                                const int32_t *__restrict__ slotQ, int n_slot,
                                                const uint64_t *__restrict__ da,
+                                               const int8_t *__restrict__ spa,
+                                               const int8_t *__restrict__ spb,
                                                const double *__restrict__ ca, int Sa,
                                                const double *__restrict__ cb, int Sb, int nrows,
                                                const int32_t *__restrict__ rn,
@@ -283,18 +291,26 @@ __global__ __launch_bounds__(256) void k_gamma(PairList pl, const int64_t *__res
                 if (pidx < 0) {
                     // no identical ket for this bra row
                 } else if (e < n1) {
+                    // particle p (in the bra), hole q (in the ket); the Coulomb weight
+                    // needs equal continuum spins and a spin-conserving excitation, the
+                    // exchange weight a particle of the ket's continuum spin and a hole
+                    // of the bra's (the spin-flip pairs of doublet-coupled triplets)
                     const int s = pl.phase[pidx];
-                    const int sp = lab_field(pl.label[pidx], 0) & 1;
-                    a = (double)s;
-                    b = sp == 0 ? (double)s : 0.0;
+                    const uint64_t lab = pl.label[pidx];
+                    const int sp = lab_field(lab, 0) & 1, sq = lab_field(lab, 1) & 1;
+                    const int sx = spa ? spa[pl.x[pidx]] : 0, sy = spb ? spb[pl.y[pidx]] : 0;
+                    a = (sx == sy && sp == sq) ? (double)s : 0.0;
+                    b = (sp == sy && sq == sx) ? (double)s : 0.0;
                 } else {
-                    // occupation of spatial orbital P in the bra determinant
+                    // occupation of spatial orbital P in the bra determinant (both spins;
+                    // the continuum spin's for the exchange weight)
                     const uint64_t *d = da + (size_t)pl.x[pidx] * W;
                     const int ka = 2 * P, kb = 2 * P + 1;
                     const int oa = (int)((d[ka >> 6] >> (ka & 63)) & 1ull);
                     const int ob = (int)((d[kb >> 6] >> (kb & 63)) & 1ull);
+                    const int sx = spa ? spa[pl.x[pidx]] : 0;
                     a = (double)(oa + ob);
-                    b = (double)oa;
+                    b = (double)(sx ? ob : oa);
                 }
                 wj[t] = a;
                 wk[t] = b;
@@ -341,17 +357,18 @@ __global__ __launch_bounds__(256) void k_gamma(PairList pl, const int64_t *__res
 
 hipError_t launch_gamma(int W, PairList pl, const int64_t *start, const int64_t *count,
                         const int64_t *sorted, const int64_t *d0, int M0, const int32_t *slotP, const int32_t *slotQ, int n_slot,
-                        const uint64_t *da, const double *ca, int Sa, const double *cb, int Sb,
-                        int nrows, const int32_t *rn, const int32_t *rn2, double *At, hipStream_t st)
+                        const uint64_t *da, const int8_t *spa, const int8_t *spb, const double *ca, int Sa,
+                        const double *cb, int Sb, int nrows, const int32_t *rn, const int32_t *rn2, double *At,
+                        hipStream_t st)
 {
     if (n_slot <= 0 || nrows <= 0) return hipSuccess;
     const size_t shm = sizeof(double) * GAM_BATCH * (size_t)(Sa + Sb);
     const dim3 g(n_slot), b(256);
     switch (W) {
-    case 1: hipLaunchKernelGGL((k_gamma<1>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
-    case 2: hipLaunchKernelGGL((k_gamma<2>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
-    case 3: hipLaunchKernelGGL((k_gamma<3>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
-    case 4: hipLaunchKernelGGL((k_gamma<4>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 1: hipLaunchKernelGGL((k_gamma<1>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, spa, spb, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 2: hipLaunchKernelGGL((k_gamma<2>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, spa, spb, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 3: hipLaunchKernelGGL((k_gamma<3>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, spa, spb, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
+    case 4: hipLaunchKernelGGL((k_gamma<4>), g, b, shm, st, pl, start, count, sorted, d0, M0, slotP, slotQ, n_slot, da, spa, spb, ca, Sa, cb, Sb, nrows, rn, rn2, At); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
