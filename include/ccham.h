@@ -438,12 +438,13 @@ typedef struct {
  * device (Sec. 3.2: often all eigenvectors are required, and a dense
  * diagonaliser serves then). A = NULL: the built matrix (n = 0 or D; not
  * for CCH_PLAN_SPARSE_L2 contexts, CCH_E_STATE); else A is n x n row-major
- * with leading dimension lda >= n, both triangles read. w[n] receives the
+ * with leading dimension lda >= n, both triangles read ((A + A^T)/2 is
+ * used). w[n] receives the
  * eigenvalues ascending; V (may be NULL: eigenvalues only) receives the
  * orthonormal eigenvectors as rows, eigenvector e at V + e * ldv (ldv >= n).
  * Householder tridiagonalisation, bisection on Sturm counts, twisted
  * factorisations with modified Gram-Schmidt inside clusters of eigenvalues
- * closer than 1e-5 ||T||, and the back-transformation in blocks of 32
+ * closer than 1e-5 ||T||, and the back-transformation in blocks of 64
  * reflectors on FP64 MFMA. Work space about 3 n^2 doubles of device memory
  * (n^2 for eigenvalues only). A, w and V are host memory, or device memory
  * with CCH_MEM_DEVICE. info may be NULL. CCH_E_INPUT for a non-finite

@@ -120,7 +120,7 @@ hipError_t launch_sparse_row_norms(const SparseMat &S, int D, double *rho, hipSt
 // full-spectrum eigensolver
 hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
                            const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
-                           hipStream_t st);
+                           hipStream_t st, double *P = nullptr, int64_t p_cap = 0);
 hipError_t launch_trd_step(double *A, int64_t lda, int n, int j, const TrdVec &V, hipStream_t st);
 hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, int n, const int32_t *bs,
                                   const int32_t *bm, const int32_t *bk, double lo, double hi, double pivmin,
@@ -131,6 +131,7 @@ hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int
 hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, hipStream_t st);
 hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, int nb, double *Vb, hipStream_t st);
 hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st);
+hipError_t launch_symmetrize(double *W, int64_t ld, int n, hipStream_t st);
 hipError_t launch_transpose_sq(const double *Z, int64_t ldz, int n, double *out, int64_t ldo, hipStream_t st);
 int64_t l2csr_scratch(int D, int Dc);
 hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, int64_t ldv, int b, double *W,
@@ -1826,7 +1827,7 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
     hipStream_t st = c->stream;
     const bool dev = flags & CCH_MEM_DEVICE;
     const int64_t ld = ((int64_t)n + 31) / 32 * 32;
-    const int NB = 32;
+    const int NB = 64;   // reflectors per block of the back-transformation (at most 64: k_larft)
     std::vector<void *> tmp;
     auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
     auto al = [&](void **p, size_t bytes) -> bool {
@@ -1835,15 +1836,18 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
         return true;
     };
     double *W = nullptr, *Z = nullptr, *S = nullptr, *vec = nullptr, *Vb = nullptr, *G = nullptr, *T = nullptr,
-           *w_d = nullptr;
+           *w_d = nullptr, *Pk = nullptr;
+    // split-K partials of the back-transformation's long products
+    const int64_t p_cap = std::max<int64_t>((int64_t)16 * NB * n, (int64_t)64 * NB * NB);
     const bool want_v = V != nullptr;
     bool ok = al((void **)&W, 8 * (size_t)n * ld) && al((void **)&vec, 8 * (size_t)10 * n + 64) &&
               al((void **)&w_d, 8 * (size_t)n);
     if (ok && want_v)
-        // S: the twisted-factorisation scratch, then two 32 x n products of the back-transformation
+        // S: the twisted-factorisation scratch, then two NB x n products of the back-transformation
         ok = al((void **)&Z, 8 * (size_t)n * ld) &&
              al((void **)&S, 8 * (size_t)std::max<int64_t>((int64_t)n * ld, (int64_t)2 * NB * n)) &&
-             al((void **)&Vb, 8 * (size_t)n * NB) && al((void **)&G, 8 * NB * NB) && al((void **)&T, 8 * NB * NB);
+             al((void **)&Vb, 8 * (size_t)n * NB) && al((void **)&G, 8 * NB * NB) && al((void **)&T, 8 * NB * NB) &&
+             al((void **)&Pk, 8 * (size_t)p_cap);
     if (!ok) {
         cleanup();
         return fail(c, CCH_E_OOM, "eigensolver work space for n = %d", n);
@@ -1867,12 +1871,13 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
         (void)hipEventDestroy(e2);
         (void)hipEventDestroy(e3);
     };
-    // the matrix into the work array (both triangles are read)
+    // the matrix into the work array, made exactly symmetric ((A + A^T) / 2)
     if (own)
         EGK(hipMemcpy2DAsync(W, 8 * ld, c->d_H, 8 * c->ld, 8 * (size_t)n, n, hipMemcpyDeviceToDevice, st));
     else
         EGK(hipMemcpy2DAsync(W, 8 * ld, A, 8 * lda, 8 * (size_t)n, n,
                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    EGK(launch_symmetrize(W, ld, n, st));
     EGK(hipEventRecord(e0, st));
     TrdVec tv{vec, vec + n, vec + 2 * (int64_t)n, vec + 3 * (int64_t)n, vec + 4 * (int64_t)n,
               vec + 5 * (int64_t)n, vec + 6 * (int64_t)n, vec + 7 * (int64_t)n};
@@ -1991,9 +1996,9 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
             double *Zs = Z + (int64_t)(j0 + 1) * ld;
             double *Wt = S, *W2 = S + (int64_t)NB * n;   // the twisted-factorisation scratch is free now
             EGK(launch_copy_reflectors(W, ld, n, j0, nb, Vb, st));
-            EGK(launch_eig_gemm(nb, nb, m, 1.0, Vb, 1, nb, Vb, nb, 1, 0.0, G, nb, st));
+            EGK(launch_eig_gemm(nb, nb, m, 1.0, Vb, 1, nb, Vb, nb, 1, 0.0, G, nb, st, Pk, p_cap));
             EGK(launch_larft(G, tv.tau + j0, nb, T, st));
-            EGK(launch_eig_gemm(nb, n, m, 1.0, Vb, 1, nb, Zs, ld, 1, 0.0, Wt, n, st));
+            EGK(launch_eig_gemm(nb, n, m, 1.0, Vb, 1, nb, Zs, ld, 1, 0.0, Wt, n, st, Pk, p_cap));
             EGK(launch_eig_gemm(nb, n, nb, 1.0, T, nb, 1, Wt, n, 1, 0.0, W2, n, st));
             EGK(launch_eig_gemm(m, n, nb, -1.0, Vb, nb, 1, W2, n, 1, 1.0, Zs, ld, st));
         }

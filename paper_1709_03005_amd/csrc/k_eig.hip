@@ -11,7 +11,7 @@
 //   2. Eigenvalues of T by bisection on Sturm counts, one thread each.
 //   3. Eigenvectors of T by twisted factorisations, one thread each, with
 //      modified Gram-Schmidt inside clusters of close eigenvalues.
-//   4. Back-transformation Z = Q Z_T in blocks of 32 reflectors, each as
+//   4. Back-transformation Z = Q Z_T in blocks of 64 reflectors, each as
 //      I - V T V^T (compact WY) by three FP64 MFMA products.
 #include <algorithm>
 #include <cmath>
@@ -30,12 +30,17 @@ typedef double ex4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 constexpr int EG_T = 64, EG_K = 16;
 
+// With P != nullptr the K range is split over blockIdx.z (kc each) and each
+// split writes its unscaled partial product to P[z][M][N]; k_eig_gemm_sum adds
+// the splits in order and applies alpha and beta (deterministic).
 __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                   int64_t sai, int64_t sak, const double *__restrict__ B, int64_t sbk,
-                                                  int64_t sbj, double beta, double *__restrict__ C, int64_t ldc)
+                                                  int64_t sbj, double beta, double *__restrict__ C, int64_t ldc,
+                                                  int kc, double *__restrict__ P)
 {
     __shared__ double As[EG_K][EG_T + 1], Bs[EG_K][EG_T + 1];
     const int i0 = blockIdx.y * EG_T, j0 = blockIdx.x * EG_T;
+    const int kb0 = P ? (int)blockIdx.z * kc : 0, kb1 = P ? min(K, kb0 + kc) : K;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv & 1, wn = wv >> 1;
     const bool a_kfast = sak == 1, b_jfast = sbj == 1;
@@ -44,19 +49,19 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = (ex4){0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += EG_K) {
+    for (int k0 = kb0; k0 < kb1; k0 += EG_K) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int ii, kk;
             if (a_kfast) { kk = t & 15; ii = (t >> 4) + 16 * u; }
             else { ii = t & 63; kk = (t >> 6) + 4 * u; }
             const int i = i0 + ii, k = k0 + kk;
-            As[kk][ii] = (i < M && k < K) ? A[(int64_t)i * sai + (int64_t)k * sak] : 0.0;
+            As[kk][ii] = (i < M && k < kb1) ? A[(int64_t)i * sai + (int64_t)k * sak] : 0.0;
             int jj, kb;
             if (b_jfast) { jj = t & 63; kb = (t >> 6) + 4 * u; }
             else { kb = t & 15; jj = (t >> 4) + 16 * u; }
             const int j = j0 + jj, kq = k0 + kb;
-            Bs[kb][jj] = (j < N && kq < K) ? B[(int64_t)kq * sbk + (int64_t)j * sbj] : 0.0;
+            Bs[kb][jj] = (j < N && kq < kb1) ? B[(int64_t)kq * sbk + (int64_t)j * sbj] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -85,19 +90,54 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
             for (int b = 0; b < 2; ++b) {
                 const int j = j0 + wn * 32 + b * 16 + (lane & 15);
                 if (j >= N) continue;
-                double *c = C + (int64_t)i * ldc + j;
-                *c = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * *c);
+                if (P) {
+                    P[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b][v];
+                } else {
+                    double *c = C + (int64_t)i * ldc + j;
+                    *c = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * *c);
+                }
             }
         }
 }
 
+__global__ void k_eig_gemm_sum(int M, int N, int ns, const double *__restrict__ P, double alpha, double beta,
+                               double *__restrict__ C, int64_t ldc)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    double s = 0.0;
+    for (int z = 0; z < ns; ++z) s += P[(int64_t)z * M * N + e];
+    double *c = C + (e / N) * ldc + e % N;
+    *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
+}
+
+// P (optional, p_cap doubles): split-K scratch for products with few output
+// tiles and a long K (the Gram and projection products of the
+// back-transformation)
 hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
                            const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
-                           hipStream_t st)
+                           hipStream_t st, double *P, int64_t p_cap)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eig_gemm, dim3((N + EG_T - 1) / EG_T, (M + EG_T - 1) / EG_T), dim3(256), 0, st, M, N, K,
-                       alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc);
+    const dim3 g((N + EG_T - 1) / EG_T, (M + EG_T - 1) / EG_T);
+    const int64_t tiles = (int64_t)g.x * g.y;
+    int ns = 1;
+    if (P && tiles < 512 && K >= 1024) {
+        ns = (int)std::min<int64_t>({(K + 255) / 256, std::max<int64_t>(1, 1024 / tiles), 64});
+        ns = (int)std::min<int64_t>(ns, p_cap / ((int64_t)M * N));
+    }
+    if (ns <= 1) {
+        hipLaunchKernelGGL(k_eig_gemm, g, dim3(256), 0, st, M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc,
+                           K, (double *)nullptr);
+        return hipGetLastError();
+    }
+    const int kc = ((K + ns - 1) / ns + EG_K - 1) / EG_K * EG_K;
+    ns = (K + kc - 1) / kc;
+    hipLaunchKernelGGL(k_eig_gemm, dim3(g.x, g.y, ns), dim3(256), 0, st, M, N, K, alpha, A, sai, sak, B, sbk, sbj,
+                       beta, C, ldc, kc, P);
+    const int64_t e = (int64_t)M * N;
+    hipLaunchKernelGGL(k_eig_gemm_sum, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, M, N, ns, P, alpha, beta,
+                       C, ldc);
     return hipGetLastError();
 }
 
@@ -196,6 +236,23 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) V.p[r] = V.tau[j] * s;
+}
+
+// W = (W + W^T) / 2 in place (the operation is defined on a symmetric matrix)
+__global__ void k_symmetrize(double *__restrict__ W, int64_t ld, int n)
+{
+    const int64_t i = blockIdx.y, j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= i) return;
+    const double a = 0.5 * (W[i * ld + j] + W[j * ld + i]);
+    W[i * ld + j] = a;
+    W[j * ld + i] = a;
+}
+
+hipError_t launch_symmetrize(double *W, int64_t ld, int n, hipStream_t st)
+{
+    if (n <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_symmetrize, dim3((n + 255) / 256, n), dim3(256), 0, st, W, ld, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_trd_step(double *A, int64_t lda, int n, int j, const TrdVec &V, hipStream_t st)
@@ -429,23 +486,34 @@ hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, i
 // T (nb x nb, upper triangular) of the compact WY form from the Gram matrix
 // G = Vb^T Vb and the scalars tau: T[i][i] = tau_i,
 // T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-__global__ void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb, double *__restrict__ T)
+// one workgroup, T built in LDS column by column (thread r forms entry r of
+// column i; the sum over q runs in order)
+constexpr int LARFT_MAX = 64;
+__global__ __launch_bounds__(64) void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb,
+                                              double *__restrict__ T)
 {
-    if (threadIdx.x != 0) return;
-    for (int i = 0; i < nb * nb; ++i) T[i] = 0.0;
+    __shared__ double Ts[LARFT_MAX][LARFT_MAX + 1];
+    const int r = threadIdx.x;
+    for (int c = 0; c < nb; ++c) Ts[r][c] = 0.0;
+    __syncthreads();
     for (int i = 0; i < nb; ++i) {
         const double ti = tau[i];
-        T[i * nb + i] = ti;
-        for (int r = 0; r < i; ++r) {
+        if (r < i) {
             double s = 0.0;
-            for (int q = r; q < i; ++q) s += T[r * nb + q] * G[q * nb + i];
-            T[r * nb + i] = -ti * s;
+            for (int q = r; q < i; ++q) s += Ts[r][q] * G[q * nb + i];
+            Ts[r][i] = -ti * s;
+        } else if (r == i) {
+            Ts[r][i] = ti;
         }
+        __syncthreads();
     }
+    if (r < nb)
+        for (int c = 0; c < nb; ++c) T[r * nb + c] = Ts[r][c];
 }
 
 hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st)
 {
+    if (nb > LARFT_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, st, G, tau, nb, T);
     return hipGetLastError();
 }
