@@ -55,6 +55,21 @@ typedef int32_t cch_status;
 #define CCH_MEM_DEVICE 1
 #define CCH_DAV_RESIDUALS 2   /* cch_davidson: evecs holds 2k rows, residuals after the vectors */
 #define CCH_DAV_SPARSE_L2 4   /* cch_davidson: the L2 block (classes 2 and 8) as CSR in the mat-vec */
+
+/* cch_dav_opts.restart. A restart rebuilds a full basis from Ritz vectors of
+ * the last Rayleigh-Ritz step (Sec. 3.2's Davidson):
+ *   CCH_RESTART_THICK  the lowest 2k Ritz vectors;
+ *   CCH_RESTART_PREV   the lowest kr = min(4k, mmax - 2k) Ritz vectors plus, for
+ *                      each wanted pair, the part of its Ritz vector of the
+ *                      iteration before that lies outside the kept ones
+ *                      (orthonormalised; parts below 1e-8 are dropped), so the
+ *                      direction in which each pair was moving survives the
+ *                      restart; the thick restart when kr < 2k;
+ *   CCH_RESTART_AUTO   (0) CCH_RESTART_PREV from a basis of 96 vectors on (the
+ *                      default from D = 20000), CCH_RESTART_THICK below. */
+#define CCH_RESTART_AUTO 0
+#define CCH_RESTART_THICK 1
+#define CCH_RESTART_PREV 2
 #define CCH_LOWER 8           /* cch_get_matrix: only the lower triangle (Sec. 2.2) is required */
 
 /* cch_plan_opts.flags */
@@ -107,7 +122,8 @@ typedef struct {
                                (0: k); pairs k..block-1 are guards: corrected
                                while any wanted pair is unconverged, never
                                tested for convergence */
-    int32_t reserved;       /* 0 */
+    int32_t restart;        /* CCH_RESTART_*: what a restart keeps when the
+                               basis is full */
 } cch_dav_opts;
 
 typedef struct {
@@ -126,6 +142,9 @@ typedef struct {
     int32_t dropped;        /* correction directions dropped by the rank test
                                (nearly inside the basis); each iteration with a
                                drop repeats its Rayleigh-Ritz step */
+    int32_t restarts;       /* restarts of the basis */
+    int32_t prev_kept;      /* directions from previous Ritz vectors kept over
+                               all restarts (CCH_RESTART_PREV) */
 } cch_dav_info;
 
 /* Library version string (static storage). */

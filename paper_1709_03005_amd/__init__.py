@@ -30,6 +30,7 @@ CCH_MEM_HOST = 0
 CCH_MEM_DEVICE = 1
 CCH_DAV_RESIDUALS = 2
 CCH_DAV_SPARSE_L2 = 4
+CCH_RESTART_AUTO, CCH_RESTART_THICK, CCH_RESTART_PREV = 0, 1, 2
 CCH_LOWER = 8
 CCH_PLAN_SPARSE_L2 = 1
 CCH_PREC_FP64 = 0
@@ -74,7 +75,7 @@ class PlanOpts(C.Structure):
 
 class DavOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_subspace", C.c_int32),
-                ("precond", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("reserved", C.c_int32)]
+                ("precond", C.c_int32), ("tol", C.c_double), ("block", C.c_int32), ("restart", C.c_int32)]
 
 
 class EigInfo(C.Structure):
@@ -87,7 +88,8 @@ class DavInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
                 ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("seconds", C.c_double),
                 ("matvec_ms", C.c_double), ("matvec_launches", C.c_int32), ("rr_fallbacks", C.c_int32),
-                ("rr_ms", C.c_double), ("rr_flops", C.c_double), ("rr_calls", C.c_int32), ("dropped", C.c_int32)]
+                ("rr_ms", C.c_double), ("rr_flops", C.c_double), ("rr_calls", C.c_int32), ("dropped", C.c_int32),
+                ("restarts", C.c_int32), ("prev_kept", C.c_int32)]
 
 
 P = C.c_void_p
@@ -387,14 +389,14 @@ class Context:
         return dict(x=x, y=y, deg=d, label=lab, phase=ph)
 
     def davidson(self, k, tol=1e-8, max_iter=200, max_subspace=0, precond=CCH_PRECOND_JACOBI,
-                 want_vectors=True, residuals=False, block=0, sparse_l2=False):
+                 want_vectors=True, residuals=False, block=0, sparse_l2=False, restart=CCH_RESTART_AUTO):
         """(eigenvalues, vectors or None, info, status); with residuals=True the
         vectors array has 2k rows, residuals H x - theta x after the vectors."""
         D, _ = self.dim()
         ev = np.zeros(k)
         vec = np.zeros((2 * k if residuals else k, D)) if (want_vectors or residuals) else None
         info = DavInfo()
-        o = DavOpts(k, max_iter, max_subspace, precond, tol, block, 0)
+        o = DavOpts(k, max_iter, max_subspace, precond, tol, block, restart)
         rc = lib.cch_davidson(self.h, C.byref(o), ev.ctypes.data_as(C.c_void_p),
                               vec.ctypes.data_as(C.c_void_p) if vec is not None else None,
                               C.byref(info), CCH_MEM_HOST | (CCH_DAV_RESIDUALS if residuals else 0)

@@ -2698,6 +2698,43 @@ struct DavBufs {
 };
 }  // namespace
 
+// Directions that carry the previous iteration's Ritz vectors over a restart.
+// y holds kp rows of nt coefficients (row e: previous Ritz vector e along the
+// nt discarded Ritz vectors, whose Ritz values are th). The rows are
+// orthonormalised in order by modified Gram-Schmidt, twice; a row whose part
+// left over is at most 1e-8 (the whole vector has norm 1) is dropped. q
+// receives the kx orthonormal columns (q[j * ldq + e], j < nt), gx the
+// projected block q^T diag(th) q (gx[e * ldg + f], symmetric). Returns kx.
+static int restart_directions(const double *y, int nt, int kp, const double *th, double *q, int ldq, double *gx,
+                              int ldg)
+{
+    std::vector<double> a(nt);
+    int kx = 0;
+    for (int e = 0; e < kp; ++e) {
+        for (int j = 0; j < nt; ++j) a[j] = y[(int64_t)e * nt + j];
+        for (int pass = 0; pass < 2; ++pass)
+            for (int f = 0; f < kx; ++f) {
+                double d = 0.0;
+                for (int j = 0; j < nt; ++j) d += q[j * ldq + f] * a[j];
+                for (int j = 0; j < nt; ++j) a[j] -= d * q[j * ldq + f];
+            }
+        double nrm = 0.0;
+        for (int j = 0; j < nt; ++j) nrm += a[j] * a[j];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 1e-8)) continue;
+        for (int j = 0; j < nt; ++j) q[j * ldq + kx] = a[j] / nrm;
+        ++kx;
+    }
+    for (int e = 0; e < kx; ++e)
+        for (int f = e; f < kx; ++f) {
+            double s = 0.0;
+            for (int j = 0; j < nt; ++j) s += q[j * ldq + e] * th[j] * q[j * ldq + f];
+            gx[e * ldg + f] = s;
+            gx[f * ldg + e] = s;
+        }
+    return kx;
+}
+
 // CSR of the L2 block of the current build (kept until the next build)
 static cch_status ensure_l2csr(cch_ctx *c, hipStream_t st)
 {
@@ -2748,8 +2785,18 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     int mmax = o->max_subspace > 0 ? o->max_subspace : (D >= 20000 ? 96 : std::max(8 * k, 64));
     mmax = std::min(mmax, 96);
     mmax = std::min(mmax, D);
-    const int kr = std::min(2 * k, D);         // kept at a thick restart; also the first block
-    if (kr + k > mmax && mmax < D) return fail(c, CCH_E_INVALID_ARG, "k too large for the subspace limit");
+    const int k0 = std::min(2 * k, D);         // the first block
+    if (k0 + k > mmax && mmax < D) return fail(c, CCH_E_INVALID_ARG, "k too large for the subspace limit");
+    if (o->restart < CCH_RESTART_AUTO || o->restart > CCH_RESTART_PREV)
+        return fail(c, CCH_E_INVALID_ARG, "unknown restart mode %d", o->restart);
+    // a restart keeps the lowest kr Ritz vectors and, with the previous
+    // iteration's Ritz vectors, up to kp more directions
+    const bool prev = o->restart == CCH_RESTART_PREV || (o->restart == CCH_RESTART_AUTO && mmax >= 96);
+    int kr = k0, kp = 0;
+    if (prev && std::min(4 * k, mmax - 2 * k) >= 2 * k) {
+        kr = std::min(4 * k, mmax - 2 * k);
+        kp = k;
+    }
     const int blk = o->block > 0 ? o->block : k;   // wanted + guard pairs corrected per iteration
     if (blk < k || blk > 16) return fail(c, CCH_E_INVALID_ARG, "block must lie in [k, 16]");
     const int max_iter = o->max_iter > 0 ? o->max_iter : 200;
@@ -2814,7 +2861,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     std::vector<int32_t> order(D);
     for (int i = 0; i < D; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return hdiag[a] < hdiag[bb]; });
-    int nb = kr;
+    int nb = k0;
     const int ns = std::min(mmax, D);
     DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
     if (c->sparse) DCK(launch_sparse_principal(sparse_mat(c), b.idx, ns, b.G, mmax, st));
@@ -2825,7 +2872,7 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
 
     int m = 0, iters = 0, matvecs = 0, nconv = 0, mv_launches = 0, fallbacks = 0;
     double mv_ms = 0.0, maxres = 0.0, best_res = 1e300, rr_ms = 0.0, rr_flops = 0.0;
-    int rr_calls = 0, dropped = 0;
+    int rr_calls = 0, dropped = 0, restarts = 0, prev_kept = 0;
     bool use_mlp = want_mlp;
     if (want_mlp) {
         if (c->sparse) DCK(launch_sparse_row_norms(sparse_mat(c), D, b.rho, st));
@@ -2839,6 +2886,10 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         int32_t rank;
         int32_t seq;   // written by the stream after each iteration's last kernel
         double res[16];
+        // a restart with the previous Ritz vectors: rows of Y past the kept
+        // columns, the discarded Ritz values, the orthonormal combination and
+        // the projected block it gives
+        double y[16 * 96], th[96], q[96 * 32], gx[16 * 16];
     };
     HostIO *hio = nullptr;
     int32_t seqno = 0;
@@ -2984,8 +3035,42 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
             break;
         }
         // G in the rotated basis
-        if (m + (int)un.size() > mmax) m = std::min(kr, m);   // thick restart
-        DCK(launch_g_ritz(b.G, mmax, m, b.theta, st));
+        if (m + (int)un.size() > mmax) {
+            const int mold = m;
+            m = std::min(kr, m);
+            ++restarts;
+            // the previous iteration's lowest kp Ritz vectors are the first kp
+            // vectors of the basis this iteration started from, rows of Y; their
+            // parts outside the kept Ritz vectors lie in the span of the
+            // discarded ones, columns m..mold-1 of Y
+            int kx = 0;
+            const int nt = mold - m;
+            if (kp > 0 && m0 >= kp && nt > 0) {
+                DCK(hipMemcpy2DAsync(hio->y, 8 * (size_t)nt, b.Y + m, 8 * (size_t)mmax, 8 * (size_t)nt, kp,
+                                     hipMemcpyDeviceToHost, st));
+                DCK(hipMemcpyAsync(hio->th, b.theta + m, 8 * (size_t)nt, hipMemcpyDeviceToHost, st));
+                DCK(hipStreamSynchronize(st));
+                kx = restart_directions(hio->y, nt, kp, hio->th, hio->q, BMAX, hio->gx, 16);
+            }
+            DCK(launch_g_ritz(b.G, mmax, m + kx, b.theta, st));
+            if (kx > 0) {
+                // V, W rows m..m+kx-1 = the discarded Ritz vectors times Q (formed
+                // beside, then copied in); G's block there = Q^T diag(theta) Q
+                DCK(hipMemcpyAsync(b.C, hio->q, 8 * (size_t)nt * BMAX, hipMemcpyHostToDevice, st));
+                DCK(launch_nn(b.V + (int64_t)m * ldv, ldv, nt, nullptr, 0, nt, D, b.C, BMAX, kx, nullptr, 0, 0.0, 1.0,
+                              b.V2 + (int64_t)m * ldv, ldv, st, b.Wv + (int64_t)m * ldv, b.W2 + (int64_t)m * ldv));
+                DCK(hipMemcpy2DAsync(b.V + (int64_t)m * ldv, 8 * ldv, b.V2 + (int64_t)m * ldv, 8 * ldv, 8 * (size_t)D,
+                                     kx, hipMemcpyDeviceToDevice, st));
+                DCK(hipMemcpy2DAsync(b.Wv + (int64_t)m * ldv, 8 * ldv, b.W2 + (int64_t)m * ldv, 8 * ldv,
+                                     8 * (size_t)D, kx, hipMemcpyDeviceToDevice, st));
+                DCK(hipMemcpy2DAsync(b.G + (int64_t)m * mmax + m, 8 * (size_t)mmax, hio->gx, 8 * 16, 8 * (size_t)kx,
+                                     kx, hipMemcpyHostToDevice, st));
+                m += kx;
+                prev_kept += kx;
+            }
+        } else {
+            DCK(launch_g_ritz(b.G, mmax, m, b.theta, st));
+        }
         // corrections for the unconverged pairs (never more than the basis has room for)
         nb = std::min((int)un.size(), mmax - m);
         if (nb <= 0) break;
@@ -3036,6 +3121,8 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
         info->rr_flops = rr_flops;
         info->rr_calls = rr_calls;
         info->dropped = dropped;
+        info->restarts = restarts;
+        info->prev_kept = prev_kept;
     }
     if (rc != CCH_OK) fail(c, rc, "Davidson did not converge in %d iterations (max residual %.3e)", max_iter, maxres);
     return rc;

@@ -1,5 +1,6 @@
 """The Davidson pairs are the lowest ones, on the large-matrix solver path
-(from D = 20000 on: basis limit 96 and the seeded first block). The
+(from D = 20000 on: basis limit 96, the seeded first block, and restarts
+that keep the previous iteration's Ritz vectors). The
 half-size precision shape (D = 20000, two-word determinants) is built on the
 GPU, its sampled elements of every block class are checked against the
 oracle, and k + 1 = 11 pairs are asked for. Each returned pair has a
@@ -43,8 +44,10 @@ def test_lowest_k_by_inertia():
         ctx.build()
         G = ctx.get_matrix()
         ev, vec, info, rc = ctx.davidson(k + 1, tol=1e-8)
-    print(f"[lowest] davidson rc={rc} iters={info.iterations}", flush=True)
+    print(f"[lowest] davidson rc={rc} iters={info.iterations} restarts={info.restarts} "
+          f"previous-vector directions kept={info.prev_kept}", flush=True)
     assert rc == cc.CCH_OK
+    assert info.restarts == 0 or info.prev_kept > 0   # the default from a basis of 96: previous Ritz vectors kept
     assert np.abs(G).max() > 0
     rng = np.random.default_rng(7)
     rows = np.concatenate([rng.integers(0, Dc, 16), rng.integers(Dc, D, 16), rng.integers(Dc, D, 16)])
