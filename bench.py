@@ -358,6 +358,9 @@ def main():
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "mlp"],
                     help="Davidson correction of the timed step: diagonal (Jacobi) or the trained network "
                          "(paper_1709_03005_amd/mlp_weights.npy)")
+    ap.add_argument("--restart", default="auto", choices=["auto", "thick", "prev"],
+                    help="Davidson restart of the timed step: the library's default (auto), the lowest 2k Ritz "
+                         "vectors (thick), or with the previous Ritz vectors kept (prev)")
     ap.add_argument("--sparse-l2", action="store_true",
                     help="timed step with the L2 block as CSR of its non-zeros in the mat-vec")
     ap.add_argument("--sparse-build", action="store_true",
@@ -438,10 +441,12 @@ def main():
         net.set_weights(np.load(os.path.join(ROOT, "paper_1709_03005_amd", "mlp_weights.npy")))
         ctx.set_mlp(net)
     pc = cc.CCH_PRECOND_MLP if args.precond == "mlp" else cc.CCH_PRECOND_JACOBI
+    restart = {"auto": cc.CCH_RESTART_AUTO, "thick": cc.CCH_RESTART_THICK, "prev": cc.CCH_RESTART_PREV}[args.restart]
 
     def step():
         ctx.build()
-        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, precond=pc, sparse_l2=args.sparse_l2)
+        ev, _, info, rc = ctx.davidson(k, tol=tol, want_vectors=False, precond=pc, sparse_l2=args.sparse_l2,
+                                       restart=restart)
         return ev, info, rc
 
     for _ in range(args.warmup):
@@ -547,7 +552,8 @@ def main():
         "config": {"workload": args.workload, "dim": D, "n_cont_rows": inst.n_cont_rows(), "n_l2": inst.n_l2,
                    "n_target_orbitals": inst.n_o, "n_electrons": inst.n_elec,
                    "symmetries": len(inst.syms), "k": k, "tol": tol},
-        "form": {"precision": args.precision, "precond": args.precond, "sparse_l2": bool(args.sparse_l2),
+        "form": {"precision": args.precision, "precond": args.precond, "restart": args.restart,
+                 "sparse_l2": bool(args.sparse_l2),
                  "sparse_build": bool(sparse_build), "device_bytes": ctx.plan_info()[0],
                  "target_energies": energies is not None,
                  "target_states": "target-Hamiltonian eigenvectors" if args.workload == "medium_te"
