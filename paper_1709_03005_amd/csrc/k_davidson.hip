@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const double *__restrict__ 
 // K8 from the lower triangle only (H symmetric): every element H[r][c] with
 // r > c is read once and used twice, for W[.][c] += H[r][c] V[.][r] (the
 // column product) and W[.][r] += H[r][c] V[.][c] (the row product); the
-// diagonal once. Half the bytes of the full product for the same MFMA work.
+// diagonal once. Half the bytes of the full product for twice the MFMA work
+// per byte.
 //
 // The lower triangle is cut into strips of SV_CW columns; a strip's rows
 // (from its diagonal down) into items of rb rows, one workgroup (8 waves)
@@ -101,6 +102,14 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const double *__restrict__ 
 // and including i's, then P1 of every item of i's strip, in a fixed order
 // (deterministic). Tiles on the diagonal zero the elements above it (and, in
 // the row product, the diagonal itself); tiles wholly above it are skipped.
+//
+// The products run on the 4x4x4 FP64 MFMA (four blocks): the B operand is a
+// 4 x 16 slab of the tile (block b takes its columns 4b..4b+3), the A operand
+// the 4 x 4 slab of V for one group of four vectors (the same in every
+// block), so a launch pays for ceil(b / 4) groups, not for 16 vectors. Lane
+// l = j + 4 blk + 16 i holds D[blk][i][j]: vector 4 g + (l >> 4), column (or
+// row) l & 15 of the strip. On this chip the 4x4x4 form also issues faster
+// per flop than the 16x16x4 one.
 // ---------------------------------------------------------------------------
 constexpr int SV_CW = 512, SV_SB = 64, SV_CH = 64, SV_NSB = SV_CW / SV_SB;
 constexpr int SV_LS = SV_SB + 1;     // LDS row strides in doubles (odd: conflict-free column reads)
@@ -108,6 +117,7 @@ constexpr int SV_LR = SV_CH + 1;
 
 __host__ __device__ inline int sv_items(int D, int J, int rb) { return (D - J * SV_CW + rb - 1) / rb; }
 
+template <int NG>
 __global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, int64_t ld, int D,
                                                   const double *__restrict__ V, int64_t ldv, int b, int rb,
                                                   double *__restrict__ P1, double *__restrict__ P2)
@@ -177,14 +187,18 @@ __global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, i
     };
     auto nsb_of = [&](int r0) { return r0 < R1 ? min(nsb_d, (r0 + SV_CH - J0 + SV_SB - 1) / SV_SB) : 0; };
     const int st = w & 3, par = w >> 2;
-    dx4m acc1[SV_NSB / 2];
+    double acc1[SV_NSB / 2][NG];
 #pragma unroll
-    for (int m = 0; m < SV_NSB / 2; ++m) acc1[m] = (dx4m){0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < SV_NSB / 2; ++m)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc1[m][g] = 0.0;
+    const int p4 = lane & 3;
     load_tile(R0, J0, true);
     for (int r0 = R0; r0 < R1; r0 += SV_CH) {
         const int nsb = nsb_of(r0), nsb_next = nsb_of(r0 + SV_CH);
-        dx4m acc2[1];
-        acc2[0] = (dx4m){0.0, 0.0, 0.0, 0.0};
+        double acc2[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc2[g] = 0.0;
 #pragma unroll
         for (int s = 0; s < SV_NSB; ++s) {
             if (s < nsb) {
@@ -202,20 +216,26 @@ __global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, i
 #pragma unroll 2
                     for (int u = 0; u < SV_CH / 4; ++u) {
                         const int rl = 4 * u + hi, cl = 16 * st + lo;
-                        const double a = Vr[lo * SV_LR + rl];
                         double h = Hs[rl * SV_LS + cl];
                         if (diag && r0 + rl < c0 + cl) h = 0.0;
-                        acc1[s >> 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, h, acc1[s >> 1], 0, 0, 0);
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            const double a = Vr[(4 * g + p4) * SV_LR + rl];
+                            acc1[s >> 1][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, h, acc1[s >> 1][g], 0, 0, 0);
+                        }
                     }
                 } else {
                     // row product: rows 16 st.., 64 columns, two chains
 #pragma unroll 2
                     for (int u = 0; u < SV_SB / 4; ++u) {
                         const int cl = 4 * u + hi, rl = 16 * st + lo;
-                        const double a = Vc[lo * SV_LS + cl];
                         double h = Hs[rl * SV_LS + cl];
                         if (diag && r0 + rl <= c0 + cl) h = 0.0;
-                        acc2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, h, acc2[0], 0, 0, 0);
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            const double a = Vc[(4 * g + p4) * SV_LS + cl];
+                            acc2[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, h, acc2[g], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -223,16 +243,16 @@ __global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, i
         __syncthreads();
         if (par == 1) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Vr[(st * 4 + v) * 64 + lane] = acc2[0][v];
+            for (int g = 0; g < NG; ++g) Vr[(st * 4 + g) * 64 + lane] = acc2[g];
         }
         __syncthreads();
         if (par == 0) {
             const int r = r0 + 16 * st + lo;
             if (r < R1) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int q = hi + 4 * v;
-                    if (q < b) P2[((int64_t)J * b + q) * D + r] = (acc2[0][v]) + Vr[(st * 4 + v) * 64 + lane];
+                for (int g = 0; g < NG; ++g) {
+                    const int q = 4 * g + hi;
+                    if (q < b) P2[((int64_t)J * b + q) * D + r] = acc2[g] + Vr[(st * 4 + g) * 64 + lane];
                 }
             }
         }
@@ -243,9 +263,9 @@ __global__ __launch_bounds__(512, 4) void k_symv(const double *__restrict__ H, i
         const int c = J0 + SV_SB * (2 * m + par) + 16 * st + lo;
         if (c < D) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int q = hi + 4 * v;
-                if (q < b) P1[(item * b + q) * SV_CW + (c - J0)] = acc1[m][v];
+            for (int g = 0; g < NG; ++g) {
+                const int q = 4 * g + hi;
+                if (q < b) P1[(item * b + q) * SV_CW + (c - J0)] = acc1[m][g];
             }
         }
     }
@@ -327,8 +347,13 @@ hipError_t launch_matvec(const double *H, int64_t ld, int D, const double *V, in
         (void)nstrip;
         for (int q0 = 0; q0 < b; q0 += 16) {
             const int bb = std::min(16, b - q0);
-            hipLaunchKernelGGL(k_symv, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, V + (int64_t)q0 * ldv, ldv,
-                               bb, rb, P1, P2);
+            const double *Vq = V + (int64_t)q0 * ldv;
+            switch ((bb + 3) / 4) {   // groups of four vectors on the 4x4x4 FP64 MFMA
+            case 1: hipLaunchKernelGGL(k_symv<1>, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, Vq, ldv, bb, rb, P1, P2); break;
+            case 2: hipLaunchKernelGGL(k_symv<2>, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, Vq, ldv, bb, rb, P1, P2); break;
+            case 3: hipLaunchKernelGGL(k_symv<3>, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, Vq, ldv, bb, rb, P1, P2); break;
+            default: hipLaunchKernelGGL(k_symv<4>, dim3((unsigned)items), dim3(512), 0, st, H, ld, D, Vq, ldv, bb, rb, P1, P2); break;
+            }
             hipLaunchKernelGGL(k_symv_reduce, dim3((D + 255) / 256, bb), dim3(256), 0, st, P1, P2, D, bb, rb,
                                W + (int64_t)q0 * ldw, ldw);
         }
