@@ -143,11 +143,15 @@ hipError_t launch_relayout(const double *ttcc, const double *tctc, int n_o, int 
 }
 
 // ---------------------------------------------------------------------------
-// K5: C = A * B with A given K-major (At[k][r]), FP64 MFMA 16x16x4.
-// Workgroup tile 64 (r) x 128 (col), 4 waves in 2 x 2, each 32 x 64 =
-// 2 x 4 MFMA tiles. K staged through LDS in slices of 16.
-// MFMA f64 16x16x4 operand layout (lane l): A[l%16][l/16], B[l/16][l%16];
-// result item v of lane l is D[l/16 + 4v][l%16] (checked on gfx950).
+// K5: C = A * B with A given K-major (At[k][r]), FP64 MFMA 4x4x4 (four
+// blocks). Workgroup tile 64 (r) x 128 (col), 4 waves in 2 x 2, each 32 x 64 =
+// 8 x 4 instructions of 4 rows x 16 columns. K staged through LDS in slices
+// of 16. Operand layout of the four-block 4x4x4 f64 MFMA (lane l = j + 4 blk +
+// 16 i, checked on gfx950): A[blk][i][k] at lane i + 4 blk + 16 k, B[blk][k][j]
+// at lane j + 4 blk + 16 k, D[blk][i][j] at lane j + 4 blk + 16 i. With the
+// same A slab in every block, an instruction multiplies 4 rows by 16 columns
+// (B's column 4 blk + j); on this chip it issues faster per flop than the
+// 16x16x4 form.
 // ---------------------------------------------------------------------------
 typedef double dx4 __attribute__((ext_vector_type(4)));
 
@@ -188,11 +192,14 @@ __device__ __forceinline__ void expand_tile_f64(const double *__restrict__ At, c
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int wm = wv % WAVES_M, wn = wv / WAVES_M;
 
-    dx4 acc[2][NT];
+    // 4x4x4 FP64 MFMA (four blocks sharing the A slab): one instruction is 4
+    // rows x 16 columns x 4 k; lane l holds row 4 m + (l >> 4), column 16 n +
+    // (l & 15) of the wave's 32 x WCOLS tile
+    double acc[8][NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < NT; ++b) acc[a][b] = (dx4){0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < NT; ++b) acc[a][b] = 0.0;
 
     double ra[AQ], rb[BQ];
     auto gload = [&](int k0) {
@@ -229,26 +236,25 @@ __device__ __forceinline__ void expand_tile_f64(const double *__restrict__ At, c
 #pragma unroll
         for (int ks = 0; ks < GBK; ks += 4) {
             const int kk = ks + (lane >> 4);
-            double af[2], bf[NT];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[kk][wm * 32 + a * 16 + (lane & 15)];
+            double bf[NT];
 #pragma unroll
             for (int b = 0; b < NT; ++b) bf[b] = Bs[kk][wn * WCOLS + b * 16 + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 8; ++a) {
+                const double af = As[kk][wm * 32 + 4 * a + (lane & 3)];
 #pragma unroll
                 for (int b = 0; b < NT; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af, bf[b], acc[a][b], 0, 0, 0);
+            }
         }
     }
     __syncthreads();   // the LDS tiles are reused by the next tile of a persistent loop
 
     // epilogue: scatter into the contracted matrix (lower triangle only)
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+    for (int a = 0; a < 8; ++a) {
+        {
+            const int r = r0 + wm * 32 + 4 * a + (lane >> 4);
             if (r >= nrows) continue;
             const int n = ep.rn[r], n2 = ep.rn2[r];
             const double ht = ep.HT[r], ov = ep.O[r];
@@ -261,7 +267,7 @@ __device__ __forceinline__ void expand_tile_f64(const double *__restrict__ At, c
                 const int64_t C = ep.row0b + (int64_t)n2 * ep.ncb + jp;
                 if (R < C) continue;
                 const int J = ep.ja0 + jj, Jp = ep.jb0 + jp;
-                double val = acc[a][b][v];
+                double val = acc[a][b];
                 if (J == Jp) val += ht;
                 val += ov * ep.h[(size_t)(ep.n_o + J) * ep.n_orb + (ep.n_o + Jp)];
                 ep.H[R * ep.ld + C] = val;
