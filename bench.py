@@ -52,13 +52,15 @@ COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC = {
     # (workload, name): (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("medium", "rayleigh_ritz"): ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
-    ("medium", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 22100.938, 98766.094),
-    ("learned", "matvec"): ("k_davidson.hip", "fbb8ec7203eb9e17", 7423127.2, 656699.2),
-    ("learned", "expansion_gemm"): ("k_gemm.hip", "25222b91e5d4a913", 16846593.3, 1562812.5),
-    ("learned", "relayout"): ("k_gemm.hip", "25222b91e5d4a913", 2000325.9, 4000000.1),
-    ("learned", "class4"): ("k_class4.hip", "039a68f494db568f", 4258166.5, 6250000.0),
-    ("learned", "l2_block"): ("k_l2.hip", "777ee4e8faee8121", 1773224.4, 6273909.5),
-    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038920.8, 14062968.8),
+    ("medium", "l2_block"): ("k_l2.hip", "d072e20157352122", 22104.250, 98764.125),
+    # the product instances of one solve (49 of three vector groups, 7 of one,
+    # 2 of two, 1 of four) averaged per launch, plus the reduction
+    ("learned", "matvec"): ("k_davidson.hip", "322f4a258a9267ee", 7412243.8, 567473.6),
+    ("learned", "expansion_gemm"): ("k_gemm.hip", "15c867937063e43b", 16520452.1, 1562812.5),
+    ("learned", "relayout"): ("k_gemm.hip", "15c867937063e43b", 2000324.2, 4000000.0),
+    ("learned", "class4"): ("k_class4.hip", "1c100f7420acfa5b", 5756553.2, 10223622.8),
+    ("learned", "l2_block"): ("k_l2.hip", "d072e20157352122", 1770334.4, 6273721.4),
+    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038936.4, 14062968.8),
 }
 
 
