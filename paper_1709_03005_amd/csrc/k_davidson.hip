@@ -515,10 +515,11 @@ hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, 
 // ---------------------------------------------------------------------------
 // out[e][i] = beta * base[e][i] + alpha * sum_{q<m} V[q][i] C[q*ldc + e], e < ne,
 // where V[q] = V1[q] for q < m1 and V2[q - m1] for m1 <= q < m
-// grid (D/256, ceil(ne/4)): four outputs per thread, C slice staged in LDS
+// grid (D/256, ceil(ne/NE)): NE outputs per thread, C slice staged in LDS.
+// Each grid row reads every input vector once, so wider slices read them
+// fewer times; the sum over q runs in the same order for any NE.
 // ---------------------------------------------------------------------------
-constexpr int NN_E = 4;
-
+template <int NE>
 __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1, int64_t ldv1, int m1,
                                                   const double *__restrict__ V2, int64_t ldv2, int m, int D,
                                                   const double *__restrict__ Cm, int ldc, int ne,
@@ -526,34 +527,34 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1,
                                                   double alpha, double *__restrict__ out, int64_t ldo,
                                                   const double *__restrict__ V1z, double *__restrict__ outz)
 {
-    extern __shared__ double cs[];   // [m][NN_E]
+    extern __shared__ double cs[];   // [m][NE]
     if (blockIdx.z == 1) {   // the second product of a pair launch: same C, other V1 and out
         V1 = V1z;
         out = outz;
     }
-    const int e0 = blockIdx.y * NN_E;
-    for (int t = threadIdx.x; t < m * NN_E; t += 256) {
-        const int q = t / NN_E, e = e0 + t % NN_E;
+    const int e0 = blockIdx.y * NE;
+    for (int t = threadIdx.x; t < m * NE; t += 256) {
+        const int q = t / NE, e = e0 + t % NE;
         cs[t] = e < ne ? Cm[(int64_t)q * ldc + e] : 0.0;
     }
     __syncthreads();
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= D) return;
-    double acc[NN_E];
+    double acc[NE];
 #pragma unroll
-    for (int e = 0; e < NN_E; ++e) acc[e] = 0.0;
+    for (int e = 0; e < NE; ++e) acc[e] = 0.0;
     for (int q = 0; q < m1; ++q) {
         const double v = V1[(int64_t)q * ldv1 + i];
 #pragma unroll
-        for (int e = 0; e < NN_E; ++e) acc[e] = fma(v, cs[q * NN_E + e], acc[e]);
+        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
     }
     for (int q = m1; q < m; ++q) {
         const double v = V2[(int64_t)(q - m1) * ldv2 + i];
 #pragma unroll
-        for (int e = 0; e < NN_E; ++e) acc[e] = fma(v, cs[q * NN_E + e], acc[e]);
+        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
     }
 #pragma unroll
-    for (int e = 0; e < NN_E; ++e) {
+    for (int e = 0; e < NE; ++e) {
         if (e0 + e < ne) {
             double r = alpha * acc[e];
             if (base) r += beta * base[(int64_t)(e0 + e) * ldb + i];
@@ -566,6 +567,8 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1,
 // thread); out must not overlap the rows read from V1 or V2.
 // With V1z and outz (and no second panel), one launch also forms
 // outz = beta * base + alpha * V1z C with the same C (the pair of rotations).
+// Slice width: 16 outputs per thread from D = 32768 on (the inputs are then
+// read ceil(ne / 16) times), 8 from 16384, else 4 (more workgroups for small D).
 hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, int64_t ldv2, int m, int D,
                      const double *C, int ldc, int ne, const double *base, int64_t ldb, double beta, double alpha,
                      double *out, int64_t ldo, hipStream_t st, const double *V1z, double *outz)
@@ -573,10 +576,18 @@ hipError_t launch_nn(const double *V1, int64_t ldv1, int m1, const double *V2, i
     if (ne <= 0 || D <= 0) return hipSuccess;
     if (m1 < 0 || m1 > m || (m1 < m && V2 == nullptr)) return hipErrorInvalidValue;
     if ((V1z == nullptr) != (outz == nullptr) || (V1z && (m1 != m || base))) return hipErrorInvalidValue;
-    const dim3 g((D + 255) / 256, (ne + NN_E - 1) / NN_E, V1z ? 2 : 1), bl(256);
-    const size_t shm = sizeof(double) * NN_E * (size_t)(m > 0 ? m : 1);
-    hipLaunchKernelGGL(k_nn_small, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta, alpha,
-                       out, ldo, V1z, outz);
+    const int NE = D >= 32768 ? 16 : (D >= 16384 ? 8 : 4);
+    const dim3 g((D + 255) / 256, (ne + NE - 1) / NE, V1z ? 2 : 1), bl(256);
+    const size_t shm = sizeof(double) * NE * (size_t)(m > 0 ? m : 1);
+    if (NE == 16)
+        hipLaunchKernelGGL(k_nn_small<16>, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta,
+                           alpha, out, ldo, V1z, outz);
+    else if (NE == 8)
+        hipLaunchKernelGGL(k_nn_small<8>, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta,
+                           alpha, out, ldo, V1z, outz);
+    else
+        hipLaunchKernelGGL(k_nn_small<4>, g, bl, shm, st, V1, ldv1, m1, V2, ldv2, m, D, C, ldc, ne, base, ldb, beta,
+                           alpha, out, ldo, V1z, outz);
     return hipGetLastError();
 }
 
