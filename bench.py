@@ -44,36 +44,60 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 # WRITE_SIZE passes (KiB per dispatch, averaged over one step), scaled by what
 # the same counters read for a plain 512 MiB device copy (bench.py --workload
 # copy: FETCH_SIZE reads half the bytes, WRITE_SIZE all of them). Keyed by
-# workload and kernel, with the source file of the kernel and its hash when
-# counted: a kernel changed since reports null. The relayout entry is the sum
-# of its two launches (J and K layouts), the mat-vec entry the sum of the
-# product and its reduction of partial sums.
+# workload and kernel family, with the hash of the family's source text when
+# counted (the region of its file between two marker lines, or the whole
+# file): a family whose source has changed since reports null. The relayout
+# entry is the sum of its two launches (J and K layouts), the mat-vec entry the
+# sum of the product and its reduction of partial sums.
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+KERNEL_SOURCE = {
+    # family: (file, first marker line, marker line after the region), None = whole file
+    "matvec": ("k_davidson.hip", "// K8 from the lower triangle only", "// K9: tall-skinny products"),
+    "expansion_gemm": ("k_gemm.hip", "// K5: C = A * B", "// Persistent form over many"),
+    "relayout": ("k_gemm.hip", "// K0: B[k][jj*ncb + jj']", "// K5: C = A * B"),
+    "class4": ("k_class4.hip", None, None),
+    "l2_block": ("k_l2.hip", "// Classes 2 and 8", "// L2 functions given as CSFs"),
+    "mirror": ("k_misc.hip", "// H[c][r] = H[r][c]", "__global__ void k_diag"),
+    "rayleigh_ritz": ("k_rr.hip", None, None),
+}
 TRAFFIC = {
-    # (workload, name): (source, sha256 prefix, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("medium", "rayleigh_ritz"): ("k_rr.hip", "ad413139aab2388c", 53.878, 25.493),
-    ("medium", "l2_block"): ("k_l2.hip", "d072e20157352122", 22104.250, 98764.125),
+    # (workload, family): (sha256 prefix of the family's source, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("medium", "rayleigh_ritz"): ("ad413139aab2388c", 53.878, 25.493),
+    ("medium", "l2_block"): ("238d74161bdf3234", 22104.250, 98764.125),
     # the product instances of one solve (49 of three vector groups, 7 of one,
     # 2 of two, 1 of four) averaged per launch, plus the reduction
-    ("learned", "matvec"): ("k_davidson.hip", "322f4a258a9267ee", 7412243.8, 567473.6),
-    ("learned", "expansion_gemm"): ("k_gemm.hip", "15c867937063e43b", 16520452.1, 1562812.5),
-    ("learned", "relayout"): ("k_gemm.hip", "15c867937063e43b", 2000324.2, 4000000.0),
-    ("learned", "class4"): ("k_class4.hip", "1c100f7420acfa5b", 5756553.2, 10223622.8),
-    ("learned", "l2_block"): ("k_l2.hip", "d072e20157352122", 1770334.4, 6273721.4),
-    ("learned", "mirror"): ("k_misc.hip", "3b1b7a60bae73db4", 7038936.4, 14062968.8),
+    ("learned", "matvec"): ("659b75f44a9c8597", 7412243.8, 567473.6),
+    ("learned", "expansion_gemm"): ("7eeac111dbc075d6", 16520452.1, 1562812.5),
+    ("learned", "relayout"): ("29b301ee4afa7f1b", 2000324.2, 4000000.0),
+    ("learned", "class4"): ("1c100f7420acfa5b", 5756553.2, 10223622.8),
+    ("learned", "l2_block"): ("238d74161bdf3234", 1770334.4, 6273721.4),
+    ("learned", "mirror"): ("e5a76a20e4f84e29", 7038936.4, 14062968.8),
 }
+
+
+def source_hash(kernel):
+    """sha256 prefix of a kernel family's source text, or None."""
+    import hashlib
+    f, a, b = KERNEL_SOURCE[kernel]
+    path = os.path.join(ROOT, "paper_1709_03005_amd", "csrc", f)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if a is not None:
+        i = text.find(a)
+        j = text.find(b, i + 1) if i >= 0 else -1
+        if i < 0 or j < 0:
+            return None
+        text = text[i:j]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def traffic_bytes(kernel, workload):
     """Counter-measured HBM bytes per launch, or None."""
-    import hashlib
     t = TRAFFIC.get((workload, kernel))
-    if t is None:
+    if t is None or source_hash(kernel) != t[0]:
         return None
-    src = os.path.join(ROOT, "paper_1709_03005_amd", "csrc", t[0])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != t[1]:
-        return None
-    return 1024.0 * (t[2] * COUNTER_SCALE["FETCH_SIZE"] + t[3] * COUNTER_SCALE["WRITE_SIZE"])
+    return 1024.0 * (t[1] * COUNTER_SCALE["FETCH_SIZE"] + t[2] * COUNTER_SCALE["WRITE_SIZE"])
 
 
 WORKLOADS = {
