@@ -374,8 +374,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="learned", choices=sorted(WORKLOADS) + ["batch", "copy", "eig_all"],
-                    help="copy: three plain 512 MiB device copies, the calibration run for HBM counters")
+    ap.add_argument("--workload", default="learned",
+                    choices=sorted(WORKLOADS) + ["batch", "copy", "eig_all", "peaks"],
+                    help="copy: three plain 512 MiB device copies, the calibration run for HBM counters; "
+                         "peaks: the measured copy rate and FP64 issue rates beside the published peaks")
     ap.add_argument("--instances", type=int, default=64, help="batch workload: number of instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the plain step only (no chosen forms)")
@@ -418,6 +420,27 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"workload": "copy", "bytes_per_copy": n * 8, "copies": 3}))
+        return None
+    if args.workload == "peaks":
+        # the roofline denominators confirmed on this device: a plain device copy
+        # (bytes read + written) and the FP64 issue rates of cch_probe_fp64
+        n = 64 << 20
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = None
+        for _ in range(6):
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        rates = cc.probe_fp64(0, torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"workload": "peaks", "copy_GBps": 2 * n * 8 / (best * 1e-3) / 1e9,
+                          "copy_bytes": 2 * n * 8, "fp64_tflops": rates,
+                          "published": {"hbm_GBps": HBM_PEAK_GBS, "fp64_mfma_tflops": FP64_MFMA_PEAK_TFLOPS,
+                                        "fp64_vector_tflops": FP64_VALU_PEAK_TFLOPS}}))
         return None
     gen, k, tol, cpu_mode = WORKLOADS[args.workload]
     t_gen = time.perf_counter()

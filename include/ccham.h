@@ -150,6 +150,17 @@ typedef struct {
 /* Library version string (static storage). */
 const char *cch_version(void);
 
+/* Measured FP64 issue rates of HIP device `device` on `hip_stream` (NULL = the
+ * null stream), in TFLOP/s: rates[0] the 16x16x4 FP64 MFMA, rates[1] the
+ * four-block 4x4x4 FP64 MFMA, rates[2] the FP64 vector FMA, each from
+ * register-only loops with independent accumulator chains over 2048
+ * workgroups (best of two timed launches after a warm-up). A calibration for
+ * the roofline figures of the FP64 kernels (the published FP64 peak of the
+ * MI355X is 78.6 TFLOP/s for both units); no context needed. rates[3] host
+ * array. CCH_E_INVALID_ARG for NULL rates, CCH_E_HIP / CCH_E_OOM from the
+ * runtime. Synchronous. */
+cch_status cch_probe_fp64(int32_t device, void *hip_stream, double *rates);
+
 /* Create a context on HIP device `device`, ordering work on `hip_stream`
  * (a hipStream_t; NULL = the null stream). *out receives the context. */
 cch_status cch_create(cch_ctx **out, int32_t device, void *hip_stream);

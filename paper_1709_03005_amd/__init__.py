@@ -45,7 +45,7 @@ CCH_PAIRS_L2 = 1
 CCH_PAIRS_L2_TARGET = 2
 
 EXPORTS = [
-    "cch_version", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
+    "cch_version", "cch_probe_fp64", "cch_create", "cch_destroy", "cch_last_error", "cch_sync", "cch_set_orbitals",
     "cch_set_integrals", "cch_add_target_symmetry", "cch_add_target_symmetry_spin", "cch_add_target_symmetry_csf", "cch_set_l2", "cch_set_l2_csf", "cch_set_target_energies", "cch_plan", "cch_build",
     "cch_get_dim", "cch_get_matrix", "cch_matrix_device", "cch_get_diagonal", "cch_get_elements", "cch_get_block", "cch_block_shape", "cch_get_labels",
     "cch_davidson", "cch_build_time", "cch_work_counts", "cch_batch_create", "cch_batch_build",
@@ -96,6 +96,7 @@ P = C.c_void_p
 i32, i64 = C.c_int32, C.c_int64
 _SIG = {
     "cch_version": (C.c_char_p, []),
+    "cch_probe_fp64": (i32, [i32, P, P]),
     "cch_create": (i32, [C.POINTER(P), i32, P]),
     "cch_destroy": (i32, [P]),
     "cch_last_error": (C.c_char_p, [P]),
@@ -157,6 +158,16 @@ class CchError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ccham error {code}: {msg}")
         self.code = code
+
+
+def probe_fp64(device=0, stream=None):
+    """cch_probe_fp64: measured FP64 rates (TFLOP/s) of the 16x16x4 MFMA, the
+    four-block 4x4x4 MFMA and the vector FMA on `device`."""
+    r = np.zeros(3)
+    rc = lib.cch_probe_fp64(device, stream, r.ctypes.data_as(C.c_void_p))
+    if rc != CCH_OK:
+        raise CchError(rc, "cch_probe_fp64 failed")
+    return {"mfma_16x16x4": float(r[0]), "mfma_4x4x4": float(r[1]), "fma": float(r[2])}
 
 
 def version() -> str:

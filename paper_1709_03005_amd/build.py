@@ -11,7 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libccham.so")
 SOURCES = ["ccham_api.hip", "k_scan.hip", "k_target.hip", "k_gemm.hip", "k_gemm_lowp.hip", "k_class4.hip", "k_mlp.hip",
            "k_l2.hip", "k_misc.hip", "k_davidson.hip", "k_rr.hip",
-           "k_sparse.hip", "k_l2sparse.hip", "k_eig.hip", "ccham_noalloc.hip"]
+           "k_sparse.hip", "k_l2sparse.hip", "k_eig.hip", "ccham_noalloc.hip", "k_probe.hip"]
 ARCH = os.environ.get("CCHAM_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # no packed FP32 instructions anywhere in the device code
