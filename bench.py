@@ -273,7 +273,7 @@ def bench_eig_all(args):
         "kernels": {
             "tridiagonalisation": {"bound": "hbm", "achieved": info.tridiag_bytes / (tri_ms * 1e-3) / 1e9,
                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "note": "16 B per trailing element per column (read and write once)"},
+                                   "note": "lower triangle of the trailing block: 8 B per element per column (its product) + 16 B per element per 32-column panel (its update)"},
             "vectors": {"bound": "mfma", "achieved": info.backtransform_flops / (vec_ms * 1e-3) / 1e12,
                         "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "note": "back-transformation 2 n^3 flops over the whole vector phase (twisted "

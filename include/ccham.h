@@ -459,8 +459,9 @@ typedef struct {
     double vectors_ms;          /* twisted factorisations, cluster orthogonalisation, back-transformation */
     int32_t clusters;           /* runs of eigenvalues closer than 1e-5 ||T|| (re-orthogonalised) */
     int32_t clustered;          /* eigenvalues in those runs */
-    double tridiag_bytes;       /* algorithmic bytes of the trailing-block passes (one read + one write per
-                                   element per column) */
+    double tridiag_bytes;       /* algorithmic bytes of the blocked reduction: the distinct (lower-triangle)
+                                   elements of the trailing block, 8 B read per column and 16 B read and
+                                   written per panel of 32 columns */
     double backtransform_flops; /* 2 n^3 when vectors are formed */
 } cch_eig_info;
 

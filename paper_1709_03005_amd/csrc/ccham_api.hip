@@ -121,14 +121,16 @@ hipError_t launch_sparse_row_norms(const SparseMat &S, int D, double *rho, hipSt
 hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
                            const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
                            hipStream_t st, double *P = nullptr, int64_t p_cap = 0);
-hipError_t launch_trd_step(double *A, int64_t lda, int n, int j, const TrdVec &V, hipStream_t st);
+hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, const TrdVec &V, const TrdPanel &P,
+                            hipStream_t st);
 hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, int n, const int32_t *bs,
                                   const int32_t *bm, const int32_t *bk, double lo, double hi, double pivmin,
                                   double *w, hipStream_t st);
 hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int32_t *bs, const int32_t *bm,
                               const double *w, double pivmin, double *Z, int64_t ldz, double *S, int64_t lds,
                               hipStream_t st);
-hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, hipStream_t st);
+hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, const double *d,
+                              const double *e, const double *w, double *S, int64_t lds, double piv, hipStream_t st);
 hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, int nb, double *Vb, hipStream_t st);
 hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st);
 hipError_t launch_symmetrize(double *W, int64_t ld, int n, hipStream_t st);
@@ -1840,8 +1842,9 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
     // split-K partials of the back-transformation's long products
     const int64_t p_cap = std::max<int64_t>((int64_t)16 * NB * n, (int64_t)64 * NB * NB);
     const bool want_v = V != nullptr;
+    double *pan = nullptr;   // the reduction's panel buffers PV, PW and the products z
     bool ok = al((void **)&W, 8 * (size_t)n * ld) && al((void **)&vec, 8 * (size_t)10 * n + 64) &&
-              al((void **)&w_d, 8 * (size_t)n);
+              al((void **)&w_d, 8 * (size_t)n) && al((void **)&pan, 8 * trd_panel_doubles(n, ld));
     if (ok && want_v)
         // S: the twisted-factorisation scratch, then two NB x n products of the back-transformation
         ok = al((void **)&Z, 8 * (size_t)n * ld) &&
@@ -1879,10 +1882,16 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     EGK(launch_symmetrize(W, ld, n, st));
     EGK(hipEventRecord(e0, st));
-    TrdVec tv{vec, vec + n, vec + 2 * (int64_t)n, vec + 3 * (int64_t)n, vec + 4 * (int64_t)n,
-              vec + 5 * (int64_t)n, vec + 6 * (int64_t)n, vec + 7 * (int64_t)n};
+    TrdVec tv{vec, vec + n, vec + 2 * (int64_t)n, vec + 3 * (int64_t)n, vec + 4 * (int64_t)n};
     double *e2v = vec + 8 * (int64_t)n;
-    for (int j = 0; j < n; ++j) EGK(launch_trd_step(W, ld, n, j, tv, st));
+    TrdPanel tp;
+    tp.PV = pan;
+    tp.PW = pan + (int64_t)2 * TRD_NB * ld;
+    tp.ldp = ld;
+    tp.z = pan + (int64_t)4 * TRD_NB * ld;
+    tp.part1 = tp.z + 2 * TRD_NB;
+    tp.part2 = tp.part1 + (int64_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS;
+    for (int j0 = 0; j0 < n; j0 += TRD_NB) EGK(launch_trd_panel(W, ld, n, j0, std::min(TRD_NB, n - j0), tv, tp, st));
     EGK(hipEventRecord(e1, st));
     // Gershgorin interval, pivot floor and the split of T into unreduced
     // blocks (off-diagonals below the rounding of their neighbours set to 0)
@@ -1986,7 +1995,10 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
                 return fail(c, CCH_E_OOM, "eigensolver cluster lists");
             }
             EGK(hipMemcpyAsync(d_cl, cl_cols.data(), 4 * cl_cols.size(), hipMemcpyHostToDevice, st));
-            for (auto &q : cl) EGK(launch_cluster_mgs(Z, ld, q[2], q[3], d_cl + q[0], q[1], st));
+            // pivot floor of the inverse-iteration solves: the rounding of ||T||
+            const double piv = 2.220446049250313e-16 * std::max(tnorm, 1e-300);
+            for (auto &q : cl)
+                EGK(launch_cluster_mgs(Z, ld, q[2], q[3], d_cl + q[0], q[1], tv.d, tv.e, w_d, S, ld, piv, st));
         }
         // Z = Q Z_T: the blocks of reflectors from the last to the first
         const int nref = n - 1;
@@ -2023,7 +2035,15 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
         info->vectors_ms = t23;
         info->clusters = clusters;
         info->clustered = clustered;
-        info->tridiag_bytes = 16.0 * ((double)n * (n - 1) * (2.0 * n - 1) / 6.0);   // sum over columns of (n-j-1)^2 reads + writes
+        // the distinct (lower-triangle) elements of the trailing block: read
+        // once per column, read and written once per panel
+        double tb = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double m = n - j - 1;
+            tb += 4.0 * m * (m + 1.0);
+            if (j % TRD_NB == 0 && j > 0) tb += 8.0 * (m + 1.0) * (m + 2.0);
+        }
+        info->tridiag_bytes = tb;
         info->backtransform_flops = want_v ? 2.0 * (double)n * n * n : 0.0;
     }
 #undef EGK

@@ -236,14 +236,31 @@ struct PackedCC {
     int jr0, nca_full;
 };
 
-// work vectors of the Householder tridiagonalisation (length n each except
-// scal): vp = v_{j-1}, wp = w_{j-1}, vn = v_j, p = tau_j A v_j; the diagonal
-// d, the off-diagonal e and the reflector scalars tau of T
+// work vectors of the Householder tridiagonalisation (length n each): wp =
+// the current column after the panel's corrections, p = tau_j A_j v_j; the
+// diagonal d, the off-diagonal e and the reflector scalars tau of T
 struct TrdVec {
-    double *vp, *wp, *vn, *p;
+    double *wp, *p;
     double *d, *e, *tau;
-    double *scal;
 };
+
+// columns per panel of the blocked tridiagonalisation
+constexpr int TRD_NB = 32;
+// rows per workgroup of the column kernel, and the stride of its partial sums
+constexpr int TRD_CR = 256, TRD_PS = 2 * TRD_NB + 8;
+struct TrdPanel {
+    double *PV, *PW;   // 2 TRD_NB rows each, ldp doubles a row
+    int64_t ldp;
+    double *z;         // 2 TRD_NB
+    double *part1;     // column kernel: TRD_PS partial sums per workgroup
+    double *part2;     // pass kernel: one partial sum per workgroup
+};
+
+// doubles of the panel buffers for dimension n with rows of ldp doubles
+inline size_t trd_panel_doubles(int n, int64_t ldp)
+{
+    return (size_t)4 * TRD_NB * ldp + 2 * TRD_NB + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4;
+}
 
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for
 // c < Dc (every row), R[r][c - Dc] for r < Dc <= c, and the L2 block's rows

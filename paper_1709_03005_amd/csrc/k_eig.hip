@@ -143,8 +143,26 @@ hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, i
 
 // ---------------------------------------------------------------------------
 // 1. tridiagonalisation (lower triangle convention: reflector j annihilates
-//    A[j+2:, j]; v_j[j+1] = 1 is stored explicitly in A[j+1][j] and below)
-// work vectors (length n each): vp = v_{j-1}, wp = w_{j-1}, vn = v_j, p = A v_j
+//    A[j+2:, j]; v_j[j+1] = 1 is stored explicitly in A[j+1][j] and below),
+//    blocked with lazy updates: in a panel of TRD_NB columns the trailing
+//    matrix A_0 is only read. The matrix after the panel's reflectors k < i is
+//    A_0 - sum_k (v_k w_k^T + w_k v_k^T), so column j is read from A_0 and
+//    corrected, and its product A_j v_j = A_0 v_j - sum_k (v_k (w_k . v_j) +
+//    w_k (v_k . v_j)); one rank-2 TRD_NB product (FP64 MFMA) updates the
+//    trailing block at the end of the panel. w_j = p - (tau_j / 2)(p . v_j) v_j
+//    with p = tau_j A_j v_j.
+// Two launches per column, both spread over the rows; a workgroup never
+// waits for another one. The column kernel adds the pass kernel's partial
+// sums of p . v (the scalar of the previous w), finishes that w, corrects
+// column j and stores, per workgroup, the partial sums of sigma = |x|^2 over
+// the part to annihilate and of the panel's vectors times it. Every
+// workgroup of the pass kernel adds those partial sums in workgroup order
+// (so all get the same reflector), forms v_j = x / (alpha - beta) as it
+// reads it, the products p and the partial sums of p . v_j.
+// panel buffers (ldp doubles a row): PV rows 2k, 2k + 1 = v_k, w_k; PW rows
+// 2k, 2k + 1 = w_k, v_k (the update is A -= PV^T PW over 2 nb rows); z[2k] =
+// v_k . v_j, z[2k + 1] = w_k . v_j. Rows of PV and PW below the reflector's
+// first row are never read.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double blk_sum(double x, double *red)
@@ -157,85 +175,185 @@ __device__ __forceinline__ double blk_sum(double x, double *red)
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// one workgroup: column j of A (rows j..n-1) after reflector j-1, its
-// reflector, and w_{j-1} = p - (tau/2)(p^T v) v from the product of the last
-// pass; j = 0: no previous reflector
-__global__ __launch_bounds__(256) void k_trd_col(double *__restrict__ A, int64_t lda, int n, int j, TrdVec V)
+// x[b stride] summed for b = b0, b0 + step, ... < b1 in that order; the
+// loads go out in batches of 8
+__device__ __forceinline__ double ordered_sum(const double *__restrict__ x, int64_t stride, int b0, int b1, int step)
 {
-    __shared__ double red[4];
-    const int t = threadIdx.x;
-    if (j > 0) {
-        // w_{j-1} over rows j..n-1 (v_{j-1} is zero above row j)
-        const double tau = V.tau[j - 1];
-        double s = 0.0;
-        for (int r = j + t; r < n; r += 256) s += V.p[r] * V.vn[r];
-        const double pv = blk_sum(s, red);
-        const double al = -0.5 * tau * pv;
-        for (int r = j + t; r < n; r += 256) {
-            const double v = V.vn[r];
-            V.vp[r] = v;
-            V.wp[r] = V.p[r] + al * v;
+    double y = 0.0;
+    for (int b = b0; b < b1; b += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = b + u * step;
+            v[u] = c < b1 ? x[(int64_t)c * stride] : 0.0;
         }
-        __syncthreads();
-        // column j (rows j..n-1) minus v w^T + w v^T at column j
-        const double vj = V.vp[j], wj = V.wp[j];
-        for (int r = j + t; r < n; r += 256) {
-            double *a = A + (int64_t)r * lda + j;
-            *a = *a - V.vp[r] * wj - V.wp[r] * vj;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y += v[u];
     }
-    if (t == 0) V.d[j] = A[(int64_t)j * lda + j];
-    if (j >= n - 1) return;
-    // reflector on x = A[j+1:, j]
-    const double alpha = A[(int64_t)(j + 1) * lda + j];
-    double s = 0.0;
-    for (int r = j + 2 + t; r < n; r += 256) {
-        const double x = A[(int64_t)r * lda + j];
-        s += x * x;
-    }
-    const double sig = blk_sum(s, red);
-    double tau = 0.0, beta = alpha, scale = 0.0;
-    if (sig > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-    }
-    for (int r = t; r < n; r += 256) {
-        double v = 0.0;
-        if (r == j + 1) v = 1.0;
-        else if (r > j + 1) v = A[(int64_t)r * lda + j] * scale;
-        V.vn[r] = v;
-        if (r > j) A[(int64_t)r * lda + j] = v;   // kept for the back-transformation
-    }
-    if (t == 0) {
-        V.e[j] = beta;
-        V.tau[j] = tau;
-    }
+    return y;
 }
 
-// rows r of the trailing block [j+1, n) x [j+1, n): apply reflector j-1's
-// rank-2 update (when j > 0), then p[r] = tau_j * sum_c A[r][c] v_j[c].
-// One wave per row, lanes over the columns, a fixed-order reduction.
-__global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_t lda, int n, int j, int upd,
-                                                  TrdVec V)
+// rows j + TRD_CR blockIdx.x + threadIdx.x. With i > 0, w of the panel's
+// reflector i - 1 (column j - 1) into PV row 2i - 1 and PW row 2i - 2 for
+// rows >= j. With col: column j of the current matrix into wp, d[j], and the
+// partial sums [sigma, PV[0] . x, ..., PV[2i - 1] . x] of this workgroup's
+// rows >= j + 2 into part1.
+__global__ __launch_bounds__(256) void k_trd_col(const double *__restrict__ A, int64_t lda, int n, int j, int i,
+                                                 int col, TrdVec V, TrdPanel P)
 {
-    const int lane = threadIdx.x & 63;
-    const int r = j + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= n) return;   // the whole wave
-    double *row = A + (int64_t)r * lda;
-    const double vr = upd ? V.vp[r] : 0.0, wr = upd ? V.wp[r] : 0.0;
-    double s = 0.0;
-    for (int c = j + 1 + lane; c < n; c += 64) {
-        double a = row[c];
-        if (upd) {
-            a = a - vr * V.wp[c] - wr * V.vp[c];
-            row[c] = a;
+    __shared__ double vw[2 * TRD_NB];   // v_k[j], w_k[j], k < i
+    __shared__ double xs[TRD_CR], ws[TRD_CR];
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int r0 = j + (int)blockIdx.x * TRD_CR, r = r0 + t;
+    const bool in = r < n;
+    double wr = 0.0;
+    if (i > 0) {
+        // -(tau / 2)(p . v) of reflector j - 1 from the pass kernel's partial sums
+        const int g2 = (n - j + 3) / 4;
+        const double al = -0.5 * V.tau[j - 1] * blk_sum(ordered_sum(P.part2, 1, t, g2, 256), red);
+        const double *vq = P.PV + (int64_t)(2 * i - 2) * P.ldp;
+        if (in) {
+            wr = V.p[r] + al * vq[r];
+            P.PV[(int64_t)(2 * i - 1) * P.ldp + r] = wr;
+            P.PW[(int64_t)(2 * i - 2) * P.ldp + r] = wr;
         }
-        s += a * V.vn[c];
+        if (col && t == 0) {
+            vw[2 * i - 2] = vq[j];
+            vw[2 * i - 1] = V.p[j] + al * vq[j];
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) V.p[r] = V.tau[j] * s;
+    if (!col) return;
+    for (int e = t; e < 2 * i - 2; e += 256) vw[e] = P.PV[(int64_t)e * P.ldp + j];
+    __syncthreads();
+    double x = 0.0;
+    if (in) {
+        x = A[(int64_t)r * lda + j];
+#pragma unroll 4
+        for (int k = 0; k < i - 1; ++k)
+            x -= P.PV[(int64_t)(2 * k) * P.ldp + r] * vw[2 * k + 1] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * vw[2 * k];
+        if (i > 0) x -= P.PV[(int64_t)(2 * i - 2) * P.ldp + r] * vw[2 * i - 1] + wr * vw[2 * i - 2];
+        V.wp[r] = x;
+        if (r == j) V.d[j] = x;
+    }
+    if (j >= n - 1) return;   // the last column has no reflector (one workgroup)
+    const bool below = in && r >= j + 2;
+    xs[t] = below ? x : 0.0;
+    ws[t] = below ? wr : 0.0;
+    const double sig = blk_sum(below ? x * x : 0.0, red);   // (its barriers publish xs, ws)
+    // PV[q] . x over this workgroup's rows: thread (q = t mod 64, g = t / 64)
+    // over the 64 rows 64 g .. 64 g + 63, then the four groups in order
+    const int q = t & 63, g = t >> 6;
+    double y = 0.0;
+    if (q < 2 * i - 1) {
+        const double *pr = P.PV + (int64_t)q * P.ldp;
+        const int lo = max(0, j + 2 - r0 - 64 * g), hi = min(64, n - r0 - 64 * g);
+#pragma unroll 16
+        for (int k = lo; k < hi; ++k) y += pr[r0 + 64 * g + k] * xs[64 * g + k];
+    } else if (q == 2 * i - 1) {   // w_{i-1}, kept in ws
+#pragma unroll 16
+        for (int k = 0; k < 64; ++k) y += ws[64 * g + k] * xs[64 * g + k];
+    }
+    __syncthreads();
+    red[t] = y;
+    __syncthreads();
+    double *out = P.part1 + (int64_t)blockIdx.x * TRD_PS;
+    if (t == 0) out[0] = sig;
+    if (t < 2 * i) out[1 + t] = red[t] + red[64 + t] + red[128 + t] + red[192 + t];
+}
+
+// rows r of the trailing block (j, n), one wave per row, lanes over the
+// columns, fixed-order reductions. Every workgroup first forms the reflector
+// of column j from the column kernel's partial sums (workgroup 0 stores e[j]
+// and tau[j]) and z; then v_j[r] into column j of A and the panel buffers,
+// p[r] = tau_j (A_0[r][j+1:] . v_j - sum_k (v_k[r] (w_k . v_j) + w_k[r]
+// (v_k . v_j))), and this workgroup's partial sum of p . v_j into part2.
+__global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_t lda, int n, int j, int i, TrdVec V,
+                                                  TrdPanel P)
+{
+    __shared__ double red[TRD_PS];
+    __shared__ double zs[2 * TRD_NB];
+    __shared__ double sc[2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int g1 = (n - j + TRD_CR - 1) / TRD_CR;
+    if (t < 2 * i + 1) red[t] = ordered_sum(P.part1 + t, TRD_PS, 0, g1, 1);
+    __syncthreads();
+    if (t == 0) {
+        const double sig = red[0], alpha = V.wp[j + 1];
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (sig > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        sc[0] = scale;
+        sc[1] = tau;
+        if (blockIdx.x == 0) {
+            V.e[j] = beta;
+            V.tau[j] = tau;
+        }
+    }
+    __syncthreads();
+    const double scale = sc[0], tau = sc[1];
+    // z[d] = PV[d] . v_j with v_j[j + 1] = 1 and v_j = scale x below
+    if (t < 2 * i) zs[t] = P.PV[(int64_t)t * P.ldp + j + 1] + scale * red[t + 1];
+    __syncthreads();
+    const int r = j + 1 + (int)blockIdx.x * 4 + wv;
+    double pv = 0.0;
+    if (r < n) {
+        double *row = A + (int64_t)r * lda;
+        double s = 0.0;
+#pragma unroll 8
+        for (int c = j + 1 + lane; c < n; c += 64) {
+            const double v = c == j + 1 ? 1.0 : V.wp[c] * scale;
+            s += row[c] * v;
+        }
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        double q = 0.0;
+        if (lane < i) {
+            const double *pk = P.PV + (int64_t)(2 * lane) * P.ldp;
+            q = pk[r] * zs[2 * lane + 1] + pk[P.ldp + r] * zs[2 * lane];
+        }
+        for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+        const double vr = r == j + 1 ? 1.0 : V.wp[r] * scale;
+        const double p = tau * (s - q);
+        if (lane == 0) {
+            V.p[r] = p;
+            row[j] = vr;   // kept for the back-transformation
+            P.PV[(int64_t)(2 * i) * P.ldp + r] = vr;
+            P.PW[(int64_t)(2 * i + 1) * P.ldp + r] = vr;
+        }
+        pv = p * vr;
+    }
+    __syncthreads();
+    if (lane == 0) red[wv] = pv;
+    __syncthreads();
+    if (t == 0) P.part2[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// columns j0 .. j0 + nbp - 1 of the reduction, then the update of the
+// trailing block [j0 + nbp, n)^2
+hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, const TrdVec &V, const TrdPanel &P,
+                            hipStream_t st)
+{
+    for (int i = 0; i < nbp; ++i) {
+        const int j = j0 + i;
+        hipLaunchKernelGGL(k_trd_col, dim3((n - j + TRD_CR - 1) / TRD_CR), dim3(256), 0, st, A, lda, n, j, i, 1, V,
+                           P);
+        if (j < n - 1)
+            hipLaunchKernelGGL(k_trd_pass, dim3((n - j - 1 + 3) / 4), dim3(256), 0, st, A, lda, n, j, i, V, P);
+    }
+    const int t = j0 + nbp;
+    if (t < n) {
+        // w of the panel's last reflector, then A -= PV^T PW on the trailing block
+        hipLaunchKernelGGL(k_trd_col, dim3((n - t + TRD_CR - 1) / TRD_CR), dim3(256), 0, st, A, lda, n, t, nbp, 0, V,
+                           P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_eig_gemm(n - t, n - t, 2 * nbp, -1.0, P.PV + t, 1, P.ldp, P.PW + t, P.ldp, 1, 1.0,
+                               A + (int64_t)t * lda + t, lda, st, nullptr, 0);
+    }
+    return hipGetLastError();
 }
 
 // W = (W + W^T) / 2 in place (the operation is defined on a symmetric matrix)
@@ -255,15 +373,6 @@ hipError_t launch_symmetrize(double *W, int64_t ld, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_trd_step(double *A, int64_t lda, int n, int j, const TrdVec &V, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_trd_col, dim3(1), dim3(256), 0, st, A, lda, n, j, V);
-    if (j < n - 1) {
-        const int rows = n - j - 1;
-        hipLaunchKernelGGL(k_trd_pass, dim3((rows + 3) / 4), dim3(256), 0, st, A, lda, n, j, j > 0 ? 1 : 0, V);
-    }
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // 2. eigenvalues of the tridiagonal T (diagonal d[0..n), off-diagonal e[0..n-1))
@@ -414,46 +523,97 @@ hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int
 
 // modified Gram-Schmidt over the columns cols[0..nc) of Z (one cluster of
 // close eigenvalues inside the unreduced block of rows [b0, b0 + m)), in
-// order. A column that loses almost all of its norm to the ones before it
-// (nearly parallel twisted vectors) is replaced by a fixed spread vector on
-// the block's rows and orthogonalised again.
+// order, each column projected twice. A column that keeps less than half of
+// its norm after the projection has collapsed towards the ones before it
+// (twisted vectors of nearly equal eigenvalues can come out nearly
+// parallel): it is refined by two steps of inverse iteration with its own
+// eigenvalue, each followed by the projection, from what is left of it, or
+// from a fixed spread vector when almost nothing is left. The solve is
+// (T_b - lambda I) y = x by the LDL^T recurrence with pivots floored at
+// piv (one thread; rare path), the product kept in Z, the pivots in column c
+// of S.
+__device__ __forceinline__ double mgs_project(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int a,
+                                              int c, double *red)
+{
+    const int t = threadIdx.x;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int q = 0; q < a; ++q) {
+            const int cq = cols[q];
+            double s = 0.0;
+            for (int i = b0 + t; i < b0 + m; i += 256) s += Z[(int64_t)i * ldz + cq] * Z[(int64_t)i * ldz + c];
+            const double dot = blk_sum(s, red);
+            for (int i = b0 + t; i < b0 + m; i += 256) Z[(int64_t)i * ldz + c] -= dot * Z[(int64_t)i * ldz + cq];
+            __syncthreads();
+        }
+    double s = 0.0;
+    for (int i = b0 + t; i < b0 + m; i += 256) s += Z[(int64_t)i * ldz + c] * Z[(int64_t)i * ldz + c];
+    return blk_sum(s, red);
+}
+
+__device__ __forceinline__ void mgs_scale(double *Z, int64_t ldz, int b0, int m, int c, double nrm2)
+{
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    for (int i = b0 + threadIdx.x; i < b0 + m; i += 256) Z[(int64_t)i * ldz + c] *= inv;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_cluster_mgs(double *__restrict__ Z, int64_t ldz, int b0, int m,
-                                                     const int32_t *__restrict__ cols, int nc)
+                                                     const int32_t *__restrict__ cols, int nc,
+                                                     const double *__restrict__ dg, const double *__restrict__ eg,
+                                                     const double *__restrict__ w, double *__restrict__ S,
+                                                     int64_t lds, double piv)
 {
     __shared__ double red[4];
     const int t = threadIdx.x;
     for (int a = 0; a < nc; ++a) {
         const int c = cols[a];
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int q = 0; q < a; ++q) {
-                const int cq = cols[q];
-                double s = 0.0;
-                for (int i = b0 + t; i < b0 + m; i += 256) s += Z[(int64_t)i * ldz + cq] * Z[(int64_t)i * ldz + c];
-                const double dot = blk_sum(s, red);
-                for (int i = b0 + t; i < b0 + m; i += 256) Z[(int64_t)i * ldz + c] -= dot * Z[(int64_t)i * ldz + cq];
+        double nrm2 = mgs_project(Z, ldz, b0, m, cols, a, c, red);
+        if (a > 0 && nrm2 < 0.25) {
+            if (nrm2 <= 1e-6) {
+                for (int i = b0 + t; i < b0 + m; i += 256)
+                    Z[(int64_t)i * ldz + c] = sin(1.0 + 0.7 * (double)(i - b0) + 1.3 * (double)a);
                 __syncthreads();
+                nrm2 = mgs_project(Z, ldz, b0, m, cols, a, c, red);
             }
-            double s = 0.0;
-            for (int i = b0 + t; i < b0 + m; i += 256) s += Z[(int64_t)i * ldz + c] * Z[(int64_t)i * ldz + c];
-            const double nrm2 = blk_sum(s, red);
-            if (nrm2 > 1e-6 || pass == 1) {
-                const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-                for (int i = b0 + t; i < b0 + m; i += 256) Z[(int64_t)i * ldz + c] *= inv;
+            for (int it = 0; it < 2; ++it) {
+                mgs_scale(Z, ldz, b0, m, c, nrm2);
+                if (t == 0) {
+                    const double lam = w[c];
+                    const double *d = dg + b0, *e = eg + b0;
+                    double *z = Z + (int64_t)b0 * ldz + c, *dp = S + (int64_t)b0 * lds + c;
+                    // forward: L z' = z and the pivots
+                    double p = d[0] - lam;
+                    if (fabs(p) < piv) p = p < 0.0 ? -piv : piv;
+                    dp[0] = p;
+                    for (int i = 1; i < m; ++i) {
+                        const double l = e[i - 1] / p;
+                        z[(int64_t)i * ldz] -= l * z[(int64_t)(i - 1) * ldz];
+                        p = d[i] - lam - l * e[i - 1];
+                        if (fabs(p) < piv) p = p < 0.0 ? -piv : piv;
+                        dp[(int64_t)i * lds] = p;
+                    }
+                    // backward: D L^T y = z'
+                    double y = z[(int64_t)(m - 1) * ldz] / dp[(int64_t)(m - 1) * lds];
+                    z[(int64_t)(m - 1) * ldz] = y;
+                    for (int i = m - 2; i >= 0; --i) {
+                        const double q = dp[(int64_t)i * lds];
+                        y = z[(int64_t)i * ldz] / q - (e[i] / q) * y;
+                        z[(int64_t)i * ldz] = y;
+                    }
+                }
                 __syncthreads();
-                break;
+                nrm2 = mgs_project(Z, ldz, b0, m, cols, a, c, red);
             }
-            // nearly inside the span of the earlier columns: restart from a spread vector
-            for (int i = b0 + t; i < b0 + m; i += 256)
-                Z[(int64_t)i * ldz + c] = sin(1.0 + 0.7 * (double)(i - b0) + 1.3 * (double)a);
-            __syncthreads();
         }
+        mgs_scale(Z, ldz, b0, m, c, nrm2);
     }
 }
 
-hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, hipStream_t st)
+hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, const double *d,
+                              const double *e, const double *w, double *S, int64_t lds, double piv, hipStream_t st)
 {
     if (nc < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(256), 0, st, Z, ldz, b0, m, cols, nc);
+    hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(256), 0, st, Z, ldz, b0, m, cols, nc, d, e, w, S, lds, piv);
     return hipGetLastError();
 }
 
