@@ -195,6 +195,7 @@ class Context:
         if rc != CCH_OK:
             raise CchError(rc, lib.cch_last_error(None).decode())
         self.h = h
+        self.device = device
 
     def close(self):
         if getattr(self, "h", None):
@@ -422,9 +423,29 @@ class Context:
                 "class4_outputs", "l2_lower_elements", "sym_pairs"]
         return dict(zip(keys, out.tolist()))
 
-    def eig_all(self, A=None, vectors=True):
+    def eig_all(self, A=None, vectors=True, device=False):
         """cch_eig_all: (eigenvalues ascending, eigenvectors as rows or None,
-        EigInfo) of a host matrix A, or of the built matrix when A is None."""
+        EigInfo) of a host matrix A, or of the built matrix when A is None.
+        With device=True the results are float64 torch tensors on the
+        context's GPU (A, if given, is then such a tensor too)."""
+        if device:
+            import torch
+            dev = torch.device("cuda", self.device)
+            if A is None:
+                n, _ = self.dim()
+                pa, lda = None, 0
+            else:
+                A = A.to(device=dev, dtype=torch.float64).contiguous()
+                n = A.shape[0]
+                pa, lda = C.c_void_p(A.data_ptr()), A.shape[1]
+            w = torch.zeros(n, dtype=torch.float64, device=dev)
+            V = torch.zeros((n, n), dtype=torch.float64, device=dev) if vectors else None
+            torch.cuda.synchronize(dev)
+            info = EigInfo()
+            self._ck(lib.cch_eig_all(self.h, pa, lda, n if A is not None else 0, C.c_void_p(w.data_ptr()),
+                                     C.c_void_p(V.data_ptr()) if vectors else None, n, CCH_MEM_DEVICE,
+                                     C.byref(info)))
+            return w, V, info
         if A is None:
             n, _ = self.dim()
             pa, lda = None, 0

@@ -129,7 +129,7 @@ hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, 
 hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int32_t *bs, const int32_t *bm,
                               const double *w, double pivmin, double *Z, int64_t ldz, double *S, int64_t lds,
                               hipStream_t st);
-hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, const double *d,
+hipError_t launch_cluster_mgs(double *Z, int64_t ldz, const int32_t *desc, int ncl, const int32_t *cols, const double *d,
                               const double *e, const double *w, double *S, int64_t lds, double piv, hipStream_t st);
 hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, int nb, double *Vb, hipStream_t st);
 hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st);
@@ -1988,17 +1988,20 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
             }
         }
         if (!cl.empty()) {
+            // the columns, then the descriptors (offset, count, block start, block rows)
+            std::vector<int32_t> lists(cl_cols);
+            for (auto &q : cl) lists.insert(lists.end(), q.begin(), q.end());
             int32_t *d_cl = nullptr;
-            if (!al((void **)&d_cl, 4 * cl_cols.size())) {
+            if (!al((void **)&d_cl, 4 * lists.size())) {
                 evclean();
                 cleanup();
                 return fail(c, CCH_E_OOM, "eigensolver cluster lists");
             }
-            EGK(hipMemcpyAsync(d_cl, cl_cols.data(), 4 * cl_cols.size(), hipMemcpyHostToDevice, st));
+            EGK(hipMemcpyAsync(d_cl, lists.data(), 4 * lists.size(), hipMemcpyHostToDevice, st));
             // pivot floor of the inverse-iteration solves: the rounding of ||T||
             const double piv = 2.220446049250313e-16 * std::max(tnorm, 1e-300);
-            for (auto &q : cl)
-                EGK(launch_cluster_mgs(Z, ld, q[2], q[3], d_cl + q[0], q[1], tv.d, tv.e, w_d, S, ld, piv, st));
+            EGK(launch_cluster_mgs(Z, ld, d_cl + cl_cols.size(), (int)cl.size(), d_cl, tv.d, tv.e, w_d, S, ld, piv,
+                                   st));
         }
         // Z = Q Z_T: the blocks of reflectors from the last to the first
         const int nref = n - 1;

@@ -395,23 +395,39 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d, const d
 }
 
 // eigenvalue t: the k-th (ascending) of the block starting at row b0 with m
-// rows, by bisection on [lo, hi] to the last bits
-__global__ void k_tri_bisect(const double *__restrict__ d, const double *__restrict__ e2, int n,
-                             const int32_t *__restrict__ bs, const int32_t *__restrict__ bm,
-                             const int32_t *__restrict__ bk, double lo0, double hi0, double pivmin,
-                             double *__restrict__ w)
+// rows, by multisection on [lo, hi]: the TRI_G lanes of a group evaluate the
+// Sturm count at TRI_G interior points, and the interval shrinks to the piece
+// between the last point with count <= k and the first with count > k, until
+// no representable point lies strictly inside. With monotone counts this ends
+// on the same pair of adjacent doubles as bisection, in about a quarter of
+// the dependent steps.
+constexpr int TRI_G = 16;
+__global__ __launch_bounds__(256) void k_tri_bisect(const double *__restrict__ d, const double *__restrict__ e2, int n,
+                                                    const int32_t *__restrict__ bs, const int32_t *__restrict__ bm,
+                                                    const int32_t *__restrict__ bk, double lo0, double hi0,
+                                                    double pivmin, double *__restrict__ w)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = gt / TRI_G, g = gt % TRI_G;
+    if (t >= n) return;   // (whole groups)
     const int b0 = bs[t], m = bm[t], k = bk[t];
+    const double f = (double)(g + 1) / (double)(TRI_G + 1);
     double lo = lo0, hi = hi0;
     for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;   // the interval is two adjacent doubles
-        if (sturm_count(d + b0, e2 + b0, m, mid, pivmin) > k) hi = mid;
-        else lo = mid;
+        const double x = lo + (hi - lo) * f;
+        const bool in = x > lo && x < hi;
+        int any = in;
+        for (int o = 1; o < TRI_G; o <<= 1) any |= __shfl_xor(any, o, TRI_G);
+        if (!any) break;   // lo and hi are adjacent doubles
+        const int cnt = in ? sturm_count(d + b0, e2 + b0, m, x, pivmin) : 0;
+        double h = in && cnt > k ? x : hi;
+        for (int o = 1; o < TRI_G; o <<= 1) h = fmin(h, __shfl_xor(h, o, TRI_G));
+        double l = in && cnt <= k && x < h ? x : lo;
+        for (int o = 1; o < TRI_G; o <<= 1) l = fmax(l, __shfl_xor(l, o, TRI_G));
+        lo = l;
+        hi = h;
     }
-    w[t] = 0.5 * (lo + hi);
+    if (g == 0) w[t] = 0.5 * (lo + hi);
 }
 
 __global__ void k_tri_prep(const double *__restrict__ e, int n, double *__restrict__ e2)
@@ -428,7 +444,8 @@ hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, 
 {
     if (n <= 0) return hipSuccess;
     if (n > 1) hipLaunchKernelGGL(k_tri_prep, dim3((n + 255) / 256), dim3(256), 0, st, e, n, e2);
-    hipLaunchKernelGGL(k_tri_bisect, dim3((n + 63) / 64), dim3(64), 0, st, d, e2, n, bs, bm, bk, lo, hi, pivmin, w);
+    hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)(((int64_t)n * TRI_G + 255) / 256)), dim3(256), 0, st, d, e2, n,
+                       bs, bm, bk, lo, hi, pivmin, w);
     return hipGetLastError();
 }
 
@@ -557,14 +574,21 @@ __device__ __forceinline__ void mgs_scale(double *Z, int64_t ldz, int b0, int m,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_cluster_mgs(double *__restrict__ Z, int64_t ldz, int b0, int m,
-                                                     const int32_t *__restrict__ cols, int nc,
+// one workgroup per cluster; cluster b is desc[4b .. 4b + 3] = (offset of its
+// columns in cols_all, number of columns, block start, block rows). The
+// clusters have disjoint columns (of Z and of S) and run concurrently.
+__global__ __launch_bounds__(256) void k_cluster_mgs(double *__restrict__ Z, int64_t ldz,
+                                                     const int32_t *__restrict__ desc,
+                                                     const int32_t *__restrict__ cols_all,
                                                      const double *__restrict__ dg, const double *__restrict__ eg,
                                                      const double *__restrict__ w, double *__restrict__ S,
                                                      int64_t lds, double piv)
 {
     __shared__ double red[4];
     const int t = threadIdx.x;
+    const int32_t *dsc = desc + 4 * (int64_t)blockIdx.x;
+    const int32_t *cols = cols_all + dsc[0];
+    const int nc = dsc[1], b0 = dsc[2], m = dsc[3];
     for (int a = 0; a < nc; ++a) {
         const int c = cols[a];
         double nrm2 = mgs_project(Z, ldz, b0, m, cols, a, c, red);
@@ -609,11 +633,12 @@ __global__ __launch_bounds__(256) void k_cluster_mgs(double *__restrict__ Z, int
     }
 }
 
-hipError_t launch_cluster_mgs(double *Z, int64_t ldz, int b0, int m, const int32_t *cols, int nc, const double *d,
-                              const double *e, const double *w, double *S, int64_t lds, double piv, hipStream_t st)
+hipError_t launch_cluster_mgs(double *Z, int64_t ldz, const int32_t *desc, int ncl, const int32_t *cols,
+                              const double *d, const double *e, const double *w, double *S, int64_t lds, double piv,
+                              hipStream_t st)
 {
-    if (nc < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(256), 0, st, Z, ldz, b0, m, cols, nc, d, e, w, S, lds, piv);
+    if (ncl <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cluster_mgs, dim3(ncl), dim3(256), 0, st, Z, ldz, desc, cols, d, e, w, S, lds, piv);
     return hipGetLastError();
 }
 
@@ -646,21 +671,25 @@ hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, i
 // T (nb x nb, upper triangular) of the compact WY form from the Gram matrix
 // G = Vb^T Vb and the scalars tau: T[i][i] = tau_i,
 // T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-// one workgroup, T built in LDS column by column (thread r forms entry r of
-// column i; the sum over q runs in order)
+// one workgroup, G and T in LDS, T built column by column (thread r forms
+// entry r of column i; the sum over q runs in order)
 constexpr int LARFT_MAX = 64;
 __global__ __launch_bounds__(64) void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb,
                                               double *__restrict__ T)
 {
     __shared__ double Ts[LARFT_MAX][LARFT_MAX + 1];
+    __shared__ double Gs[LARFT_MAX][LARFT_MAX + 1];
+    __shared__ double ts[LARFT_MAX];
     const int r = threadIdx.x;
     for (int c = 0; c < nb; ++c) Ts[r][c] = 0.0;
+    for (int e = r; e < nb * nb; e += 64) Gs[e / nb][e % nb] = G[e];
+    if (r < nb) ts[r] = tau[r];
     __syncthreads();
     for (int i = 0; i < nb; ++i) {
-        const double ti = tau[i];
+        const double ti = ts[i];
         if (r < i) {
             double s = 0.0;
-            for (int q = r; q < i; ++q) s += Ts[r][q] * G[q * nb + i];
+            for (int q = r; q < i; ++q) s += Ts[r][q] * Gs[q][i];
             Ts[r][i] = -ti * s;
         } else if (r == i) {
             Ts[r][i] = ti;

@@ -148,6 +148,10 @@ def test_device_arrays_and_refusals():
                                 C.c_void_p(tV.data_ptr()), n, cc.CCH_MEM_DEVICE, None)
         assert rc == cc.CCH_OK
         assert np.array_equal(tw.cpu().numpy(), w_h) and np.array_equal(tV.cpu().numpy(), V_h)
+        # the binding's device form: tensors in and out
+        w_t, V_t, _ = ctx.eig_all(tA, device=True)
+        assert w_t.is_cuda and V_t.is_cuda
+        assert np.array_equal(w_t.cpu().numpy(), w_h) and np.array_equal(V_t.cpu().numpy(), V_h)
         bad = M.copy()
         bad[3, 4] = bad[4, 3] = np.nan
         with pytest.raises(cc.CchError) as e:
