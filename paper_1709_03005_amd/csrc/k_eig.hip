@@ -263,11 +263,13 @@ __global__ __launch_bounds__(256) void k_trd_col(const double *__restrict__ A, i
 }
 
 // rows r of the trailing block (j, n), one wave per row, lanes over the
-// columns, fixed-order reductions. Every workgroup first forms the reflector
-// of column j from the column kernel's partial sums (workgroup 0 stores e[j]
-// and tau[j]) and z; then v_j[r] into column j of A and the panel buffers,
-// p[r] = tau_j (A_0[r][j+1:] . v_j - sum_k (v_k[r] (w_k . v_j) + w_k[r]
-// (v_k . v_j))), and this workgroup's partial sum of p . v_j into part2.
+// columns, fixed-order reductions: v_j[r] into column j of A and the panel
+// buffers, p[r] = tau_j (A_0[r][j+1:] . v_j - sum_k (v_k[r] (w_k . v_j) +
+// w_k[r] (v_k . v_j))), and this workgroup's partial sum of p . v_j into
+// part2. The row is streamed first as A_0[r][j+1] + scale (A_0[r][j+2:] . x)
+// (v_j = 1 at row j + 1 and scale x below), while every workgroup forms the
+// reflector of column j from the column kernel's partial sums (workgroup 0
+// stores e[j] and tau[j]) and z.
 __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_t lda, int n, int j, int i, TrdVec V,
                                                   TrdPanel P)
 {
@@ -276,10 +278,40 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
     __shared__ double sc[2];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int g1 = (n - j + TRD_CR - 1) / TRD_CR;
-    if (t < 2 * i + 1) red[t] = ordered_sum(P.part1 + t, TRD_PS, 0, g1, 1);
+    const int r = j + 1 + (int)blockIdx.x * 4 + wv;
+    const bool in = r < n;
+    // loads first: the partial sums, z's panel entries at row j + 1, alpha,
+    // this row's panel entries and x at this row
+    double ps = 0.0;
+    if (t < 2 * i + 1) {
+        double u[32];
+#pragma unroll
+        for (int b = 0; b < 32; ++b) u[b] = b < g1 ? P.part1[(int64_t)b * TRD_PS + t] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 32; ++b) ps += u[b];
+        for (int b = 32; b < g1; ++b) ps += P.part1[(int64_t)b * TRD_PS + t];
+    }
+    const double pz = t < 2 * i ? P.PV[(int64_t)t * P.ldp + j + 1] : 0.0;
+    const double alpha = t == 0 ? V.wp[j + 1] : 0.0;
+    double k0 = 0.0, k1 = 0.0, xr = 0.0;
+    if (in && lane < i) {
+        k0 = P.PV[(int64_t)(2 * lane) * P.ldp + r];
+        k1 = P.PV[(int64_t)(2 * lane + 1) * P.ldp + r];
+    }
+    if (in) xr = V.wp[r];
+    // the row: A_0[r][j+1] and A_0[r][j+2:] . x
+    double s1 = 0.0, s2 = 0.0;
+    if (in) {
+        const double *row = A + (int64_t)r * lda;
+        if (lane == 0) s1 = row[j + 1];
+#pragma unroll 8
+        for (int c = j + 2 + lane; c < n; c += 64) s2 += row[c] * V.wp[c];
+        for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    }
+    if (t < 2 * i + 1) red[t] = ps;
     __syncthreads();
     if (t == 0) {
-        const double sig = red[0], alpha = V.wp[j + 1];
+        const double sig = red[0];
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (sig > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + sig), alpha);
@@ -296,30 +328,18 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
     __syncthreads();
     const double scale = sc[0], tau = sc[1];
     // z[d] = PV[d] . v_j with v_j[j + 1] = 1 and v_j = scale x below
-    if (t < 2 * i) zs[t] = P.PV[(int64_t)t * P.ldp + j + 1] + scale * red[t + 1];
+    if (t < 2 * i) zs[t] = pz + scale * red[t + 1];
     __syncthreads();
-    const int r = j + 1 + (int)blockIdx.x * 4 + wv;
     double pv = 0.0;
-    if (r < n) {
-        double *row = A + (int64_t)r * lda;
-        double s = 0.0;
-#pragma unroll 8
-        for (int c = j + 1 + lane; c < n; c += 64) {
-            const double v = c == j + 1 ? 1.0 : V.wp[c] * scale;
-            s += row[c] * v;
-        }
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        double q = 0.0;
-        if (lane < i) {
-            const double *pk = P.PV + (int64_t)(2 * lane) * P.ldp;
-            q = pk[r] * zs[2 * lane + 1] + pk[P.ldp + r] * zs[2 * lane];
-        }
+    if (in) {
+        double q = lane < i ? k0 * zs[2 * lane + 1] + k1 * zs[2 * lane] : 0.0;
         for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
-        const double vr = r == j + 1 ? 1.0 : V.wp[r] * scale;
-        const double p = tau * (s - q);
+        const double sr = __shfl(s1, 0, 64) + scale * s2;
+        const double vr = r == j + 1 ? 1.0 : xr * scale;
+        const double p = tau * (sr - q);
         if (lane == 0) {
             V.p[r] = p;
-            row[j] = vr;   // kept for the back-transformation
+            A[(int64_t)r * lda + j] = vr;   // kept for the back-transformation
             P.PV[(int64_t)(2 * i) * P.ldp + r] = vr;
             P.PW[(int64_t)(2 * i + 1) * P.ldp + r] = vr;
         }
