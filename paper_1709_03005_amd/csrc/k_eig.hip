@@ -1,16 +1,16 @@
 // Every eigenpair of a dense real symmetric matrix in FP64 on one GPU (the
 // paper's Sec. 3.2 notes that often all eigenvectors are wanted and a dense
 // diagonaliser is used then):
-//   1. Householder tridiagonalisation Q^T A Q = T, one reflector per column.
-//      Each column takes two launches: a one-workgroup step that applies the
-//      previous reflector to the new column, finishes the previous w vector
-//      and forms the new reflector; and a pass over the trailing block that
-//      applies the previous rank-2 update to every row and, from the updated
-//      row, forms the product with the new reflector (one read and one write
-//      of the trailing block per column, the HBM-bound part).
-//   2. Eigenvalues of T by bisection on Sturm counts, one thread each.
+//   1. Householder tridiagonalisation Q^T A Q = T, one reflector per column,
+//      blocked in panels of TRD_NB columns with lazy updates: two launches
+//      per column spread over the rows (the corrected column with its
+//      partial sums; the product of the trailing block with the reflector,
+//      one read of it per column, the HBM-bound part) and one rank-2 TRD_NB
+//      FP64 MFMA update of the trailing block per panel.
+//   2. Eigenvalues of T by multisection on Sturm counts, 16 lanes each.
 //   3. Eigenvectors of T by twisted factorisations, one thread each, with
-//      modified Gram-Schmidt inside clusters of close eigenvalues.
+//      modified Gram-Schmidt (and inverse iteration for vectors that
+//      collapse) inside clusters of close eigenvalues, one workgroup each.
 //   4. Back-transformation Z = Q Z_T in blocks of 64 reflectors, each as
 //      I - V T V^T (compact WY) by three FP64 MFMA products.
 #include <algorithm>
@@ -702,7 +702,10 @@ __global__ __launch_bounds__(64) void k_larft(const double *__restrict__ G, cons
     __shared__ double ts[LARFT_MAX];
     const int r = threadIdx.x;
     for (int c = 0; c < nb; ++c) Ts[r][c] = 0.0;
-    for (int e = r; e < nb * nb; e += 64) Gs[e / nb][e % nb] = G[e];
+    // G row by row, a row per pass of the 64 threads (the loads batched)
+#pragma unroll 16
+    for (int q = 0; q < nb; ++q)
+        if (r < nb) Gs[q][r] = G[q * nb + r];
     if (r < nb) ts[r] = tau[r];
     __syncthreads();
     for (int i = 0; i < nb; ++i) {
