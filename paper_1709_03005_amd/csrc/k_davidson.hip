@@ -517,8 +517,39 @@ hipError_t launch_tn(const double *X1, int64_t ldx1, int na1, const double *X2, 
 // where V[q] = V1[q] for q < m1 and V2[q - m1] for m1 <= q < m
 // grid (D/256, ceil(ne/NE)): NE outputs per thread, C slice staged in LDS.
 // Each grid row reads every input vector once, so wider slices read them
-// fewer times; the sum over q runs in the same order for any NE.
+// fewer times; the sum over q runs in the same order for any NE. A thread
+// loads NN_QB rows of V at a time before it multiplies (one row per step
+// left a wave with a single load in flight, at about one wave per SIMD).
 // ---------------------------------------------------------------------------
+constexpr int NN_QB = 16;
+
+// acc[e] += V[q][i] cs[q][e] for q in [q0, q1), V[q] = Vp[(q - qoff) ldv]
+template <int NE>
+__device__ __forceinline__ void nn_accum(const double *__restrict__ Vp, int64_t ldv, int q0, int q1, int qoff, int i,
+                                         const double *cs, double (&acc)[NE])
+{
+    int q = q0;
+    for (; q + NN_QB <= q1; q += NN_QB) {
+        double v[NN_QB];
+#pragma unroll
+        for (int u = 0; u < NN_QB; ++u) v[u] = Vp[(int64_t)(q + u - qoff) * ldv + i];
+        __builtin_amdgcn_sched_barrier(0);   // all NN_QB loads go out before the products
+#pragma unroll
+        for (int u = 0; u < NN_QB; ++u) {
+            double c[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) c[e] = cs[(q + u) * NE + e];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) acc[e] = fma(v[u], c[e], acc[e]);
+        }
+    }
+    for (; q < q1; ++q) {
+        const double v = Vp[(int64_t)(q - qoff) * ldv + i];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
+    }
+}
+
 template <int NE>
 __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1, int64_t ldv1, int m1,
                                                   const double *__restrict__ V2, int64_t ldv2, int m, int D,
@@ -543,16 +574,8 @@ __global__ __launch_bounds__(256) void k_nn_small(const double *__restrict__ V1,
     double acc[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) acc[e] = 0.0;
-    for (int q = 0; q < m1; ++q) {
-        const double v = V1[(int64_t)q * ldv1 + i];
-#pragma unroll
-        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
-    }
-    for (int q = m1; q < m; ++q) {
-        const double v = V2[(int64_t)(q - m1) * ldv2 + i];
-#pragma unroll
-        for (int e = 0; e < NE; ++e) acc[e] = fma(v, cs[q * NE + e], acc[e]);
-    }
+    nn_accum<NE>(V1, ldv1, 0, m1, 0, i, cs, acc);
+    if (m1 < m) nn_accum<NE>(V2, ldv2, m1, m, m1, i, cs, acc);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         if (e0 + e < ne) {
