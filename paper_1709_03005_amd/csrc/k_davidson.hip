@@ -278,15 +278,35 @@ __global__ void k_symv_reduce(const double *__restrict__ P1, const double *__res
     const int q = blockIdx.y;
     if (i >= D || q >= b) return;
     const int J = i / SV_CW;
-    double s = 0.0;
     int base = 0;
-    for (int j = 0; j < J; ++j) {
-        s += P2[((int64_t)j * b + q) * D + i];
-        base += sv_items(D, j, rb);
-    }
-    s += P2[((int64_t)J * b + q) * D + i];
+    for (int j = 0; j < J; ++j) base += sv_items(D, j, rb);
     const int n = sv_items(D, J, rb);
-    for (int t = 0; t < n; ++t) s += P1[((int64_t)(base + t) * b + q) * SV_CW + (i - J * SV_CW)];
+    // P2 of strips 0 .. J, then P1 of the items of strip J, in that order;
+    // the loads go out eight at a time (one at a time left about one load in
+    // flight per wave)
+    double s = 0.0;
+    int j = 0;
+    for (; j + 8 <= J + 1; j += 8) {
+        double u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = P2[((int64_t)(j + k) * b + q) * D + i];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += u[k];
+    }
+    for (; j <= J; ++j) s += P2[((int64_t)j * b + q) * D + i];
+    const double *p1 = P1 + ((int64_t)base * b + q) * SV_CW + (i - J * SV_CW);
+    const int64_t st1 = (int64_t)b * SV_CW;
+    int t = 0;
+    for (; t + 8 <= n; t += 8) {
+        double u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = p1[(t + k) * st1];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += u[k];
+    }
+    for (; t < n; ++t) s += p1[t * st1];
     Wo[(int64_t)q * ldw + i] = s;
 }
 
