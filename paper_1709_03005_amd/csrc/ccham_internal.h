@@ -248,18 +248,30 @@ struct TrdVec {
 constexpr int TRD_NB = 32;
 // rows per workgroup of the column kernel, and the stride of its partial sums
 constexpr int TRD_CR = 256, TRD_PS = 2 * TRD_NB + 8;
+// trailing blocks of at least TRD_TILE_MIN rows are multiplied from their
+// lower triangle in TRD_TT x TRD_TT tiles (below that the row pass reads
+// whole rows)
+constexpr int TRD_TT = 128, TRD_TILE_MIN = 3072;
+constexpr int TRD_SR = 32;   // rows per workgroup of the tiled pass's row sums
 struct TrdPanel {
     double *PV, *PW;   // 2 TRD_NB rows each, ldp doubles a row
     int64_t ldp;
     double *z;         // 2 TRD_NB
     double *part1;     // column kernel: TRD_PS partial sums per workgroup
-    double *part2;     // pass kernel: one partial sum per workgroup
+    double *part2;     // row pass: one partial sum per workgroup
+    double *rowp, *colp;   // tiled pass: [tile column][n] row sums, [tile row][n] column sums
+    double *zb;            // tiled pass: [0] scale, [1 + d] z[d] of its reflector
 };
+
+// tiles per side of the tiled pass over m trailing rows
+__host__ __device__ inline int trd_tiles(int m) { return (m + TRD_TT - 1) / TRD_TT; }
 
 // doubles of the panel buffers for dimension n with rows of ldp doubles
 inline size_t trd_panel_doubles(int n, int64_t ldp)
 {
-    return (size_t)4 * TRD_NB * ldp + 2 * TRD_NB + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4;
+    const size_t T = (size_t)trd_tiles(n);
+    return (size_t)4 * TRD_NB * ldp + 2 * TRD_NB + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4 +
+           2 * T * (size_t)n + 2 * TRD_NB + 8;
 }
 
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for

@@ -2,11 +2,13 @@
 // paper's Sec. 3.2 notes that often all eigenvectors are wanted and a dense
 // diagonaliser is used then):
 //   1. Householder tridiagonalisation Q^T A Q = T, one reflector per column,
-//      blocked in panels of TRD_NB columns with lazy updates: two launches
-//      per column spread over the rows (the corrected column with its
-//      partial sums; the product of the trailing block with the reflector,
-//      one read of it per column, the HBM-bound part) and one rank-2 TRD_NB
-//      FP64 MFMA update of the trailing block per panel.
+//      blocked in panels of TRD_NB columns with lazy updates: per column
+//      the corrected column with its partial sums, then the product of the
+//      trailing block with the reflector (the HBM-bound part: from the lower
+//      triangle in tiles, plus a kernel that adds the tiles' partial sums,
+//      while the block has at least TRD_TILE_MIN rows; by whole rows below
+//      that), and one rank-2 TRD_NB FP64 MFMA update of the trailing block
+//      per panel.
 //   2. Eigenvalues of T by multisection on Sturm counts, 16 lanes each.
 //   3. Eigenvectors of T by twisted factorisations, one thread each, with
 //      modified Gram-Schmidt (and inverse iteration for vectors that
@@ -151,14 +153,16 @@ hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, i
 //    w_k (v_k . v_j)); one rank-2 TRD_NB product (FP64 MFMA) updates the
 //    trailing block at the end of the panel. w_j = p - (tau_j / 2)(p . v_j) v_j
 //    with p = tau_j A_j v_j.
-// Two launches per column, both spread over the rows; a workgroup never
-// waits for another one. The column kernel adds the pass kernel's partial
-// sums of p . v (the scalar of the previous w), finishes that w, corrects
-// column j and stores, per workgroup, the partial sums of sigma = |x|^2 over
-// the part to annihilate and of the panel's vectors times it. Every
-// workgroup of the pass kernel adds those partial sums in workgroup order
-// (so all get the same reflector), forms v_j = x / (alpha - beta) as it
-// reads it, the products p and the partial sums of p . v_j.
+// Per column a column kernel and a pass, each spread over the rows; a
+// workgroup never waits for another one. The column kernel adds the pass's
+// partial sums of p . v (the scalar of the previous w), finishes that w,
+// corrects column j and stores, per workgroup, the partial sums of sigma =
+// |x|^2 over the part to annihilate and of the panel's vectors times it.
+// Every workgroup of the pass adds those partial sums in workgroup order (so
+// all get the same reflector) and forms v_j = x / (alpha - beta) as it reads
+// it; the pass leaves p and the partial sums of p . v_j. For trailing blocks
+// of at least TRD_TILE_MIN rows the pass reads only the lower triangle, in
+// tiles, and a second kernel adds each row's tile sums.
 // panel buffers (ldp doubles a row): PV rows 2k, 2k + 1 = v_k, w_k; PW rows
 // 2k, 2k + 1 = w_k, v_k (the update is A -= PV^T PW over 2 nb rows); z[2k] =
 // v_k . v_j, z[2k + 1] = w_k . v_j. Rows of PV and PW below the reflector's
@@ -209,18 +213,21 @@ __global__ __launch_bounds__(256) void k_trd_col(const double *__restrict__ A, i
     const bool in = r < n;
     double wr = 0.0;
     if (i > 0) {
-        // -(tau / 2)(p . v) of reflector j - 1 from the pass kernel's partial sums
-        const int g2 = (n - j + 3) / 4;
-        const double al = -0.5 * V.tau[j - 1] * blk_sum(ordered_sum(P.part2, 1, t, g2, 256), red);
+        // p of reflector j - 1 (rows >= j) and the scalar -(tau / 2)(p . v) of its w
         const double *vq = P.PV + (int64_t)(2 * i - 2) * P.ldp;
+        // (the row pass leaves one partial sum of p . v per 4 rows, the sum
+        // kernel of the tiled pass one per TRD_SR rows)
+        const int g2 = n - j < TRD_TILE_MIN ? (n - j + 3) / 4 : (n - j + TRD_SR - 1) / TRD_SR;
+        const double al = -0.5 * V.tau[j - 1] * blk_sum(ordered_sum(P.part2, 1, t, g2, 256), red);
+        const double pr = in ? V.p[r] : 0.0, pj = t == 0 ? V.p[j] : 0.0;
         if (in) {
-            wr = V.p[r] + al * vq[r];
+            wr = pr + al * vq[r];
             P.PV[(int64_t)(2 * i - 1) * P.ldp + r] = wr;
             P.PW[(int64_t)(2 * i - 2) * P.ldp + r] = wr;
         }
         if (col && t == 0) {
             vw[2 * i - 2] = vq[j];
-            vw[2 * i - 1] = V.p[j] + al * vq[j];
+            vw[2 * i - 1] = pj + al * vq[j];
         }
     }
     if (!col) return;
@@ -351,6 +358,160 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
     if (t == 0) P.part2[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// the product of the trailing block (j, n) with v_j from its lower triangle
+// only, for trailing blocks of at least TRD_TILE_MIN rows: one workgroup per
+// TRD_TT x TRD_TT tile (rt, ct), ct <= rt, of the block (tile rows and columns
+// counted from row j + 1). A tile stores the row sums of its rows (columns up
+// to the diagonal) into rowp[ct], the column sums of its columns (rows below
+// the diagonal) into colp[rt]; k_trd_tile_sum adds them per row in a fixed
+// order. As in the row
+// pass every workgroup first forms the reflector of column j; workgroup 0
+// stores e[j], tau[j], scale and z, and the tiles of column 0 store v_j for
+// their rows.
+__global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, int64_t lda, int n, int j, int i, TrdVec V,
+                                                   TrdPanel P)
+{
+    __shared__ double red[TRD_PS];
+    __shared__ double sc[2];
+    __shared__ double vr[TRD_TT], vc[TRD_TT], rsum[TRD_TT];
+    __shared__ double cs[4][TRD_TT];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int b = blockIdx.x;
+    int rt = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((rt + 1) * (rt + 2) / 2 <= b) ++rt;
+    while (rt * (rt + 1) / 2 > b) --rt;
+    const int ct = b - rt * (rt + 1) / 2;
+    const int R0 = j + 1 + TRD_TT * rt, C0 = j + 1 + TRD_TT * ct;
+    // the reflector of column j (as in the row pass)
+    const int g1 = (n - j + TRD_CR - 1) / TRD_CR;
+    const double ps = t < 2 * i + 1 ? ordered_sum(P.part1 + t, TRD_PS, 0, g1, 1) : 0.0;
+    const double pz = t < 2 * i ? P.PV[(int64_t)t * P.ldp + j + 1] : 0.0;
+    const double alpha = t == 0 ? V.wp[j + 1] : 0.0;
+    const int e = t < TRD_TT ? R0 + t : C0 + t - TRD_TT;   // this thread's row (t < TT) or column of x
+    const double xe = e < n ? V.wp[e] : 0.0;
+    if (t < 2 * i + 1) red[t] = ps;
+    __syncthreads();
+    if (t == 0) {
+        const double sig = red[0];
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (sig > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        sc[0] = scale;
+        if (b == 0) {
+            V.e[j] = beta;
+            V.tau[j] = tau;
+            P.zb[0] = scale;
+        }
+    }
+    __syncthreads();
+    const double scale = sc[0];
+    const double ve = e < n ? (e == j + 1 ? 1.0 : xe * scale) : 0.0;
+    if (t < TRD_TT) vr[t] = ve;
+    else vc[t - TRD_TT] = ve;
+    if (b == 0 && t < 2 * i) P.zb[1 + t] = pz + scale * red[t + 1];
+    if (ct == 0 && t < TRD_TT && e < n) {
+        A[(int64_t)e * lda + j] = ve;   // kept for the back-transformation
+        P.PV[(int64_t)(2 * i) * P.ldp + e] = ve;
+        P.PW[(int64_t)(2 * i + 1) * P.ldp + e] = ve;
+    }
+    __syncthreads();
+    // wave wv: tile rows 32 wv .. 32 wv + 31 in four groups of 8, lanes over
+    // 64 columns at a time; row sums per lane, then over the lanes
+    const bool diag = ct == rt;
+    double colacc[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const int rl0 = 32 * wv + 8 * g;
+        double racc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) racc[u] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) {
+            const int cl = 64 * ch + lane, c = C0 + cl;
+            const double vcl = vc[cl];
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = R0 + rl0 + u;
+                a[u] = (r < n && c < n && (!diag || cl <= rl0 + u)) ? A[(int64_t)r * lda + c] : 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                racc[u] += a[u] * vcl;   // row part: c <= r
+                colacc[ch] += ((!diag || cl < rl0 + u) ? a[u] : 0.0) * vr[rl0 + u];   // column part: r > c
+            }
+        }
+        // the 8 row sums over the 64 lanes (halving exchanges in a fixed pattern)
+        const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+        double h4[4], h2[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            h4[k] = (b5 ? racc[4 + k] : racc[k]) + __shfl_xor(b5 ? racc[k] : racc[4 + k], 32, 64);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) h2[k] = (b4 ? h4[2 + k] : h4[k]) + __shfl_xor(b4 ? h4[k] : h4[2 + k], 16, 64);
+        double h1 = (b3 ? h2[1] : h2[0]) + __shfl_xor(b3 ? h2[0] : h2[1], 8, 64);
+        h1 += __shfl_xor(h1, 4, 64);
+        h1 += __shfl_xor(h1, 2, 64);
+        h1 += __shfl_xor(h1, 1, 64);
+        if ((lane & 7) == 0) rsum[rl0 + 4 * b5 + 2 * b4 + (b3 ? 1 : 0)] = h1;
+    }
+    cs[wv][lane] = colacc[0];
+    cs[wv][64 + lane] = colacc[1];
+    __syncthreads();
+    if (t < TRD_TT) {
+        const int r = R0 + t, c = C0 + t;
+        if (r < n) P.rowp[(int64_t)ct * n + r] = rsum[t];
+        if (c < n) P.colp[(int64_t)rt * n + c] = cs[0][t] + cs[1][t] + cs[2][t] + cs[3][t];
+    }
+}
+
+// p[r] = tau_j (A_0 v_j - sum_k (v_k (w_k . v_j) + w_k (v_k . v_j)))[r] for the
+// rows r of the tiled pass of column j: eight lanes per row add its row sums
+// (tile columns up to its own) and column sums (tile rows from its own down),
+// lane l taking items l, l + 8, ..., then the eight lanes in a fixed pattern;
+// p into V.p and this workgroup's partial sum of p . v_j into part2 (as the
+// row pass leaves them)
+__global__ __launch_bounds__(256) void k_trd_tile_sum(int n, int j, int i, TrdVec V, TrdPanel P)
+{
+    __shared__ double red[256];
+    const int t = threadIdx.x, l = t & 7;
+    const int r = j + 1 + (int)blockIdx.x * TRD_SR + (t >> 3);
+    const int T = trd_tiles(n - j - 1);
+    double s = 0.0, q = 0.0;
+    if (r < n) {
+        const int rt = (r - j - 1) / TRD_TT;
+        // item b <= rt: rowp[b][r]; item b > rt: colp[b - 1][r]
+        for (int b0 = l; b0 <= T; b0 += 32) {
+            double u[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int b = b0 + 8 * k;
+                u[k] = b > T ? 0.0 : (b <= rt ? P.rowp[(int64_t)b * n + r] : P.colp[(int64_t)(b - 1) * n + r]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += u[k];
+        }
+        for (int k = l; k < i; k += 8)
+            q += P.PV[(int64_t)(2 * k) * P.ldp + r] * P.zb[2 + 2 * k] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * P.zb[1 + 2 * k];
+    }
+    for (int o = 4; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 8);
+        q += __shfl_xor(q, o, 8);
+    }
+    double pv = 0.0;
+    if (r < n && l == 0) {
+        const double p = V.tau[j] * (s - q);
+        V.p[r] = p;
+        pv = p * P.PV[(int64_t)(2 * i) * P.ldp + r];
+    }
+    pv = blk_sum(pv, red);   // (rows in order of their first lane; the others add 0)
+    if (t == 0) P.part2[blockIdx.x] = pv;
+}
+
 // columns j0 .. j0 + nbp - 1 of the reduction, then the update of the
 // trailing block [j0 + nbp, n)^2
 hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, const TrdVec &V, const TrdPanel &P,
@@ -360,8 +521,16 @@ hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, cons
         const int j = j0 + i;
         hipLaunchKernelGGL(k_trd_col, dim3((n - j + TRD_CR - 1) / TRD_CR), dim3(256), 0, st, A, lda, n, j, i, 1, V,
                            P);
-        if (j < n - 1)
-            hipLaunchKernelGGL(k_trd_pass, dim3((n - j - 1 + 3) / 4), dim3(256), 0, st, A, lda, n, j, i, V, P);
+        if (j < n - 1) {
+            const int m = n - j - 1;
+            if (m >= TRD_TILE_MIN) {
+                const int T = trd_tiles(m);
+                hipLaunchKernelGGL(k_trd_tiles, dim3(T * (T + 1) / 2), dim3(256), 0, st, A, lda, n, j, i, V, P);
+                hipLaunchKernelGGL(k_trd_tile_sum, dim3((m + TRD_SR - 1) / TRD_SR), dim3(256), 0, st, n, j, i, V, P);
+            } else {
+                hipLaunchKernelGGL(k_trd_pass, dim3((m + 3) / 4), dim3(256), 0, st, A, lda, n, j, i, V, P);
+            }
+        }
     }
     const int t = j0 + nbp;
     if (t < n) {

@@ -4,7 +4,8 @@ that often all eigenvectors are required): eigenvalues against LAPACK
 residual ||A v - lambda v|| and orthonormality within 1e-10 (scaled by the
 spectral radius), and by overlap with LAPACK's where the eigenvalue is well
 separated. Random matrices of sizes 1 to 1000 (one to many 32-reflector
-blocks, ragged tails), matrices with exactly repeated and tightly clustered
+blocks, ragged tails) and of size 4500 (the tiled product of the trailing
+block, then the row pass), matrices with exactly repeated and tightly clustered
 eigenvalues, a diagonal and a zero matrix, the built contracted matrices of
 the tiny and small instances and of the medium one (D = 8000), and device
 arrays."""
@@ -44,6 +45,25 @@ def test_random_symmetric(n):
         w, V, info = ctx.eig_all(M)
         w2, V2, _ = ctx.eig_all(M, vectors=False)
     assert V2 is None and np.array_equal(w, w2)
+    _check(M, w, V)
+
+
+def test_random_symmetric_tiled_pass():
+    # from 3072 trailing rows on, the reduction multiplies the trailing block
+    # from its lower triangle in 128 x 128 tiles: n = 4500 switches from that
+    # to the row pass after 1428 columns, and its first tiles' last tile row
+    # holds 19 rows
+    import paper_1709_03005_amd as cc
+    n = 4500
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n))
+    M = M + M.T
+    print(f"[eig_all] tiled pass n = {n}", flush=True)
+    with cc.Context(0) as ctx:
+        w, V, info = ctx.eig_all(M)
+        w2, V2, _ = ctx.eig_all(M)
+    # every sum runs in a fixed order: a second call repeats the first bit for bit
+    assert np.array_equal(w, w2) and np.array_equal(V, V2)
     _check(M, w, V)
 
 
