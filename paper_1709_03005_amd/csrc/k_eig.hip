@@ -575,7 +575,23 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d, const d
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
-    for (int i = 1; i < m; ++i) {
+    int i = 1;
+    for (; i + 8 <= m; i += 8) {   // the loads of 8 steps go out before the chain
+        double dv[8], ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dv[u] = d[i + u];
+            ev[u] = e2[i + u - 1];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            q = dv[u] - x - ev[u] / q;
+            if (fabs(q) < pivmin) q = -pivmin;
+            c += q < 0.0;
+        }
+    }
+    for (; i < m; ++i) {
         q = d[i] - x - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
@@ -664,11 +680,33 @@ __global__ void k_tri_vectors(const double *__restrict__ dg, const double *__res
         Z[k] = 1.0;
         return;
     }
+    // Every loop below is a dependent chain over the rows; the loads of
+    // TV_B steps go out before the chain runs through them (same arithmetic
+    // in the same order).
+    constexpr int TV_B = 8;
     // forward: dp_i into S, l_i into Z (both column k)
     double dp = d[0] - lam;
     if (fabs(dp) < pivmin) dp = -pivmin;
     S[k] = dp;
-    for (int i = 0; i < m - 1; ++i) {
+    int i = 0;
+    for (; i + TV_B <= m - 1; i += TV_B) {
+        double dv[TV_B], ev[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            dv[u] = d[i + u + 1];
+            ev[u] = e[i + u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            const double l = ev[u] / dp;
+            Z[(int64_t)(i + u) * ldz + k] = l;
+            dp = dv[u] - lam - l * ev[u];
+            if (fabs(dp) < pivmin) dp = -pivmin;
+            S[(int64_t)(i + u + 1) * lds + k] = dp;
+        }
+    }
+    for (; i < m - 1; ++i) {
         const double l = e[i] / dp;
         Z[(int64_t)i * ldz + k] = l;
         dp = d[i + 1] - lam - l * e[i];
@@ -680,7 +718,29 @@ __global__ void k_tri_vectors(const double *__restrict__ dg, const double *__res
     if (fabs(dm) < pivmin) dm = -pivmin;
     int r = m - 1;
     double best = fabs(S[(int64_t)(m - 1) * lds + k] + dm - (d[m - 1] - lam));
-    for (int i = m - 2; i >= 0; --i) {
+    i = m - 2;
+    for (; i - (TV_B - 1) >= 0; i -= TV_B) {
+        double dv[TV_B], ev[TV_B], sv[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            dv[u] = d[i - u];
+            ev[u] = e[i - u];
+            sv[u] = S[(int64_t)(i - u) * lds + k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            const double uu = ev[u] / dm;
+            dm = dv[u] - lam - uu * ev[u];
+            if (fabs(dm) < pivmin) dm = -pivmin;
+            const double g = fabs(sv[u] + dm - (dv[u] - lam));
+            if (g < best) {
+                best = g;
+                r = i - u;
+            }
+        }
+    }
+    for (; i >= 0; --i) {
         const double u = e[i] / dm;
         dm = d[i] - lam - u * e[i];
         if (fabs(dm) < pivmin) dm = -pivmin;
@@ -693,7 +753,24 @@ __global__ void k_tri_vectors(const double *__restrict__ dg, const double *__res
     // u_i for i >= r again (backward from the end), into S rows i >= r
     dm = d[m - 1] - lam;
     if (fabs(dm) < pivmin) dm = -pivmin;
-    for (int i = m - 2; i >= r; --i) {
+    i = m - 2;
+    for (; i - (TV_B - 1) >= r; i -= TV_B) {
+        double dv[TV_B], ev[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            dv[u] = d[i - u];
+            ev[u] = e[i - u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            const double uu = ev[u] / dm;
+            S[(int64_t)(i - u) * lds + k] = uu;
+            dm = dv[u] - lam - uu * ev[u];
+            if (fabs(dm) < pivmin) dm = -pivmin;
+        }
+    }
+    for (; i >= r; --i) {
         const double u = e[i] / dm;
         S[(int64_t)i * lds + k] = u;
         dm = d[i] - lam - u * e[i];
@@ -701,20 +778,55 @@ __global__ void k_tri_vectors(const double *__restrict__ dg, const double *__res
     }
     // the vector (z_r = 1), its norm
     double nrm = 1.0, z = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
+    i = r - 1;
+    for (; i - (TV_B - 1) >= 0; i -= TV_B) {
+        double lv[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) lv[u] = Z[(int64_t)(i - u) * ldz + k];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            z = -lv[u] * z;
+            Z[(int64_t)(i - u) * ldz + k] = z;
+            nrm += z * z;
+        }
+    }
+    for (; i >= 0; --i) {
         z = -Z[(int64_t)i * ldz + k] * z;
         Z[(int64_t)i * ldz + k] = z;
         nrm += z * z;
     }
     Z[(int64_t)r * ldz + k] = 1.0;
     z = 1.0;
-    for (int i = r; i < m - 1; ++i) {
+    i = r;
+    for (; i + TV_B <= m - 1; i += TV_B) {
+        double uv[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) uv[u] = S[(int64_t)(i + u) * lds + k];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) {
+            z = -uv[u] * z;
+            Z[(int64_t)(i + u + 1) * ldz + k] = z;
+            nrm += z * z;
+        }
+    }
+    for (; i < m - 1; ++i) {
         z = -S[(int64_t)i * lds + k] * z;
         Z[(int64_t)(i + 1) * ldz + k] = z;
         nrm += z * z;
     }
     const double inv = 1.0 / sqrt(nrm);
-    for (int i = 0; i < m; ++i) Z[(int64_t)i * ldz + k] *= inv;
+    i = 0;
+    for (; i + TV_B <= m; i += TV_B) {
+        double zv[TV_B];
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) zv[u] = Z[(int64_t)(i + u) * ldz + k];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < TV_B; ++u) Z[(int64_t)(i + u) * ldz + k] = zv[u] * inv;
+    }
+    for (; i < m; ++i) Z[(int64_t)i * ldz + k] *= inv;
 }
 
 hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int32_t *bs, const int32_t *bm,

@@ -4,8 +4,8 @@ that often all eigenvectors are required): eigenvalues against LAPACK
 residual ||A v - lambda v|| and orthonormality within 1e-10 (scaled by the
 spectral radius), and by overlap with LAPACK's where the eigenvalue is well
 separated. Random matrices of sizes 1 to 1000 (one to many 32-reflector
-blocks, ragged tails) and of size 4500 (the tiled product of the trailing
-block, then the row pass), matrices with exactly repeated and tightly clustered
+blocks, ragged tails) and of sizes 4500 (the tiled product of the trailing
+block, then the row pass) and 8300 (on the device), matrices with exactly repeated and tightly clustered
 eigenvalues, a diagonal and a zero matrix, the built contracted matrices of
 the tiny and small instances and of the medium one (D = 8000), and device
 arrays."""
@@ -146,6 +146,32 @@ def test_medium_all_eigenpairs():
     R = G @ V[pick].T - V[pick].T * w[pick][None, :]
     assert np.abs(R).max() <= 1e-10 * scale
     O = V[pick] @ V.T
+    O[np.arange(len(pick)), pick] -= 1.0
+    assert np.abs(O).max() <= 1e-10
+
+
+def test_random_symmetric_large():
+    # n = 8300: more than 32 column-kernel workgroups and more than 64 tiles a
+    # side at the start of the reduction; matrix and vectors stay on the GPU
+    import torch
+    import paper_1709_03005_amd as cc
+    n = 8300
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n))
+    M = M + M.T
+    print(f"[eig_all] random n = {n}", flush=True)
+    with cc.Context(0, torch.cuda.current_stream().cuda_stream) as ctx:
+        w_t, V_t, info = ctx.eig_all(torch.from_numpy(M), device=True)
+        w = w_t.cpu().numpy()
+        pick = np.concatenate([np.arange(8), n - 8 + np.arange(8), rng.choice(n, 84, replace=False)])
+        Vp = V_t[torch.from_numpy(pick).cuda()].cpu().numpy()
+        O = (V_t[torch.from_numpy(pick).cuda()] @ V_t.T).cpu().numpy()
+    wl = np.linalg.eigvalsh(M)
+    scale = np.abs(wl).max()
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - wl).max() <= 1e-10 * scale
+    R = M @ Vp.T - Vp.T * w[pick][None, :]
+    assert np.abs(R).max() <= 1e-10 * scale
     O[np.arange(len(pick)), pick] -= 1.0
     assert np.abs(O).max() <= 1e-10
 
