@@ -28,7 +28,9 @@ typedef double ex4 __attribute__((ext_vector_type(4)));
 // general FP64 MFMA product C = alpha A B + beta C (row-major C)
 //   A(i, k) = A[i * sai + k * sak], B(k, j) = B[k * sbk + j * sbj]
 // 64 x 64 tile per workgroup (4 waves of 32 x 32), K staged through LDS in
-// slices of 16; loads follow whichever index of an operand has stride 1
+// slices of 16 (the next slice loaded into registers during the products);
+// loads follow whichever index of an operand has stride 1; C, when the
+// product adds to it, is loaded at entry
 // ---------------------------------------------------------------------------
 constexpr int EG_T = 64, EG_K = 16;
 
@@ -46,26 +48,57 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv & 1, wn = wv >> 1;
     const bool a_kfast = sak == 1, b_jfast = sbj == 1;
+    // C of this thread's outputs, loaded at entry when the product adds to it
+    const bool addc = P == nullptr && beta != 0.0;
+    double cin[2][4][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+                const int j = j0 + wn * 32 + b * 16 + (lane & 15);
+                cin[a][v][b] = addc && i < M && j < N ? C[(int64_t)i * ldc + j] : 0.0;
+            }
     ex4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = (ex4){0.0, 0.0, 0.0, 0.0};
-    for (int k0 = kb0; k0 < kb1; k0 += EG_K) {
+    // the K slices pass through registers: the next one is loaded while the
+    // current one is multiplied from LDS
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int ii, kk;
             if (a_kfast) { kk = t & 15; ii = (t >> 4) + 16 * u; }
             else { ii = t & 63; kk = (t >> 6) + 4 * u; }
             const int i = i0 + ii, k = k0 + kk;
-            As[kk][ii] = (i < M && k < kb1) ? A[(int64_t)i * sai + (int64_t)k * sak] : 0.0;
+            ra[u] = (i < M && k < kb1) ? A[(int64_t)i * sai + (int64_t)k * sak] : 0.0;
             int jj, kb;
             if (b_jfast) { jj = t & 63; kb = (t >> 6) + 4 * u; }
             else { kb = t & 15; jj = (t >> 4) + 16 * u; }
             const int j = j0 + jj, kq = k0 + kb;
-            Bs[kb][jj] = (j < N && kq < kb1) ? B[(int64_t)kq * sbk + (int64_t)j * sbj] : 0.0;
+            rb[u] = (j < N && kq < kb1) ? B[(int64_t)kq * sbk + (int64_t)j * sbj] : 0.0;
+        }
+    };
+    if (kb0 < kb1) load(kb0);
+    for (int k0 = kb0; k0 < kb1; k0 += EG_K) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int ii, kk;
+            if (a_kfast) { kk = t & 15; ii = (t >> 4) + 16 * u; }
+            else { ii = t & 63; kk = (t >> 6) + 4 * u; }
+            As[kk][ii] = ra[u];
+            int jj, kb;
+            if (b_jfast) { jj = t & 63; kb = (t >> 6) + 4 * u; }
+            else { kb = t & 15; jj = (t >> 4) + 16 * u; }
+            Bs[kb][jj] = rb[u];
         }
         __syncthreads();
+        if (k0 + EG_K < kb1) load(k0 + EG_K);
 #pragma unroll
         for (int ks = 0; ks < EG_K; ks += 4) {
             const int kk = ks + (lane >> 4);
@@ -92,12 +125,8 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
             for (int b = 0; b < 2; ++b) {
                 const int j = j0 + wn * 32 + b * 16 + (lane & 15);
                 if (j >= N) continue;
-                if (P) {
-                    P[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b][v];
-                } else {
-                    double *c = C + (int64_t)i * ldc + j;
-                    *c = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * *c);
-                }
+                if (P) P[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b][v];
+                else C[(int64_t)i * ldc + j] = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * cin[a][v][b]);
             }
         }
 }
