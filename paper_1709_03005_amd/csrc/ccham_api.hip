@@ -2884,11 +2884,14 @@ cch_status cch_davidson(cch_ctx *c, const cch_dav_opts *o, double *evals, double
     std::vector<double> hdiag(D);
     DCK(hipMemcpyAsync(hdiag.data(), c->d_diag, 8 * (size_t)D, hipMemcpyDeviceToHost, st));
     DCK(hipStreamSynchronize(st));
-    std::vector<int32_t> order(D);
-    for (int i = 0; i < D; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return hdiag[a] < hdiag[bb]; });
     int nb = k0;
     const int ns = std::min(mmax, D);
+    // only the first ns of the order (by value, then index) are needed
+    std::vector<int32_t> order(D);
+    for (int i = 0; i < D; ++i) order[i] = i;
+    std::partial_sort(order.begin(), order.begin() + ns, order.end(), [&](int a, int bb) {
+        return hdiag[a] < hdiag[bb] || (!(hdiag[bb] < hdiag[a]) && a < bb);
+    });
     DCK(hipMemcpy(b.idx, order.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
     if (c->sparse) DCK(launch_sparse_principal(sparse_mat(c), b.idx, ns, b.G, mmax, st));
     else DCK(launch_gather_principal(c->d_H, c->ld, b.idx, ns, b.G, mmax, st));
