@@ -1000,43 +1000,72 @@ hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, i
 
 // T (nb x nb, upper triangular) of the compact WY form from the Gram matrix
 // G = Vb^T Vb and the scalars tau: T[i][i] = tau_i,
-// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-// one workgroup, G and T in LDS, T built column by column (thread r forms
-// entry r of column i; the sum over q runs in order)
+// T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]. One workgroup, all in LDS: the
+// four diagonal blocks of 16 by that column recurrence side by side (one
+// wave each; thread r forms entry r, its sum in order), then neighbouring
+// blocks joined, 16 -> 32 -> 64, by T12 = -T11 G12 T22 (the same T: the
+// product of the first reflectors times that of the next ones)
 constexpr int LARFT_MAX = 64;
-__global__ __launch_bounds__(64) void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb,
-                                              double *__restrict__ T)
+__global__ __launch_bounds__(256) void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb,
+                                               double *__restrict__ T)
 {
     __shared__ double Ts[LARFT_MAX][LARFT_MAX + 1];
     __shared__ double Gs[LARFT_MAX][LARFT_MAX + 1];
+    __shared__ double Ws[LARFT_MAX / 2][LARFT_MAX / 2 + 1];
     __shared__ double ts[LARFT_MAX];
-    const int r = threadIdx.x;
-    for (int c = 0; c < nb; ++c) Ts[r][c] = 0.0;
-    // G row by row, a row per pass of the 64 threads (the loads batched)
-#pragma unroll 16
-    for (int q = 0; q < nb; ++q)
-        if (r < nb) Gs[q][r] = G[q * nb + r];
-    if (r < nb) ts[r] = tau[r];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int e = t; e < LARFT_MAX * LARFT_MAX; e += 256) Ts[e / LARFT_MAX][e % LARFT_MAX] = 0.0;
+#pragma unroll 4
+    for (int e = t; e < nb * nb; e += 256) Gs[e / nb][e % nb] = G[e];
+    if (t < nb) ts[t] = tau[t];
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-        const double ti = ts[i];
-        if (r < i) {
-            double s = 0.0;
-            for (int q = r; q < i; ++q) s += Ts[r][q] * Gs[q][i];
-            Ts[r][i] = -ti * s;
-        } else if (r == i) {
-            Ts[r][i] = ti;
+    // the diagonal blocks [16 wv, 16 wv + 16)
+    const int b0 = 16 * wv, bl = max(0, min(16, nb - b0));
+    for (int i = 0; i < 16; ++i) {
+        if (i < bl) {
+            const int c = b0 + i;
+            if (lane < i) {
+                double acc = 0.0;
+                for (int q = lane; q < i; ++q) acc += Ts[b0 + lane][b0 + q] * Gs[b0 + q][c];
+                Ts[b0 + lane][c] = -ts[c] * acc;
+            } else if (lane == i) {
+                Ts[c][c] = ts[c];
+            }
         }
         __syncthreads();
     }
-    if (r < nb)
-        for (int c = 0; c < nb; ++c) T[r * nb + c] = Ts[r][c];
+    // joins: rows [a0, a0 + h) (T11) with columns [c0, c0 + h2) (T22), c0 = a0 + h
+    for (int h = 16; h < nb; h *= 2) {
+        const int np = (nb + 2 * h - 1) / (2 * h);
+        // W = G12 T22 (h x h2 per pair; T22 upper triangular)
+        for (int p = 0; p < np; ++p) {
+            const int a0 = 2 * h * p, c0 = a0 + h;
+            if (c0 >= nb) break;
+            const int h2 = min(h, nb - c0);
+            for (int e = t; e < h * h2; e += 256) {
+                const int r = e / h2, cc = e % h2;
+                double acc = 0.0;
+                for (int q = 0; q <= cc; ++q) acc += Gs[a0 + r][c0 + q] * Ts[c0 + q][c0 + cc];
+                Ws[r][cc] = acc;
+            }
+            __syncthreads();
+            // T12 = -T11 W (T11 upper triangular)
+            for (int e = t; e < h * h2; e += 256) {
+                const int r = e / h2, cc = e % h2;
+                double acc = 0.0;
+                for (int q = r; q < h; ++q) acc += Ts[a0 + r][a0 + q] * Ws[q][cc];
+                Ts[a0 + r][c0 + cc] = -acc;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = t; e < nb * nb; e += 256) T[e] = Ts[e / nb][e % nb];
 }
 
 hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st)
 {
     if (nb > LARFT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, st, G, tau, nb, T);
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(256), 0, st, G, tau, nb, T);
     return hipGetLastError();
 }
 
