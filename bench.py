@@ -227,7 +227,7 @@ def cpu_baseline(inst, mode="rows", budget_s=20.0):
 
 def bench_eig_all(args):
     """Every eigenpair of the medium workload's built matrix (D = 8000) by
-    cch_eig_all (Householder tridiagonalisation, bisection, twisted
+    cch_eig_all (Householder tridiagonalisation, multisection, twisted
     factorisations, MFMA back-transformation), device phase times from the
     library's HIP events; the roofline entries are the reduction's HBM bytes
     and the back-transformation's FP64 MFMA flops."""

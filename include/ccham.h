@@ -455,7 +455,7 @@ cch_status cch_subspace_eig_noalloc(cch_ctx *ctx, const double *G, int32_t ldg, 
 /* Timing and work of cch_eig_all (device times from HIP events). */
 typedef struct {
     double tridiag_ms;          /* Householder tridiagonalisation */
-    double eigenvalues_ms;      /* bisection on Sturm counts */
+    double eigenvalues_ms;      /* multisection on Sturm counts */
     double vectors_ms;          /* twisted factorisations, cluster orthogonalisation, back-transformation */
     int32_t clusters;           /* runs of eigenvalues closer than 1e-5 ||T|| (re-orthogonalised) */
     int32_t clustered;          /* eigenvalues in those runs */
@@ -473,10 +473,12 @@ typedef struct {
  * used). w[n] receives the
  * eigenvalues ascending; V (may be NULL: eigenvalues only) receives the
  * orthonormal eigenvectors as rows, eigenvector e at V + e * ldv (ldv >= n).
- * Householder tridiagonalisation, bisection on Sturm counts, twisted
- * factorisations with modified Gram-Schmidt inside clusters of eigenvalues
- * closer than 1e-5 ||T||, and the back-transformation in blocks of 64
- * reflectors on FP64 MFMA. Work space about 3 n^2 doubles of device memory
+ * Householder tridiagonalisation (blocked in panels of 32 columns),
+ * multisection on Sturm counts, twisted factorisations with modified
+ * Gram-Schmidt (and inverse iteration for vectors that collapse) inside
+ * clusters of eigenvalues closer than 1e-5 ||T||, and the
+ * back-transformation in blocks of 64 reflectors on FP64 MFMA. Every sum
+ * runs in a fixed order: the same input gives the same bits. Work space about 3 n^2 doubles of device memory
  * (n^2 for eigenvalues only). A, w and V are host memory, or device memory
  * with CCH_MEM_DEVICE. info may be NULL. CCH_E_INPUT for a non-finite
  * matrix. Synchronous. */
