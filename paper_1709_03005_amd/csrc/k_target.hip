@@ -199,22 +199,72 @@ __global__ void k_slot_scatter(int64_t n, const int32_t *__restrict__ key,
     sorted[pos] = i;
 }
 
-// rank sort inside each bucket (values are distinct pair indices)
+// sort inside each bucket (values are distinct pair indices), one workgroup
+// per bucket: chunks of BS_CHUNK sorted in LDS by a bitonic network (padded
+// with the largest value), then neighbouring runs merged pass by pass between
+// sorted and tmp: an element goes to its index in its own run plus the number
+// of the other run's elements below it (binary search). O(n log^2 n) per
+// bucket; the result is the ascending order.
+constexpr int BS_CHUNK = 512;
 __global__ __launch_bounds__(256) void k_bucket_sort(const int64_t *__restrict__ start,
                                                      const int64_t *__restrict__ count,
                                                      int64_t *__restrict__ sorted,
                                                      int64_t *__restrict__ tmp)
 {
+    __shared__ int64_t buf[BS_CHUNK];
     const int k = blockIdx.x;
     const int64_t s0 = start[k], n = count[k];
     if (n <= 1) return;
-    for (int64_t a = threadIdx.x; a < n; a += 256) tmp[s0 + a] = sorted[s0 + a];
-    __syncthreads();
-    for (int64_t a = threadIdx.x; a < n; a += 256) {
-        const int64_t v = tmp[s0 + a];
-        int64_t r = 0;
-        for (int64_t b = 0; b < n; ++b) r += tmp[s0 + b] < v;
-        sorted[s0 + r] = v;
+    const int64_t big = 0x7fffffffffffffffLL;
+    for (int64_t c0 = 0; c0 < n; c0 += BS_CHUNK) {
+        const int cn = (int)min((int64_t)BS_CHUNK, n - c0);
+        int p2 = 1;
+        while (p2 < cn) p2 <<= 1;
+        for (int a = threadIdx.x; a < p2; a += 256) buf[a] = a < cn ? sorted[s0 + c0 + a] : big;
+        __syncthreads();
+        for (int size = 2; size <= p2; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int a = threadIdx.x; a < p2 / 2; a += 256) {
+                    const int i = 2 * a - (a & (stride - 1)), jx = i + stride;   // bit `stride` of i clear
+                    const bool up = (i & size) == 0;
+                    const int64_t x = buf[i], y = buf[jx];
+                    if ((x > y) == up) {
+                        buf[i] = y;
+                        buf[jx] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        for (int a = threadIdx.x; a < cn; a += 256) sorted[s0 + c0 + a] = buf[a];
+        __syncthreads();
+    }
+    int64_t *src = sorted + s0, *dst = tmp + s0;
+    for (int64_t run = BS_CHUNK; run < n; run *= 2) {
+        for (int64_t a = threadIdx.x; a < n; a += 256) {
+            const int64_t r0 = a / (2 * run) * (2 * run);
+            const int64_t mid = min(n, r0 + run), end = min(n, r0 + 2 * run);
+            const int64_t v = src[a];
+            int64_t lo = mid, hi = end, pos = a - r0;   // v in the left run: count the right run's smaller
+            if (a >= mid) {
+                lo = r0;
+                hi = mid;
+                pos = a - mid;
+            }
+            const int64_t base = lo;
+            while (lo < hi) {
+                const int64_t m = (lo + hi) / 2;
+                if (src[m] < v) lo = m + 1;
+                else hi = m;
+            }
+            dst[r0 + pos + (lo - base)] = v;
+        }
+        __syncthreads();
+        int64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != sorted + s0) {
+        for (int64_t a = threadIdx.x; a < n; a += 256) sorted[s0 + a] = src[a];
     }
 }
 
