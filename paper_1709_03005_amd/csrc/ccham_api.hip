@@ -1888,12 +1888,11 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
     tp.PV = pan;
     tp.PW = pan + (int64_t)2 * TRD_NB * ld;
     tp.ldp = ld;
-    tp.z = pan + (int64_t)4 * TRD_NB * ld;
-    tp.part1 = tp.z + 2 * TRD_NB;
+    tp.part1 = pan + (int64_t)4 * TRD_NB * ld;
     tp.part2 = tp.part1 + (int64_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS;
     tp.rowp = tp.part2 + (n + 3) / 4;
     tp.colp = tp.rowp + (int64_t)trd_tiles(n) * n;
-    tp.zb = tp.colp + (int64_t)trd_tiles(n) * n;
+    tp.z = tp.colp + (int64_t)trd_tiles(n) * n;
     for (int j0 = 0; j0 < n; j0 += TRD_NB) EGK(launch_trd_panel(W, ld, n, j0, std::min(TRD_NB, n - j0), tv, tp, st));
     EGK(hipEventRecord(e1, st));
     // Gershgorin interval, pivot floor and the split of T into unreduced

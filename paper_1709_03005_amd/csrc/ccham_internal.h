@@ -256,11 +256,10 @@ constexpr int TRD_SR = 32;   // rows per workgroup of the tiled pass's row sums
 struct TrdPanel {
     double *PV, *PW;   // 2 TRD_NB rows each, ldp doubles a row
     int64_t ldp;
-    double *z;         // 2 TRD_NB
     double *part1;     // column kernel: TRD_PS partial sums per workgroup
     double *part2;     // row pass: one partial sum per workgroup
     double *rowp, *colp;   // tiled pass: [tile column][n] row sums, [tile row][n] column sums
-    double *zb;            // tiled pass: [0] scale, [1 + d] z[d] of its reflector
+    double *z;             // tiled pass: z[d] of its reflector (2 TRD_NB)
 };
 
 // tiles per side of the tiled pass over m trailing rows
@@ -270,8 +269,8 @@ __host__ __device__ inline int trd_tiles(int m) { return (m + TRD_TT - 1) / TRD_
 inline size_t trd_panel_doubles(int n, int64_t ldp)
 {
     const size_t T = (size_t)trd_tiles(n);
-    return (size_t)4 * TRD_NB * ldp + 2 * TRD_NB + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4 +
-           2 * T * (size_t)n + 2 * TRD_NB + 8;
+    return (size_t)4 * TRD_NB * ldp + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4 +
+           2 * T * (size_t)n + 2 * TRD_NB;
 }
 
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for

@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
 // the diagonal) into colp[rt]; k_trd_tile_sum adds them per row in a fixed
 // order. As in the row
 // pass every workgroup first forms the reflector of column j; workgroup 0
-// stores e[j], tau[j], scale and z, and the tiles of column 0 store v_j for
+// stores e[j], tau[j] and z, and the tiles of column 0 store v_j for
 // their rows.
 __global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, int64_t lda, int n, int j, int i, TrdVec V,
                                                    TrdPanel P)
@@ -432,7 +432,6 @@ __global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, in
         if (b == 0) {
             V.e[j] = beta;
             V.tau[j] = tau;
-            P.zb[0] = scale;
         }
     }
     __syncthreads();
@@ -440,7 +439,7 @@ __global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, in
     const double ve = e < n ? (e == j + 1 ? 1.0 : xe * scale) : 0.0;
     if (t < TRD_TT) vr[t] = ve;
     else vc[t - TRD_TT] = ve;
-    if (b == 0 && t < 2 * i) P.zb[1 + t] = pz + scale * red[t + 1];
+    if (b == 0 && t < 2 * i) P.z[t] = pz + scale * red[t + 1];
     if (ct == 0 && t < TRD_TT && e < n) {
         A[(int64_t)e * lda + j] = ve;   // kept for the back-transformation
         P.PV[(int64_t)(2 * i) * P.ldp + e] = ve;
@@ -525,7 +524,7 @@ __global__ __launch_bounds__(256) void k_trd_tile_sum(int n, int j, int i, TrdVe
             for (int k = 0; k < 4; ++k) s += u[k];
         }
         for (int k = l; k < i; k += 8)
-            q += P.PV[(int64_t)(2 * k) * P.ldp + r] * P.zb[2 + 2 * k] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * P.zb[1 + 2 * k];
+            q += P.PV[(int64_t)(2 * k) * P.ldp + r] * P.z[2 * k + 1] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * P.z[2 * k];
     }
     for (int o = 4; o > 0; o >>= 1) {
         s += __shfl_xor(s, o, 8);
