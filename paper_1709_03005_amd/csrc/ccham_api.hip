@@ -1885,10 +1885,11 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
     TrdVec tv{vec, vec + n, vec + 2 * (int64_t)n, vec + 3 * (int64_t)n, vec + 4 * (int64_t)n};
     double *e2v = vec + 8 * (int64_t)n;
     TrdPanel tp;
-    tp.PV = pan;
-    tp.PW = pan + (int64_t)2 * TRD_NB * ld;
+    tp.PVt = pan;
+    tp.PV = pan + (int64_t)2 * TRD_NB * n;
+    tp.PW = tp.PV + (int64_t)2 * TRD_NB * ld;
     tp.ldp = ld;
-    tp.part1 = pan + (int64_t)4 * TRD_NB * ld;
+    tp.part1 = tp.PV + (int64_t)4 * TRD_NB * ld;
     tp.part2 = tp.part1 + (int64_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS;
     tp.rowp = tp.part2 + (n + 3) / 4;
     tp.colp = tp.rowp + (int64_t)trd_tiles(n) * n;

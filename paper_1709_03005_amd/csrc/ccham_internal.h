@@ -248,14 +248,16 @@ struct TrdVec {
 constexpr int TRD_NB = 32;
 // rows per workgroup of the column kernel, and the stride of its partial sums
 constexpr int TRD_CR = 256, TRD_PS = 2 * TRD_NB + 8;
+constexpr int TRD_PT = 2 * TRD_NB;   // doubles per row of PVt
 // trailing blocks of at least TRD_TILE_MIN rows are multiplied from their
 // lower triangle in TRD_TT x TRD_TT tiles (below that the row pass reads
 // whole rows)
 constexpr int TRD_TT = 128, TRD_TILE_MIN = 3072;
 constexpr int TRD_SR = 32;   // rows per workgroup of the tiled pass's row sums
 struct TrdPanel {
-    double *PV, *PW;   // 2 TRD_NB rows each, ldp doubles a row
+    double *PV, *PW;   // 2 TRD_NB rows each, ldp doubles a row (the panel update's operands)
     int64_t ldp;
+    double *PVt;       // PV by matrix row: PVt[r][d] = PV[d][r], 2 TRD_NB doubles a row
     double *part1;     // column kernel: TRD_PS partial sums per workgroup
     double *part2;     // row pass: one partial sum per workgroup
     double *rowp, *colp;   // tiled pass: [tile column][n] row sums, [tile row][n] column sums
@@ -269,8 +271,8 @@ __host__ __device__ inline int trd_tiles(int m) { return (m + TRD_TT - 1) / TRD_
 inline size_t trd_panel_doubles(int n, int64_t ldp)
 {
     const size_t T = (size_t)trd_tiles(n);
-    return (size_t)4 * TRD_NB * ldp + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS + (size_t)(n + 3) / 4 +
-           2 * T * (size_t)n + 2 * TRD_NB;
+    return (size_t)2 * TRD_NB * n + (size_t)4 * TRD_NB * ldp + (size_t)((n + TRD_CR - 1) / TRD_CR) * TRD_PS +
+           (size_t)(n + 3) / 4 + 2 * T * (size_t)n + 2 * TRD_NB;
 }
 
 // a matrix whose L2 block (classes 2 and 8) is held as CSR: P[r][c] for

@@ -193,9 +193,11 @@ hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, i
 // of at least TRD_TILE_MIN rows the pass reads only the lower triangle, in
 // tiles, and a second kernel adds each row's tile sums.
 // panel buffers (ldp doubles a row): PV rows 2k, 2k + 1 = v_k, w_k; PW rows
-// 2k, 2k + 1 = w_k, v_k (the update is A -= PV^T PW over 2 nb rows); z[2k] =
-// v_k . v_j, z[2k + 1] = w_k . v_j. Rows of PV and PW below the reflector's
-// first row are never read.
+// 2k, 2k + 1 = w_k, v_k (the update is A -= PV^T PW over 2 nb rows); PVt the
+// same values by matrix row (PVt[r][d] = PV[d][r]: a row's panel entries are
+// contiguous for the kernels that read them per row); z[2k] = v_k . v_j,
+// z[2k + 1] = w_k . v_j. Entries below the reflector's first row are never
+// read.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double blk_sum(double x, double *red)
@@ -243,32 +245,33 @@ __global__ __launch_bounds__(256) void k_trd_col(const double *__restrict__ A, i
     double wr = 0.0;
     if (i > 0) {
         // p of reflector j - 1 (rows >= j) and the scalar -(tau / 2)(p . v) of its w
-        const double *vq = P.PV + (int64_t)(2 * i - 2) * P.ldp;
+        const double *vq = P.PVt + (2 * i - 2);   // v of reflector i - 1, stride 2 TRD_NB
         // (the row pass leaves one partial sum of p . v per 4 rows, the sum
         // kernel of the tiled pass one per TRD_SR rows)
         const int g2 = n - j < TRD_TILE_MIN ? (n - j + 3) / 4 : (n - j + TRD_SR - 1) / TRD_SR;
         const double al = -0.5 * V.tau[j - 1] * blk_sum(ordered_sum(P.part2, 1, t, g2, 256), red);
         const double pr = in ? V.p[r] : 0.0, pj = t == 0 ? V.p[j] : 0.0;
         if (in) {
-            wr = pr + al * vq[r];
+            wr = pr + al * vq[(int64_t)r * TRD_PT];
             P.PV[(int64_t)(2 * i - 1) * P.ldp + r] = wr;
             P.PW[(int64_t)(2 * i - 2) * P.ldp + r] = wr;
+            P.PVt[(int64_t)r * TRD_PT + 2 * i - 1] = wr;
         }
         if (col && t == 0) {
-            vw[2 * i - 2] = vq[j];
-            vw[2 * i - 1] = pj + al * vq[j];
+            vw[2 * i - 2] = vq[(int64_t)j * TRD_PT];
+            vw[2 * i - 1] = pj + al * vq[(int64_t)j * TRD_PT];
         }
     }
     if (!col) return;
-    for (int e = t; e < 2 * i - 2; e += 256) vw[e] = P.PV[(int64_t)e * P.ldp + j];
+    for (int e = t; e < 2 * i - 2; e += 256) vw[e] = P.PVt[(int64_t)j * TRD_PT + e];
     __syncthreads();
     double x = 0.0;
     if (in) {
         x = A[(int64_t)r * lda + j];
 #pragma unroll 4
         for (int k = 0; k < i - 1; ++k)
-            x -= P.PV[(int64_t)(2 * k) * P.ldp + r] * vw[2 * k + 1] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * vw[2 * k];
-        if (i > 0) x -= P.PV[(int64_t)(2 * i - 2) * P.ldp + r] * vw[2 * i - 1] + wr * vw[2 * i - 2];
+            x -= P.PVt[(int64_t)r * TRD_PT + 2 * k] * vw[2 * k + 1] + P.PVt[(int64_t)r * TRD_PT + 2 * k + 1] * vw[2 * k];
+        if (i > 0) x -= P.PVt[(int64_t)r * TRD_PT + 2 * i - 2] * vw[2 * i - 1] + wr * vw[2 * i - 2];
         V.wp[r] = x;
         if (r == j) V.d[j] = x;
     }
@@ -282,10 +285,11 @@ __global__ __launch_bounds__(256) void k_trd_col(const double *__restrict__ A, i
     const int q = t & 63, g = t >> 6;
     double y = 0.0;
     if (q < 2 * i - 1) {
-        const double *pr = P.PV + (int64_t)q * P.ldp;
+        // (the 64 lanes read 64 consecutive entries of one row of PVt)
+        const double *pr = P.PVt + (int64_t)(r0 + 64 * g) * TRD_PT + q;
         const int lo = max(0, j + 2 - r0 - 64 * g), hi = min(64, n - r0 - 64 * g);
 #pragma unroll 16
-        for (int k = lo; k < hi; ++k) y += pr[r0 + 64 * g + k] * xs[64 * g + k];
+        for (int k = lo; k < hi; ++k) y += pr[(int64_t)k * TRD_PT] * xs[64 * g + k];
     } else if (q == 2 * i - 1) {   // w_{i-1}, kept in ws
 #pragma unroll 16
         for (int k = 0; k < 64; ++k) y += ws[64 * g + k] * xs[64 * g + k];
@@ -327,12 +331,12 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
         for (int b = 0; b < 32; ++b) ps += u[b];
         for (int b = 32; b < g1; ++b) ps += P.part1[(int64_t)b * TRD_PS + t];
     }
-    const double pz = t < 2 * i ? P.PV[(int64_t)t * P.ldp + j + 1] : 0.0;
+    const double pz = t < 2 * i ? P.PVt[(int64_t)(j + 1) * TRD_PT + t] : 0.0;
     const double alpha = t == 0 ? V.wp[j + 1] : 0.0;
     double k0 = 0.0, k1 = 0.0, xr = 0.0;
     if (in && lane < i) {
-        k0 = P.PV[(int64_t)(2 * lane) * P.ldp + r];
-        k1 = P.PV[(int64_t)(2 * lane + 1) * P.ldp + r];
+        k0 = P.PVt[(int64_t)r * TRD_PT + 2 * lane];
+        k1 = P.PVt[(int64_t)r * TRD_PT + 2 * lane + 1];
     }
     if (in) xr = V.wp[r];
     // the row: A_0[r][j+1] and A_0[r][j+2:] . x
@@ -378,6 +382,7 @@ __global__ __launch_bounds__(256) void k_trd_pass(double *__restrict__ A, int64_
             A[(int64_t)r * lda + j] = vr;   // kept for the back-transformation
             P.PV[(int64_t)(2 * i) * P.ldp + r] = vr;
             P.PW[(int64_t)(2 * i + 1) * P.ldp + r] = vr;
+            P.PVt[(int64_t)r * TRD_PT + 2 * i] = vr;
         }
         pv = p * vr;
     }
@@ -414,7 +419,7 @@ __global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, in
     // the reflector of column j (as in the row pass)
     const int g1 = (n - j + TRD_CR - 1) / TRD_CR;
     const double ps = t < 2 * i + 1 ? ordered_sum(P.part1 + t, TRD_PS, 0, g1, 1) : 0.0;
-    const double pz = t < 2 * i ? P.PV[(int64_t)t * P.ldp + j + 1] : 0.0;
+    const double pz = t < 2 * i ? P.PVt[(int64_t)(j + 1) * TRD_PT + t] : 0.0;
     const double alpha = t == 0 ? V.wp[j + 1] : 0.0;
     const int e = t < TRD_TT ? R0 + t : C0 + t - TRD_TT;   // this thread's row (t < TT) or column of x
     const double xe = e < n ? V.wp[e] : 0.0;
@@ -444,6 +449,7 @@ __global__ __launch_bounds__(256, 4) void k_trd_tiles(double *__restrict__ A, in
         A[(int64_t)e * lda + j] = ve;   // kept for the back-transformation
         P.PV[(int64_t)(2 * i) * P.ldp + e] = ve;
         P.PW[(int64_t)(2 * i + 1) * P.ldp + e] = ve;
+        P.PVt[(int64_t)e * TRD_PT + 2 * i] = ve;
     }
     __syncthreads();
     // wave wv: tile rows 32 wv .. 32 wv + 31 in four groups of 8, lanes over
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(256) void k_trd_tile_sum(int n, int j, int i, TrdVe
             for (int k = 0; k < 4; ++k) s += u[k];
         }
         for (int k = l; k < i; k += 8)
-            q += P.PV[(int64_t)(2 * k) * P.ldp + r] * P.z[2 * k + 1] + P.PV[(int64_t)(2 * k + 1) * P.ldp + r] * P.z[2 * k];
+            q += P.PVt[(int64_t)r * TRD_PT + 2 * k] * P.z[2 * k + 1] + P.PVt[(int64_t)r * TRD_PT + 2 * k + 1] * P.z[2 * k];
     }
     for (int o = 4; o > 0; o >>= 1) {
         s += __shfl_xor(s, o, 8);
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(256) void k_trd_tile_sum(int n, int j, int i, TrdVe
     if (r < n && l == 0) {
         const double p = V.tau[j] * (s - q);
         V.p[r] = p;
-        pv = p * P.PV[(int64_t)(2 * i) * P.ldp + r];
+        pv = p * P.PVt[(int64_t)r * TRD_PT + 2 * i];
     }
     pv = blk_sum(pv, red);   // (rows in order of their first lane; the others add 0)
     if (t == 0) P.part2[blockIdx.x] = pv;
