@@ -5,7 +5,8 @@ residual ||A v - lambda v|| and orthonormality within 1e-10 (scaled by the
 spectral radius), and by overlap with LAPACK's where the eigenvalue is well
 separated. Random matrices of sizes 1 to 1000 (one to many 32-reflector
 blocks, ragged tails) and of sizes 4500 (the tiled product of the trailing
-block, then the row pass) and 8300 (on the device), matrices with exactly repeated and tightly clustered
+block, then the row pass) and 8300 (on the device), a diagonal matrix of
+size 3300 (every column already reduced, through both passes), matrices with exactly repeated and tightly clustered
 eigenvalues, a diagonal and a zero matrix, the built contracted matrices of
 the tiny and small instances and of the medium one (D = 8000), and device
 arrays."""
@@ -65,6 +66,27 @@ def test_random_symmetric_tiled_pass():
     # every sum runs in a fixed order: a second call repeats the first bit for bit
     assert np.array_equal(w, w2) and np.array_equal(V, V2)
     _check(M, w, V)
+
+
+def test_large_diagonal_tiled_pass():
+    # every column is already reduced (sigma = 0, tau = 0), through the tiled
+    # product (n - 1 >= 3072 trailing rows) and then the row pass; T splits
+    # into 1 x 1 blocks
+    import paper_1709_03005_amd as cc
+    n = 3300
+    rng = np.random.default_rng(7)
+    d = rng.uniform(-5.0, 5.0, n)
+    d[100:110] = 1.25                     # a repeated value
+    M = np.diag(d)
+    with cc.Context(0) as ctx:
+        w, V, info = ctx.eig_all(M)
+    ds = np.sort(d)
+    assert np.abs(w - ds).max() <= 1e-14 * np.abs(d).max()
+    assert np.abs(V @ V.T - np.eye(n)).max() <= 1e-12
+    # each eigenvector is a unit vector on a row holding its eigenvalue
+    piv = np.abs(V).argmax(axis=1)
+    assert np.allclose(np.abs(V[np.arange(n), piv]), 1.0)
+    assert np.abs(d[piv] - w).max() <= 1e-14 * np.abs(d).max()
 
 
 def test_repeated_and_clustered():
