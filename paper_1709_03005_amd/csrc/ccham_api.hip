@@ -120,7 +120,7 @@ hipError_t launch_sparse_row_norms(const SparseMat &S, int D, double *rho, hipSt
 // full-spectrum eigensolver
 hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
                            const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
-                           hipStream_t st, double *P = nullptr, int64_t p_cap = 0);
+                           hipStream_t st, double *P = nullptr, int64_t p_cap = 0, int lowq = -1);
 hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, const TrdVec &V, const TrdPanel &P,
                             hipStream_t st);
 hipError_t launch_tri_eigenvalues(const double *d, const double *e, double *e2, int n, const int32_t *bs,

@@ -40,8 +40,11 @@ constexpr int EG_T = 64, EG_K = 16;
 __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                   int64_t sai, int64_t sak, const double *__restrict__ B, int64_t sbk,
                                                   int64_t sbj, double beta, double *__restrict__ C, int64_t ldc,
-                                                  int kc, double *__restrict__ P)
+                                                  int kc, double *__restrict__ P, int lowq)
 {
+    // lowq >= 0: only the tiles on and below the diagonal, and every tile of
+    // the square of tile rows and columns >= lowq
+    if (lowq >= 0 && (int)blockIdx.x > (int)blockIdx.y && ((int)blockIdx.x < lowq || (int)blockIdx.y < lowq)) return;
     __shared__ double As[EG_K][EG_T + 1], Bs[EG_K][EG_T + 1];
     const int i0 = blockIdx.y * EG_T, j0 = blockIdx.x * EG_T;
     const int kb0 = P ? (int)blockIdx.z * kc : 0, kb1 = P ? min(K, kb0 + kc) : K;
@@ -147,25 +150,25 @@ __global__ void k_eig_gemm_sum(int M, int N, int ns, const double *__restrict__ 
 // back-transformation)
 hipError_t launch_eig_gemm(int M, int N, int K, double alpha, const double *A, int64_t sai, int64_t sak,
                            const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc,
-                           hipStream_t st, double *P, int64_t p_cap)
+                           hipStream_t st, double *P, int64_t p_cap, int lowq)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const dim3 g((N + EG_T - 1) / EG_T, (M + EG_T - 1) / EG_T);
     const int64_t tiles = (int64_t)g.x * g.y;
     int ns = 1;
-    if (P && tiles < 512 && K >= 1024) {
+    if (P && lowq < 0 && tiles < 512 && K >= 1024) {
         ns = (int)std::min<int64_t>({(K + 255) / 256, std::max<int64_t>(1, 1024 / tiles), 64});
         ns = (int)std::min<int64_t>(ns, p_cap / ((int64_t)M * N));
     }
     if (ns <= 1) {
         hipLaunchKernelGGL(k_eig_gemm, g, dim3(256), 0, st, M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc,
-                           K, (double *)nullptr);
+                           K, (double *)nullptr, lowq);
         return hipGetLastError();
     }
     const int kc = ((K + ns - 1) / ns + EG_K - 1) / EG_K * EG_K;
     ns = (K + kc - 1) / kc;
     hipLaunchKernelGGL(k_eig_gemm, dim3(g.x, g.y, ns), dim3(256), 0, st, M, N, K, alpha, A, sai, sak, B, sbk, sbj,
-                       beta, C, ldc, kc, P);
+                       beta, C, ldc, kc, P, -1);
     const int64_t e = (int64_t)M * N;
     hipLaunchKernelGGL(k_eig_gemm_sum, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, M, N, ns, P, alpha, beta,
                        C, ldc);
@@ -573,8 +576,13 @@ hipError_t launch_trd_panel(double *A, int64_t lda, int n, int j0, int nbp, cons
                            P);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        // while the trailing block has TRD_TILE_MIN rows or more it is read
+        // only below the diagonal (tiled product, column kernel, reflectors);
+        // the row pass reads whole rows of the last TRD_TILE_MIN, so the
+        // square from a tile row at or before n - TRD_TILE_MIN is updated whole
+        const int lowq = n - TRD_TILE_MIN - t > 0 ? (n - TRD_TILE_MIN - t) / EG_T : 0;
         return launch_eig_gemm(n - t, n - t, 2 * nbp, -1.0, P.PV + t, 1, P.ldp, P.PW + t, P.ldp, 1, 1.0,
-                               A + (int64_t)t * lda + t, lda, st, nullptr, 0);
+                               A + (int64_t)t * lda + t, lda, st, nullptr, 0, lowq);
     }
     return hipGetLastError();
 }
