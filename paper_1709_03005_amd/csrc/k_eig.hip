@@ -9,7 +9,7 @@
 //      while the block has at least TRD_TILE_MIN rows; by whole rows below
 //      that), and one rank-2 TRD_NB FP64 MFMA update of the trailing block
 //      per panel.
-//   2. Eigenvalues of T by multisection on Sturm counts, 16 lanes each.
+//   2. Eigenvalues of T by multisection on Sturm counts, 8 lanes each.
 //   3. Eigenvectors of T by twisted factorisations, one thread each, with
 //      modified Gram-Schmidt (and inverse iteration for vectors that
 //      collapse) inside clusters of close eigenvalues, one workgroup each.
@@ -646,9 +646,11 @@ __device__ __forceinline__ int sturm_count(const double *__restrict__ d, const d
 // Sturm count at TRI_G interior points, and the interval shrinks to the piece
 // between the last point with count <= k and the first with count > k, until
 // no representable point lies strictly inside. With monotone counts this ends
-// on the same pair of adjacent doubles as bisection, in about a quarter of
-// the dependent steps.
-constexpr int TRI_G = 16;
+// on the same pair of adjacent doubles as bisection, in about a third of the
+// dependent steps. (8 lanes: 12.7 ms for the 8000 eigenvalues of the D =
+// 8000 matrix; 16 lanes 13.6 ms, 32 lanes 19.0 ms, 64 lanes 29.5 ms: the
+// counts are bound by issue, not by the length of the chain.)
+constexpr int TRI_G = 8;
 __global__ __launch_bounds__(256) void k_tri_bisect(const double *__restrict__ d, const double *__restrict__ e2, int n,
                                                     const int32_t *__restrict__ bs, const int32_t *__restrict__ bm,
                                                     const int32_t *__restrict__ bk, double lo0, double hi0,
