@@ -22,12 +22,11 @@
 
 namespace cch {
 
-typedef double ex4 __attribute__((ext_vector_type(4)));
-
 // ---------------------------------------------------------------------------
 // general FP64 MFMA product C = alpha A B + beta C (row-major C)
 //   A(i, k) = A[i * sai + k * sak], B(k, j) = B[k * sbk + j * sbj]
-// 64 x 64 tile per workgroup (4 waves of 32 x 32), K staged through LDS in
+// 64 x 64 tile per workgroup (4 waves of 32 x 32, on the 4x4x4 form: it
+// issues faster per flop than 16x16x4 on this chip), K staged through LDS in
 // slices of 16 (the next slice loaded into registers during the products);
 // loads follow whichever index of an operand has stride 1; C, when the
 // product adds to it, is loaded at entry
@@ -53,22 +52,24 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
     const bool a_kfast = sak == 1, b_jfast = sbj == 1;
     // C of this thread's outputs, loaded at entry when the product adds to it
     const bool addc = P == nullptr && beta != 0.0;
-    double cin[2][4][2];
+    // 4x4x4 FP64 MFMA, four blocks with the same A: an instruction multiplies
+    // 4 rows (A at lane i + 16 k, any block) by 16 columns (B at lane
+    // j + 16 k), the result D[i][j] at lane j + 16 i. A wave's 32 x 32 tile is
+    // 8 row quads x 2 column groups.
+    double cin[8][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int b = 0; b < 2; ++b) {
+            const int i = i0 + wm * 32 + 4 * a + (lane >> 4);
+            const int j = j0 + wn * 32 + 16 * b + (lane & 15);
+            cin[a][b] = addc && i < M && j < N ? C[(int64_t)i * ldc + j] : 0.0;
+        }
+    double acc[8][2];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-                const int j = j0 + wn * 32 + b * 16 + (lane & 15);
-                cin[a][v][b] = addc && i < M && j < N ? C[(int64_t)i * ldc + j] : 0.0;
-            }
-    ex4 acc[2][2];
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (ex4){0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 2; ++b) acc[a][b] = 0.0;
     // the K slices pass through registers: the next one is loaded while the
     // current one is multiplied from LDS
     double ra[4], rb[4];
@@ -105,33 +106,31 @@ __global__ __launch_bounds__(256) void k_eig_gemm(int M, int N, int K, double al
 #pragma unroll
         for (int ks = 0; ks < EG_K; ks += 4) {
             const int kk = ks + (lane >> 4);
-            double af[2], bf[2];
+            double af[8], bf[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[kk][wm * 32 + a * 16 + (lane & 15)];
+            for (int a = 0; a < 8; ++a) af[a] = As[kk][wm * 32 + 4 * a + (lane & 3)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk][wn * 32 + b * 16 + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk][wn * 32 + 16 * b + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 8; ++a) {
+        const int i = i0 + wm * 32 + 4 * a + (lane >> 4);
+        if (i >= M) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-            if (i >= M) continue;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int j = j0 + wn * 32 + b * 16 + (lane & 15);
-                if (j >= N) continue;
-                if (P) P[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b][v];
-                else C[(int64_t)i * ldc + j] = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * cin[a][v][b]);
-            }
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + wn * 32 + 16 * b + (lane & 15);
+            if (j >= N) continue;
+            if (P) P[((int64_t)blockIdx.z * M + i) * N + j] = acc[a][b];
+            else C[(int64_t)i * ldc + j] = alpha * acc[a][b] + (beta == 0.0 ? 0.0 : beta * cin[a][b]);
         }
+    }
 }
 
 __global__ void k_eig_gemm_sum(int M, int N, int ns, const double *__restrict__ P, double alpha, double beta,
