@@ -132,7 +132,7 @@ hipError_t launch_tri_vectors(const double *d, const double *e, int n, const int
 hipError_t launch_cluster_mgs(double *Z, int64_t ldz, const int32_t *desc, int ncl, const int32_t *cols, const double *d,
                               const double *e, const double *w, double *S, int64_t lds, double piv, hipStream_t st);
 hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, int nb, double *Vb, hipStream_t st);
-hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st);
+hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, double *X, hipStream_t st);
 hipError_t launch_symmetrize(double *W, int64_t ld, int n, hipStream_t st);
 hipError_t launch_transpose_sq(const double *Z, int64_t ldz, int n, double *out, int64_t ldo, hipStream_t st);
 int64_t l2csr_scratch(int D, int Dc);
@@ -1829,7 +1829,7 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
     hipStream_t st = c->stream;
     const bool dev = flags & CCH_MEM_DEVICE;
     const int64_t ld = ((int64_t)n + 31) / 32 * 32;
-    const int NB = 64;   // reflectors per block of the back-transformation (at most 64: k_larft)
+    const int NB = 128;   // reflectors per block of the back-transformation (at most 128: launch_larft)
     std::vector<void *> tmp;
     auto cleanup = [&]() { for (void *p : tmp) (void)hipFree(p); };
     auto al = [&](void **p, size_t bytes) -> bool {
@@ -2015,7 +2015,7 @@ cch_status cch_eig_all(cch_ctx *c, const double *A, int64_t lda, int32_t n, doub
             double *Wt = S, *W2 = S + (int64_t)NB * n;   // the twisted-factorisation scratch is free now
             EGK(launch_copy_reflectors(W, ld, n, j0, nb, Vb, st));
             EGK(launch_eig_gemm(nb, nb, m, 1.0, Vb, 1, nb, Vb, nb, 1, 0.0, G, nb, st, Pk, p_cap));
-            EGK(launch_larft(G, tv.tau + j0, nb, T, st));
+            EGK(launch_larft(G, tv.tau + j0, nb, T, Pk, st));   // (Pk is free between the products)
             EGK(launch_eig_gemm(nb, n, m, 1.0, Vb, 1, nb, Zs, ld, 1, 0.0, Wt, n, st, Pk, p_cap));
             EGK(launch_eig_gemm(nb, n, nb, 1.0, T, nb, 1, Wt, n, 1, 0.0, W2, n, st));
             EGK(launch_eig_gemm(m, n, nb, -1.0, Vb, nb, 1, W2, n, 1, 1.0, Zs, ld, st));

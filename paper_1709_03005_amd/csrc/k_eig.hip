@@ -1020,8 +1020,8 @@ hipError_t launch_copy_reflectors(const double *A, int64_t lda, int n, int j0, i
 // blocks joined, 16 -> 32 -> 64, by T12 = -T11 G12 T22 (the same T: the
 // product of the first reflectors times that of the next ones)
 constexpr int LARFT_MAX = 64;
-__global__ __launch_bounds__(256) void k_larft(const double *__restrict__ G, const double *__restrict__ tau, int nb,
-                                               double *__restrict__ T)
+__global__ __launch_bounds__(256) void k_larft(const double *__restrict__ G, int ldg, const double *__restrict__ tau,
+                                               int nb, double *__restrict__ T, int ldt)
 {
     __shared__ double Ts[LARFT_MAX][LARFT_MAX + 1];
     __shared__ double Gs[LARFT_MAX][LARFT_MAX + 1];
@@ -1030,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_larft(const double *__restrict__ G, con
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int e = t; e < LARFT_MAX * LARFT_MAX; e += 256) Ts[e / LARFT_MAX][e % LARFT_MAX] = 0.0;
 #pragma unroll 4
-    for (int e = t; e < nb * nb; e += 256) Gs[e / nb][e % nb] = G[e];
+    for (int e = t; e < nb * nb; e += 256) Gs[e / nb][e % nb] = G[(int64_t)(e / nb) * ldg + e % nb];
     if (t < nb) ts[t] = tau[t];
     __syncthreads();
     // the diagonal blocks [16 wv, 16 wv + 16)
@@ -1073,14 +1073,32 @@ __global__ __launch_bounds__(256) void k_larft(const double *__restrict__ G, con
             __syncthreads();
         }
     }
-    for (int e = t; e < nb * nb; e += 256) T[e] = Ts[e / nb][e % nb];
+    for (int e = t; e < nb * nb; e += 256) T[(int64_t)(e / nb) * ldt + e % nb] = Ts[e / nb][e % nb];
 }
 
-hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, hipStream_t st)
+// T (nb x nb, row-major) for nb <= 2 LARFT_MAX: up to LARFT_MAX in one
+// workgroup; above, the two diagonal blocks of LARFT_MAX and n2 = nb -
+// LARFT_MAX reflectors, joined by T12 = -T1 (G12 T2) (two FP64 MFMA
+// products; X: LARFT_MAX x n2 doubles of scratch)
+hipError_t launch_larft(const double *G, const double *tau, int nb, double *T, double *X, hipStream_t st)
 {
-    if (nb > LARFT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_larft, dim3(1), dim3(256), 0, st, G, tau, nb, T);
-    return hipGetLastError();
+    if (nb > 2 * LARFT_MAX) return hipErrorInvalidValue;
+    if (nb <= LARFT_MAX) {
+        hipLaunchKernelGGL(k_larft, dim3(1), dim3(256), 0, st, G, nb, tau, nb, T, nb);
+        return hipGetLastError();
+    }
+    const int h = LARFT_MAX, n2 = nb - h;
+    hipError_t e = launch_fill_f64(T, 0.0, (int64_t)nb * nb, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(256), 0, st, G, nb, tau, h, T, nb);
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(256), 0, st, G + (int64_t)h * nb + h, nb, tau + h, n2,
+                       T + (int64_t)h * nb + h, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // X = G12 T2, then T12 = -T1 X
+    if ((e = launch_eig_gemm(h, n2, n2, 1.0, G + h, nb, 1, T + (int64_t)h * nb + h, nb, 1, 0.0, X, n2, st, nullptr,
+                             0, -1)) != hipSuccess)
+        return e;
+    return launch_eig_gemm(h, n2, h, -1.0, T, nb, 1, X, n2, 1, 0.0, T + h, nb, st, nullptr, 0, -1);
 }
 
 // out[k][i] = Z[i][k]
