@@ -477,7 +477,7 @@ typedef struct {
  * multisection on Sturm counts, twisted factorisations with modified
  * Gram-Schmidt (and inverse iteration for vectors that collapse) inside
  * clusters of eigenvalues closer than 1e-5 ||T||, and the
- * back-transformation in blocks of 64 reflectors on FP64 MFMA. Every sum
+ * back-transformation in blocks of 128 reflectors on FP64 MFMA. Every sum
  * runs in a fixed order: the same input gives the same bits. Work space about 3 n^2 doubles of device memory
  * (n^2 for eigenvalues only). A, w and V are host memory, or device memory
  * with CCH_MEM_DEVICE. info may be NULL. CCH_E_INPUT for a non-finite

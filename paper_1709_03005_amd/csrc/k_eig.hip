@@ -13,7 +13,7 @@
 //   3. Eigenvectors of T by twisted factorisations, one thread each, with
 //      modified Gram-Schmidt (and inverse iteration for vectors that
 //      collapse) inside clusters of close eigenvalues, one workgroup each.
-//   4. Back-transformation Z = Q Z_T in blocks of 64 reflectors, each as
+//   4. Back-transformation Z = Q Z_T in blocks of 128 reflectors, each as
 //      I - V T V^T (compact WY) by three FP64 MFMA products.
 #include <algorithm>
 #include <cmath>
