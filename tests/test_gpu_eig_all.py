@@ -4,7 +4,8 @@ that often all eigenvectors are required): eigenvalues against LAPACK
 residual ||A v - lambda v|| and orthonormality within 1e-10 (scaled by the
 spectral radius), and by overlap with LAPACK's where the eigenvalue is well
 separated. Random matrices of sizes 1 to 1000 (one to many 32-reflector
-blocks, ragged tails) and of sizes 4500 (the tiled product of the trailing
+panels and 128-reflector back-transformation blocks, ragged tails: 66 gives
+a block of 65, 130 a last block of one) and of sizes 4500 (the tiled product of the trailing
 block, then the row pass) and 8300 (on the device), a diagonal matrix of
 size 3300 (every column already reduced, through both passes), matrices with exactly repeated and tightly clustered
 eigenvalues, a diagonal and a zero matrix, the built contracted matrices of
@@ -36,7 +37,7 @@ def _check(M, w, V, tol=1e-10, lapack_vectors=True):
             assert np.all(np.abs(ov[sep] - 1.0) < 1e-8)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 64, 100, 257, 1000])
+@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 64, 66, 100, 129, 130, 257, 1000])
 def test_random_symmetric(n):
     import paper_1709_03005_amd as cc
     rng = np.random.default_rng(n)
